@@ -1,0 +1,243 @@
+/*
+ * ib_lbm.h — C ABI of the MI355X (gfx950) immersed-boundary lattice
+ * Boltzmann library.
+ *
+ * The library advances D2Q9 lattice-Boltzmann fields coupled to rigid
+ * circular bodies represented by Lagrangian markers, following Jo,
+ * "Mechanism-Resolved Interface Momentum Transfer in Immersed-Boundary
+ * Lattice Boltzmann Simulations" (arXiv 2609.02298):
+ *   - collision BGK with Guo forcing (Sec. 2.1, Eq. 1-4), TRT (Sec. 2.2) or
+ *     central-moment MRT (Sec. 2.2, Eq. 5), fused with streaming;
+ *   - immersed boundary with the hat (Eq. 9) or Peskin 4-point (Eq. 10)
+ *     regularized delta (Eq. 6-8), enforced by direct forcing (Eq. 11),
+ *     multi-direct forcing (Eq. 12-14) or distribution-function correction
+ *     (Eq. 15-20);
+ *   - hydrodynamic force and torque (Sec. 2.7), rigid-body Velocity-Verlet
+ *     update (Eq. 21-23) with the explicit internal-mass force (Eq. A3).
+ *
+ * Units: lattice units, dx = dt = 1.  Populations are nine planes
+ * f[i][y][x] with x fastest and directions
+ *   e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0) e4=(0,-1)
+ *   e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an ib_lbm_status; no C++ exception crosses the ABI.
+ *     The message of the last failure of a sim is ib_lbm_last_error().
+ *   - After IB_LBM_E_DEVICE (a failed HIP call) the sim is unusable and every
+ *     later call on it returns IB_LBM_E_STATE; only ib_lbm_destroy remains.
+ *   - Host pointers ("host") are read or written before the call returns and
+ *     are not retained.  The library owns every device buffer it allocates
+ *     and frees them in ib_lbm_destroy / ib_lbm_batch_destroy.
+ *   - Work is queued on the HIP stream given at creation; calls that return
+ *     host data synchronise that stream first.
+ *   - One sim is used by one host thread at a time.
+ */
+#ifndef IB_LBM_H
+#define IB_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IB_LBM_ABI_VERSION 1u
+
+typedef enum {
+  IB_LBM_OK = 0,
+  IB_LBM_E_INVALID = -1,  /* an argument or configuration is not supported */
+  IB_LBM_E_NOMEM = -2,    /* device allocation failed */
+  IB_LBM_E_DEVICE = -3,   /* a HIP runtime call failed */
+  IB_LBM_E_DIVERGED = -4, /* a non-finite force was produced; the sim halted */
+  IB_LBM_E_RANGE = -5,    /* a marker support left the lattice, or two bodies' supports met */
+  IB_LBM_E_STATE = -6     /* the call is not allowed in the current state */
+} ib_lbm_status;
+
+enum { IB_LBM_FP64 = 0, IB_LBM_FP32_SHIFTED = 1 };
+enum { IB_LBM_BGK = 0, IB_LBM_TRT = 1, IB_LBM_CMMRT = 2 };
+/* Face closures.  PERIODIC must be set on both faces of an axis; the
+ * zero-gradient face is supported on the east face only. */
+enum { IB_LBM_PERIODIC = 0, IB_LBM_BOUNCE_BACK = 1, IB_LBM_VEL_PARABOLIC = 2,
+       IB_LBM_VEL_UNIFORM = 3, IB_LBM_ZERO_GRADIENT = 4 };
+enum { IB_LBM_DF = 0, IB_LBM_MDF = 1, IB_LBM_DFC = 2 };
+enum { IB_LBM_HAT = 0, IB_LBM_PESKIN4 = 1 };
+enum { IB_LBM_FIXED = 0, IB_LBM_PRESCRIBED_SIN = 1, IB_LBM_FREE = 2 };
+enum { IB_LBM_IM_NONE = 0, IB_LBM_IM_FENG = 1 };
+enum { IB_LBM_SPREAD_GATHER = 0, IB_LBM_SPREAD_ATOMIC = 1 };
+
+/* Body flags reported in ib_lbm_body_state.flags */
+enum { IB_LBM_FLAG_NONFINITE = 1, IB_LBM_FLAG_RANGE = 2, IB_LBM_FLAG_OVERLAP = 4 };
+
+/* Optional device allocator (for example a caching allocator).  alloc returns
+ * device memory of at least `bytes` usable on `stream`, or NULL. */
+typedef struct {
+  void *ctx;
+  void *(*alloc)(void *ctx, size_t bytes, void *stream);
+  void (*free)(void *ctx, void *ptr, void *stream);
+} ib_lbm_allocator;
+
+/* Lattice configuration (Sec. 2.1-2.2, App. A.1).  tau > 1/2 sets the
+ * viscosity nu = (tau - 1/2)/3; trt_magic is Lambda_eo (default 1/4);
+ * cm_s_q / cm_s_eps are the third- and fourth-order central-moment rates
+ * (1.2 / 1.4).  gravity acts on bodies only (reduced pressure, Eq. 22);
+ * fluid_force is a uniform body-force density on the fluid (zero in the
+ * paper's runs, used for forced channel flows).  history_capacity: number of
+ * most recent steps kept per body in the device history ring (0 -> 4096). */
+typedef struct {
+  uint32_t abi_version; /* must equal IB_LBM_ABI_VERSION */
+  int32_t nx, ny;       /* nodes, x streamwise; 3 <= nx, ny; nx*ny < 2^31 */
+  int32_t precision;    /* IB_LBM_FP64 | IB_LBM_FP32_SHIFTED */
+  int32_t collision;    /* IB_LBM_BGK | IB_LBM_TRT | IB_LBM_CMMRT */
+  int32_t history_capacity;
+  double tau;
+  double trt_magic;
+  double cm_s_q, cm_s_eps;
+  double rho0;          /* reference density, 1 in the paper */
+  int32_t bc[4];        /* faces W, E, S, N */
+  double u_bc;          /* u_max of a parabolic inlet or u_inf of a uniform face */
+  double gravity[2];
+  double fluid_force[2];
+  void *stream;         /* hipStream_t; NULL = the null stream */
+  const ib_lbm_allocator *alloc; /* NULL = hipMalloc / hipFree */
+} ib_lbm_config;
+
+/* A rigid circular body (Sec. 2.3-2.7).  n_markers = 0 -> round(pi D)
+ * evenly spaced markers (Table I), arc spacing ds = pi D / n_markers.
+ * MDF: mdf_iters passes (Eq. 12-14) with relaxation mdf_omega, or
+ * 1/||A||_inf computed once here when mdf_omega <= 0 (Sec. 2.5.2).
+ * PRESCRIBED_SIN: X_c(t) = X_c0 + amp sin(2 pi freq t + phase).
+ * FREE: density_ratio rho_s/rho0, internal_mass selects scheme (A) or the
+ * Feng explicit-history correction (App. A.5).  All bodies of one sim use
+ * the same scheme. */
+typedef struct {
+  double xc, yc, diameter;
+  int32_t n_markers;
+  int32_t scheme;   /* IB_LBM_DF | IB_LBM_MDF | IB_LBM_DFC */
+  int32_t kernel;   /* IB_LBM_HAT | IB_LBM_PESKIN4 */
+  int32_t mdf_iters;
+  double mdf_omega;
+  int32_t motion;   /* IB_LBM_FIXED | IB_LBM_PRESCRIBED_SIN | IB_LBM_FREE */
+  int32_t internal_mass;
+  double amp[2], freq, phase;
+  double density_ratio;
+} ib_lbm_body_desc;
+
+/* State of a body after the last completed step.  Forces are on the body
+ * (Newton's third law for DF/MDF).  slip_* are |interp(u) - U_d| over the
+ * markers with the post-IB velocity; mdf_residual is max_k |U_d - U^(N)| of
+ * the last MDF pass. */
+typedef struct {
+  int64_t step;
+  double fx, fy, torque;
+  double xc, yc, vx, vy, omega;
+  double slip_mean, slip_max, mdf_residual;
+  double mdf_omega;
+  int32_t mdf_iters, flags;
+} ib_lbm_body_state;
+
+/* Launch shape of the collide-stream kernel: block_x threads along x (a
+ * multiple of 64), block_y thread rows, rows_per_thread nodes per thread
+ * along y.  The tile is block_x x (block_y * rows_per_thread) nodes. */
+typedef struct {
+  int32_t block_x, block_y, rows_per_thread;
+  int32_t xcd_remap; /* 1: keep neighbouring tiles on one XCD */
+} ib_lbm_launch;
+
+typedef struct ib_lbm_sim ib_lbm_sim;
+typedef struct ib_lbm_batch ib_lbm_batch;
+
+/* Library version, equal to IB_LBM_ABI_VERSION of the build. */
+uint32_t ib_lbm_abi_version(void);
+
+/* Create a sim: validates cfg (IB_LBM_E_INVALID), allocates two population
+ * lattices and the force field on the device and sets f = f^eq(rho0, u_init)
+ * with u_init the parabolic inlet profile (W face parabolic), u_bc (any
+ * uniform face) or 0.  *out receives the handle. */
+ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out);
+
+/* Add a body before the first step (IB_LBM_E_STATE afterwards).  Places the
+ * markers, checks that every support lies inside the lattice and does not
+ * meet another body's support (IB_LBM_E_RANGE), computes omega_MDF, uploads
+ * the marker tables.  *body_id receives the index (0, 1, ...). */
+ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t *body_id);
+
+/* Queue nsteps time steps on the sim's stream (asynchronous).  Each step:
+ * body kinematics for t+1, fused collide+stream with the force of the last
+ * IB pass, IB pass on the new populations, force/torque, body update. */
+ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps);
+
+/* Synchronise and return the state of body_id.  Returns IB_LBM_E_DIVERGED or
+ * IB_LBM_E_RANGE (state still filled) when the body's flags are set. */
+ib_lbm_status ib_lbm_forces(ib_lbm_sim *s, int32_t body_id, ib_lbm_body_state *out);
+
+/* Copy `count` history rows of body_id starting at step `first` (1-based step
+ * numbers, within the last history_capacity steps) to host out[count][16]:
+ * step fx fy torque xc yc vx vy omega slip_mean slip_max mdf_residual
+ * mdf_iters flags 0 0. */
+ib_lbm_status ib_lbm_history(ib_lbm_sim *s, int32_t body_id, int64_t first, int64_t count,
+                             double *out);
+
+/* Density and velocity (Eq. 4, with the IB force still to be applied by the
+ * next collision) into host arrays of nx*ny doubles, x fastest. */
+ib_lbm_status ib_lbm_fields(ib_lbm_sim *s, double *rho, double *ux, double *uy);
+
+/* Current populations f (FP64, host, 9*ny*nx) — read and overwrite.  For the
+ * FP32 shifted store the values are converted from / to g = f - w_i rho0. */
+ib_lbm_status ib_lbm_get_populations(ib_lbm_sim *s, double *f);
+ib_lbm_status ib_lbm_set_populations(ib_lbm_sim *s, const double *f);
+
+/* Eulerian IB force density of the last IB pass (host, ny*nx each). */
+ib_lbm_status ib_lbm_force_field(ib_lbm_sim *s, double *fx, double *fy);
+
+/* Per-marker data of the last step (host, n_markers rows of 8 doubles):
+ * X Y Udx Udy Fx Fy lambda ds.  Fx,Fy are the accumulated Lagrangian force
+ * F_L (DF/MDF) or the particle-side F_s (DFC).  Returns the marker count in
+ * *n_markers. */
+ib_lbm_status ib_lbm_markers(ib_lbm_sim *s, int32_t body_id, double *out, int32_t *n_markers);
+
+/* Completed steps (synchronises). */
+ib_lbm_status ib_lbm_steps_done(ib_lbm_sim *s, int64_t *steps);
+ib_lbm_status ib_lbm_sync(ib_lbm_sim *s);
+ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s);
+const char *ib_lbm_last_error(const ib_lbm_sim *s);
+
+/* Device bytes a sim of this configuration holds with the given bodies. */
+size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_t *n_markers);
+
+/* Launch shape of the collide-stream kernel (validated; IB_LBM_E_INVALID if
+ * block_x is not a multiple of 64 or the block exceeds 1024 threads). */
+ib_lbm_status ib_lbm_set_launch(ib_lbm_sim *s, const ib_lbm_launch *l);
+ib_lbm_status ib_lbm_get_launch(const ib_lbm_sim *s, ib_lbm_launch *l);
+/* Spreading variant: marker-sorted gather (default, deterministic) or
+ * per-marker atomic scatter (order-dependent rounding). */
+ib_lbm_status ib_lbm_set_spread(ib_lbm_sim *s, int32_t mode);
+/* hipGraph use: steps_per_graph > 0 captures that many steps once and
+ * replays them; 0 launches kernels directly. */
+ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph);
+
+/* Kernel timing with HIP events on the sim's stream (direct launches only).
+ * which: 0 collide-stream, 1 immersed boundary.  Reset with enable. */
+ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on);
+ib_lbm_status ib_lbm_timing_read(ib_lbm_sim *s, int32_t which, double *total_ms, int64_t *launches);
+
+/* ---- batching: many independent sims stepped by shared launches ----
+ * All sims of a batch share one precision and one stream.  A batch step is
+ * one collide-stream launch per collision model present and one IB launch
+ * for every body of every attached sim; each sim keeps its own step count
+ * and target and stops at its own target (ib_lbm_batch_set_target). */
+ib_lbm_status ib_lbm_batch_create(void *stream, int32_t precision, ib_lbm_batch **out);
+ib_lbm_status ib_lbm_batch_attach(ib_lbm_batch *b, ib_lbm_sim *s);
+ib_lbm_status ib_lbm_batch_detach(ib_lbm_batch *b, ib_lbm_sim *s);
+/* Run sims of the batch until each reaches step `target` (set per sim). */
+ib_lbm_status ib_lbm_batch_set_target(ib_lbm_batch *b, ib_lbm_sim *s, int64_t target);
+ib_lbm_status ib_lbm_batch_step(ib_lbm_batch *b, int64_t nsteps);
+ib_lbm_status ib_lbm_batch_set_graph(ib_lbm_batch *b, int32_t steps_per_graph);
+ib_lbm_status ib_lbm_batch_sync(ib_lbm_batch *b);
+ib_lbm_status ib_lbm_batch_destroy(ib_lbm_batch *b);
+const char *ib_lbm_batch_last_error(const ib_lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IB_LBM_H */

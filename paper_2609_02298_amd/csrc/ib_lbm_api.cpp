@@ -1,0 +1,1055 @@
+// C ABI of the IB-LBM library: state ownership, validation, launch tables,
+// graph capture and kernel timing.  Every step of the method runs in the HIP
+// kernels of lbm_kernels.hip and ibm_kernels.hip; the host code here only
+// allocates, validates, sizes the per-body workspaces and enqueues launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/ib_lbm.h"
+#include "ib_lbm_internal.h"
+
+using namespace iblbm;
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct HostBody {
+  ib_lbm_body_desc d;
+  BodyDesc dev;  // host copy of the device description
+  DevBuf cos_t, sin_t, ws, markers, lambda, history, state;
+};
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+struct Timing {
+  bool on = false;
+  std::vector<EventPair> ev[2];
+  std::vector<EventPair> pool;
+  double folded_ms[2] = {0, 0};
+  int64_t folded_n[2] = {0, 0};
+};
+
+}  // namespace
+
+struct ib_lbm_sim {
+  ib_lbm_config cfg;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool broken = false;
+  bool started = false;
+  bool tables_dirty = true;
+  std::string err;
+  CaseDesc cd;  // host copy
+  DevBuf f0, f1, force, state;
+  std::vector<HostBody> bodies;
+  DevBuf d_bodies, d_case, d_prefix, d_slots, d_tmp;
+  int nslots = 0;
+  ib_lbm_launch launch = {64, 4, 2, 1};
+  int spread_mode = 0;
+  int graph_steps = 0;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_len = 0;
+  Timing timing;
+  int64_t host_steps = 0;
+  ib_lbm_batch *batch = nullptr;
+  int lds_bytes = 0;
+};
+
+struct ib_lbm_batch {
+  hipStream_t stream = nullptr;
+  int precision = 0;
+  bool dirty = true;
+  bool broken = false;
+  std::string err;
+  std::vector<ib_lbm_sim *> sims;
+  DevBuf d_cases, d_prefix, d_slots;
+  struct Group {
+    int collision, first, count, ntiles, prefix_off;
+  };
+  std::vector<Group> groups;
+  int nslots = 0;
+  int lds_bytes = 0;
+  ib_lbm_launch launch = {64, 4, 2, 1};
+  int spread_mode = 0;
+  int graph_steps = 0;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_len = 0;
+};
+
+namespace {
+
+void set_err(std::string *e, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  *e = buf;
+}
+
+#define HIPCHK(sim, call)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_err(&(sim)->err, "%s failed: %s", #call, hipGetErrorString(e_));            \
+      (sim)->broken = true;                                                           \
+      return IB_LBM_E_DEVICE;                                                         \
+    }                                                                                 \
+  } while (0)
+
+ib_lbm_status dev_alloc(ib_lbm_sim *s, DevBuf *b, size_t bytes) {
+  b->bytes = bytes;
+  if (bytes == 0) return IB_LBM_OK;
+  if (s->cfg.alloc && s->cfg.alloc->alloc) {
+    b->p = s->cfg.alloc->alloc(s->cfg.alloc->ctx, bytes, (void *)s->stream);
+    if (!b->p) {
+      set_err(&s->err, "allocator returned NULL for %zu bytes", bytes);
+      return IB_LBM_E_NOMEM;
+    }
+    return IB_LBM_OK;
+  }
+  hipError_t e = hipMalloc(&b->p, bytes);
+  if (e != hipSuccess) {
+    b->p = nullptr;
+    set_err(&s->err, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? IB_LBM_E_NOMEM : IB_LBM_E_DEVICE;
+  }
+  return IB_LBM_OK;
+}
+
+void dev_free(ib_lbm_sim *s, DevBuf *b) {
+  if (!b->p) return;
+  if (s->cfg.alloc && s->cfg.alloc->free) s->cfg.alloc->free(s->cfg.alloc->ctx, b->p, (void *)s->stream);
+  else (void)hipFree(b->p);
+  b->p = nullptr;
+  b->bytes = 0;
+}
+
+bool is_vel(int b) { return b == IB_LBM_VEL_PARABOLIC || b == IB_LBM_VEL_UNIFORM; }
+
+// Regularized delta (Eq. 9, 10) for host-side sizing and omega_MDF.
+double host_delta(int kernel, double r) {
+  const double a = std::fabs(r);
+  if (kernel == IB_LBM_HAT) return a < 1.0 ? 1.0 - a : 0.0;
+  if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + std::sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+  if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - std::sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+  return 0.0;
+}
+
+// Node count of the device's row-interval support description for a body
+// centred at (xc, yc) (used to size the workspace).
+int support_count(double xc, double yc, double R, int nb, int ns, const std::vector<double> &ct,
+                  const std::vector<double> &stab, int *rows_used) {
+  const int s = ns / 2;
+  const int ylo = (int)std::floor(yc - R) - ns;
+  const int mr = (int)std::ceil(2 * R) + 2 * ns + 4;
+  std::vector<int> lmin(mr, 1 << 30), lmax(mr, -1), rmin(mr, 1 << 30), rmax(mr, -1);
+  int rmx = 0;
+  for (int k = 0; k < nb; k++) {
+    const double X = xc + R * ct[k], Y = yc + R * stab[k];
+    const int ix0 = (int)std::floor(X) - (s - 1), iy0 = (int)std::floor(Y) - (s - 1);
+    for (int j = 0; j < ns; j++) {
+      const int r = iy0 + j - ylo;
+      if (r < 0 || r >= mr) continue;
+      rmx = std::max(rmx, r);
+      if (X < xc) { lmin[r] = std::min(lmin[r], ix0); lmax[r] = std::max(lmax[r], ix0 + ns - 1); }
+      else { rmin[r] = std::min(rmin[r], ix0); rmax[r] = std::max(rmax[r], ix0 + ns - 1); }
+    }
+  }
+  int total = 0;
+  for (int r = 0; r < mr; r++) {
+    const bool lv = lmax[r] >= 0, rv = rmax[r] >= 0;
+    if (lv && rv && rmin[r] <= lmax[r] + 1) total += std::max(lmax[r], rmax[r]) - std::min(lmin[r], rmin[r]) + 1;
+    else {
+      if (lv) total += lmax[r] - lmin[r] + 1;
+      if (rv) total += rmax[r] - rmin[r] + 1;
+    }
+  }
+  if (rows_used) *rows_used = rmx + 1;
+  return total;
+}
+
+// omega_MDF = 1 / ||A||_inf, ||A||_inf = ds max_l sum_x D_h(x-X_l) W(x),
+// W(x) = sum_m D_h(x-X_m) (Sec. 2.5.2), on a dense local box.
+double host_omega_mdf(double xc, double yc, double R, int nb, int kernel, double ds,
+                      const std::vector<double> &ct, const std::vector<double> &stab) {
+  const int ns = kernel == IB_LBM_HAT ? 2 : 4, s = ns / 2;
+  const int x0 = (int)std::floor(xc - R) - ns - 1, y0 = (int)std::floor(yc - R) - ns - 1;
+  const int w = (int)std::ceil(2 * R) + 2 * ns + 4;
+  std::vector<double> W((size_t)w * w, 0.0);
+  std::vector<double> X(nb), Y(nb);
+  for (int k = 0; k < nb; k++) { X[k] = xc + R * ct[k]; Y[k] = yc + R * stab[k]; }
+  for (int k = 0; k < nb; k++) {
+    const int ix0 = (int)std::floor(X[k]) - (s - 1), iy0 = (int)std::floor(Y[k]) - (s - 1);
+    for (int jy = 0; jy < ns; jy++)
+      for (int jx = 0; jx < ns; jx++)
+        W[(size_t)(iy0 + jy - y0) * w + (ix0 + jx - x0)] +=
+            host_delta(kernel, ix0 + jx - X[k]) * host_delta(kernel, iy0 + jy - Y[k]);
+  }
+  double mx = 0.0;
+  for (int k = 0; k < nb; k++) {
+    const int ix0 = (int)std::floor(X[k]) - (s - 1), iy0 = (int)std::floor(Y[k]) - (s - 1);
+    double acc = 0.0;
+    for (int jy = 0; jy < ns; jy++)
+      for (int jx = 0; jx < ns; jx++)
+        acc += W[(size_t)(iy0 + jy - y0) * w + (ix0 + jx - x0)] *
+               host_delta(kernel, ix0 + jx - X[k]) * host_delta(kernel, iy0 + jy - Y[k]);
+    mx = std::max(mx, acc);
+  }
+  return 1.0 / (ds * mx);
+}
+
+int ws_doubles_for(int nb, int ns, int mr, int mn) {
+  const size_t dbl = (size_t)nb * (4 + 2 * ns + 4 + 2 + 9) + (size_t)mn * 6;
+  const size_t ints = (size_t)nb * (2 + ns * ns) + (size_t)mr * 8 + 1 + (size_t)mn * 2;
+  return (int)(dbl + (ints + 1) / 2 + 8);
+}
+
+void fill_case_tiles(CaseDesc *c, const ib_lbm_launch &l) {
+  const int TX = l.block_x, TY = l.block_y * l.rows_per_thread;
+  c->tiles_x = (c->nx + TX - 1) / TX;
+  c->tiles_y = (c->ny + TY - 1) / TY;
+}
+
+ib_lbm_status check_launch(const ib_lbm_launch *l, std::string *err) {
+  if (!l || l->block_x <= 0 || l->block_x % 64 || l->block_y <= 0 || l->rows_per_thread <= 0 ||
+      l->block_x * l->block_y > 1024 || l->rows_per_thread > 64) {
+    set_err(err, "invalid launch shape");
+    return IB_LBM_E_INVALID;
+  }
+  return IB_LBM_OK;
+}
+
+// Device tables of a sim stepped on its own: one case, its IB slots.
+ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
+  if (!s->tables_dirty) return IB_LBM_OK;
+  std::vector<BodyDesc> bd;
+  int maxws = 0;
+  for (auto &hb : s->bodies) {
+    bd.push_back(hb.dev);
+    maxws = std::max(maxws, hb.dev.ws_doubles);
+  }
+  if (!bd.empty()) {
+    if (!s->d_bodies.p || s->d_bodies.bytes < bd.size() * sizeof(BodyDesc)) {
+      dev_free(s, &s->d_bodies);
+      ib_lbm_status st = dev_alloc(s, &s->d_bodies, bd.size() * sizeof(BodyDesc));
+      if (st) return st;
+    }
+    HIPCHK(s, hipMemcpy(s->d_bodies.p, bd.data(), bd.size() * sizeof(BodyDesc), hipMemcpyHostToDevice));
+  }
+  s->cd.bodies = (BodyDesc *)s->d_bodies.p;
+  s->cd.nbodies = (int)bd.size();
+  fill_case_tiles(&s->cd, s->launch);
+  if (!s->d_case.p) {
+    ib_lbm_status st = dev_alloc(s, &s->d_case, sizeof(CaseDesc));
+    if (st) return st;
+    st = dev_alloc(s, &s->d_prefix, sizeof(int32_t) * 2);
+    if (st) return st;
+    st = dev_alloc(s, &s->d_slots, sizeof(IbmSlot) * kMaxBodiesPerCase);
+    if (st) return st;
+  }
+  HIPCHK(s, hipMemcpy(s->d_case.p, &s->cd, sizeof(CaseDesc), hipMemcpyHostToDevice));
+  int32_t pre[2] = {0, s->cd.tiles_x * s->cd.tiles_y};
+  HIPCHK(s, hipMemcpy(s->d_prefix.p, pre, sizeof pre, hipMemcpyHostToDevice));
+  std::vector<IbmSlot> slots;
+  const int n = std::max(1, (int)bd.size());
+  for (int b = 0; b < n; b++) slots.push_back(IbmSlot{0, bd.empty() ? -1 : b, n, 0});
+  HIPCHK(s, hipMemcpy(s->d_slots.p, slots.data(), slots.size() * sizeof(IbmSlot), hipMemcpyHostToDevice));
+  s->nslots = n;
+  s->lds_bytes = std::min(ibm_max_lds_bytes(), maxws * 8);
+  if (maxws * 8 > ibm_max_lds_bytes()) s->lds_bytes = 0;  // too large: global workspace
+  s->tables_dirty = false;
+  if (s->graph_exec) {
+    (void)hipGraphExecDestroy(s->graph_exec);
+    s->graph_exec = nullptr;
+  }
+  return IB_LBM_OK;
+}
+
+EventPair take_pair(Timing &t) {
+  if (!t.pool.empty()) {
+    EventPair p = t.pool.back();
+    t.pool.pop_back();
+    return p;
+  }
+  EventPair p;
+  (void)hipEventCreate(&p.a);
+  (void)hipEventCreate(&p.b);
+  return p;
+}
+
+// Enqueue one step of a sim: collide-stream, then the IB pass.
+ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed) {
+  LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
+  const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
+  EventPair p0{}, p1{};
+  if (timed) {
+    p0 = take_pair(s->timing);
+    HIPCHK(s, hipEventRecord(p0.a, s->stream));
+  }
+  HIPCHK(s, launch_collide_stream(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
+                                  (const int32_t *)s->d_prefix.p, 1, ntiles, sh, s->stream));
+  if (timed) {
+    HIPCHK(s, hipEventRecord(p0.b, s->stream));
+    s->timing.ev[0].push_back(p0);
+    p1 = take_pair(s->timing);
+    HIPCHK(s, hipEventRecord(p1.a, s->stream));
+  }
+  HIPCHK(s, launch_ibm(s->cd.precision, (const CaseDesc *)s->d_case.p, (const IbmSlot *)s->d_slots.p,
+                       s->nslots, s->lds_bytes, s->spread_mode, s->stream));
+  if (timed) {
+    HIPCHK(s, hipEventRecord(p1.b, s->stream));
+    s->timing.ev[1].push_back(p1);
+  }
+  return IB_LBM_OK;
+}
+
+ib_lbm_status usable(ib_lbm_sim *s) {
+  if (!s) return IB_LBM_E_INVALID;
+  if (s->broken) return IB_LBM_E_STATE;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status read_state(ib_lbm_sim *s, CaseState *cs) {
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemcpy(cs, s->state.p, sizeof(CaseState), hipMemcpyDeviceToHost));
+  return IB_LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t ib_lbm_abi_version(void) { return IB_LBM_ABI_VERSION; }
+
+size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_t *n_markers) {
+  if (!cfg) return 0;
+  const size_t elem = cfg->precision == IB_LBM_FP64 ? 8 : 4;
+  const size_t n = (size_t)cfg->nx * cfg->ny;
+  size_t bytes = 2 * 9 * n * elem + 2 * n * elem + sizeof(CaseState) + sizeof(CaseDesc) + 256;
+  const int hist = cfg->history_capacity > 0 ? cfg->history_capacity : 4096;
+  for (int b = 0; b < n_bodies; b++) {
+    const int nb = n_markers ? n_markers[b] : 256;
+    // workspace upper estimate (P4), marker tables, history
+    const double D = nb / M_PI;
+    const int mr = (int)std::ceil(D) + 12, mn = (int)(8 * M_PI * D + 8 * mr + 64);
+    bytes += (size_t)ws_doubles_for(nb, 4, mr, mn) * 8 + (size_t)nb * (8 + 1 + 2) * 8 +
+             (size_t)hist * kHistCols * 8 + sizeof(BodyState) + sizeof(BodyDesc);
+  }
+  return bytes;
+}
+
+ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out) {
+  if (!cfg || !out) return IB_LBM_E_INVALID;
+  *out = nullptr;
+  ib_lbm_sim *s = new ib_lbm_sim();
+  s->cfg = *cfg;
+  auto fail = [&](ib_lbm_status st, const char *msg) {
+    fprintf(stderr, "ib_lbm_create: %s\n", msg);
+    ib_lbm_destroy(s);
+    return st;
+  };
+  if (cfg->abi_version != IB_LBM_ABI_VERSION) return fail(IB_LBM_E_INVALID, "abi_version mismatch");
+  if (cfg->nx < 3 || cfg->ny < 3 || (int64_t)cfg->nx * cfg->ny >= (1ll << 31) || cfg->nx >= 65535 ||
+      cfg->ny >= 32767)
+    return fail(IB_LBM_E_INVALID, "lattice size out of range");
+  if (!(cfg->tau > 0.5) || !std::isfinite(cfg->tau)) return fail(IB_LBM_E_INVALID, "tau must exceed 1/2");
+  if (cfg->precision != IB_LBM_FP64 && cfg->precision != IB_LBM_FP32_SHIFTED)
+    return fail(IB_LBM_E_INVALID, "unknown precision");
+  if (cfg->collision < IB_LBM_BGK || cfg->collision > IB_LBM_CMMRT)
+    return fail(IB_LBM_E_INVALID, "unknown collision");
+  for (int f = 0; f < 4; f++)
+    if (cfg->bc[f] < IB_LBM_PERIODIC || cfg->bc[f] > IB_LBM_ZERO_GRADIENT)
+      return fail(IB_LBM_E_INVALID, "unknown face closure");
+  if ((cfg->bc[0] == IB_LBM_PERIODIC) != (cfg->bc[1] == IB_LBM_PERIODIC) ||
+      (cfg->bc[2] == IB_LBM_PERIODIC) != (cfg->bc[3] == IB_LBM_PERIODIC))
+    return fail(IB_LBM_E_INVALID, "periodic faces must come in pairs");
+  if (cfg->bc[0] == IB_LBM_ZERO_GRADIENT || cfg->bc[2] == IB_LBM_ZERO_GRADIENT ||
+      cfg->bc[3] == IB_LBM_ZERO_GRADIENT)
+    return fail(IB_LBM_E_INVALID, "zero-gradient closure only on the east face");
+  if (cfg->bc[2] == IB_LBM_VEL_PARABOLIC || cfg->bc[3] == IB_LBM_VEL_PARABOLIC)
+    return fail(IB_LBM_E_INVALID, "parabolic profile only on the west or east face");
+  if (cfg->collision == IB_LBM_TRT && !(cfg->trt_magic > 0.0))
+    return fail(IB_LBM_E_INVALID, "TRT needs a positive magic parameter");
+  if (!(cfg->rho0 > 0.0)) return fail(IB_LBM_E_INVALID, "rho0 must be positive");
+  if (cfg->stream) {
+    s->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(IB_LBM_E_DEVICE, "stream creation failed");
+    s->own_stream = true;
+  }
+  CaseDesc &c = s->cd;
+  memset(&c, 0, sizeof c);
+  c.nx = cfg->nx;
+  c.ny = cfg->ny;
+  c.collision = cfg->collision;
+  c.precision = cfg->precision;
+  for (int f = 0; f < 4; f++) c.bc[f] = cfg->bc[f];
+  c.plane = (int64_t)cfg->nx * cfg->ny;
+  c.omega = 1.0 / cfg->tau;
+  // TRT (Sec. 2.2): the even rate sets the viscosity; Lambda_o = Lambda_eo / Lambda_e.
+  c.s_e = 1.0 / cfg->tau;
+  {
+    const double lam_e = cfg->tau - 0.5;
+    const double lam_o = (cfg->trt_magic > 0 ? cfg->trt_magic : 0.25) / lam_e;
+    c.s_o = 1.0 / (lam_o + 0.5);
+  }
+  c.s_q = cfg->cm_s_q;
+  c.s_eps = cfg->cm_s_eps;
+  c.rho0 = cfg->rho0;
+  c.u_bc = cfg->u_bc;
+  c.inv_ny2 = 1.0 / ((double)cfg->ny * cfg->ny);
+  c.fluid_fx = cfg->fluid_force[0];
+  c.fluid_fy = cfg->fluid_force[1];
+  c.grav_x = cfg->gravity[0];
+  c.grav_y = cfg->gravity[1];
+  const size_t elem = cfg->precision == IB_LBM_FP64 ? 8 : 4;
+  ib_lbm_status st;
+  if ((st = dev_alloc(s, &s->f0, 9 * (size_t)c.plane * elem))) return fail(st, s->err.c_str());
+  if ((st = dev_alloc(s, &s->f1, 9 * (size_t)c.plane * elem))) return fail(st, s->err.c_str());
+  if ((st = dev_alloc(s, &s->force, 2 * (size_t)c.plane * elem))) return fail(st, s->err.c_str());
+  if ((st = dev_alloc(s, &s->state, sizeof(CaseState)))) return fail(st, s->err.c_str());
+  c.f[0] = s->f0.p;
+  c.f[1] = s->f1.p;
+  c.force = s->force.p;
+  c.state = (CaseState *)s->state.p;
+  CaseState cs{};
+  cs.step = 0;
+  cs.target = std::numeric_limits<int64_t>::max();
+  cs.cur = 0;
+  if (hipMemcpy(s->state.p, &cs, sizeof cs, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(IB_LBM_E_DEVICE, "state upload failed");
+  if (launch_init_equilibrium(c, 0, s->stream) != hipSuccess ||
+      launch_init_equilibrium(c, 1, s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return fail(IB_LBM_E_DEVICE, "initialisation kernel failed");
+  *out = s;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t *body_id) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!b) return IB_LBM_E_INVALID;
+  if (s->started || s->batch) {
+    set_err(&s->err, "bodies can only be added before the first step");
+    return IB_LBM_E_STATE;
+  }
+  if ((int)s->bodies.size() >= kMaxBodiesPerCase) {
+    set_err(&s->err, "at most %d bodies per sim", kMaxBodiesPerCase);
+    return IB_LBM_E_INVALID;
+  }
+  if (!(b->diameter > 0) || b->scheme < IB_LBM_DF || b->scheme > IB_LBM_DFC || b->kernel < 0 ||
+      b->kernel > 1 || b->motion < 0 || b->motion > 2 || b->n_markers < 0 ||
+      (b->scheme == IB_LBM_MDF && (b->mdf_iters < 1 || b->mdf_iters > 1000)) ||
+      (b->motion == IB_LBM_FREE && !(b->density_ratio > 0))) {
+    set_err(&s->err, "invalid body description");
+    return IB_LBM_E_INVALID;
+  }
+  if (!s->bodies.empty() && s->bodies[0].d.scheme != b->scheme) {
+    set_err(&s->err, "all bodies of a sim must use the same scheme");
+    return IB_LBM_E_INVALID;
+  }
+  HostBody hb;
+  hb.d = *b;
+  BodyDesc &B = hb.dev;
+  memset(&B, 0, sizeof B);
+  const int nb = b->n_markers > 0 ? b->n_markers : (int)std::lround(M_PI * b->diameter);
+  if (nb < 1 || nb > 32768) {
+    set_err(&s->err, "marker count out of range");
+    return IB_LBM_E_INVALID;
+  }
+  B.nb = nb;
+  B.scheme = b->scheme;
+  B.kernel = b->kernel;
+  B.mdf_iters = b->scheme == IB_LBM_MDF ? b->mdf_iters : 1;
+  B.motion = b->motion;
+  B.internal_mass = b->internal_mass;
+  B.ns = b->kernel == IB_LBM_HAT ? 2 : 4;
+  B.radius = 0.5 * b->diameter;
+  B.ds = M_PI * b->diameter / nb;
+  B.dtheta = 2.0 * M_PI / nb;
+  B.xc0 = b->xc;
+  B.yc0 = b->yc;
+  B.amp[0] = b->amp[0];
+  B.amp[1] = b->amp[1];
+  B.freq = b->freq;
+  B.phase = b->phase;
+  const double area = M_PI * B.radius * B.radius;
+  B.ms = (b->motion == IB_LBM_FREE ? b->density_ratio : 1.0) * s->cfg.rho0 * area;
+  B.mf = s->cfg.rho0 * area;
+  B.Is = 0.5 * B.ms * B.radius * B.radius;
+  // marker directions, theta_k = 2 pi k / N_b starting at angle 0
+  std::vector<double> ct(nb), stb(nb);
+  for (int k = 0; k < nb; k++) {
+    const double th = 2.0 * M_PI * (double)k / (double)nb;
+    ct[k] = std::cos(th);
+    stb[k] = std::sin(th);
+  }
+  // every support inside the lattice at the start position
+  const int sw = B.ns / 2;
+  auto inside = [&](double xc, double yc) {
+    for (int k = 0; k < nb; k++) {
+      const double X = xc + B.radius * ct[k], Y = yc + B.radius * stb[k];
+      const int ix0 = (int)std::floor(X) - (sw - 1), iy0 = (int)std::floor(Y) - (sw - 1);
+      if (ix0 < 0 || iy0 < 0 || ix0 + B.ns - 1 > s->cfg.nx - 1 || iy0 + B.ns - 1 > s->cfg.ny - 1) return false;
+    }
+    return true;
+  };
+  if (!inside(b->xc, b->yc) ||
+      (b->motion == IB_LBM_PRESCRIBED_SIN &&
+       (!inside(b->xc + std::fabs(b->amp[0]), b->yc + std::fabs(b->amp[1])) ||
+        !inside(b->xc - std::fabs(b->amp[0]), b->yc - std::fabs(b->amp[1]))))) {
+    set_err(&s->err, "a marker support leaves the lattice");
+    return IB_LBM_E_RANGE;
+  }
+  for (auto &o : s->bodies) {
+    const double dx = o.d.xc - b->xc, dy = o.d.yc - b->yc;
+    const double lim = o.dev.radius + B.radius + o.dev.ns + B.ns + 4.0;
+    if (dx * dx + dy * dy <= lim * lim) {
+      set_err(&s->err, "body supports would meet; bodies must stay apart");
+      return IB_LBM_E_RANGE;
+    }
+  }
+  // workspace sizing over sub-lattice positions of the centre
+  int maxn = 0, maxr = 0;
+  for (int a = 0; a < 4; a++)
+    for (int q = 0; q < 4; q++) {
+      int rows = 0;
+      const int n = support_count(100.0 + 0.25 * a + 0.0625, 100.0 + 0.25 * q + 0.125, B.radius, nb,
+                                  B.ns, ct, stb, &rows);
+      maxn = std::max(maxn, n);
+      maxr = std::max(maxr, rows);
+    }
+  B.max_rows = (int)std::ceil(2 * B.radius) + 2 * B.ns + 4;
+  B.max_nodes = maxn + maxn / 4 + 64;
+  B.ws_doubles = ws_doubles_for(nb, B.ns, B.max_rows, B.max_nodes);
+  // gather window: a node within s*sqrt(2) of marker k lies within angle
+  // 2 asin(s / sqrt(2 R (R - s sqrt 2))) of it
+  {
+    const double sr = sw * std::sqrt(2.0);
+    double dmax = M_PI;
+    if (B.radius > sr + 0.5) dmax = 2.0 * std::asin(std::min(1.0, sw / std::sqrt(2.0 * B.radius * (B.radius - sr))));
+    int w = (int)std::ceil(dmax / B.dtheta) + 2;
+    if (2 * w + 1 >= nb) w = nb;
+    B.window = w;
+  }
+  B.omega_mdf = b->scheme == IB_LBM_MDF
+                    ? (b->mdf_omega > 0 ? b->mdf_omega
+                                        : host_omega_mdf(b->xc, b->yc, B.radius, nb, b->kernel, B.ds, ct, stb))
+                    : 1.0;
+  B.hist_cap = s->cfg.history_capacity > 0 ? s->cfg.history_capacity : 4096;
+  if ((st = dev_alloc(s, &hb.cos_t, nb * 8))) return st;
+  if ((st = dev_alloc(s, &hb.sin_t, nb * 8))) return st;
+  if ((st = dev_alloc(s, &hb.ws, (size_t)B.ws_doubles * 8))) return st;
+  if ((st = dev_alloc(s, &hb.markers, (size_t)nb * 8 * 8))) return st;
+  if ((st = dev_alloc(s, &hb.lambda, (size_t)nb * 8))) return st;
+  if ((st = dev_alloc(s, &hb.history, (size_t)B.hist_cap * kHistCols * 8))) return st;
+  if ((st = dev_alloc(s, &hb.state, sizeof(BodyState)))) return st;
+  HIPCHK(s, hipMemcpy(hb.cos_t.p, ct.data(), nb * 8, hipMemcpyHostToDevice));
+  HIPCHK(s, hipMemcpy(hb.sin_t.p, stb.data(), nb * 8, hipMemcpyHostToDevice));
+  HIPCHK(s, hipMemset(hb.markers.p, 0, (size_t)nb * 64));
+  HIPCHK(s, hipMemset(hb.history.p, 0, (size_t)B.hist_cap * kHistCols * 8));
+  B.cos_t = (const double *)hb.cos_t.p;
+  B.sin_t = (const double *)hb.sin_t.p;
+  B.ws = (double *)hb.ws.p;
+  B.markers_out = (double *)hb.markers.p;
+  B.lambda_cache = (double *)hb.lambda.p;
+  B.history = (double *)hb.history.p;
+  B.state = (BodyState *)hb.state.p;
+  BodyState bst;
+  memset(&bst, 0, sizeof bst);
+  bst.xc = b->xc;
+  bst.yc = b->yc;
+  HIPCHK(s, hipMemcpy(hb.state.p, &bst, sizeof bst, hipMemcpyHostToDevice));
+  s->bodies.push_back(hb);
+  s->tables_dirty = true;
+  if (body_id) *body_id = (int32_t)s->bodies.size() - 1;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (nsteps < 0) return IB_LBM_E_INVALID;
+  if (s->batch) {
+    set_err(&s->err, "sim is attached to a batch; step the batch");
+    return IB_LBM_E_STATE;
+  }
+  if ((st = build_sim_tables(s))) return st;
+  s->started = true;
+  int64_t left = nsteps;
+  if (s->graph_steps > 0 && !s->timing.on && left >= s->graph_steps) {
+    if (!s->graph_exec || s->graph_len != s->graph_steps) {
+      if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+      s->graph_exec = nullptr;
+      hipGraph_t g;
+      HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < s->graph_steps; i++) {
+        st = enqueue_sim_step(s, false);
+        if (st) {
+          hipGraph_t dummy;
+          (void)hipStreamEndCapture(s->stream, &dummy);
+          return st;
+        }
+      }
+      HIPCHK(s, hipStreamEndCapture(s->stream, &g));
+      HIPCHK(s, hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(g);
+      s->graph_len = s->graph_steps;
+    }
+    while (left >= s->graph_len) {
+      HIPCHK(s, hipGraphLaunch(s->graph_exec, s->stream));
+      left -= s->graph_len;
+    }
+  }
+  for (int64_t i = 0; i < left; i++)
+    if ((st = enqueue_sim_step(s, s->timing.on))) return st;
+  s->host_steps += nsteps;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_forces(ib_lbm_sim *s, int32_t body_id, ib_lbm_body_state *out) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!out || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  BodyState b;
+  HIPCHK(s, hipMemcpy(&b, s->bodies[body_id].state.p, sizeof b, hipMemcpyDeviceToHost));
+  out->step = cs.step;
+  out->fx = b.fhx;
+  out->fy = b.fhy;
+  out->torque = b.torque;
+  out->xc = b.xc;
+  out->yc = b.yc;
+  const bool freeb = s->bodies[body_id].d.motion == IB_LBM_FREE;
+  out->vx = freeb ? b.vx : b.vhx;
+  out->vy = freeb ? b.vy : b.vhy;
+  out->omega = freeb ? b.om : b.omh;
+  out->slip_mean = b.slip_mean;
+  out->slip_max = b.slip_max;
+  out->mdf_residual = b.mdf_res;
+  out->mdf_omega = s->bodies[body_id].dev.omega_mdf;
+  out->mdf_iters = b.mdf_iters_done;
+  out->flags = b.flags;
+  if (b.flags & IB_LBM_FLAG_NONFINITE) {
+    set_err(&s->err, "non-finite force or velocity at body %d", body_id);
+    return IB_LBM_E_DIVERGED;
+  }
+  if (b.flags & (IB_LBM_FLAG_RANGE | IB_LBM_FLAG_OVERLAP | kFlagCapacity)) {
+    set_err(&s->err, "body %d left the lattice or met another body (flags %d)", body_id, b.flags);
+    return IB_LBM_E_RANGE;
+  }
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_history(ib_lbm_sim *s, int32_t body_id, int64_t first, int64_t count,
+                             double *out) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!out || body_id < 0 || body_id >= (int)s->bodies.size() || count < 0 || first < 1)
+    return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  const int cap = s->bodies[body_id].dev.hist_cap;
+  if (first + count - 1 > cs.step || first <= cs.step - cap) {
+    set_err(&s->err, "history rows outside the kept window");
+    return IB_LBM_E_RANGE;
+  }
+  const double *h = (const double *)s->bodies[body_id].history.p;
+  for (int64_t i = 0; i < count; i++) {
+    const int64_t row = (first - 1 + i) % cap;
+    HIPCHK(s, hipMemcpy(out + i * kHistCols, h + row * kHistCols, kHistCols * 8, hipMemcpyDeviceToHost));
+  }
+  return IB_LBM_OK;
+}
+
+static ib_lbm_status ensure_tmp(ib_lbm_sim *s, size_t bytes) {
+  if (s->d_tmp.bytes >= bytes) return IB_LBM_OK;
+  dev_free(s, &s->d_tmp);
+  return dev_alloc(s, &s->d_tmp, bytes);
+}
+
+ib_lbm_status ib_lbm_fields(ib_lbm_sim *s, double *rho, double *ux, double *uy) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!rho || !ux || !uy) return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  const size_t n = (size_t)s->cd.plane;
+  if ((st = ensure_tmp(s, 3 * n * 8))) return st;
+  double *d = (double *)s->d_tmp.p;
+  HIPCHK(s, launch_fields(s->cd, cs.cur, d, d + n, d + 2 * n, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemcpy(rho, d, n * 8, hipMemcpyDeviceToHost));
+  HIPCHK(s, hipMemcpy(ux, d + n, n * 8, hipMemcpyDeviceToHost));
+  HIPCHK(s, hipMemcpy(uy, d + 2 * n, n * 8, hipMemcpyDeviceToHost));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_get_populations(ib_lbm_sim *s, double *f) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!f) return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  const size_t n = (size_t)s->cd.plane;
+  if ((st = ensure_tmp(s, 9 * n * 8))) return st;
+  HIPCHK(s, launch_export(s->cd, cs.cur, (double *)s->d_tmp.p, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemcpy(f, s->d_tmp.p, 9 * n * 8, hipMemcpyDeviceToHost));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_set_populations(ib_lbm_sim *s, const double *f) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!f) return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  const size_t n = (size_t)s->cd.plane;
+  if ((st = ensure_tmp(s, 9 * n * 8))) return st;
+  HIPCHK(s, hipMemcpy(s->d_tmp.p, f, 9 * n * 8, hipMemcpyHostToDevice));
+  HIPCHK(s, launch_import(s->cd, cs.cur, (const double *)s->d_tmp.p, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_force_field(ib_lbm_sim *s, double *fx, double *fy) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!fx || !fy) return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  const size_t n = (size_t)s->cd.plane;
+  if ((st = ensure_tmp(s, 2 * n * 8))) return st;
+  double *d = (double *)s->d_tmp.p;
+  HIPCHK(s, launch_force_export(s->cd, d, d + n, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemcpy(fx, d, n * 8, hipMemcpyDeviceToHost));
+  HIPCHK(s, hipMemcpy(fy, d + n, n * 8, hipMemcpyDeviceToHost));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_markers(ib_lbm_sim *s, int32_t body_id, double *out, int32_t *n_markers) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (body_id < 0 || body_id >= (int)s->bodies.size()) return IB_LBM_E_INVALID;
+  const int nb = s->bodies[body_id].dev.nb;
+  if (n_markers) *n_markers = nb;
+  if (!out) return IB_LBM_OK;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemcpy(out, s->bodies[body_id].markers.p, (size_t)nb * 64, hipMemcpyDeviceToHost));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_steps_done(ib_lbm_sim *s, int64_t *steps) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!steps) return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  *steps = cs.step;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_sync(ib_lbm_sim *s) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s) {
+  if (!s) return IB_LBM_E_INVALID;
+  if (s->batch) ib_lbm_batch_detach(s->batch, s);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  for (int k = 0; k < 2; k++)
+    for (auto &p : s->timing.ev[k]) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto &p : s->timing.pool) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto &hb : s->bodies) {
+    dev_free(s, &hb.cos_t); dev_free(s, &hb.sin_t); dev_free(s, &hb.ws); dev_free(s, &hb.markers);
+    dev_free(s, &hb.lambda); dev_free(s, &hb.history); dev_free(s, &hb.state);
+  }
+  dev_free(s, &s->f0); dev_free(s, &s->f1); dev_free(s, &s->force); dev_free(s, &s->state);
+  dev_free(s, &s->d_bodies); dev_free(s, &s->d_case); dev_free(s, &s->d_prefix);
+  dev_free(s, &s->d_slots); dev_free(s, &s->d_tmp);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return IB_LBM_OK;
+}
+
+const char *ib_lbm_last_error(const ib_lbm_sim *s) { return s ? s->err.c_str() : "null sim"; }
+
+ib_lbm_status ib_lbm_set_launch(ib_lbm_sim *s, const ib_lbm_launch *l) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if ((st = check_launch(l, &s->err))) return st;
+  s->launch = *l;
+  s->tables_dirty = true;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_get_launch(const ib_lbm_sim *s, ib_lbm_launch *l) {
+  if (!s || !l) return IB_LBM_E_INVALID;
+  *l = s->launch;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_set_spread(ib_lbm_sim *s, int32_t mode) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (mode != IB_LBM_SPREAD_GATHER && mode != IB_LBM_SPREAD_ATOMIC) return IB_LBM_E_INVALID;
+  s->spread_mode = mode;
+  s->tables_dirty = true;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (steps_per_graph < 0 || steps_per_graph > 100000) return IB_LBM_E_INVALID;
+  s->graph_steps = steps_per_graph;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (int k = 0; k < 2; k++) {
+    for (auto &p : s->timing.ev[k]) s->timing.pool.push_back(p);
+    s->timing.ev[k].clear();
+    s->timing.folded_ms[k] = 0;
+    s->timing.folded_n[k] = 0;
+  }
+  s->timing.on = on != 0;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_timing_read(ib_lbm_sim *s, int32_t which, double *total_ms, int64_t *launches) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (which < 0 || which > 1 || !total_ms || !launches) return IB_LBM_E_INVALID;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  double ms = s->timing.folded_ms[which];
+  for (auto &p : s->timing.ev[which]) {
+    float t = 0;
+    HIPCHK(s, hipEventElapsedTime(&t, p.a, p.b));
+    ms += t;
+  }
+  *total_ms = ms;
+  *launches = s->timing.folded_n[which] + (int64_t)s->timing.ev[which].size();
+  return IB_LBM_OK;
+}
+
+// ------------------------------------------------------------------ batches
+#define BHIPCHK(b, call)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_err(&(b)->err, "%s failed: %s", #call, hipGetErrorString(e_));              \
+      (b)->broken = true;                                                             \
+      return IB_LBM_E_DEVICE;                                                         \
+    }                                                                                 \
+  } while (0)
+
+ib_lbm_status ib_lbm_batch_create(void *stream, int32_t precision, ib_lbm_batch **out) {
+  if (!out || (precision != IB_LBM_FP64 && precision != IB_LBM_FP32_SHIFTED)) return IB_LBM_E_INVALID;
+  ib_lbm_batch *b = new ib_lbm_batch();
+  b->stream = (hipStream_t)stream;
+  b->precision = precision;
+  *out = b;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_attach(ib_lbm_batch *b, ib_lbm_sim *s) {
+  if (!b || !s) return IB_LBM_E_INVALID;
+  if (b->broken || s->broken) return IB_LBM_E_STATE;
+  if (s->batch) {
+    set_err(&b->err, "sim already attached to a batch");
+    return IB_LBM_E_STATE;
+  }
+  if (s->cd.precision != b->precision || s->stream != b->stream) {
+    set_err(&b->err, "sim precision or stream differs from the batch");
+    return IB_LBM_E_INVALID;
+  }
+  ib_lbm_status st = build_sim_tables(s);
+  if (st) return st;
+  s->batch = b;
+  s->started = true;
+  b->sims.push_back(s);
+  b->dirty = true;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_detach(ib_lbm_batch *b, ib_lbm_sim *s) {
+  if (!b || !s) return IB_LBM_E_INVALID;
+  auto it = std::find(b->sims.begin(), b->sims.end(), s);
+  if (it == b->sims.end()) return IB_LBM_E_INVALID;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  b->sims.erase(it);
+  s->batch = nullptr;
+  b->dirty = true;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_set_target(ib_lbm_batch *b, ib_lbm_sim *s, int64_t target) {
+  if (!b || !s || s->batch != b || target < 0) return IB_LBM_E_INVALID;
+  CaseState cs;
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  BHIPCHK(b, hipMemcpy(&cs, s->state.p, sizeof cs, hipMemcpyDeviceToHost));
+  cs.target = target;
+  BHIPCHK(b, hipMemcpy(s->state.p, &cs, sizeof cs, hipMemcpyHostToDevice));
+  return IB_LBM_OK;
+}
+
+static ib_lbm_status batch_tables(ib_lbm_batch *b) {
+  if (!b->dirty) return IB_LBM_OK;
+  if (b->graph_exec) {
+    (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+  }
+  std::vector<CaseDesc> cases;
+  std::vector<int32_t> prefix;
+  std::vector<IbmSlot> slots;
+  b->groups.clear();
+  int maxws = 0;
+  for (int col = 0; col < 3; col++) {
+    ib_lbm_batch::Group g{col, (int)cases.size(), 0, 0, (int)prefix.size()};
+    int tiles = 0;
+    for (auto *s : b->sims) {
+      if (s->cd.collision != col) continue;
+      CaseDesc c = s->cd;
+      fill_case_tiles(&c, b->launch);
+      prefix.push_back(tiles);
+      tiles += c.tiles_x * c.tiles_y;
+      cases.push_back(c);
+      g.count++;
+      for (auto &hb : s->bodies) maxws = std::max(maxws, hb.dev.ws_doubles);
+    }
+    prefix.push_back(tiles);
+    g.ntiles = tiles;
+    if (g.count) b->groups.push_back(g);
+  }
+  for (int ci = 0; ci < (int)cases.size(); ci++) {
+    const int n = std::max(1, cases[ci].nbodies);
+    for (int k = 0; k < n; k++) slots.push_back(IbmSlot{ci, cases[ci].nbodies ? k : -1, n, 0});
+  }
+  auto upload = [&](DevBuf *d, const void *src, size_t bytes) -> ib_lbm_status {
+    if (d->bytes < bytes) {
+      if (d->p) (void)hipFree(d->p);
+      d->p = nullptr;
+      if (hipMalloc(&d->p, bytes) != hipSuccess) {
+        set_err(&b->err, "batch table allocation failed");
+        return IB_LBM_E_NOMEM;
+      }
+      d->bytes = bytes;
+    }
+    BHIPCHK(b, hipMemcpy(d->p, src, bytes, hipMemcpyHostToDevice));
+    return IB_LBM_OK;
+  };
+  ib_lbm_status st;
+  if (!cases.empty()) {
+    if ((st = upload(&b->d_cases, cases.data(), cases.size() * sizeof(CaseDesc)))) return st;
+    if ((st = upload(&b->d_prefix, prefix.data(), prefix.size() * sizeof(int32_t)))) return st;
+    if ((st = upload(&b->d_slots, slots.data(), slots.size() * sizeof(IbmSlot)))) return st;
+  }
+  b->nslots = (int)slots.size();
+  b->lds_bytes = maxws * 8 > ibm_max_lds_bytes() ? 0 : maxws * 8;
+  b->dirty = false;
+  return IB_LBM_OK;
+}
+
+static ib_lbm_status batch_enqueue_step(ib_lbm_batch *b) {
+  LaunchShape sh{b->launch.block_x, b->launch.block_y, b->launch.rows_per_thread, b->launch.xcd_remap};
+  for (auto &g : b->groups) {
+    BHIPCHK(b, launch_collide_stream(b->precision, g.collision, (const CaseDesc *)b->d_cases.p + g.first,
+                                     (const int32_t *)b->d_prefix.p + g.prefix_off, g.count, g.ntiles,
+                                     sh, b->stream));
+  }
+  BHIPCHK(b, launch_ibm(b->precision, (const CaseDesc *)b->d_cases.p, (const IbmSlot *)b->d_slots.p,
+                        b->nslots, b->lds_bytes, b->spread_mode, b->stream));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_step(ib_lbm_batch *b, int64_t nsteps) {
+  if (!b || nsteps < 0) return IB_LBM_E_INVALID;
+  if (b->broken) return IB_LBM_E_STATE;
+  ib_lbm_status st = batch_tables(b);
+  if (st) return st;
+  if (b->sims.empty()) return IB_LBM_OK;
+  int64_t left = nsteps;
+  if (b->graph_steps > 0 && left >= b->graph_steps) {
+    if (!b->graph_exec || b->graph_len != b->graph_steps) {
+      if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+      b->graph_exec = nullptr;
+      hipGraph_t g;
+      BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < b->graph_steps; i++) {
+        if ((st = batch_enqueue_step(b))) {
+          hipGraph_t dummy;
+          (void)hipStreamEndCapture(b->stream, &dummy);
+          return st;
+        }
+      }
+      BHIPCHK(b, hipStreamEndCapture(b->stream, &g));
+      BHIPCHK(b, hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(g);
+      b->graph_len = b->graph_steps;
+    }
+    while (left >= b->graph_len) {
+      BHIPCHK(b, hipGraphLaunch(b->graph_exec, b->stream));
+      left -= b->graph_len;
+    }
+  }
+  for (int64_t i = 0; i < left; i++)
+    if ((st = batch_enqueue_step(b))) return st;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_set_graph(ib_lbm_batch *b, int32_t steps_per_graph) {
+  if (!b || steps_per_graph < 0 || steps_per_graph > 100000) return IB_LBM_E_INVALID;
+  b->graph_steps = steps_per_graph;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_sync(ib_lbm_batch *b) {
+  if (!b) return IB_LBM_E_INVALID;
+  if (b->broken) return IB_LBM_E_STATE;
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_destroy(ib_lbm_batch *b) {
+  if (!b) return IB_LBM_E_INVALID;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto *s : b->sims) s->batch = nullptr;
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->d_cases.p) (void)hipFree(b->d_cases.p);
+  if (b->d_prefix.p) (void)hipFree(b->d_prefix.p);
+  if (b->d_slots.p) (void)hipFree(b->d_slots.p);
+  delete b;
+  return IB_LBM_OK;
+}
+
+const char *ib_lbm_batch_last_error(const ib_lbm_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

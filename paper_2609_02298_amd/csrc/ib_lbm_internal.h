@@ -1,0 +1,125 @@
+// Internal device/host data structures of the IB-LBM library (gfx950).
+//
+// A "case" is one lattice with its bodies.  Kernels never take per-step
+// scalar arguments: every case carries its own step counter, target and
+// current-buffer index in device memory, so a batch of cases of different
+// sizes and step counts is advanced by the same launches, and a captured
+// graph of launches stays valid while the batch composition is unchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace iblbm {
+
+enum { kPrecFP64 = 0, kPrecFP32 = 1 };
+enum { kBGK = 0, kTRT = 1, kCMMRT = 2 };
+enum { kPeriodic = 0, kBounceBack = 1, kVelParabolic = 2, kVelUniform = 3, kZeroGradient = 4 };
+enum { kFaceW = 0, kFaceE = 1, kFaceS = 2, kFaceN = 3 };
+enum { kDF = 0, kMDF = 1, kDFC = 2 };
+enum { kHat = 0, kPeskin4 = 1 };
+enum { kFixed = 0, kPrescribedSin = 1, kFree = 2 };
+enum { kImNone = 0, kImFeng = 1 };
+
+// body flags (same values as the public IB_LBM_FLAG_*)
+enum { kFlagNonfinite = 1, kFlagRange = 2, kFlagOverlap = 4, kFlagCapacity = 8 };
+// case flags
+enum { kCaseHalted = 1 };
+
+constexpr int kMaxBodiesPerCase = 8;
+constexpr int kIbmThreads = 512;
+constexpr int kHistCols = 16;
+
+// Mutable per-case state, device resident.
+struct CaseState {
+  int64_t step;    // completed steps
+  int64_t target;  // kernels do nothing once step >= target
+  int32_t cur;     // buffer holding the current post-stream populations
+  int32_t flags;   // kCaseHalted
+  int32_t done;    // IB workgroups of this step that have finished
+  int32_t pad;
+};
+
+// Mutable per-body state, device resident.
+struct BodyState {
+  double xc, yc;        // centre at the last completed step
+  double vx, vy;        // velocity v^n
+  double vpx, vpy;      // v^(n-1)
+  double om;            // angular velocity
+  double vhx, vhy, omh; // half-step values used for U_d in the last step
+  double fhx, fhy, torque;
+  double dimx, dimy;    // internal-mass force held over the step
+  double slip_mean, slip_max, mdf_res;
+  int32_t mdf_iters_done;
+  int32_t flags;
+  int32_t box[4];       // x0 y0 x1 y1 of the nodes that carry IB force
+  int32_t box_valid;
+  int32_t lambda_valid; // DFC cache filled (fixed bodies)
+};
+
+// Constant per-body description plus pointers to the body's device buffers.
+struct BodyDesc {
+  int32_t nb, scheme, kernel, mdf_iters;
+  int32_t motion, internal_mass;
+  int32_t ns;           // support width: 2 (hat) or 4 (P4)
+  int32_t window;       // half width of the angular marker window of the gather
+  int32_t max_rows, max_nodes;
+  int32_t ws_doubles;   // workspace size
+  int32_t hist_cap;
+  double radius, ds, dtheta, omega_mdf;
+  double xc0, yc0, amp[2], freq, phase;
+  double ms, mf, Is;
+  const double *cos_t, *sin_t;  // marker directions (n_b each)
+  double *ws;           // global workspace (used when it does not fit in LDS)
+  double *markers_out;  // n_b x 8: X Y Udx Udy Fx Fy lambda ds
+  double *lambda_cache; // n_b
+  double *history;      // hist_cap x kHistCols
+  BodyState *state;
+};
+
+// Constant per-case description (copied into a device table by a batch).
+struct CaseDesc {
+  int32_t nx, ny;
+  int32_t collision, precision;
+  int32_t bc[4];
+  int32_t tiles_x, tiles_y;
+  int32_t nbodies, pad;
+  int64_t plane;        // nx*ny
+  double omega, s_e, s_o, s_q, s_eps;  // relaxation rates
+  double rho0, u_bc, inv_ny2;
+  double fluid_fx, fluid_fy;
+  double grav_x, grav_y;  // gravity acting on bodies (Eq. 22)
+  void *f[2];           // two population lattices (9 planes each)
+  void *force;          // IB force density, 2 planes
+  CaseState *state;
+  BodyDesc *bodies;     // device array of nbodies
+};
+
+// One IB workgroup: the body `body` of case `cas` (body = -1: a case without
+// bodies, which only advances the step counter).
+struct IbmSlot {
+  int32_t cas;
+  int32_t body;
+  int32_t slots_in_case;
+  int32_t pad;
+};
+
+struct LaunchShape {
+  int32_t block_x, block_y, rows_per_thread, xcd_remap;
+};
+
+// ---- kernel launchers (defined in the .hip files) ----
+hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
+                                 const int32_t *tile_prefix, int ncases, int ntiles,
+                                 LaunchShape shape, hipStream_t stream);
+hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
+                      int lds_bytes, int spread_mode, hipStream_t stream);
+hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
+hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
+                         hipStream_t stream);
+hipError_t launch_export(const CaseDesc &c, int buf, double *out, hipStream_t stream);
+hipError_t launch_import(const CaseDesc &c, int buf, const double *in, hipStream_t stream);
+hipError_t launch_force_export(const CaseDesc &c, double *fx, double *fy, hipStream_t stream);
+int ibm_max_lds_bytes();
+
+}  // namespace iblbm

@@ -1,0 +1,453 @@
+// Fused D2Q9 collide + stream for gfx950.
+//
+// One thread owns one node per row it visits: it reads the node's nine
+// post-stream populations (coalesced: nine planes, x fastest), collides them
+// with BGK + Guo forcing (Eq. 1-4), TRT (Sec. 2.2) or the central-moment
+// operator (Eq. 5), and pushes the nine results to the neighbours of the
+// other lattice ("two-lattice push"), applying the face closures on the fly.
+// The kernel is HBM-bound: 9 reads + 9 writes per node, 144 B (FP64) or
+// 72 B (FP32 shifted) of algorithmic traffic per node update.  Nothing here
+// is a dense contraction, so there is no MFMA.
+//
+// The FP32 path stores and collides the shifted populations
+// g_i = f_i - w_i rho0 with FP32 arithmetic; bounce-back and the velocity
+// closure are linear in g because w_opp(i) = w_i.
+#include "ib_lbm_internal.h"
+
+namespace iblbm {
+
+__constant__ int c_ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int c_ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+#define EXI(i) ((i) == 1 || (i) == 5 || (i) == 8 ? 1 : ((i) == 3 || (i) == 6 || (i) == 7 ? -1 : 0))
+#define EYI(i) ((i) == 2 || (i) == 5 || (i) == 6 ? 1 : ((i) == 4 || (i) == 7 || (i) == 8 ? -1 : 0))
+#define OPPI(i) ((i) == 0 ? 0 : ((i) <= 4 ? (((i) + 1) & 3) + 1 : (((i) - 3) & 3) + 5))
+
+template <typename R>
+__device__ __forceinline__ R wgt(int i) {
+  return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
+}
+
+// ---------------------------------------------------------------- collision
+// f holds the stored values (f, or g = f - w rho0 when SHIFT).  sum_f is
+// sum_i f_i, so the equilibrium in either form is w_i (sum_f + rho P_i(u)).
+template <typename R, bool SHIFT, int COL>
+__device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c) {
+  const R sum = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const R rho = SHIFT ? R(c.rho0) + sum : sum;
+  const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const R inv_rho = R(1) / rho;
+  const R ux = (jx + R(0.5) * Fx) * inv_rho;
+  const R uy = (jy + R(0.5) * Fy) * inv_rho;
+
+  if constexpr (COL == kBGK || COL == kTRT) {
+    const R uu = ux * ux + uy * uy;
+    const R uF = ux * Fx + uy * Fy;
+    R eq[9], S[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+      const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
+      const R eF = R(EXI(i)) * Fx + R(EYI(i)) * Fy;
+      eq[i] = wgt<R>(i) * (sum + rho * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
+      S[i] = wgt<R>(i) * (R(3) * (eF - uF) + R(9) * eu * eF);
+    }
+    if constexpr (COL == kBGK) {
+      const R om = R(c.omega);
+      const R pf = R(1) - R(0.5) * om;
+#pragma unroll
+      for (int i = 0; i < 9; i++) f[i] = f[i] - om * (f[i] - eq[i]) + pf * S[i];
+    } else {
+      const R se = R(c.s_e), so = R(c.s_o);
+      const R pe = R(1) - R(0.5) * se, po = R(1) - R(0.5) * so;
+      f[0] = f[0] - se * (f[0] - eq[0]) + pe * S[0];
+#pragma unroll
+      for (int i = 1; i <= 8; i++) {
+        const int j = OPPI(i);
+        if (j < i) continue;
+        const R fp = R(0.5) * (f[i] + f[j]), fm = R(0.5) * (f[i] - f[j]);
+        const R ep = R(0.5) * (eq[i] + eq[j]), em = R(0.5) * (eq[i] - eq[j]);
+        const R sp = R(0.5) * (S[i] + S[j]), sm = R(0.5) * (S[i] - S[j]);
+        const R even = -se * (fp - ep) + pe * sp;
+        const R odd = -so * (fm - em) + po * sm;
+        f[i] = f[i] + even + odd;
+        f[j] = f[j] + even - odd;
+      }
+    }
+  } else {
+    // Central moments k_pq = sum_i f_i (e_x - u_x)^p (e_y - u_y)^q.  D2Q9 is
+    // the tensor product of {-1,0,1} x {-1,0,1}, so the transform factorises
+    // into a 3-point transform along x for each row e_y, then along y.
+    // Grid index [ey+1][ex+1] -> population: row -1: 7 4 8, row 0: 3 0 1,
+    // row +1: 6 2 5.
+    R a[3][3];
+    a[0][0] = f[7]; a[0][1] = f[4]; a[0][2] = f[8];
+    a[1][0] = f[3]; a[1][1] = f[0]; a[1][2] = f[1];
+    a[2][0] = f[6]; a[2][1] = f[2]; a[2][2] = f[5];
+    R kx[3][3];  // kx[row][p]
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      const R m0 = a[r][0] + a[r][1] + a[r][2];
+      const R m1 = a[r][2] - a[r][0];
+      const R m2 = a[r][2] + a[r][0];
+      kx[r][0] = m0;
+      kx[r][1] = m1 - ux * m0;
+      kx[r][2] = m2 - R(2) * ux * m1 + ux * ux * m0;
+    }
+    R k[3][3];  // k[p][q]
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+      const R n0 = kx[0][p] + kx[1][p] + kx[2][p];
+      const R n1 = kx[2][p] - kx[0][p];
+      const R n2 = kx[2][p] + kx[0][p];
+      k[p][0] = n0;
+      k[p][1] = n1 - uy * n0;
+      k[p][2] = n2 - R(2) * uy * n1 + uy * uy * n0;
+    }
+    // Relaxation, Eq. (5): Lambda = diag(0,0,0,w,w,w,s_q,s_q,s_eps).
+    // Equilibrium central moments (rho, 0, 0, rho/3, rho/3, 0, 0, 0, rho/9),
+    // forcing central moments (0, Fx, Fy, 0, 0, 0, Fy/3, Fx/3, 0).  In the
+    // shifted form the central moments of rho0 w_i are subtracted from the
+    // equilibrium: they factorise as c_p(ux) c_q(uy) with c = (1, -u, 1/3+u^2).
+    const R om = R(c.omega), sq = R(c.s_q), seps = R(c.s_eps);
+    const R r0 = SHIFT ? R(c.rho0) : R(0);
+    const R ux2 = ux * ux, uy2 = uy * uy;
+    const R third = R(1) / R(3);
+    const R base = sum;  // rho (unshifted) or rho - rho0 (shifted)
+    const R E20 = base * third - r0 * ux2;
+    const R E02 = base * third - r0 * uy2;
+    const R E11 = -r0 * ux * uy;
+    const R E21 = r0 * uy * (third + ux2);
+    const R E12 = r0 * ux * (third + uy2);
+    const R E22 = base * (R(1) / R(9)) - r0 * (third * (ux2 + uy2) + ux2 * uy2);
+    k[1][0] += Fx;
+    k[0][1] += Fy;
+    k[2][0] = (R(1) - om) * k[2][0] + om * E20;
+    k[0][2] = (R(1) - om) * k[0][2] + om * E02;
+    k[1][1] = (R(1) - om) * k[1][1] + om * E11;
+    const R pq = R(1) - R(0.5) * sq;
+    k[2][1] = (R(1) - sq) * k[2][1] + sq * E21 + pq * third * Fy;
+    k[1][2] = (R(1) - sq) * k[1][2] + sq * E12 + pq * third * Fx;
+    k[2][2] = (R(1) - seps) * k[2][2] + seps * E22;
+    // Back to populations: central -> raw along y, then solve the 3-point
+    // system (values at -1, 0, 1 from moments 0, 1, 2), then along x.
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+      const R M0 = k[p][0];
+      const R M1 = k[p][1] + uy * M0;
+      const R M2 = k[p][2] + R(2) * uy * k[p][1] + uy2 * M0;
+      kx[1][p] = M0 - M2;
+      kx[2][p] = R(0.5) * (M2 + M1);
+      kx[0][p] = R(0.5) * (M2 - M1);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      const R M0 = kx[r][0];
+      const R M1 = kx[r][1] + ux * M0;
+      const R M2 = kx[r][2] + R(2) * ux * kx[r][1] + ux2 * M0;
+      a[r][1] = M0 - M2;
+      a[r][2] = R(0.5) * (M2 + M1);
+      a[r][0] = R(0.5) * (M2 - M1);
+    }
+    f[7] = a[0][0]; f[4] = a[0][1]; f[8] = a[0][2];
+    f[3] = a[1][0]; f[0] = a[1][1]; f[1] = a[1][2];
+    f[6] = a[2][0]; f[2] = a[2][1]; f[5] = a[2][2];
+  }
+}
+
+// ------------------------------------------------------------ streaming
+template <typename T>
+__device__ __forceinline__ void st(T *dst, int64_t plane, int i, int64_t idx, T v) {
+  dst[(int64_t)i * plane + idx] = v;
+}
+
+__device__ __forceinline__ bool is_vel(int b) { return b == kVelParabolic || b == kVelUniform; }
+
+// Push population i of node (x,y) with value v, applying the face closures:
+//   periodic faces wrap; a link leaving through the zero-gradient east face
+//   is dropped (the entering populations of the east column are written as
+//   copies of the column nx-2, see zg_dup); a link leaving through a wall
+//   returns as opp(i) at the node (half-way bounce-back); through a velocity
+//   face it returns as opp(i) - 6 w_i rho0 (e_i . u_w), u_w evaluated at the
+//   link mid-point.  A link leaving through a wall and a velocity face is a
+//   wall link; among velocity faces the first of W, E, S, N is used.
+template <typename T>
+__device__ __forceinline__ void zg_dup(const CaseDesc &c, T *dst, int j, int xs, int ys, T v) {
+  if (c.bc[kFaceE] == kZeroGradient && xs == c.nx - 2 && (j == 3 || j == 6 || j == 7))
+    st(dst, c.plane, j, (int64_t)ys * c.nx + (c.nx - 1), v);
+}
+
+template <typename T>
+__device__ __forceinline__ void push_boundary(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
+  const int nx = c.nx, ny = c.ny;
+  int xd = x + c_ex[i], yd = y + c_ey[i];
+  bool cw = xd < 0, ce = xd >= nx, cs = yd < 0, cn = yd >= ny;
+  if (cw && c.bc[kFaceW] == kPeriodic) { xd += nx; cw = false; }
+  if (ce && c.bc[kFaceE] == kPeriodic) { xd -= nx; ce = false; }
+  if (cs && c.bc[kFaceS] == kPeriodic) { yd += ny; cs = false; }
+  if (cn && c.bc[kFaceN] == kPeriodic) { yd -= ny; cn = false; }
+  if (!(cw || ce || cs || cn)) {
+    st(dst, c.plane, i, (int64_t)yd * nx + xd, v);
+    zg_dup(c, dst, i, xd, yd, v);
+    return;
+  }
+  if (ce && c.bc[kFaceE] == kZeroGradient) return;
+  const int j = OPPI(i);
+  const bool wall = (cw && c.bc[kFaceW] == kBounceBack) || (ce && c.bc[kFaceE] == kBounceBack) ||
+                    (cs && c.bc[kFaceS] == kBounceBack) || (cn && c.bc[kFaceN] == kBounceBack);
+  if (wall) {
+    st(dst, c.plane, j, (int64_t)y * nx + x, v);
+    zg_dup(c, dst, j, x, y, v);
+    return;
+  }
+  int vf = -1;
+  if (cw && is_vel(c.bc[kFaceW])) vf = kFaceW;
+  else if (ce && is_vel(c.bc[kFaceE])) vf = kFaceE;
+  else if (cs && is_vel(c.bc[kFaceS])) vf = kFaceS;
+  else if (cn && is_vel(c.bc[kFaceN])) vf = kFaceN;
+  if (vf < 0) return;
+  T uw;
+  if (c.bc[vf] == kVelParabolic) {
+    const T ym = T(y) + T(0.5) * T(c_ey[i]);
+    uw = T(4) * T(c.u_bc) * (ym + T(0.5)) * (T(ny) - T(0.5) - ym) * T(c.inv_ny2);
+  } else {
+    uw = T(c.u_bc);
+  }
+  const T w = wgt<T>(i);
+  v = v - T(6) * w * T(c.rho0) * (T(c_ex[i]) * uw);
+  st(dst, c.plane, j, (int64_t)y * nx + x, v);
+  zg_dup(c, dst, j, x, y, v);
+}
+
+template <typename T, int COL>
+__global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__restrict__ cases,
+                                                              const int32_t *__restrict__ tile_prefix,
+                                                              int ncases, int ntiles, int rpt,
+                                                              int xcd_remap) {
+  const int nb = gridDim.x;
+  int t = blockIdx.x;
+  if (xcd_remap) t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  if (t >= ntiles) return;
+  int ci = 0;
+  if (ncases > 1) {
+    int lo = 0, hi = ncases - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    ci = lo;
+  }
+  const CaseDesc &c = cases[ci];
+  const CaseState *cs = c.state;
+  if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
+  const int cur = cs->cur;
+  const T *__restrict__ src = (const T *)c.f[cur];
+  T *__restrict__ dst = (T *)c.f[cur ^ 1];
+  T *__restrict__ frc = (T *)c.force;
+  const int local = t - tile_prefix[ci];
+  const int tx = local % c.tiles_x, ty = local / c.tiles_x;
+  const int TX = blockDim.x, TY = blockDim.y * rpt;
+  const int nx = c.nx, ny = c.ny;
+  const int64_t plane = c.plane;
+  const int x = tx * TX + threadIdx.x;
+  const int ybase = ty * TY;
+  // IB force only inside the union of the bodies' force boxes
+  int fb0 = 1 << 30, fb1 = -1, fy0 = 1 << 30, fy1 = -1;
+  for (int b = 0; b < c.nbodies; b++) {
+    const BodyState *bs = c.bodies[b].state;
+    if (bs->box_valid) {
+      fb0 = min(fb0, bs->box[0]); fy0 = min(fy0, bs->box[1]);
+      fb1 = max(fb1, bs->box[2]); fy1 = max(fy1, bs->box[3]);
+    }
+  }
+  const int xt0 = tx * TX, xt1 = xt0 + TX - 1, yt1 = ybase + TY - 1;
+  const bool tile_force = !(fb1 < xt0 || fb0 > xt1 || fy1 < ybase || fy0 > yt1);
+  const bool interior = xt0 >= 1 && xt1 <= nx - 3 && ybase >= 1 && yt1 <= ny - 2;
+  const T ffx = T(c.fluid_fx), ffy = T(c.fluid_fy);
+
+  for (int r = 0; r < rpt; r++) {
+    const int y = ybase + threadIdx.y + r * blockDim.y;
+    if (x >= nx || y >= ny) continue;
+    const int64_t p = (int64_t)y * nx + x;
+    T f[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) f[i] = src[i * plane + p];
+    T Fx = ffx, Fy = ffy;
+    if (tile_force && x >= fb0 && x <= fb1 && y >= fy0 && y <= fy1) {
+      const T a = frc[p], b = frc[plane + p];
+      if (a != T(0) || b != T(0)) {
+        Fx += a;
+        Fy += b;
+        frc[p] = T(0);
+        frc[plane + p] = T(0);
+      }
+    }
+    collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
+    if (interior) {
+#pragma unroll
+      for (int i = 0; i < 9; i++) dst[i * plane + p + EXI(i) + (int64_t)EYI(i) * nx] = f[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; i++) push_boundary<T>(c, dst, x, y, i, f[i]);
+    }
+  }
+}
+
+hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
+                                 const int32_t *tile_prefix, int ncases, int ntiles,
+                                 LaunchShape shape, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  int grid = ntiles;
+  if (shape.xcd_remap) grid = (ntiles + 7) / 8 * 8;
+  dim3 block(shape.block_x, shape.block_y);
+  const int rpt = shape.rows_per_thread;
+  const int remap = shape.xcd_remap;
+#define IBL_LAUNCH(T, C)                                                                        \
+  hipLaunchKernelGGL((collide_stream_kernel<T, C>), dim3(grid), block, 0, stream, cases,        \
+                     tile_prefix, ncases, ntiles, rpt, remap)
+  if (precision == kPrecFP64) {
+    if (collision == kBGK) IBL_LAUNCH(double, kBGK);
+    else if (collision == kTRT) IBL_LAUNCH(double, kTRT);
+    else IBL_LAUNCH(double, kCMMRT);
+  } else {
+    if (collision == kBGK) IBL_LAUNCH(float, kBGK);
+    else if (collision == kTRT) IBL_LAUNCH(float, kTRT);
+    else IBL_LAUNCH(float, kCMMRT);
+  }
+#undef IBL_LAUNCH
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ utilities
+// Equilibrium start state f^eq(rho0, u_init): u_init is the parabolic inlet
+// profile (W face parabolic), u_bc (any uniform face) or 0.
+template <typename T>
+__global__ void init_eq_kernel(CaseDesc c, int buf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= c.plane) return;
+  const int y = (int)(p / c.nx);
+  double ux = 0.0;
+  if (c.bc[kFaceW] == kVelParabolic)
+    ux = 4.0 * c.u_bc * (y + 0.5) * (c.ny - 0.5 - y) * c.inv_ny2;
+  else if (c.bc[0] == kVelUniform || c.bc[1] == kVelUniform || c.bc[2] == kVelUniform ||
+           c.bc[3] == kVelUniform)
+    ux = c.u_bc;
+  T *f = (T *)c.f[buf];
+  const bool shift = sizeof(T) == 4;
+  for (int i = 0; i < 9; i++) {
+    const double eu = c_ex[i] * ux;
+    const double w = wgt<double>(i);
+    const double feq = w * c.rho0 * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * ux * ux);
+    f[i * c.plane + p] = (T)(shift ? feq - w * c.rho0 : feq);
+  }
+  T *frc = (T *)c.force;
+  frc[p] = T(0);
+  frc[c.plane + p] = T(0);
+}
+
+hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)((c.plane + threads - 1) / threads);
+  if (c.precision == kPrecFP64)
+    hipLaunchKernelGGL(init_eq_kernel<double>, dim3(blocks), dim3(threads), 0, stream, c, buf);
+  else
+    hipLaunchKernelGGL(init_eq_kernel<float>, dim3(blocks), dim3(threads), 0, stream, c, buf);
+  return hipGetLastError();
+}
+
+// Density and velocity of the current state, Eq. (4), FP64 output.
+template <typename T>
+__global__ void fields_kernel(CaseDesc c, int buf, double *rho, double *ux, double *uy) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= c.plane) return;
+  const T *f = (const T *)c.f[buf];
+  const T *frc = (const T *)c.force;
+  const bool shift = sizeof(T) == 4;
+  double s = 0, jx = 0, jy = 0;
+  for (int i = 0; i < 9; i++) {
+    const double v = (double)f[i * c.plane + p] + (shift ? wgt<double>(i) * c.rho0 : 0.0);
+    s += v;
+    jx += v * c_ex[i];
+    jy += v * c_ey[i];
+  }
+  const double Fx = (double)frc[p] + c.fluid_fx, Fy = (double)frc[c.plane + p] + c.fluid_fy;
+  rho[p] = s;
+  ux[p] = (jx + 0.5 * Fx) / s;
+  uy[p] = (jy + 0.5 * Fy) / s;
+}
+
+hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
+                         hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)((c.plane + threads - 1) / threads);
+  if (c.precision == kPrecFP64)
+    hipLaunchKernelGGL(fields_kernel<double>, dim3(blocks), dim3(threads), 0, stream, c, buf, rho,
+                       ux, uy);
+  else
+    hipLaunchKernelGGL(fields_kernel<float>, dim3(blocks), dim3(threads), 0, stream, c, buf, rho,
+                       ux, uy);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void export_kernel(CaseDesc c, int buf, double *out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= c.plane) return;
+  const T *f = (const T *)c.f[buf];
+  const bool shift = sizeof(T) == 4;
+  for (int i = 0; i < 9; i++)
+    out[i * c.plane + p] = (double)f[i * c.plane + p] + (shift ? wgt<double>(i) * c.rho0 : 0.0);
+}
+
+template <typename T>
+__global__ void import_kernel(CaseDesc c, int buf, const double *in) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= c.plane) return;
+  T *f = (T *)c.f[buf];
+  const bool shift = sizeof(T) == 4;
+  for (int i = 0; i < 9; i++)
+    f[i * c.plane + p] = (T)(in[i * c.plane + p] - (shift ? wgt<double>(i) * c.rho0 : 0.0));
+}
+
+template <typename T>
+__global__ void force_export_kernel(CaseDesc c, double *fx, double *fy) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= c.plane) return;
+  const T *frc = (const T *)c.force;
+  fx[p] = (double)frc[p];
+  fy[p] = (double)frc[c.plane + p];
+}
+
+hipError_t launch_export(const CaseDesc &c, int buf, double *out, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)((c.plane + threads - 1) / threads);
+  if (c.precision == kPrecFP64)
+    hipLaunchKernelGGL(export_kernel<double>, dim3(blocks), dim3(threads), 0, stream, c, buf, out);
+  else
+    hipLaunchKernelGGL(export_kernel<float>, dim3(blocks), dim3(threads), 0, stream, c, buf, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_import(const CaseDesc &c, int buf, const double *in, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)((c.plane + threads - 1) / threads);
+  if (c.precision == kPrecFP64)
+    hipLaunchKernelGGL(import_kernel<double>, dim3(blocks), dim3(threads), 0, stream, c, buf, in);
+  else
+    hipLaunchKernelGGL(import_kernel<float>, dim3(blocks), dim3(threads), 0, stream, c, buf, in);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_export(const CaseDesc &c, double *fx, double *fy, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)((c.plane + threads - 1) / threads);
+  if (c.precision == kPrecFP64)
+    hipLaunchKernelGGL(force_export_kernel<double>, dim3(blocks), dim3(threads), 0, stream, c, fx,
+                       fy);
+  else
+    hipLaunchKernelGGL(force_export_kernel<float>, dim3(blocks), dim3(threads), 0, stream, c, fx,
+                       fy);
+  return hipGetLastError();
+}
+
+}  // namespace iblbm

@@ -1,0 +1,407 @@
+"""Python binding of the C ABI in ``include/ib_lbm.h`` (argument marshalling only).
+
+Every step of the method runs in the gfx950 HIP kernels of ``libib_lbm.so``.
+This module only converts Python values to the ABI's structs, passes HIP
+streams and (optionally) PyTorch's caching allocator through, and raises on
+error statuses.  There is no CPU fallback: if the library is missing or no
+HIP device is present, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libib_lbm.so")
+ABI_VERSION = 1
+
+FP64, FP32_SHIFTED = 0, 1
+BGK, TRT, CMMRT = 0, 1, 2
+PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM, ZERO_GRADIENT = 0, 1, 2, 3, 4
+DF, MDF, DFC = 0, 1, 2
+HAT, PESKIN4 = 0, 1
+FIXED, PRESCRIBED_SIN, FREE = 0, 1, 2
+IM_NONE, IM_FENG = 0, 1
+SPREAD_GATHER, SPREAD_ATOMIC = 0, 1
+FLAG_NONFINITE, FLAG_RANGE, FLAG_OVERLAP = 1, 2, 4
+
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_DIVERGED",
+          -5: "E_RANGE", -6: "E_STATE"}
+
+# Exported symbols declared in include/ib_lbm.h (checked by the CPU tests).
+EXPORTS = [
+    "ib_lbm_abi_version", "ib_lbm_create", "ib_lbm_add_body", "ib_lbm_step", "ib_lbm_forces",
+    "ib_lbm_history", "ib_lbm_fields", "ib_lbm_get_populations", "ib_lbm_set_populations",
+    "ib_lbm_force_field", "ib_lbm_markers", "ib_lbm_steps_done", "ib_lbm_sync",
+    "ib_lbm_destroy", "ib_lbm_last_error", "ib_lbm_footprint", "ib_lbm_set_launch",
+    "ib_lbm_get_launch", "ib_lbm_set_spread", "ib_lbm_set_graph", "ib_lbm_timing_enable",
+    "ib_lbm_timing_read", "ib_lbm_batch_create", "ib_lbm_batch_attach", "ib_lbm_batch_detach",
+    "ib_lbm_batch_set_target", "ib_lbm_batch_step", "ib_lbm_batch_set_graph",
+    "ib_lbm_batch_sync", "ib_lbm_batch_destroy", "ib_lbm_batch_last_error",
+]
+
+
+class IbLbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p),
+                ("alloc", C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p))]
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("precision", C.c_int32), ("collision", C.c_int32),
+                ("history_capacity", C.c_int32), ("tau", C.c_double), ("trt_magic", C.c_double),
+                ("cm_s_q", C.c_double), ("cm_s_eps", C.c_double), ("rho0", C.c_double),
+                ("bc", C.c_int32 * 4), ("u_bc", C.c_double), ("gravity", C.c_double * 2),
+                ("fluid_force", C.c_double * 2), ("stream", C.c_void_p),
+                ("alloc", C.POINTER(Allocator))]
+
+
+class BodyDesc(C.Structure):
+    _fields_ = [("xc", C.c_double), ("yc", C.c_double), ("diameter", C.c_double),
+                ("n_markers", C.c_int32), ("scheme", C.c_int32), ("kernel", C.c_int32),
+                ("mdf_iters", C.c_int32), ("mdf_omega", C.c_double), ("motion", C.c_int32),
+                ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
+                ("phase", C.c_double), ("density_ratio", C.c_double)]
+
+
+class BodyState(C.Structure):
+    _fields_ = [("step", C.c_int64), ("fx", C.c_double), ("fy", C.c_double),
+                ("torque", C.c_double), ("xc", C.c_double), ("yc", C.c_double),
+                ("vx", C.c_double), ("vy", C.c_double), ("omega", C.c_double),
+                ("slip_mean", C.c_double), ("slip_max", C.c_double),
+                ("mdf_residual", C.c_double), ("mdf_omega", C.c_double),
+                ("mdf_iters", C.c_int32), ("flags", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Launch(C.Structure):
+    _fields_ = [("block_x", C.c_int32), ("block_y", C.c_int32), ("rows_per_thread", C.c_int32),
+                ("xcd_remap", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libib_lbm.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2609_02298_amd/build.py "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    vp = C.c_void_p
+    L.ib_lbm_abi_version.restype = C.c_uint32
+    L.ib_lbm_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+    L.ib_lbm_add_body.argtypes = [vp, C.POINTER(BodyDesc), C.POINTER(C.c_int32)]
+    L.ib_lbm_step.argtypes = [vp, C.c_int64]
+    L.ib_lbm_forces.argtypes = [vp, C.c_int32, C.POINTER(BodyState)]
+    L.ib_lbm_history.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, dp]
+    L.ib_lbm_fields.argtypes = [vp, dp, dp, dp]
+    L.ib_lbm_get_populations.argtypes = [vp, dp]
+    L.ib_lbm_set_populations.argtypes = [vp, dp]
+    L.ib_lbm_force_field.argtypes = [vp, dp, dp]
+    L.ib_lbm_markers.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int32)]
+    L.ib_lbm_steps_done.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.ib_lbm_sync.argtypes = [vp]
+    L.ib_lbm_destroy.argtypes = [vp]
+    L.ib_lbm_last_error.restype = C.c_char_p
+    L.ib_lbm_last_error.argtypes = [vp]
+    L.ib_lbm_footprint.restype = C.c_size_t
+    L.ib_lbm_footprint.argtypes = [C.POINTER(Config), C.c_int32, C.POINTER(C.c_int32)]
+    L.ib_lbm_set_launch.argtypes = [vp, C.POINTER(Launch)]
+    L.ib_lbm_get_launch.argtypes = [vp, C.POINTER(Launch)]
+    L.ib_lbm_set_spread.argtypes = [vp, C.c_int32]
+    L.ib_lbm_set_graph.argtypes = [vp, C.c_int32]
+    L.ib_lbm_timing_enable.argtypes = [vp, C.c_int32]
+    L.ib_lbm_timing_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
+    L.ib_lbm_batch_create.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+    L.ib_lbm_batch_attach.argtypes = [vp, vp]
+    L.ib_lbm_batch_detach.argtypes = [vp, vp]
+    L.ib_lbm_batch_set_target.argtypes = [vp, vp, C.c_int64]
+    L.ib_lbm_batch_step.argtypes = [vp, C.c_int64]
+    L.ib_lbm_batch_set_graph.argtypes = [vp, C.c_int32]
+    L.ib_lbm_batch_sync.argtypes = [vp]
+    L.ib_lbm_batch_destroy.argtypes = [vp]
+    L.ib_lbm_batch_last_error.restype = C.c_char_p
+    L.ib_lbm_batch_last_error.argtypes = [vp]
+    if L.ib_lbm_abi_version() != ABI_VERSION:
+        raise ImportError("libib_lbm.so ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _torch_stream(stream):
+    if stream is not None:
+        return int(stream)
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device available (the library has no CPU path)")
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+class _TorchAllocator:
+    """Routes the library's device allocations through PyTorch's caching
+    allocator (so lattices share torch's memory pool)."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        self._keep = {}
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+                return int(p)
+            except Exception:
+                return None
+
+        def _free(ctx, ptr, stream):
+            if ptr:
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.struct = Allocator(None, Allocator._fields_[1][1](_alloc), Allocator._fields_[2][1](_free))
+
+
+def make_config(case: dict, precision: int = FP64, stream=None, allocator=None,
+                history_capacity: int = 0) -> Config:
+    c = Config()
+    c.abi_version = ABI_VERSION
+    c.nx, c.ny = int(case["nx"]), int(case["ny"])
+    c.precision = int(precision)
+    c.collision = int(case.get("collision", BGK))
+    c.history_capacity = int(history_capacity)
+    c.tau = float(case["tau"])
+    c.trt_magic = float(case.get("trt_magic", 0.25))
+    c.cm_s_q = float(case.get("cm_s_q", 1.2))
+    c.cm_s_eps = float(case.get("cm_s_eps", 1.4))
+    c.rho0 = float(case.get("rho0", 1.0))
+    for i, b in enumerate(case.get("bc", (PERIODIC,) * 4)):
+        c.bc[i] = int(b)
+    c.u_bc = float(case.get("u_bc", 0.0))
+    g = case.get("gravity", (0.0, 0.0))
+    c.gravity[0], c.gravity[1] = float(g[0]), float(g[1])
+    ff = case.get("fluid_force", (0.0, 0.0))
+    c.fluid_force[0], c.fluid_force[1] = float(ff[0]), float(ff[1])
+    c.stream = stream
+    c.alloc = C.pointer(allocator.struct) if allocator is not None else None
+    return c
+
+
+def make_body(b: dict) -> BodyDesc:
+    d = BodyDesc()
+    d.xc, d.yc, d.diameter = float(b["xc"]), float(b["yc"]), float(b["diameter"])
+    d.n_markers = int(b.get("n_markers", 0))
+    d.scheme = int(b.get("scheme", DF))
+    d.kernel = int(b.get("kernel", HAT))
+    d.mdf_iters = int(b.get("mdf_iters", 5))
+    d.mdf_omega = float(b.get("mdf_omega", 0.0))
+    d.motion = int(b.get("motion", FIXED))
+    d.internal_mass = int(b.get("internal_mass", IM_NONE))
+    amp = b.get("amp", (0.0, 0.0))
+    d.amp[0], d.amp[1] = float(amp[0]), float(amp[1])
+    d.freq = float(b.get("freq", 0.0))
+    d.phase = float(b.get("phase", 0.0))
+    d.density_ratio = float(b.get("density_ratio", 1.0))
+    return d
+
+
+def footprint(case: dict, precision: int = FP64) -> int:
+    L = load_library()
+    c = make_config(case, precision)
+    bodies = case.get("bodies", [])
+    nm = (C.c_int32 * max(1, len(bodies)))(*[
+        int(b.get("n_markers", 0)) or int(round(math.pi * b["diameter"])) for b in bodies])
+    return int(L.ib_lbm_footprint(C.byref(c), len(bodies), nm))
+
+
+class Sim:
+    """One IB-LBM simulation on the HIP device (the ABI's ``ib_lbm_sim``)."""
+
+    def __init__(self, case: dict, precision: int = FP64, stream=None, torch_allocator: bool = False,
+                 history_capacity: int = 0, add_bodies: bool = True):
+        self.L = load_library()
+        self.case = dict(case)
+        self.precision = precision
+        self._alloc = _TorchAllocator() if torch_allocator else None
+        self.stream = _torch_stream(stream)
+        self._cfg = make_config(case, precision, self.stream, self._alloc, history_capacity)
+        self.nx, self.ny = self._cfg.nx, self._cfg.ny
+        h = C.c_void_p()
+        self._check(self.L.ib_lbm_create(C.byref(self._cfg), C.byref(h)), None)
+        self.h = h
+        self.nmarkers = []
+        if add_bodies:
+            for b in case.get("bodies", []):
+                self.add_body(b)
+
+    def _check(self, st, h=None):
+        if st != 0:
+            msg = self.L.ib_lbm_last_error(h if h is not None else getattr(self, "h", None))
+            raise IbLbmError(st, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ib_lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_body(self, body: dict) -> int:
+        d = make_body(body)
+        bid = C.c_int32()
+        self._check(self.L.ib_lbm_add_body(self.h, C.byref(d), C.byref(bid)), self.h)
+        n = C.c_int32()
+        self._check(self.L.ib_lbm_markers(self.h, bid.value, None, C.byref(n)), self.h)
+        self.nmarkers.append(n.value)
+        return bid.value
+
+    def step(self, n: int = 1):
+        self._check(self.L.ib_lbm_step(self.h, int(n)), self.h)
+
+    def sync(self):
+        self._check(self.L.ib_lbm_sync(self.h), self.h)
+
+    def forces(self, body: int = 0, check: bool = True) -> dict:
+        st = BodyState()
+        r = self.L.ib_lbm_forces(self.h, body, C.byref(st))
+        if check:
+            self._check(r, self.h)
+        d = st.as_dict()
+        d["status"] = r
+        return d
+
+    def history(self, body: int, first: int, count: int) -> np.ndarray:
+        out = np.zeros((count, 16))
+        self._check(self.L.ib_lbm_history(self.h, body, first, count, _dp(out)), self.h)
+        return out
+
+    def fields(self):
+        r = np.empty((self.ny, self.nx)); ux = np.empty_like(r); uy = np.empty_like(r)
+        self._check(self.L.ib_lbm_fields(self.h, _dp(r), _dp(ux), _dp(uy)), self.h)
+        return r, ux, uy
+
+    def populations(self) -> np.ndarray:
+        f = np.empty((9, self.ny, self.nx))
+        self._check(self.L.ib_lbm_get_populations(self.h, _dp(f)), self.h)
+        return f
+
+    def set_populations(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, np.float64)
+        assert f.shape == (9, self.ny, self.nx)
+        self._check(self.L.ib_lbm_set_populations(self.h, _dp(f)), self.h)
+
+    def force(self):
+        fx = np.empty((self.ny, self.nx)); fy = np.empty_like(fx)
+        self._check(self.L.ib_lbm_force_field(self.h, _dp(fx), _dp(fy)), self.h)
+        return fx, fy
+
+    def markers(self, body: int = 0) -> np.ndarray:
+        out = np.zeros((self.nmarkers[body], 8))
+        n = C.c_int32()
+        self._check(self.L.ib_lbm_markers(self.h, body, _dp(out), C.byref(n)), self.h)
+        return out
+
+    @property
+    def steps_done(self) -> int:
+        v = C.c_int64()
+        self._check(self.L.ib_lbm_steps_done(self.h, C.byref(v)), self.h)
+        return v.value
+
+    def set_launch(self, block_x=64, block_y=4, rows_per_thread=2, xcd_remap=1):
+        l = Launch(block_x, block_y, rows_per_thread, xcd_remap)
+        self._check(self.L.ib_lbm_set_launch(self.h, C.byref(l)), self.h)
+
+    def get_launch(self) -> dict:
+        l = Launch()
+        self._check(self.L.ib_lbm_get_launch(self.h, C.byref(l)), self.h)
+        return {n: getattr(l, n) for n, _ in Launch._fields_}
+
+    def set_spread(self, mode: int):
+        self._check(self.L.ib_lbm_set_spread(self.h, int(mode)), self.h)
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(self.L.ib_lbm_set_graph(self.h, int(steps_per_graph)), self.h)
+
+    def timing(self, on: bool):
+        self._check(self.L.ib_lbm_timing_enable(self.h, 1 if on else 0), self.h)
+
+    def timing_read(self, which: int):
+        ms = C.c_double(); n = C.c_int64()
+        self._check(self.L.ib_lbm_timing_read(self.h, which, C.byref(ms), C.byref(n)), self.h)
+        return ms.value, n.value
+
+
+class Batch:
+    """Many sims advanced by shared launches (the ABI's ``ib_lbm_batch``)."""
+
+    def __init__(self, precision: int = FP32_SHIFTED, stream=None):
+        self.L = load_library()
+        self.stream = _torch_stream(stream)
+        h = C.c_void_p()
+        st = self.L.ib_lbm_batch_create(self.stream, precision, C.byref(h))
+        if st != 0:
+            raise IbLbmError(st, "batch creation failed")
+        self.h = h
+        self.sims = []
+
+    def _check(self, st):
+        if st != 0:
+            raise IbLbmError(st, (self.L.ib_lbm_batch_last_error(self.h) or b"").decode())
+
+    def attach(self, sim: Sim, target: int | None = None):
+        self._check(self.L.ib_lbm_batch_attach(self.h, sim.h))
+        self.sims.append(sim)
+        if target is not None:
+            self.set_target(sim, target)
+
+    def detach(self, sim: Sim):
+        self._check(self.L.ib_lbm_batch_detach(self.h, sim.h))
+        self.sims.remove(sim)
+
+    def set_target(self, sim: Sim, target: int):
+        self._check(self.L.ib_lbm_batch_set_target(self.h, sim.h, int(target)))
+
+    def step(self, n: int):
+        self._check(self.L.ib_lbm_batch_step(self.h, int(n)))
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(self.L.ib_lbm_batch_set_graph(self.h, int(steps_per_graph)))
+
+    def sync(self):
+        self._check(self.L.ib_lbm_batch_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ib_lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

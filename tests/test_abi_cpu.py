@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, and the ctypes mirrors match the C struct layouts."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2609_02298_amd as ib
+from paper_2609_02298_amd import ib_lbm as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ib_lbm.h")
+
+
+def _ensure_built():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2609_02298_amd.build import build
+        build()
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ib_lbm_\w+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert header_functions() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    _ensure_built()
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\b(ib_lbm_\w+)\b", out))
+    assert set(header_functions()) <= exported
+
+
+def test_abi_version_and_footprint_without_device():
+    _ensure_built()
+    L = ib.load_library()
+    assert L.ib_lbm_abi_version() == B.ABI_VERSION
+    case = dict(nx=2000, ny=800, tau=0.62, bodies=[dict(xc=500, yc=400, diameter=80)])
+    f64 = ib.footprint(case, ib.FP64)
+    f32 = ib.footprint(case, ib.FP32_SHIFTED)
+    n = 2000 * 800
+    assert f64 >= 20 * n * 8 and f32 >= 20 * n * 4
+    assert f64 > f32
+
+
+@pytest.mark.parametrize("name", ["Config", "BodyDesc", "BodyState", "Launch", "Allocator"])
+def test_struct_layouts_match_header(name, tmp_path):
+    cname = {"Config": "ib_lbm_config", "BodyDesc": "ib_lbm_body_desc",
+             "BodyState": "ib_lbm_body_state", "Launch": "ib_lbm_launch",
+             "Allocator": "ib_lbm_allocator"}[name]
+    st = getattr(B, name)
+    lines = [f'printf("%zu\\n", sizeof({cname}));']
+    for fname, _ in st._fields_:
+        lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ib_lbm.h"\nint main(){' +
+                   "".join(lines) + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(st)
+    for (fname, _), off in zip(st._fields_, vals[1:]):
+        assert getattr(st, fname).offset == off, fname
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2609_02298_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, fn
+                assert "iblbm_oracle" not in txt, fn

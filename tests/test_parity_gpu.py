@@ -1,0 +1,395 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path velocity / populations max-abs relative 1e-12, drag
+1e-10 relative; FP32 shifted path velocity 1e-5 relative, drag 1e-4
+relative.  "Relative" for a field is max|a - b| / max|b| over the nodes.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import ib_cases
+import oracle
+import paper_2609_02298_amd as ib
+
+pytestmark = pytest.mark.gpu
+
+F64_FIELD, F64_DRAG = 1e-12, 1e-10
+F32_FIELD, F32_DRAG = 1e-5, 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    ib.load_library()
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+def make_pair(case, precision=ib.FP64, pops=None):
+    sim = ib.Sim(case, precision=precision)
+    ref = oracle.OracleSim(case)
+    for b in case.get("bodies", []):
+        ref.add_body(b)
+    if pops is not None:
+        sim.set_populations(pops)
+        ref.set_populations(pops)
+    return sim, ref
+
+
+def compare_fields(sim, ref, tol):
+    _, ux, uy = sim.fields()
+    _, rx, ry = ref.fields()
+    scale = max(np.abs(rx).max(), np.abs(ry).max())
+    e = max(np.abs(ux - rx).max(), np.abs(uy - ry).max()) / scale
+    return e
+
+
+# ------------------------------------------------------------------ lattice
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+@pytest.mark.parametrize("col", [ib.BGK, ib.TRT, ib.CMMRT])
+def test_periodic_box(col, prec):
+    say(f"periodic box col={col} prec={prec}")
+    case = dict(nx=67, ny=29, collision=col, tau=0.73, bc=(ib.PERIODIC,) * 4,
+                fluid_force=(3e-6, -2e-6))
+    pops = ib_cases.random_populations(67, 29, 1, amp=0.02, u=(0.03, 0.01))
+    sim, ref = make_pair(case, prec, pops)
+    sim.step(40)
+    ref.step(40)
+    if prec == ib.FP64:
+        assert rel(sim.populations(), ref.populations()) < F64_FIELD
+    assert compare_fields(sim, ref, None) < (F64_FIELD if prec == ib.FP64 else F32_FIELD)
+    assert sim.steps_done == 40
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+@pytest.mark.parametrize("col", [ib.BGK, ib.TRT, ib.CMMRT])
+@pytest.mark.parametrize("faces", ["channel", "farfield", "box"])
+def test_faces(col, prec, faces):
+    """Every face closure on a ragged lattice (not a multiple of the tile)."""
+    say(f"faces {faces} col={col} prec={prec}")
+    if faces == "channel":
+        bc, u = (ib.VEL_PARABOLIC, ib.ZERO_GRADIENT, ib.BOUNCE_BACK, ib.BOUNCE_BACK), 0.05
+    elif faces == "farfield":
+        bc, u = (ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.VEL_UNIFORM, ib.VEL_UNIFORM), 0.08
+    else:
+        bc, u = (ib.BOUNCE_BACK,) * 4, 0.0
+    case = dict(nx=77, ny=41, collision=col, tau=0.66, bc=bc, u_bc=u)
+    pops = ib_cases.random_populations(77, 41, 2, amp=0.01, u=(u * 0.5, 0.0))
+    sim, ref = make_pair(case, prec, pops)
+    sim.step(60)
+    ref.step(60)
+    if prec == ib.FP64:
+        assert rel(sim.populations(), ref.populations()) < F64_FIELD
+    assert compare_fields(sim, ref, None) < (F64_FIELD if prec == ib.FP64 else F32_FIELD)
+
+
+def test_set_get_populations_roundtrip():
+    case = dict(nx=33, ny=17, tau=0.8, bc=(ib.PERIODIC,) * 4)
+    pops = ib_cases.random_populations(33, 17, 3)
+    sim = ib.Sim(case, precision=ib.FP64)
+    sim.set_populations(pops)
+    np.testing.assert_array_equal(sim.populations(), pops)
+    s32 = ib.Sim(case, precision=ib.FP32_SHIFTED)
+    s32.set_populations(pops)
+    assert np.abs(s32.populations() - pops).max() < 1e-8
+
+
+def test_initial_state_matches_oracle():
+    for case in (ib_cases.fixed_cylinder_channel(), ib_cases.unsteady_cylinder(nx=120, ny=60, diameter=12)):
+        case = dict(case, bodies=[])
+        sim, ref = make_pair(case)
+        assert rel(sim.populations(), ref.populations()) < 1e-15
+
+
+# ------------------------------------------------------------------ bodies
+COMBOS = [(s, k, c) for s in (ib.DF, ib.MDF, ib.DFC) for k in (ib.HAT, ib.PESKIN4)
+          for c in (ib.BGK, ib.TRT, ib.CMMRT)]
+
+
+def body_case(scheme, kernel, col, nx=96, ny=64, D=16.0, **bkw):
+    body = dict(xc=nx / 3 + 0.37, yc=ny / 2 - 0.21, diameter=D, scheme=scheme, kernel=kernel,
+                mdf_iters=5)
+    body.update(bkw)
+    return dict(nx=nx, ny=ny, collision=col, tau=0.7, trt_magic=0.25, cm_s_q=1.2, cm_s_eps=1.4,
+                bc=(ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.VEL_UNIFORM, ib.VEL_UNIFORM), u_bc=0.06,
+                bodies=[body])
+
+
+@pytest.mark.parametrize("scheme,kernel,col", COMBOS)
+def test_fixed_body_fp64(scheme, kernel, col):
+    say(f"fixed body scheme={scheme} kernel={kernel} col={col}")
+    case = body_case(scheme, kernel, col)
+    sim, ref = make_pair(case)
+    for _ in range(3):
+        sim.step(8)
+        ref.step(8)
+        fs, fr = sim.forces(0), ref.body_state(0)
+        assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < F64_DRAG
+        assert abs(fs["fy"] - fr["fy"]) < F64_DRAG * abs(fr["fx"])
+        assert abs(fs["torque"] - fr["torque"]) < 1e-9 * abs(fr["fx"]) * 8
+        assert abs(fs["slip_mean"] - fr["slip_mean"]) < 1e-10 * max(fr["slip_mean"], 1e-12)
+        if scheme == ib.MDF:
+            assert abs(fs["mdf_residual"] - fr["mdf_residual"]) < 1e-10 * fr["mdf_residual"]
+            assert abs(fs["mdf_omega"] - ref.mdf_omega(0)) < 1e-13 * ref.mdf_omega(0)
+    assert rel(sim.populations(), ref.populations()) < F64_FIELD
+    if scheme != ib.DFC:
+        gx, gy = sim.force()
+        rx, ry = ref.force()
+        assert rel(np.stack([gx, gy]), np.stack([rx, ry])) < F64_FIELD
+    ms, mr = sim.markers(0), ref.markers(0)
+    np.testing.assert_allclose(ms[:, :4], mr[:, :4], rtol=0, atol=1e-12)
+    assert rel(ms[:, 4:6], mr[:, 4:6]) < 1e-11
+    if scheme == ib.DFC:
+        assert rel(ms[:, 6], mr[:, 6]) < 1e-13
+
+
+@pytest.mark.parametrize("scheme,kernel,col", [(ib.DF, ib.HAT, ib.BGK), (ib.MDF, ib.PESKIN4, ib.TRT),
+                                               (ib.DFC, ib.PESKIN4, ib.CMMRT),
+                                               (ib.DFC, ib.HAT, ib.BGK)])
+def test_fixed_body_fp32(scheme, kernel, col):
+    say(f"fixed body fp32 scheme={scheme} kernel={kernel} col={col}")
+    case = body_case(scheme, kernel, col)
+    sim, ref = make_pair(case, ib.FP32_SHIFTED)
+    sim.step(150)
+    ref.step(150)
+    assert compare_fields(sim, ref, None) < F32_FIELD
+    fs, fr = sim.forces(0), ref.body_state(0)
+    assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < F32_DRAG
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+def test_prescribed_oscillation(prec):
+    say(f"prescribed oscillation prec={prec}")
+    case = body_case(ib.MDF, ib.PESKIN4, ib.TRT, nx=120, ny=80, D=16.0,
+                     motion=ib.PRESCRIBED_SIN, amp=(0.0, 3.2), freq=0.004, phase=0.0)
+    sim, ref = make_pair(case, prec)
+    for _ in range(4):
+        sim.step(25)
+        ref.step(25)
+        fs, fr = sim.forces(0), ref.body_state(0)
+        tol = F64_DRAG if prec == ib.FP64 else F32_DRAG
+        assert abs(fs["yc"] - fr["yc"]) < 1e-12
+        assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < tol
+        assert abs(fs["fy"] - fr["fy"]) < tol * abs(fr["fx"]) * 5
+    assert compare_fields(sim, ref, None) < (F64_FIELD if prec == ib.FP64 else F32_FIELD)
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+@pytest.mark.parametrize("pair", [False, True])
+@pytest.mark.parametrize("im", [ib.IM_NONE, ib.IM_FENG])
+def test_free_bodies(prec, pair, im):
+    say(f"free bodies pair={pair} im={im} prec={prec}")
+    case = ib_cases.sedimentation(pair=pair, nx=80, ny=200, diameter=12.0, internal_mass=im)
+    case["gravity"] = (0.0, -4e-4)
+    for b in case["bodies"]:
+        b["yc"] -= 0
+    if pair:
+        case["bodies"][0].update(xc=39.0, yc=140.0)
+        case["bodies"][1].update(xc=41.0, yc=170.0)
+    else:
+        case["bodies"][0].update(xc=40.0, yc=160.0)
+    sim, ref = make_pair(case, prec)
+    for _ in range(4):
+        sim.step(40)
+        ref.step(40)
+        for b in range(len(case["bodies"])):
+            fs, fr = sim.forces(b), ref.body_state(b)
+            tol = 1e-10 if prec == ib.FP64 else F32_DRAG
+            assert abs(fs["vy"] - fr["vy"]) < tol * abs(fr["vy"]), (b, fs["vy"], fr["vy"])
+            assert abs(fs["yc"] - fr["yc"]) < 1e-9
+            assert abs(fs["fy"] - fr["fy"]) < tol * abs(fr["fy"]) + 1e-15
+    assert fr["vy"] < 0
+
+
+# ---------------------------------------------------------- full workloads
+@pytest.fixture(scope="module")
+def cylinder_channel_ref():
+    case = ib_cases.fixed_cylinder_channel(steps=5000)
+    ref = oracle.OracleSim(case)
+    for b in case["bodies"]:
+        ref.add_body(b)
+    ref.step(case["steps"])
+    return case, ref
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+def test_cylinder_channel_full_run(cylinder_channel_ref, prec):
+    """200x80 channel, D = 20 cylinder, DF + hat, BGK, Re = 20: 5000 steps."""
+    say(f"cylinder channel 5000 steps prec={prec}")
+    case, ref = cylinder_channel_ref
+    sim = ib.Sim(case, precision=prec)
+    sim.step(case["steps"])
+    e = compare_fields(sim, ref, None)
+    fs, fr = sim.forces(0), ref.body_state(0)
+    cd_s = 2 * fs["fx"] / (case["u_ref"] ** 2 * case["diameter"])
+    cd_r = 2 * fr["fx"] / (case["u_ref"] ** 2 * case["diameter"])
+    say(f"  velocity err {e:.3e}  Cd gpu {cd_s:.12f} oracle {cd_r:.12f}")
+    if prec == ib.FP64:
+        assert e < F64_FIELD and abs(cd_s - cd_r) / abs(cd_r) < F64_DRAG
+    else:
+        assert e < F32_FIELD and abs(cd_s - cd_r) / abs(cd_r) < F32_DRAG
+
+
+@pytest.mark.parametrize("scheme,kernel,col,steps", [
+    (ib.MDF, ib.PESKIN4, ib.TRT, 6), (ib.DF, ib.HAT, ib.BGK, 10), (ib.DFC, ib.PESKIN4, ib.CMMRT, 4)])
+def test_unsteady_cylinder_full_size_window(scheme, kernel, col, steps):
+    """2000x800, D = 80, 251 markers: the benchmark lattice, short window."""
+    say(f"2000x800 window scheme={scheme} kernel={kernel} col={col}")
+    case = ib_cases.unsteady_cylinder(scheme=scheme, kernel=kernel, collision=col, re=100.0)
+    sim, ref = make_pair(case)
+    sim.step(steps)
+    ref.step(steps)
+    assert rel(sim.populations(), ref.populations()) < F64_FIELD
+    fs, fr = sim.forces(0), ref.body_state(0)
+    assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < F64_DRAG
+
+
+def test_oscillating_cylinder_full_size_window():
+    case = ib_cases.oscillating_cylinder()
+    sim, ref = make_pair(case)
+    sim.step(8)
+    ref.step(8)
+    assert rel(sim.populations(), ref.populations()) < F64_FIELD
+    fs, fr = sim.forces(0), ref.body_state(0)
+    assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < F64_DRAG
+    assert abs(fs["slip_mean"] - fr["slip_mean"]) < 1e-9 * fr["slip_mean"]
+
+
+@pytest.mark.parametrize("pair", [False, True])
+def test_sedimentation_full_size_window(pair):
+    case = ib_cases.sedimentation(pair=pair)
+    sim, ref = make_pair(case)
+    sim.step(6)
+    ref.step(6)
+    assert rel(sim.populations(), ref.populations()) < F64_FIELD
+    for b in range(len(case["bodies"])):
+        fs, fr = sim.forces(b), ref.body_state(b)
+        assert abs(fs["vy"] - fr["vy"]) < 1e-10 * abs(fr["vy"])
+
+
+# ------------------------------------------------------------- properties
+def test_run_to_run_bitwise_and_gather_vs_atomic():
+    case = body_case(ib.MDF, ib.PESKIN4, ib.CMMRT)
+    a = ib.Sim(case); b = ib.Sim(case); c = ib.Sim(case)
+    c.set_spread(ib.SPREAD_ATOMIC)
+    for s in (a, b, c):
+        s.step(30)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+    assert rel(c.populations(), a.populations()) < 1e-13
+    assert abs(c.forces(0)["fx"] - a.forces(0)["fx"]) < 1e-12 * abs(a.forces(0)["fx"])
+    dcase = body_case(ib.DFC, ib.HAT, ib.TRT)
+    d = ib.Sim(dcase); e = ib.Sim(dcase)
+    e.set_spread(ib.SPREAD_ATOMIC)
+    d.step(20); e.step(20)
+    assert rel(e.populations(), d.populations()) < 1e-13
+
+
+def test_graph_replay_matches_direct_launches():
+    case = body_case(ib.DFC, ib.PESKIN4, ib.TRT)
+    a = ib.Sim(case); g = ib.Sim(case)
+    g.set_graph(5)
+    for rep in range(3):
+        a.step(10)
+        g.step(10)
+        # eager work between replays
+        _ = g.forces(0)
+        np.testing.assert_array_equal(a.populations(), g.populations())
+    assert g.steps_done == 30
+
+
+def test_batch_matches_alone():
+    import torch
+    cases = [body_case(ib.DF, ib.HAT, ib.BGK, nx=96, ny=48, D=12.0),
+             body_case(ib.MDF, ib.PESKIN4, ib.TRT, nx=150, ny=70, D=14.0),
+             body_case(ib.DFC, ib.PESKIN4, ib.CMMRT, nx=81, ny=63, D=10.0),
+             dict(nx=40, ny=30, tau=0.8, bc=(ib.PERIODIC,) * 4, bodies=[])]
+    targets = [25, 40, 33, 17]
+    alone = []
+    for c, t in zip(cases, targets):
+        s = ib.Sim(c, precision=ib.FP32_SHIFTED)
+        s.step(t)
+        alone.append(s.populations())
+    stream = torch.cuda.current_stream().cuda_stream
+    batch = ib.Batch(ib.FP32_SHIFTED, stream=stream)
+    sims = [ib.Sim(c, precision=ib.FP32_SHIFTED, stream=stream) for c in cases]
+    for s, t in zip(sims, targets):
+        batch.attach(s, target=t)
+    batch.set_graph(4)
+    batch.step(50)
+    batch.sync()
+    for s, t, ref in zip(sims, targets, alone):
+        assert s.steps_done == t
+        np.testing.assert_array_equal(s.populations(), ref)
+
+
+def test_history_matches_forces():
+    case = body_case(ib.MDF, ib.HAT, ib.BGK)
+    s = ib.Sim(case, history_capacity=64)
+    rows = []
+    for _ in range(5):
+        s.step(1)
+        rows.append(s.forces(0))
+    h = s.history(0, 1, 5)
+    for i, r in enumerate(rows):
+        assert h[i, 0] == i + 1
+        assert h[i, 1] == r["fx"] and h[i, 2] == r["fy"] and h[i, 3] == r["torque"]
+
+
+# ------------------------------------------------------------- edge cases
+def test_invalid_configurations_are_rejected():
+    base = dict(nx=40, ny=30, tau=0.8, bc=(ib.PERIODIC,) * 4)
+    for bad in (dict(base, tau=0.5), dict(base, bc=(ib.PERIODIC, ib.BOUNCE_BACK, 0, 0)),
+                dict(base, bc=(ib.ZERO_GRADIENT, ib.ZERO_GRADIENT, 1, 1)), dict(base, nx=2)):
+        with pytest.raises(ib.IbLbmError):
+            ib.Sim(bad)
+
+
+def test_body_outside_lattice_is_rejected():
+    case = dict(nx=40, ny=30, tau=0.8, bc=(ib.PERIODIC,) * 4)
+    s = ib.Sim(case)
+    with pytest.raises(ib.IbLbmError) as e:
+        s.add_body(dict(xc=4.0, yc=15.0, diameter=8.0, kernel=ib.PESKIN4))
+    assert e.value.status == -5
+    with pytest.raises(ib.IbLbmError):
+        s.add_body(dict(xc=20.0, yc=15.0, diameter=8.0, scheme=ib.MDF, mdf_iters=0))
+
+
+def test_body_reaching_wall_halts_like_the_oracle():
+    case = dict(nx=40, ny=60, collision=ib.BGK, tau=0.8, bc=(ib.BOUNCE_BACK,) * 4,
+                gravity=(0.0, -2e-3),
+                bodies=[dict(xc=20.0, yc=22.0, diameter=10.0, scheme=ib.DFC, kernel=ib.PESKIN4,
+                             motion=ib.FREE, density_ratio=3.0)])
+    sim, ref = make_pair(case)
+    r = 0
+    for _ in range(400):
+        r = ref.step(1)
+        if r != 0:
+            break
+    assert r == -5
+    n_ok = ref.steps_done
+    sim.step(400)
+    st = sim.forces(0, check=False)
+    assert st["status"] == -5 and st["flags"] & ib.ib_lbm.FLAG_RANGE
+    assert sim.steps_done == n_ok
+
+
+def test_empty_lattice_and_zero_steps():
+    case = dict(nx=5, ny=4, tau=0.9, bc=(ib.PERIODIC,) * 4)
+    sim, ref = make_pair(case, pops=ib_cases.random_populations(5, 4, 9))
+    sim.step(0)
+    assert sim.steps_done == 0
+    sim.step(7)
+    ref.step(7)
+    assert rel(sim.populations(), ref.populations()) < F64_FIELD
