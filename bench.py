@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the IB-LBM hot path on one MI355X.
+
+One "step" is one full IB-LBM time step of the workload: fused collide +
+stream over the lattice, then the immersed-boundary pass (interpolation,
+scheme update, spreading, FP64 force/torque reductions, body update).
+
+Default workload: the unsteady fixed cylinder on the 2000 x 800 lattice,
+D = 80 (251 markers), Re = 100, MDF (k = 5) with the Peskin 4-point kernel
+and TRT collision, FP32 shifted populations (FP64 reductions).  The line
+also carries the FP64 run of the same workload, the collide-stream
+roofline (achieved GB/s of algorithmic bytes from HIP events on the
+library's stream), and the FP64 oracle timed on the host on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--extra]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "ib_lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2609_02298_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per collide-stream launch from the committed rocprofv3
+    counter summary, or None if absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "collide_stream_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload_key)
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def run_gpu(case, precision, steps, warmup, graph=0, launch=None):
+    import torch
+    import paper_2609_02298_amd as ib
+
+    sim = ib.Sim(case, precision=precision)
+    if launch:
+        sim.set_launch(**launch)
+    if graph:
+        sim.set_graph(graph)
+    sim.step(warmup)
+    sim.sync()
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lbm_ms, n_lbm = sim.timing_read(0)
+    ibm_ms, n_ibm = sim.timing_read(1)
+    sim.timing(False)
+    st = sim.forces(0, check=False)
+    out = dict(seconds=t1 - t0, lbm_ms=lbm_ms, n_lbm=n_lbm, ibm_ms=ibm_ms, n_ibm=n_ibm,
+               fx=st["fx"], status=st["status"], steps_done=sim.steps_done)
+    sim.close()
+    return out
+
+
+def cpu_baseline(case, target_seconds=12.0):
+    """The FP64 oracle (single-threaded, as written) on a bounded number of
+    steps of the same workload."""
+    import oracle
+
+    ref = oracle.OracleSim(case)
+    for b in case["bodies"]:
+        ref.add_body(b)
+    t0 = time.perf_counter()
+    ref.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, min(200, int(target_seconds / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    ref.step(n)
+    dt = time.perf_counter() - t0
+    ref.close()
+    nodes = case["nx"] * case["ny"]
+    return dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{n} steps of {case['name']} (after 1 untimed), single-threaded FP64 C "
+                       f"oracle, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--scheme", default="MDF")
+    ap.add_argument("--kernel", default="P4")
+    ap.add_argument("--collision", default="TRT")
+    ap.add_argument("--re", type=float, default=100.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--extra", action="store_true", help="also time every scheme/kernel/collision")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "multi-GPU runs are not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import ib_cases
+    import paper_2609_02298_amd as ib
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(1)
+    ib.load_library()
+    case = ib_cases.unsteady_cylinder(scheme=args.scheme, kernel=args.kernel,
+                                      collision=args.collision, re=args.re)
+    nodes = case["nx"] * case["ny"]
+    prec = ib.FP32_SHIFTED if args.precision == "fp32" else ib.FP64
+    bpn = 72 if prec == ib.FP32_SHIFTED else 144
+
+    r = run_gpu(case, prec, args.steps, args.warmup, graph=args.graph)
+    mlups = nodes * args.steps / r["seconds"] / 1e6
+    lbm_avg_s = r["lbm_ms"] / max(r["n_lbm"], 1) * 1e-3
+    achieved = bpn * nodes / lbm_avg_s / 1e9
+    key = f"{case['name']}-{args.precision}-{args.collision}"
+    traffic = measured_traffic(key)
+
+    line = {
+        "metric": "MLUPS (IB-LBM step, FP32-shifted) + HBM roofline %",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["seconds"] / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == ib.FP32_SHIFTED else "f64",
+        "data": "synthetic (parametric flow case, no dataset)",
+        "config": {"workload": case["name"], "nx": case["nx"], "ny": case["ny"],
+                   "diameter": case["diameter"], "markers": 251, "re": args.re,
+                   "scheme": args.scheme, "kernel": args.kernel, "collision": args.collision,
+                   "precision": "fp32-shifted" if prec == ib.FP32_SHIFTED else "fp64",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "collide_stream_kernel",
+                     "bytes_per_node": bpn,
+                     "avg_launch_us": round(lbm_avg_s * 1e6, 3)},
+        "ib_pass_avg_us": round(r["ibm_ms"] / max(r["n_ibm"], 1) * 1e3, 3),
+        "hbm_fraction_of_step": round(bpn * nodes * args.steps / r["seconds"] / 1e9 / HBM_PEAK_GBS, 4),
+        "lattice_bytes": 2 * 9 * nodes * (bpn // 18),
+        "mall_resident_note": "2 lattices of this size fit in the 256 MB Infinity Cache",
+    }
+    if not args.no_fp64 and prec == ib.FP32_SHIFTED:
+        r64 = run_gpu(case, ib.FP64, max(args.steps // 2, 50), args.warmup // 2)
+        s64 = max(args.steps // 2, 50)
+        a64 = 144 * nodes / (r64["lbm_ms"] / max(r64["n_lbm"], 1) * 1e-3) / 1e9
+        line["fp64"] = {"value": round(nodes * s64 / r64["seconds"] / 1e6, 2), "unit": "MLUPS",
+                        "roofline_achieved_GBs": round(a64, 1),
+                        "roofline_frac": round(a64 / HBM_PEAK_GBS, 4),
+                        "avg_launch_us": round(r64["lbm_ms"] / max(r64["n_lbm"], 1) * 1e3, 3),
+                        "ib_pass_avg_us": round(r64["ibm_ms"] / max(r64["n_ibm"], 1) * 1e3, 3)}
+    if args.extra:
+        combos = {}
+        for sch in ("DF", "MDF", "DFC"):
+            for ker in ("hat", "P4"):
+                for col in ("BGK", "TRT", "CMMRT"):
+                    c = ib_cases.unsteady_cylinder(scheme=sch, kernel=ker, collision=col, re=args.re)
+                    for pname, p in (("fp32", ib.FP32_SHIFTED), ("fp64", ib.FP64)):
+                        rr = run_gpu(c, p, 100, 10)
+                        combos[f"{sch}/{ker}/{col}/{pname}"] = round(nodes * 100 / rr["seconds"] / 1e6, 1)
+        line["combos_mlups"] = combos
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -28,7 +28,7 @@ struct DevBuf {
 struct HostBody {
   ib_lbm_body_desc d;
   BodyDesc dev;  // host copy of the device description
-  DevBuf cos_t, sin_t, ws, markers, lambda, history, state;
+  DevBuf cos_t, sin_t, ws, tab, acc, markers, lambda, history, state;
 };
 
 struct EventPair {
@@ -47,8 +47,8 @@ struct Timing {
 
 struct ib_lbm_sim {
   ib_lbm_config cfg;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
+  hipStream_t stream = nullptr;          // the caller's stream (NULL: null stream)
+  hipStream_t cap_stream = nullptr;      // private stream used only for graph capture
   bool broken = false;
   bool started = false;
   bool tables_dirty = true;
@@ -71,6 +71,7 @@ struct ib_lbm_sim {
 
 struct ib_lbm_batch {
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
   int precision = 0;
   bool dirty = true;
   bool broken = false;
@@ -213,11 +214,13 @@ double host_omega_mdf(double xc, double yc, double R, int nb, int kernel, double
   return 1.0 / (ds * mx);
 }
 
-int ws_doubles_for(int nb, int ns, int mr, int mn) {
-  const size_t dbl = (size_t)nb * (4 + 2 * ns + 4 + 2 + 9) + (size_t)mn * 6;
-  const size_t ints = (size_t)nb * (2 + ns * ns) + (size_t)mr * 8 + 1 + (size_t)mn * 2;
-  return (int)(dbl + (ints + 1) / 2 + 8);
+int ws_doubles_for(int scheme, int nb, int ns, int mr, int mn) {
+  return ws_tab_total(nb, ns, mr, mn) + ws_dyn_doubles(scheme, nb, mn);
 }
+
+// LDS bytes for an IB launch: enough for the largest workspace that fits;
+// bodies with larger workspaces use their global buffer.
+int lds_budget(int maxws_fitting) { return maxws_fitting * 8; }
 
 void fill_case_tiles(CaseDesc *c, const ib_lbm_launch &l) {
   const int TX = l.block_x, TY = l.block_y * l.rows_per_thread;
@@ -241,7 +244,7 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   int maxws = 0;
   for (auto &hb : s->bodies) {
     bd.push_back(hb.dev);
-    maxws = std::max(maxws, hb.dev.ws_doubles);
+    if (hb.dev.ws_doubles * 8 <= ibm_max_lds_bytes()) maxws = std::max(maxws, hb.dev.ws_doubles);
   }
   if (!bd.empty()) {
     if (!s->d_bodies.p || s->d_bodies.bytes < bd.size() * sizeof(BodyDesc)) {
@@ -270,8 +273,7 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   for (int b = 0; b < n; b++) slots.push_back(IbmSlot{0, bd.empty() ? -1 : b, n, 0});
   HIPCHK(s, hipMemcpy(s->d_slots.p, slots.data(), slots.size() * sizeof(IbmSlot), hipMemcpyHostToDevice));
   s->nslots = n;
-  s->lds_bytes = std::min(ibm_max_lds_bytes(), maxws * 8);
-  if (maxws * 8 > ibm_max_lds_bytes()) s->lds_bytes = 0;  // too large: global workspace
+  s->lds_bytes = lds_budget(maxws);
   s->tables_dirty = false;
   if (s->graph_exec) {
     (void)hipGraphExecDestroy(s->graph_exec);
@@ -293,26 +295,26 @@ EventPair take_pair(Timing &t) {
 }
 
 // Enqueue one step of a sim: collide-stream, then the IB pass.
-ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed) {
+ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
   const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
   EventPair p0{}, p1{};
   if (timed) {
     p0 = take_pair(s->timing);
-    HIPCHK(s, hipEventRecord(p0.a, s->stream));
+    HIPCHK(s, hipEventRecord(p0.a, stream));
   }
   HIPCHK(s, launch_collide_stream(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
-                                  (const int32_t *)s->d_prefix.p, 1, ntiles, sh, s->stream));
+                                  (const int32_t *)s->d_prefix.p, 1, ntiles, sh, stream));
   if (timed) {
-    HIPCHK(s, hipEventRecord(p0.b, s->stream));
+    HIPCHK(s, hipEventRecord(p0.b, stream));
     s->timing.ev[0].push_back(p0);
     p1 = take_pair(s->timing);
-    HIPCHK(s, hipEventRecord(p1.a, s->stream));
+    HIPCHK(s, hipEventRecord(p1.a, stream));
   }
   HIPCHK(s, launch_ibm(s->cd.precision, (const CaseDesc *)s->d_case.p, (const IbmSlot *)s->d_slots.p,
-                       s->nslots, s->lds_bytes, s->spread_mode, s->stream));
+                       s->nslots, s->lds_bytes, s->spread_mode, stream));
   if (timed) {
-    HIPCHK(s, hipEventRecord(p1.b, s->stream));
+    HIPCHK(s, hipEventRecord(p1.b, stream));
     s->timing.ev[1].push_back(p1);
   }
   return IB_LBM_OK;
@@ -347,7 +349,8 @@ size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_
     // workspace upper estimate (P4), marker tables, history
     const double D = nb / M_PI;
     const int mr = (int)std::ceil(D) + 12, mn = (int)(8 * M_PI * D + 8 * mr + 64);
-    bytes += (size_t)ws_doubles_for(nb, 4, mr, mn) * 8 + (size_t)nb * (8 + 1 + 2) * 8 +
+    bytes += (size_t)(ws_doubles_for(kDFC, nb, 4, mr, mn) + ws_tab_total(nb, 4, mr, mn) + 2 * mn) * 8 +
+             (size_t)nb * (8 + 1 + 2) * 8 +
              (size_t)hist * kHistCols * 8 + sizeof(BodyState) + sizeof(BodyDesc);
   }
   return bytes;
@@ -386,13 +389,7 @@ ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out) {
   if (cfg->collision == IB_LBM_TRT && !(cfg->trt_magic > 0.0))
     return fail(IB_LBM_E_INVALID, "TRT needs a positive magic parameter");
   if (!(cfg->rho0 > 0.0)) return fail(IB_LBM_E_INVALID, "rho0 must be positive");
-  if (cfg->stream) {
-    s->stream = (hipStream_t)cfg->stream;
-  } else {
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
-      return fail(IB_LBM_E_DEVICE, "stream creation failed");
-    s->own_stream = true;
-  }
+  s->stream = (hipStream_t)cfg->stream;
   CaseDesc &c = s->cd;
   memset(&c, 0, sizeof c);
   c.nx = cfg->nx;
@@ -537,8 +534,9 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
       maxr = std::max(maxr, rows);
     }
   B.max_rows = (int)std::ceil(2 * B.radius) + 2 * B.ns + 4;
-  B.max_nodes = maxn + maxn / 4 + 64;
-  B.ws_doubles = ws_doubles_for(nb, B.ns, B.max_rows, B.max_nodes);
+  B.max_nodes = maxn + maxn / 10 + 32;
+  B.ws_tab = ws_tab_total(nb, B.ns, B.max_rows, B.max_nodes);
+  B.ws_doubles = ws_doubles_for(b->scheme, nb, B.ns, B.max_rows, B.max_nodes);
   // gather window: a node within s*sqrt(2) of marker k lies within angle
   // 2 asin(s / sqrt(2 R (R - s sqrt 2))) of it
   {
@@ -557,6 +555,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   if ((st = dev_alloc(s, &hb.cos_t, nb * 8))) return st;
   if ((st = dev_alloc(s, &hb.sin_t, nb * 8))) return st;
   if ((st = dev_alloc(s, &hb.ws, (size_t)B.ws_doubles * 8))) return st;
+  if ((st = dev_alloc(s, &hb.tab, (size_t)B.ws_tab * 8))) return st;
+  if ((st = dev_alloc(s, &hb.acc, (size_t)B.max_nodes * 2 * 8))) return st;
   if ((st = dev_alloc(s, &hb.markers, (size_t)nb * 8 * 8))) return st;
   if ((st = dev_alloc(s, &hb.lambda, (size_t)nb * 8))) return st;
   if ((st = dev_alloc(s, &hb.history, (size_t)B.hist_cap * kHistCols * 8))) return st;
@@ -568,6 +568,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.cos_t = (const double *)hb.cos_t.p;
   B.sin_t = (const double *)hb.sin_t.p;
   B.ws = (double *)hb.ws.p;
+  B.tab_cache = (double *)hb.tab.p;
+  B.acc = (double *)hb.acc.p;
   B.markers_out = (double *)hb.markers.p;
   B.lambda_cache = (double *)hb.lambda.p;
   B.history = (double *)hb.history.p;
@@ -598,17 +600,20 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
     if (!s->graph_exec || s->graph_len != s->graph_steps) {
       if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
       s->graph_exec = nullptr;
+      // capture on a private stream (the caller's may be the null stream),
+      // replay on the caller's stream
+      if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
       hipGraph_t g;
-      HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+      HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int i = 0; i < s->graph_steps; i++) {
-        st = enqueue_sim_step(s, false);
+        st = enqueue_sim_step(s, false, s->cap_stream);
         if (st) {
           hipGraph_t dummy;
-          (void)hipStreamEndCapture(s->stream, &dummy);
+          (void)hipStreamEndCapture(s->cap_stream, &dummy);
           return st;
         }
       }
-      HIPCHK(s, hipStreamEndCapture(s->stream, &g));
+      HIPCHK(s, hipStreamEndCapture(s->cap_stream, &g));
       HIPCHK(s, hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0));
       (void)hipGraphDestroy(g);
       s->graph_len = s->graph_steps;
@@ -619,7 +624,7 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
     }
   }
   for (int64_t i = 0; i < left; i++)
-    if ((st = enqueue_sim_step(s, s->timing.on))) return st;
+    if ((st = enqueue_sim_step(s, s->timing.on, s->stream))) return st;
   s->host_steps += nsteps;
   return IB_LBM_OK;
 }
@@ -786,12 +791,13 @@ ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s) {
   for (auto &p : s->timing.pool) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto &hb : s->bodies) {
     dev_free(s, &hb.cos_t); dev_free(s, &hb.sin_t); dev_free(s, &hb.ws); dev_free(s, &hb.markers);
+    dev_free(s, &hb.tab); dev_free(s, &hb.acc);
     dev_free(s, &hb.lambda); dev_free(s, &hb.history); dev_free(s, &hb.state);
   }
   dev_free(s, &s->f0); dev_free(s, &s->f1); dev_free(s, &s->force); dev_free(s, &s->state);
   dev_free(s, &s->d_bodies); dev_free(s, &s->d_case); dev_free(s, &s->d_prefix);
   dev_free(s, &s->d_slots); dev_free(s, &s->d_tmp);
-  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
   return IB_LBM_OK;
 }
@@ -943,7 +949,8 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
       tiles += c.tiles_x * c.tiles_y;
       cases.push_back(c);
       g.count++;
-      for (auto &hb : s->bodies) maxws = std::max(maxws, hb.dev.ws_doubles);
+      for (auto &hb : s->bodies)
+        if (hb.dev.ws_doubles * 8 <= ibm_max_lds_bytes()) maxws = std::max(maxws, hb.dev.ws_doubles);
     }
     prefix.push_back(tiles);
     g.ntiles = tiles;
@@ -973,20 +980,20 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
     if ((st = upload(&b->d_slots, slots.data(), slots.size() * sizeof(IbmSlot)))) return st;
   }
   b->nslots = (int)slots.size();
-  b->lds_bytes = maxws * 8 > ibm_max_lds_bytes() ? 0 : maxws * 8;
+  b->lds_bytes = lds_budget(maxws);
   b->dirty = false;
   return IB_LBM_OK;
 }
 
-static ib_lbm_status batch_enqueue_step(ib_lbm_batch *b) {
+static ib_lbm_status batch_enqueue_step(ib_lbm_batch *b, hipStream_t stream) {
   LaunchShape sh{b->launch.block_x, b->launch.block_y, b->launch.rows_per_thread, b->launch.xcd_remap};
   for (auto &g : b->groups) {
     BHIPCHK(b, launch_collide_stream(b->precision, g.collision, (const CaseDesc *)b->d_cases.p + g.first,
                                      (const int32_t *)b->d_prefix.p + g.prefix_off, g.count, g.ntiles,
-                                     sh, b->stream));
+                                     sh, stream));
   }
   BHIPCHK(b, launch_ibm(b->precision, (const CaseDesc *)b->d_cases.p, (const IbmSlot *)b->d_slots.p,
-                        b->nslots, b->lds_bytes, b->spread_mode, b->stream));
+                        b->nslots, b->lds_bytes, b->spread_mode, stream));
   return IB_LBM_OK;
 }
 
@@ -1001,16 +1008,17 @@ ib_lbm_status ib_lbm_batch_step(ib_lbm_batch *b, int64_t nsteps) {
     if (!b->graph_exec || b->graph_len != b->graph_steps) {
       if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
       b->graph_exec = nullptr;
+      if (!b->cap_stream) BHIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
       hipGraph_t g;
-      BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      BHIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int i = 0; i < b->graph_steps; i++) {
-        if ((st = batch_enqueue_step(b))) {
+        if ((st = batch_enqueue_step(b, b->cap_stream))) {
           hipGraph_t dummy;
-          (void)hipStreamEndCapture(b->stream, &dummy);
+          (void)hipStreamEndCapture(b->cap_stream, &dummy);
           return st;
         }
       }
-      BHIPCHK(b, hipStreamEndCapture(b->stream, &g));
+      BHIPCHK(b, hipStreamEndCapture(b->cap_stream, &g));
       BHIPCHK(b, hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
       (void)hipGraphDestroy(g);
       b->graph_len = b->graph_steps;
@@ -1021,7 +1029,7 @@ ib_lbm_status ib_lbm_batch_step(ib_lbm_batch *b, int64_t nsteps) {
     }
   }
   for (int64_t i = 0; i < left; i++)
-    if ((st = batch_enqueue_step(b))) return st;
+    if ((st = batch_enqueue_step(b, b->stream))) return st;
   return IB_LBM_OK;
 }
 
@@ -1043,6 +1051,7 @@ ib_lbm_status ib_lbm_batch_destroy(ib_lbm_batch *b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   for (auto *s : b->sims) s->batch = nullptr;
   if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_cases.p) (void)hipFree(b->d_cases.p);
   if (b->d_prefix.p) (void)hipFree(b->d_prefix.p);
   if (b->d_slots.p) (void)hipFree(b->d_slots.p);

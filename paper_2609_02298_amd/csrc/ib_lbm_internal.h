@@ -37,7 +37,8 @@ struct CaseState {
   int32_t cur;     // buffer holding the current post-stream populations
   int32_t flags;   // kCaseHalted
   int32_t done;    // IB workgroups of this step that have finished
-  int32_t pad;
+  int32_t fbox_valid;  // the union of the bodies' force boxes below is set
+  int32_t fbox[4];     // x0 y0 x1 y1 of the nodes that carry IB force
 };
 
 // Mutable per-body state, device resident.
@@ -55,6 +56,8 @@ struct BodyState {
   int32_t box[4];       // x0 y0 x1 y1 of the nodes that carry IB force
   int32_t box_valid;
   int32_t lambda_valid; // DFC cache filled (fixed bodies)
+  int32_t tables_valid; // geometry tables cached (fixed bodies)
+  int32_t pad;
 };
 
 // Constant per-body description plus pointers to the body's device buffers.
@@ -71,6 +74,9 @@ struct BodyDesc {
   double ms, mf, Is;
   const double *cos_t, *sin_t;  // marker directions (n_b each)
   double *ws;           // global workspace (used when it does not fit in LDS)
+  double *tab_cache;    // cached geometry tables of a fixed body (ws_tab doubles)
+  double *acc;          // 2 x max_nodes scratch of the atomic-scatter variant
+  int32_t ws_tab;       // doubles of the table part of the workspace
   double *markers_out;  // n_b x 8: X Y Udx Udy Fx Fy lambda ds
   double *lambda_cache; // n_b
   double *history;      // hist_cap x kHistCols
@@ -94,6 +100,26 @@ struct CaseDesc {
   CaseState *state;
   BodyDesc *bodies;     // device array of nbodies
 };
+
+// Workspace of one body, in doubles.  The table part (marker geometry,
+// compact support description) comes first so that it can be cached and
+// copied in bulk; the per-step arrays follow.
+//   doubles: X Y Udx Udy (nb each), wx wy (nb*ns each)
+//   ints:    ix0 iy0 (nb each), nidx (nb*ns*ns), ra1 rl1 ra2 (mr each),
+//            off (mr+1), nxy nkc (mn each), S (1)            [padded to even]
+//   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each)
+//   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), nW nux nuy (mn each)
+__host__ __device__ inline int ws_table_doubles(int nb, int ns) { return nb * (4 + 2 * ns); }
+__host__ __device__ inline int ws_table_ints(int nb, int ns, int mr, int mn) {
+  const int n = nb * (2 + ns * ns) + 4 * mr + 1 + 2 * mn + 1;
+  return (n + 1) & ~1;
+}
+__host__ __device__ inline int ws_tab_total(int nb, int ns, int mr, int mn) {
+  return ws_table_doubles(nb, ns) + ws_table_ints(nb, ns, mr, mn) / 2;
+}
+__host__ __device__ inline int ws_dyn_doubles(int scheme, int nb, int mn) {
+  return scheme == 2 ? nb * 12 + mn * 3 : nb * 5 + mn * 3;
+}
 
 // One IB workgroup: the body `body` of case `cas` (body = -1: a case without
 // bodies, which only advances the step counter).

@@ -16,11 +16,13 @@
 //            correction, spread the correction into the populations;
 //   5. reduces force, torque, slip and MDF residual in FP64 with a fixed
 //      order (wave shuffles, then LDS), and finishes the body update.
+// Steps 2-3 depend only on the body position: for a fixed body they run
+// once and are cached, later steps copy the tables in bulk.
 // Spreading is a gather: each support node sums over the markers of an
 // angular window around it, in marker order, so results are reproducible
 // run to run.  An atomic-scatter variant is kept for comparison.
-// The node and marker arrays live in LDS when they fit, else in a global
-// workspace of the body (the same code reaches both through flat pointers).
+// The workspace lives in LDS when it fits, else in a global buffer of the
+// body (the same code reaches both through flat pointers).
 #include "ib_lbm_internal.h"
 
 namespace iblbm {
@@ -30,6 +32,8 @@ __constant__ int c_eyi[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __constant__ int c_oppi[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 __constant__ double c_w[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+constexpr int kIbmDynLds = 150 * 1024;
 
 // Regularized delta kernels: hat (Eq. 9) and Peskin 4-point (Eq. 10).
 __device__ __forceinline__ double delta1(int kernel, double r) {
@@ -64,56 +68,73 @@ __device__ void block_reduce4(double &a, double &b, double &c, double &m, double
   __syncthreads();
 }
 
-// Exclusive prefix sum of cnt[0..n) into off[0..n], off[n] = total.  Serial
-// per wave chunk, then across waves; n is at most a few thousand.
-__device__ void block_scan(const int *cnt, int *off, int n, int *sh) {
-  const int nth = blockDim.x;
+// Exclusive prefix sum of cnt[0..n) into off[0..n], off[n] = total.  Each
+// thread sums a contiguous chunk, chunk sums are scanned with wave shuffles
+// and one pass over the wave totals.  wsum holds at least 33 ints.
+__device__ void block_scan(const int *cnt, int *off, int n, int *wsum) {
+  const int nth = blockDim.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int per = (n + nth - 1) / nth;
   const int b0 = min(n, threadIdx.x * per), b1 = min(n, b0 + per);
   int s = 0;
   for (int i = b0; i < b1; i++) s += cnt[i];
-  // inclusive scan of per-thread sums through LDS (Hillis-Steele)
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < nth; o <<= 1) {
-    const int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
+  int inc = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
   }
-  int run = sh[threadIdx.x] - s;
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < (nth + 63) / 64; w++) {
+      const int t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+    wsum[32] = run;
+  }
+  __syncthreads();
+  int run = wsum[wv] + inc - s;
   for (int i = b0; i < b1; i++) { off[i] = run; run += cnt[i]; }
-  if (threadIdx.x == nth - 1) off[n] = sh[nth - 1];
+  if (threadIdx.x == 0) off[n] = wsum[32];
   __syncthreads();
 }
 
 struct WsLayout {
-  // doubles
-  double *X, *Y, *Udx, *Udy, *wx, *wy, *Fx, *Fy, *Ftx, *Fty, *rhoX, *lam, *dlt;
-  double *nrho, *nux, *nuy, *nW, *accx, *accy;
-  // ints
-  int *ix0, *iy0, *nidx, *rmin, *rmax, *lmin, *lmax, *ra1, *rl1, *ra2, *cnt, *off, *nxy, *nkc;
+  double *X, *Y, *Udx, *Udy, *wx, *wy;                           // table doubles
+  int *ix0, *iy0, *nidx, *ra1, *rl1, *ra2, *off, *nxy, *nkc, *S;  // table ints
+  double *rhoX, *Fx, *Fy, *Ftx, *Fty, *lam, *dlt;                // per-step, markers
+  double *nrho, *nux, *nuy, *nW;                                 // per-step, nodes
+  int *lmin, *lmax, *rmin, *rmax, *cnt;  // construction scratch (aliases the node arrays)
 };
 
-__device__ __forceinline__ WsLayout carve(double *base, int nb, int ns, int mr, int mn) {
+__device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
+  const int nb = B.nb, ns = B.ns, mr = B.max_rows, mn = B.max_nodes;
   WsLayout L;
   double *p = base;
   L.X = p; p += nb; L.Y = p; p += nb; L.Udx = p; p += nb; L.Udy = p; p += nb;
   L.wx = p; p += nb * ns; L.wy = p; p += nb * ns;
-  L.Fx = p; p += nb; L.Fy = p; p += nb; L.Ftx = p; p += nb; L.Fty = p; p += nb;
-  L.rhoX = p; p += nb; L.lam = p; p += nb; L.dlt = p; p += 9 * nb;
-  L.nrho = p; p += mn; L.nux = p; p += mn; L.nuy = p; p += mn; L.nW = p; p += mn;
-  L.accx = p; p += mn; L.accy = p; p += mn;
   int *q = (int *)p;
   L.ix0 = q; q += nb; L.iy0 = q; q += nb; L.nidx = q; q += nb * ns * ns;
-  L.lmin = q; q += mr; L.lmax = q; q += mr; L.rmin = q; q += mr; L.rmax = q; q += mr;
-  L.ra1 = q; q += mr; L.rl1 = q; q += mr; L.ra2 = q; q += mr; L.cnt = q; q += mr;
-  L.off = q; q += mr + 1; L.nxy = q; q += mn; L.nkc = q; q += mn;
+  L.ra1 = q; q += mr; L.rl1 = q; q += mr; L.ra2 = q; q += mr; L.off = q; q += mr + 1;
+  L.nxy = q; q += mn; L.nkc = q; q += mn; L.S = q;
+  double *d = base + ws_tab_total(nb, ns, mr, mn);
+  L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = nullptr;
+  if (B.scheme != kDFC) {
+    L.rhoX = d; d += nb; L.Fx = d; d += nb; L.Fy = d; d += nb; L.Ftx = d; d += nb; L.Fty = d; d += nb;
+    L.nrho = d; d += mn;
+  } else {
+    L.Ftx = d; d += nb; L.Fty = d; d += nb; L.lam = d; d += nb; L.dlt = d; d += 9 * nb;
+    L.nW = d; d += mn;
+  }
+  L.nux = d; d += mn; L.nuy = d; d += mn;
+  int *c = (int *)(base + ws_tab_total(nb, ns, mr, mn) + (B.scheme != kDFC ? 5 * nb : 12 * nb));
+  L.lmin = c; c += mr; L.lmax = c; c += mr; L.rmin = c; c += mr; L.rmax = c; c += mr; L.cnt = c;
   return L;
 }
 
 // Gather over the angular marker window of node (x,y): sum_k v_k D_h for two
-// marker arrays at once.
+// marker arrays at once, in increasing marker order from kc - win.
 __device__ __forceinline__ void gather2(const WsLayout &L, int nb, int ns, int win, int kc, int x,
                                         int y, const double *va, const double *vb, double &oa,
                                         double &ob) {
@@ -134,7 +155,7 @@ __device__ __forceinline__ void gather2(const WsLayout &L, int nb, int ns, int w
   ob = b;
 }
 
-// Interpolation of a node array to marker k (Eq. 7).
+// Interpolation of node arrays to marker k (Eq. 7).
 __device__ __forceinline__ double interp1(const WsLayout &L, int ns, int k, const double *nv) {
   double acc = 0.0;
   for (int jy = 0; jy < ns; jy++) {
@@ -145,64 +166,35 @@ __device__ __forceinline__ double interp1(const WsLayout &L, int ns, int k, cons
   return acc;
 }
 
-template <typename T>
-__device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, double *dyn,
-                          int lds_doubles, int spread_mode, double *red, int *ish, double *bsh) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  BodyState *bs = B.state;
-  const int nb = B.nb, ns = B.ns, s = ns / 2;
-  const bool shift = sizeof(T) == 4;
-  const double rho0 = c.rho0;
-  const int nx = c.nx, ny = c.ny;
-  const int64_t plane = c.plane;
-
-  // ---- 1. kinematics for t_{n+1}
-  if (tid == 0) {
-    double xc = bs->xc, yc = bs->yc, vhx = 0, vhy = 0, omh = 0;
-    if (B.motion == kPrescribedSin) {
-      const double t1 = (double)(step + 1);
-      const double ph = 2.0 * M_PI * B.freq * t1 + B.phase;
-      const double sn = sin(ph), cn = cos(ph);
-      xc = B.xc0 + B.amp[0] * sn;
-      yc = B.yc0 + B.amp[1] * sn;
-      vhx = B.amp[0] * 2.0 * M_PI * B.freq * cn;
-      vhy = B.amp[1] * 2.0 * M_PI * B.freq * cn;
-      bs->vx = vhx;
-      bs->vy = vhy;
-    } else if (B.motion == kFree) {
-      // Eq. (23) first half-kick and drift with the lagged internal-mass
-      // force of Eq. (A3) and the net gravity of Eq. (22).
-      const double fgx = (B.ms - B.mf) * c.grav_x;
-      const double fgy = (B.ms - B.mf) * c.grav_y;
-      const double dimx = B.internal_mass == kImFeng ? B.mf * (bs->vx - bs->vpx) : 0.0;
-      const double dimy = B.internal_mass == kImFeng ? B.mf * (bs->vy - bs->vpy) : 0.0;
-      bs->vpx = bs->vx;
-      bs->vpy = bs->vy;
-      bs->dimx = dimx;
-      bs->dimy = dimy;
-      vhx = bs->vx + (bs->fhx + fgx + dimx) / (2.0 * B.ms);
-      vhy = bs->vy + (bs->fhy + fgy + dimy) / (2.0 * B.ms);
-      xc += vhx;
-      yc += vhy;
-      omh = bs->om + bs->torque / (2.0 * B.Is);
+__device__ __forceinline__ void interp2(const WsLayout &L, int ns, int k, const double *na,
+                                        const double *nb_, double &oa, double &ob) {
+  double a = 0.0, b = 0.0;
+  for (int jy = 0; jy < ns; jy++) {
+    double ra = 0.0, rb = 0.0;
+    for (int jx = 0; jx < ns; jx++) {
+      const int j = L.nidx[(k * ns + jy) * ns + jx];
+      const double w = L.wx[k * ns + jx];
+      ra += na[j] * w;
+      rb += nb_[j] * w;
     }
-    bs->xc = xc; bs->yc = yc;
-    bs->vhx = vhx; bs->vhy = vhy; bs->omh = omh;
-    bsh[0] = xc; bsh[1] = yc; bsh[2] = vhx; bsh[3] = vhy; bsh[4] = omh;
-    ish[0] = 0;  // error flags
+    a += ra * L.wy[k * ns + jy];
+    b += rb * L.wy[k * ns + jy];
   }
-  const bool in_lds = lds_doubles >= B.ws_doubles;
-  double *base = in_lds ? dyn : B.ws;
-  const WsLayout L = carve(base, nb, ns, B.max_rows, B.max_nodes);
-  // row tables start empty
+  oa = a;
+  ob = b;
+}
+
+// Steps 2-3: markers, weights and the compact support.  Returns the node
+// count, or -1 with error flags in ish[0].
+__device__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout &L, double xc,
+                            double yc, double vhx, double vhy, double omh, int ylo, int *ish,
+                            int *wsum) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int nb = B.nb, ns = B.ns, s = ns / 2, nx = c.nx, ny = c.ny;
   for (int r = tid; r < B.max_rows; r += nth) {
     L.lmin[r] = 1 << 30; L.lmax[r] = -1; L.rmin[r] = 1 << 30; L.rmax[r] = -1;
   }
   __syncthreads();
-  const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
-  const int ylo = (int)floor(yc - B.radius) - ns;
-
-  // ---- 2. markers, weights, row intervals
   for (int k = tid; k < nb; k += nth) {
     const double X = xc + B.radius * B.cos_t[k];
     const double Y = yc + B.radius * B.sin_t[k];
@@ -227,11 +219,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     }
   }
   __syncthreads();
-  if (ish[0]) {
-    if (tid == 0) { bs->flags |= ish[0]; bs->box_valid = 0; }
-    return;
-  }
-  // ---- 3. row intervals -> compact node list
+  if (ish[0]) return -1;
   for (int r = tid; r < B.max_rows; r += nth) {
     const bool lv = L.lmax[r] >= 0, rv = L.rmax[r] >= 0;
     int a1 = 0, l1 = 0, a2 = 0, l2 = 0;
@@ -248,15 +236,13 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     L.ra1[r] = a1; L.rl1[r] = l1; L.ra2[r] = a2; L.cnt[r] = l1 + l2;
   }
   __syncthreads();
-  block_scan(L.cnt, L.off, B.max_rows, ish + 16);
+  block_scan(L.cnt, L.off, B.max_rows, wsum);
   const int S = L.off[B.max_rows];
   if (S > B.max_nodes) {
-    if (tid == 0) { bs->flags |= kFlagCapacity; bs->box_valid = 0; }
-    return;
+    if (tid == 0) ish[0] |= kFlagCapacity;
+    __syncthreads();
+    return -1;
   }
-  const T *fpop = (const T *)c.f[c.state->cur ^ 1];
-  T *fpop_w = (T *)c.f[c.state->cur ^ 1];
-  // nodes: coordinates, angular window centre, moments
   const double inv_dth = 1.0 / B.dtheta;
   for (int j = tid; j < S; j += nth) {
     int lo = 0, hi = B.max_rows - 1;
@@ -273,23 +259,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     kc %= nb;
     if (kc < 0) kc += nb;
     L.nkc[j] = kc;
-    if (B.scheme != kDFC) {
-      const int64_t p = (int64_t)y * nx + x;
-      double sm = 0, jx = 0, jy = 0;
-      for (int i = 0; i < 9; i++) {
-        const double v = (double)fpop[i * plane + p] + (shift ? c_w[i] * rho0 : 0.0);
-        sm += v;
-        jx += v * c_exi[i];
-        jy += v * c_eyi[i];
-      }
-      L.nrho[j] = sm;
-      L.nux[j] = jx / sm;
-      L.nuy[j] = jy / sm;
-    }
-    L.accx[j] = 0.0;
-    L.accy[j] = 0.0;
   }
-  // marker -> node indices
   for (int k = tid; k < nb; k += nth) {
     for (int jy = 0; jy < ns; jy++) {
       const int r = L.iy0[k] + jy - ylo;
@@ -301,12 +271,115 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
       }
     }
   }
+  if (tid == 0) L.S[0] = S;
   __syncthreads();
+  return S;
+}
 
+__device__ __forceinline__ void copy_doubles(double *dst, const double *src, int n) {
+  // 16-byte copies (workspace bases are 16-byte aligned)
+  const int n2 = n >> 1;
+  const double2 *s2 = (const double2 *)src;
+  double2 *d2 = (double2 *)dst;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) d2[i] = s2[i];
+  if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
+}
+
+template <typename T>
+__device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, double *dyn,
+                          int lds_doubles, int spread_mode, double *red, int *ish, double *bsh) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  BodyState *bs = B.state;
+  const int nb = B.nb, ns = B.ns;
+  const bool shift = sizeof(T) == 4;
+  const double rho0 = c.rho0;
+  const int nx = c.nx;
+  const uint32_t plane = (uint32_t)c.plane;
+
+  // ---- 1. kinematics for t_{n+1}
+  if (tid == 0) {
+    double xc = bs->xc, yc = bs->yc, vhx = 0, vhy = 0, omh = 0;
+    if (B.motion == kPrescribedSin) {
+      const double t1 = (double)(step + 1);
+      const double ph = 2.0 * M_PI * B.freq * t1 + B.phase;
+      const double sn = sin(ph), cn = cos(ph);
+      xc = B.xc0 + B.amp[0] * sn;
+      yc = B.yc0 + B.amp[1] * sn;
+      vhx = B.amp[0] * 2.0 * M_PI * B.freq * cn;
+      vhy = B.amp[1] * 2.0 * M_PI * B.freq * cn;
+      bs->vx = vhx;
+      bs->vy = vhy;
+    } else if (B.motion == kFree) {
+      // Eq. (23) first half-kick and drift, with the internal-mass force of
+      // Eq. (A3) held over the step and the net gravity of Eq. (22).
+      const double fgx = (B.ms - B.mf) * c.grav_x;
+      const double fgy = (B.ms - B.mf) * c.grav_y;
+      const double dimx = B.internal_mass == kImFeng ? B.mf * (bs->vx - bs->vpx) : 0.0;
+      const double dimy = B.internal_mass == kImFeng ? B.mf * (bs->vy - bs->vpy) : 0.0;
+      bs->vpx = bs->vx;
+      bs->vpy = bs->vy;
+      bs->dimx = dimx;
+      bs->dimy = dimy;
+      vhx = bs->vx + (bs->fhx + fgx + dimx) / (2.0 * B.ms);
+      vhy = bs->vy + (bs->fhy + fgy + dimy) / (2.0 * B.ms);
+      xc += vhx;
+      yc += vhy;
+      omh = bs->om + bs->torque / (2.0 * B.Is);
+    }
+    bs->xc = xc; bs->yc = yc;
+    bs->vhx = vhx; bs->vhy = vhy; bs->omh = omh;
+    bsh[0] = xc; bsh[1] = yc; bsh[2] = vhx; bsh[3] = vhy; bsh[4] = omh;
+    ish[0] = 0;
+    ish[1] = bs->tables_valid;
+    ish[2] = bs->lambda_valid;
+  }
+  __syncthreads();
+  const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
+  const bool in_lds = lds_doubles >= B.ws_doubles;
+  double *base = in_lds ? dyn : B.ws;
+  const WsLayout L = carve(base, B);
+  const int ylo = (int)floor(yc - B.radius) - ns;
+  const bool fixed = B.motion == kFixed;
+
+  // ---- 2-3. tables: cached for fixed bodies
+  int S;
+  if (fixed && ish[1]) {
+    if (in_lds) copy_doubles(base, B.tab_cache, B.ws_tab);
+    __syncthreads();
+    S = L.S[0];
+  } else {
+    S = build_tables(c, B, L, xc, yc, vhx, vhy, omh, ylo, ish, ish + 16);
+    if (S < 0) {
+      if (tid == 0) { bs->flags |= ish[0]; bs->box_valid = 0; }
+      return;
+    }
+    if (fixed) {
+      if (in_lds) copy_doubles(B.tab_cache, base, B.ws_tab);
+      if (tid == 0) bs->tables_valid = 1;
+    }
+  }
+  const T *fpop = (const T *)c.f[c.state->cur ^ 1];
+  T *fpop_w = (T *)c.f[c.state->cur ^ 1];
   const double ds = B.ds;
   double fsum_x = 0, fsum_y = 0, tq = 0, resmax = 0;
+
   if (B.scheme != kDFC) {
     // ---- 4a. DF (one pass, omega 1) / MDF (N passes, omega_MDF)
+    for (int j = tid; j < S; j += nth) {
+      const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
+      const uint32_t p = (uint32_t)y * nx + x;
+      double sm = 0, jx = 0, jy = 0;
+      for (int i = 0; i < 9; i++) {
+        const double v = (double)fpop[i * plane + p] + (shift ? c_w[i] * rho0 : 0.0);
+        sm += v;
+        jx += v * c_exi[i];
+        jy += v * c_eyi[i];
+      }
+      L.nrho[j] = sm;
+      L.nux[j] = jx / sm;
+      L.nuy[j] = jy / sm;
+    }
+    __syncthreads();
     const int N = B.scheme == kDF ? 1 : B.mdf_iters;
     const double om = B.scheme == kDF ? 1.0 : B.omega_mdf;
     for (int k = tid; k < nb; k += nth) {
@@ -314,10 +387,11 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
       L.Ftx[k] = 0.0;
       L.Fty[k] = 0.0;
     }
+    double *accx = B.acc, *accy = B.acc + B.max_nodes;
     for (int n = 1; n <= N; n++) {
-      __syncthreads();
       for (int k = tid; k < nb; k += nth) {
-        const double Ux = interp1(L, ns, k, L.nux), Uy = interp1(L, ns, k, L.nuy);
+        double Ux, Uy;
+        interp2(L, ns, k, L.nux, L.nuy, Ux, Uy);
         const double ex = L.Udx[k] - Ux, ey = L.Udy[k] - Uy;
         const double Fx = 2.0 * L.rhoX[k] * ex, Fy = 2.0 * L.rhoX[k] * ey;
         L.Fx[k] = om * Fx;
@@ -337,23 +411,23 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
           L.nuy[j] += sy * ds * h;
         }
       } else {
+        for (int j = tid; j < S; j += nth) { accx[j] = 0.0; accy[j] = 0.0; }
+        __syncthreads();
         for (int k = tid; k < nb; k += nth)
           for (int q = 0; q < ns * ns; q++) {
             const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
-            atomicAdd(&L.accx[L.nidx[k * ns * ns + q]], L.Fx[k] * w);
-            atomicAdd(&L.accy[L.nidx[k * ns * ns + q]], L.Fy[k] * w);
+            atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.Fx[k] * w);
+            atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.Fy[k] * w);
           }
         __syncthreads();
         for (int j = tid; j < S; j += nth) {
           const double h = 1.0 / (2.0 * L.nrho[j]);
-          L.nux[j] += L.accx[j] * ds * h;
-          L.nuy[j] += L.accy[j] * ds * h;
-          L.accx[j] = 0.0;
-          L.accy[j] = 0.0;
+          L.nux[j] += accx[j] * ds * h;
+          L.nuy[j] += accy[j] * ds * h;
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
     // Eulerian force f(x) = sum_k F_total D_h ds (Eq. 8) into the force field
     T *frc = (T *)c.force;
     if (spread_mode == 0) {
@@ -361,25 +435,25 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double fx, fy;
         gather2(L, nb, ns, B.window, L.nkc[j], x, y, L.Ftx, L.Fty, fx, fy);
-        const int64_t p = (int64_t)y * nx + x;
+        const uint32_t p = (uint32_t)y * nx + x;
         frc[p] = (T)(fx * ds);
         frc[plane + p] = (T)(fy * ds);
       }
     } else {
+      for (int j = tid; j < S; j += nth) { accx[j] = 0.0; accy[j] = 0.0; }
+      __syncthreads();
       for (int k = tid; k < nb; k += nth)
         for (int q = 0; q < ns * ns; q++) {
           const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
-          atomicAdd(&L.accx[L.nidx[k * ns * ns + q]], L.Ftx[k] * w);
-          atomicAdd(&L.accy[L.nidx[k * ns * ns + q]], L.Fty[k] * w);
+          atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.Ftx[k] * w);
+          atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.Fty[k] * w);
         }
       __syncthreads();
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-        const int64_t p = (int64_t)y * nx + x;
-        frc[p] = (T)(L.accx[j] * ds);
-        frc[plane + p] = (T)(L.accy[j] * ds);
-        L.accx[j] = 0.0;
-        L.accy[j] = 0.0;
+        const uint32_t p = (uint32_t)y * nx + x;
+        frc[p] = (T)(accx[j] * ds);
+        frc[plane + p] = (T)(accy[j] * ds);
       }
     }
     // force on the body: -sum_k F_total ds sum_x D_h (Newton's third law),
@@ -394,7 +468,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     }
   } else {
     // ---- 4b. DFC
-    if (!bs->lambda_valid) {
+    if (!(fixed && ish[2])) {
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double wt = 0.0;
@@ -408,7 +482,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
           if ((unsigned)jx < (unsigned)ns && (unsigned)jy < (unsigned)ns)
             wt += L.wx[k * ns + jx] * L.wy[k * ns + jy];
         }
-        L.nW[j] = wt;
+        L.nW[j] = wt;  // W_total(x) of Eq. (17)
       }
       __syncthreads();
       for (int k = tid; k < nb; k += nth) {
@@ -416,6 +490,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
         L.lam[k] = 1.0 / (2.0 * rho0 * ds * wsum);
         B.lambda_cache[k] = L.lam[k];
       }
+      if (fixed && tid == 0) bs->lambda_valid = 1;
     } else {
       for (int k = tid; k < nb; k += nth) L.lam[k] = B.lambda_cache[k];
     }
@@ -430,7 +505,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
         for (int jx = 0; jx < ns; jx++) {
           const int x = L.ix0[k] + jx;
           const double w = L.wx[k * ns + jx] * L.wy[k * ns + jy];
-          const int64_t p = (int64_t)y * nx + x;
+          const uint32_t p = (uint32_t)y * nx + x;
           for (int i = 0; i < 9; i++) gi[i] += (double)fpop[i * plane + p] * w;
         }
       }
@@ -466,7 +541,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
             for (int i = 0; i < 9; i++) corr[i] += L.dlt[9 * k + i] * w;
           }
         }
-        const int64_t p = (int64_t)y * nx + x;
+        const uint32_t p = (uint32_t)y * nx + x;
         double sm = 0, jxs = 0, jys = 0;
         for (int i = 0; i < 9; i++) {
           const T nv = (T)((double)fpop[i * plane + p] + corr[i] * ds);
@@ -480,29 +555,29 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
         L.nuy[j] = jys / sm;
       }
     } else {
-      // atomic scatter of the nine corrections, two components at a time
+      double *accx = B.acc, *accy = B.acc + B.max_nodes;
       for (int i0 = 0; i0 < 9; i0 += 2) {
+        for (int j = tid; j < S; j += nth) { accx[j] = 0.0; accy[j] = 0.0; }
+        __syncthreads();
         for (int k = tid; k < nb; k += nth)
           for (int q = 0; q < ns * ns; q++) {
             const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
-            atomicAdd(&L.accx[L.nidx[k * ns * ns + q]], L.dlt[9 * k + i0] * w);
-            if (i0 + 1 < 9) atomicAdd(&L.accy[L.nidx[k * ns * ns + q]], L.dlt[9 * k + i0 + 1] * w);
+            atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.dlt[9 * k + i0] * w);
+            if (i0 + 1 < 9) atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.dlt[9 * k + i0 + 1] * w);
           }
         __syncthreads();
         for (int j = tid; j < S; j += nth) {
           const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-          const int64_t p = (int64_t)y * nx + x;
-          fpop_w[i0 * plane + p] = (T)((double)fpop[i0 * plane + p] + L.accx[j] * ds);
+          const uint32_t p = (uint32_t)y * nx + x;
+          fpop_w[i0 * plane + p] = (T)((double)fpop[i0 * plane + p] + accx[j] * ds);
           if (i0 + 1 < 9)
-            fpop_w[(i0 + 1) * plane + p] = (T)((double)fpop[(i0 + 1) * plane + p] + L.accy[j] * ds);
-          L.accx[j] = 0.0;
-          L.accy[j] = 0.0;
+            fpop_w[(i0 + 1) * plane + p] = (T)((double)fpop[(i0 + 1) * plane + p] + accy[j] * ds);
         }
         __syncthreads();
       }
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-        const int64_t p = (int64_t)y * nx + x;
+        const uint32_t p = (uint32_t)y * nx + x;
         double sm = 0, jxs = 0, jys = 0;
         for (int i = 0; i < 9; i++) {
           const double v = (double)fpop[i * plane + p] + (shift ? c_w[i] * rho0 : 0.0);
@@ -524,7 +599,8 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
   // ---- 5. slip with the post-IB velocity, reductions, body update
   double slip_sum = 0, slip_max = 0;
   for (int k = tid; k < nb; k += nth) {
-    const double Ux = interp1(L, ns, k, L.nux), Uy = interp1(L, ns, k, L.nuy);
+    double Ux, Uy;
+    interp2(L, ns, k, L.nux, L.nuy, Ux, Uy);
     const double e = sqrt((Ux - L.Udx[k]) * (Ux - L.Udx[k]) + (Uy - L.Udy[k]) * (Uy - L.Udy[k]));
     slip_sum += e;
     slip_max = fmax(slip_max, e);
@@ -548,12 +624,11 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     bs->mdf_iters_done = B.scheme == kDFC ? 0 : (B.scheme == kDF ? 1 : B.mdf_iters);
     if (B.scheme == kDFC) {
       bs->box_valid = 0;
-      if (B.motion == kFixed) bs->lambda_valid = 1;
     } else {
       bs->box[0] = max(0, (int)floor(xc - B.radius) - ns);
       bs->box[1] = max(0, (int)floor(yc - B.radius) - ns);
       bs->box[2] = min(nx - 1, (int)floor(xc + B.radius) + ns + 1);
-      bs->box[3] = min(ny - 1, (int)floor(yc + B.radius) + ns + 1);
+      bs->box[3] = min(c.ny - 1, (int)floor(yc + B.radius) + ns + 1);
       bs->box_valid = 1;
     }
     if (B.motion == kFree) {
@@ -582,7 +657,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
                                                           int lds_doubles, int spread_mode) {
   extern __shared__ double dyn[];
   __shared__ double red[4 * (kIbmThreads / 64)];
-  __shared__ int ish[16 + kIbmThreads];
+  __shared__ int ish[16 + 40];
   __shared__ double bsh[16];
   const IbmSlot sl = slots[blockIdx.x];
   const CaseDesc &c = cases[sl.cas];
@@ -590,9 +665,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
   const int64_t step = cs->step;
   const bool active = step < cs->target && !(cs->flags & kCaseHalted);
   if (!active) return;
-  if (sl.body >= 0) {
-    body_step<T>(c, c.bodies[sl.body], step, dyn, lds_doubles, spread_mode, red, ish, bsh);
-  }
+  if (sl.body >= 0) body_step<T>(c, c.bodies[sl.body], step, dyn, lds_doubles, spread_mode, red, ish, bsh);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -602,11 +675,20 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
       // A body that failed this step (support outside the lattice, work
       // space too small, non-finite force) stops the case without completing
       // the step; bodies whose supports could meet within the next step stop
-      // it after completing this one.
-      int bflags = 0;
-      for (int b = 0; b < c.nbodies; b++)
-        bflags |= __hip_atomic_load(&c.bodies[b].state->flags, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
+      // it after completing this one.  The union of the bodies' force boxes
+      // tells the next collide-stream launch where to read the IB force.
+      int bflags = 0, bv = 0, b0 = 1 << 30, b1 = 1 << 30, b2 = -1, b3 = -1;
+      for (int b = 0; b < c.nbodies; b++) {
+        BodyState *st = c.bodies[b].state;
+        bflags |= __hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__hip_atomic_load(&st->box_valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          bv = 1;
+          b0 = min(b0, __hip_atomic_load(&st->box[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          b1 = min(b1, __hip_atomic_load(&st->box[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          b2 = max(b2, __hip_atomic_load(&st->box[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          b3 = max(b3, __hip_atomic_load(&st->box[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        }
+      }
       bool meet = false;
       for (int a = 0; a < c.nbodies && !bflags; a++)
         for (int b = a + 1; b < c.nbodies; b++) {
@@ -625,6 +707,8 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
       if (bflags) {
         cs->flags |= kCaseHalted;
       } else {
+        cs->fbox[0] = b0; cs->fbox[1] = b1; cs->fbox[2] = b2; cs->fbox[3] = b3;
+        cs->fbox_valid = bv;
         cs->cur ^= 1;
         cs->step = step + 1;
         if (meet) cs->flags |= kCaseHalted;
@@ -634,7 +718,6 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
   }
 }
 
-constexpr int kIbmDynLds = 128 * 1024;
 int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,

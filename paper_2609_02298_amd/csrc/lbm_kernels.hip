@@ -31,6 +31,19 @@ __device__ __forceinline__ R wgt(int i) {
 // ---------------------------------------------------------------- collision
 // f holds the stored values (f, or g = f - w rho0 when SHIFT).  sum_f is
 // sum_i f_i, so the equilibrium in either form is w_i (sum_f + rho P_i(u)).
+// Everything is computed in place to keep the register footprint small.
+template <typename R>
+__device__ __forceinline__ R eq_term(int i, R sum, R rho, R ux, R uy, R uu) {
+  const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
+  return wgt<R>(i) * (sum + rho * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
+}
+template <typename R>
+__device__ __forceinline__ R guo_term(int i, R ux, R uy, R Fx, R Fy, R uF) {
+  const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
+  const R eF = R(EXI(i)) * Fx + R(EYI(i)) * Fy;
+  return wgt<R>(i) * (R(3) * (eF - uF) + R(9) * eu * eF);
+}
+
 template <typename R, bool SHIFT, int COL>
 __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c) {
   const R sum = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
@@ -41,182 +54,173 @@ __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c
   const R ux = (jx + R(0.5) * Fx) * inv_rho;
   const R uy = (jy + R(0.5) * Fy) * inv_rho;
 
-  if constexpr (COL == kBGK || COL == kTRT) {
+  if constexpr (COL == kBGK) {
     const R uu = ux * ux + uy * uy;
     const R uF = ux * Fx + uy * Fy;
-    R eq[9], S[9];
+    const R om = R(c.omega);
+    const R pf = R(1) - R(0.5) * om;
 #pragma unroll
-    for (int i = 0; i < 9; i++) {
-      const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
-      const R eF = R(EXI(i)) * Fx + R(EYI(i)) * Fy;
-      eq[i] = wgt<R>(i) * (sum + rho * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
-      S[i] = wgt<R>(i) * (R(3) * (eF - uF) + R(9) * eu * eF);
-    }
-    if constexpr (COL == kBGK) {
-      const R om = R(c.omega);
-      const R pf = R(1) - R(0.5) * om;
+    for (int i = 0; i < 9; i++)
+      f[i] = f[i] - om * (f[i] - eq_term<R>(i, sum, rho, ux, uy, uu)) +
+             pf * guo_term<R>(i, ux, uy, Fx, Fy, uF);
+  } else if constexpr (COL == kTRT) {
+    const R uu = ux * ux + uy * uy;
+    const R uF = ux * Fx + uy * Fy;
+    const R se = R(c.s_e), so = R(c.s_o);
+    const R pe = R(1) - R(0.5) * se, po = R(1) - R(0.5) * so;
+    f[0] = f[0] - se * (f[0] - eq_term<R>(0, sum, rho, ux, uy, uu)) +
+           pe * guo_term<R>(0, ux, uy, Fx, Fy, uF);
 #pragma unroll
-      for (int i = 0; i < 9; i++) f[i] = f[i] - om * (f[i] - eq[i]) + pf * S[i];
-    } else {
-      const R se = R(c.s_e), so = R(c.s_o);
-      const R pe = R(1) - R(0.5) * se, po = R(1) - R(0.5) * so;
-      f[0] = f[0] - se * (f[0] - eq[0]) + pe * S[0];
-#pragma unroll
-      for (int i = 1; i <= 8; i++) {
-        const int j = OPPI(i);
-        if (j < i) continue;
-        const R fp = R(0.5) * (f[i] + f[j]), fm = R(0.5) * (f[i] - f[j]);
-        const R ep = R(0.5) * (eq[i] + eq[j]), em = R(0.5) * (eq[i] - eq[j]);
-        const R sp = R(0.5) * (S[i] + S[j]), sm = R(0.5) * (S[i] - S[j]);
-        const R even = -se * (fp - ep) + pe * sp;
-        const R odd = -so * (fm - em) + po * sm;
-        f[i] = f[i] + even + odd;
-        f[j] = f[j] + even - odd;
-      }
+    for (int i = 1; i <= 8; i++) {
+      const int j = OPPI(i);
+      if (j < i) continue;
+      const R ei = eq_term<R>(i, sum, rho, ux, uy, uu), ej = eq_term<R>(j, sum, rho, ux, uy, uu);
+      const R si = guo_term<R>(i, ux, uy, Fx, Fy, uF), sj = guo_term<R>(j, ux, uy, Fx, Fy, uF);
+      const R fp = R(0.5) * (f[i] + f[j]), fm = R(0.5) * (f[i] - f[j]);
+      const R even = -se * (fp - R(0.5) * (ei + ej)) + pe * R(0.5) * (si + sj);
+      const R odd = -so * (fm - R(0.5) * (ei - ej)) + po * R(0.5) * (si - sj);
+      f[i] = f[i] + even + odd;
+      f[j] = f[j] + even - odd;
     }
   } else {
     // Central moments k_pq = sum_i f_i (e_x - u_x)^p (e_y - u_y)^q.  D2Q9 is
     // the tensor product of {-1,0,1} x {-1,0,1}, so the transform factorises
-    // into a 3-point transform along x for each row e_y, then along y.
-    // Grid index [ey+1][ex+1] -> population: row -1: 7 4 8, row 0: 3 0 1,
-    // row +1: 6 2 5.
-    R a[3][3];
-    a[0][0] = f[7]; a[0][1] = f[4]; a[0][2] = f[8];
-    a[1][0] = f[3]; a[1][1] = f[0]; a[1][2] = f[1];
-    a[2][0] = f[6]; a[2][1] = f[2]; a[2][2] = f[5];
-    R kx[3][3];  // kx[row][p]
-#pragma unroll
-    for (int r = 0; r < 3; r++) {
-      const R m0 = a[r][0] + a[r][1] + a[r][2];
-      const R m1 = a[r][2] - a[r][0];
-      const R m2 = a[r][2] + a[r][0];
-      kx[r][0] = m0;
-      kx[r][1] = m1 - ux * m0;
-      kx[r][2] = m2 - R(2) * ux * m1 + ux * ux * m0;
+    // into a 3-point transform along x for each row e_y, then along y.  The
+    // grid [ey+1][ex+1] of populations is row -1: 7 4 8, row 0: 3 0 1,
+    // row +1: 6 2 5; all transforms run in place on these nine values.
+    R a00 = f[7], a01 = f[4], a02 = f[8];
+    R a10 = f[3], a11 = f[0], a12 = f[1];
+    R a20 = f[6], a21 = f[2], a22 = f[5];
+    const R ux2 = ux * ux, uy2 = uy * uy;
+    // forward along x: (v-1, v0, v1) -> (k0, k1, k2)
+#define IBL_FWD(u, u2, m, z, p)                                  \
+    {                                                            \
+      const R s0 = (m) + (z) + (p), s1 = (p) - (m), s2 = (p) + (m); \
+      (m) = s0;                                                  \
+      (z) = s1 - (u) * s0;                                       \
+      (p) = s2 - R(2) * (u) * s1 + (u2) * s0;                    \
     }
-    R k[3][3];  // k[p][q]
-#pragma unroll
-    for (int p = 0; p < 3; p++) {
-      const R n0 = kx[0][p] + kx[1][p] + kx[2][p];
-      const R n1 = kx[2][p] - kx[0][p];
-      const R n2 = kx[2][p] + kx[0][p];
-      k[p][0] = n0;
-      k[p][1] = n1 - uy * n0;
-      k[p][2] = n2 - R(2) * uy * n1 + uy * uy * n0;
-    }
-    // Relaxation, Eq. (5): Lambda = diag(0,0,0,w,w,w,s_q,s_q,s_eps).
-    // Equilibrium central moments (rho, 0, 0, rho/3, rho/3, 0, 0, 0, rho/9),
-    // forcing central moments (0, Fx, Fy, 0, 0, 0, Fy/3, Fx/3, 0).  In the
-    // shifted form the central moments of rho0 w_i are subtracted from the
-    // equilibrium: they factorise as c_p(ux) c_q(uy) with c = (1, -u, 1/3+u^2).
+    IBL_FWD(ux, ux2, a00, a01, a02);
+    IBL_FWD(ux, ux2, a10, a11, a12);
+    IBL_FWD(ux, ux2, a20, a21, a22);
+    // forward along y for p = 0, 1, 2 (columns): k[p][q] lands in a[q][p]
+    IBL_FWD(uy, uy2, a00, a10, a20);
+    IBL_FWD(uy, uy2, a01, a11, a21);
+    IBL_FWD(uy, uy2, a02, a12, a22);
+#undef IBL_FWD
+    // now a[q][p] = k_pq.  Relaxation, Eq. (5): Lambda =
+    // diag(0,0,0,w,w,w,s_q,s_q,s_eps); equilibrium central moments
+    // (rho,0,0,rho/3,rho/3,0,0,0,rho/9); forcing central moments
+    // (0,Fx,Fy,0,0,0,Fy/3,Fx/3,0).  The shifted form subtracts the central
+    // moments of rho0 w_i, which factorise as c_p(ux) c_q(uy) with
+    // c = (1, -u, 1/3 + u^2).
     const R om = R(c.omega), sq = R(c.s_q), seps = R(c.s_eps);
     const R r0 = SHIFT ? R(c.rho0) : R(0);
-    const R ux2 = ux * ux, uy2 = uy * uy;
     const R third = R(1) / R(3);
-    const R base = sum;  // rho (unshifted) or rho - rho0 (shifted)
-    const R E20 = base * third - r0 * ux2;
-    const R E02 = base * third - r0 * uy2;
+    const R E20 = sum * third - r0 * ux2;
+    const R E02 = sum * third - r0 * uy2;
     const R E11 = -r0 * ux * uy;
     const R E21 = r0 * uy * (third + ux2);
     const R E12 = r0 * ux * (third + uy2);
-    const R E22 = base * (R(1) / R(9)) - r0 * (third * (ux2 + uy2) + ux2 * uy2);
-    k[1][0] += Fx;
-    k[0][1] += Fy;
-    k[2][0] = (R(1) - om) * k[2][0] + om * E20;
-    k[0][2] = (R(1) - om) * k[0][2] + om * E02;
-    k[1][1] = (R(1) - om) * k[1][1] + om * E11;
-    const R pq = R(1) - R(0.5) * sq;
-    k[2][1] = (R(1) - sq) * k[2][1] + sq * E21 + pq * third * Fy;
-    k[1][2] = (R(1) - sq) * k[1][2] + sq * E12 + pq * third * Fx;
-    k[2][2] = (R(1) - seps) * k[2][2] + seps * E22;
-    // Back to populations: central -> raw along y, then solve the 3-point
-    // system (values at -1, 0, 1 from moments 0, 1, 2), then along x.
-#pragma unroll
-    for (int p = 0; p < 3; p++) {
-      const R M0 = k[p][0];
-      const R M1 = k[p][1] + uy * M0;
-      const R M2 = k[p][2] + R(2) * uy * k[p][1] + uy2 * M0;
-      kx[1][p] = M0 - M2;
-      kx[2][p] = R(0.5) * (M2 + M1);
-      kx[0][p] = R(0.5) * (M2 - M1);
+    const R E22 = sum * (R(1) / R(9)) - r0 * (third * (ux2 + uy2) + ux2 * uy2);
+    const R pq = (R(1) - R(0.5) * sq) * third;
+    a01 += Fx;                                       // k10
+    a10 += Fy;                                       // k01
+    a02 = a02 - om * (a02 - E20);                    // k20
+    a20 = a20 - om * (a20 - E02);                    // k02
+    a11 = a11 - om * (a11 - E11);                    // k11
+    a12 = a12 - sq * (a12 - E21) + pq * Fy;          // k21
+    a21 = a21 - sq * (a21 - E12) + pq * Fx;          // k12
+    a22 = a22 - seps * (a22 - E22);                  // k22
+    // back: central -> raw moments, then the 3-point values at -1, 0, 1
+#define IBL_BWD(u, u2, m, z, p)                                  \
+    {                                                            \
+      const R M0 = (m);                                          \
+      const R M1 = (z) + (u) * M0;                               \
+      const R M2 = (p) + R(2) * (u) * (z) + (u2) * M0;           \
+      (z) = M0 - M2;                                             \
+      (p) = R(0.5) * (M2 + M1);                                  \
+      (m) = R(0.5) * (M2 - M1);                                  \
     }
-#pragma unroll
-    for (int r = 0; r < 3; r++) {
-      const R M0 = kx[r][0];
-      const R M1 = kx[r][1] + ux * M0;
-      const R M2 = kx[r][2] + R(2) * ux * kx[r][1] + ux2 * M0;
-      a[r][1] = M0 - M2;
-      a[r][2] = R(0.5) * (M2 + M1);
-      a[r][0] = R(0.5) * (M2 - M1);
-    }
-    f[7] = a[0][0]; f[4] = a[0][1]; f[8] = a[0][2];
-    f[3] = a[1][0]; f[0] = a[1][1]; f[1] = a[1][2];
-    f[6] = a[2][0]; f[2] = a[2][1]; f[5] = a[2][2];
+    IBL_BWD(uy, uy2, a00, a10, a20);
+    IBL_BWD(uy, uy2, a01, a11, a21);
+    IBL_BWD(uy, uy2, a02, a12, a22);
+    IBL_BWD(ux, ux2, a00, a01, a02);
+    IBL_BWD(ux, ux2, a10, a11, a12);
+    IBL_BWD(ux, ux2, a20, a21, a22);
+#undef IBL_BWD
+    f[7] = a00; f[4] = a01; f[8] = a02;
+    f[3] = a10; f[0] = a11; f[1] = a12;
+    f[6] = a20; f[2] = a21; f[5] = a22;
   }
 }
 
 // ------------------------------------------------------------ streaming
-template <typename T>
-__device__ __forceinline__ void st(T *dst, int64_t plane, int i, int64_t idx, T v) {
-  dst[(int64_t)i * plane + idx] = v;
-}
-
 __device__ __forceinline__ bool is_vel(int b) { return b == kVelParabolic || b == kVelUniform; }
 
 // Push population i of node (x,y) with value v, applying the face closures:
 //   periodic faces wrap; a link leaving through the zero-gradient east face
 //   is dropped (the entering populations of the east column are written as
-//   copies of the column nx-2, see zg_dup); a link leaving through a wall
-//   returns as opp(i) at the node (half-way bounce-back); through a velocity
-//   face it returns as opp(i) - 6 w_i rho0 (e_i . u_w), u_w evaluated at the
-//   link mid-point.  A link leaving through a wall and a velocity face is a
-//   wall link; among velocity faces the first of W, E, S, N is used.
+//   copies of the column nx-2, see the duplicate store below); a link
+//   leaving through a wall returns as opp(i) at the node (half-way
+//   bounce-back); through a velocity face it returns as
+//   opp(i) - 6 w_i rho0 (e_i . u_w), u_w evaluated at the link mid-point.  A
+//   link leaving through a wall and a velocity face is a wall link; among
+//   velocity faces the first of W, E, S, N is used.
 template <typename T>
-__device__ __forceinline__ void zg_dup(const CaseDesc &c, T *dst, int j, int xs, int ys, T v) {
-  if (c.bc[kFaceE] == kZeroGradient && xs == c.nx - 2 && (j == 3 || j == 6 || j == 7))
-    st(dst, c.plane, j, (int64_t)ys * c.nx + (c.nx - 1), v);
-}
-
-template <typename T>
-__device__ __forceinline__ void push_boundary(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
+__device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
   const int nx = c.nx, ny = c.ny;
+  const uint32_t plane = (uint32_t)c.plane;
   int xd = x + c_ex[i], yd = y + c_ey[i];
   bool cw = xd < 0, ce = xd >= nx, cs = yd < 0, cn = yd >= ny;
   if (cw && c.bc[kFaceW] == kPeriodic) { xd += nx; cw = false; }
   if (ce && c.bc[kFaceE] == kPeriodic) { xd -= nx; ce = false; }
   if (cs && c.bc[kFaceS] == kPeriodic) { yd += ny; cs = false; }
   if (cn && c.bc[kFaceN] == kPeriodic) { yd -= ny; cn = false; }
-  if (!(cw || ce || cs || cn)) {
-    st(dst, c.plane, i, (int64_t)yd * nx + xd, v);
-    zg_dup(c, dst, i, xd, yd, v);
-    return;
+  int j = i, xs = xd, ys = yd;
+  if (cw || ce || cs || cn) {
+    if (ce && c.bc[kFaceE] == kZeroGradient) return;
+    j = OPPI(i);
+    xs = x;
+    ys = y;
+    const bool wall = (cw && c.bc[kFaceW] == kBounceBack) || (ce && c.bc[kFaceE] == kBounceBack) ||
+                      (cs && c.bc[kFaceS] == kBounceBack) || (cn && c.bc[kFaceN] == kBounceBack);
+    if (!wall) {
+      int vf = -1;
+      if (cw && is_vel(c.bc[kFaceW])) vf = kFaceW;
+      else if (ce && is_vel(c.bc[kFaceE])) vf = kFaceE;
+      else if (cs && is_vel(c.bc[kFaceS])) vf = kFaceS;
+      else if (cn && is_vel(c.bc[kFaceN])) vf = kFaceN;
+      if (vf < 0) return;
+      T uw;
+      if (c.bc[vf] == kVelParabolic) {
+        const T ym = T(y) + T(0.5) * T(c_ey[i]);
+        uw = T(4) * T(c.u_bc) * (ym + T(0.5)) * (T(ny) - T(0.5) - ym) * T(c.inv_ny2);
+      } else {
+        uw = T(c.u_bc);
+      }
+      v = v - T(6) * wgt<T>(i) * T(c.rho0) * (T(c_ex[i]) * uw);
+    }
   }
-  if (ce && c.bc[kFaceE] == kZeroGradient) return;
-  const int j = OPPI(i);
-  const bool wall = (cw && c.bc[kFaceW] == kBounceBack) || (ce && c.bc[kFaceE] == kBounceBack) ||
-                    (cs && c.bc[kFaceS] == kBounceBack) || (cn && c.bc[kFaceN] == kBounceBack);
-  if (wall) {
-    st(dst, c.plane, j, (int64_t)y * nx + x, v);
-    zg_dup(c, dst, j, x, y, v);
-    return;
-  }
-  int vf = -1;
-  if (cw && is_vel(c.bc[kFaceW])) vf = kFaceW;
-  else if (ce && is_vel(c.bc[kFaceE])) vf = kFaceE;
-  else if (cs && is_vel(c.bc[kFaceS])) vf = kFaceS;
-  else if (cn && is_vel(c.bc[kFaceN])) vf = kFaceN;
-  if (vf < 0) return;
-  T uw;
-  if (c.bc[vf] == kVelParabolic) {
-    const T ym = T(y) + T(0.5) * T(c_ey[i]);
-    uw = T(4) * T(c.u_bc) * (ym + T(0.5)) * (T(ny) - T(0.5) - ym) * T(c.inv_ny2);
-  } else {
-    uw = T(c.u_bc);
-  }
-  const T w = wgt<T>(i);
-  v = v - T(6) * w * T(c.rho0) * (T(c_ex[i]) * uw);
-  st(dst, c.plane, j, (int64_t)y * nx + x, v);
-  zg_dup(c, dst, j, x, y, v);
+  dst[(uint32_t)j * plane + (uint32_t)ys * nx + xs] = v;
+  if (c.bc[kFaceE] == kZeroGradient && xs == nx - 2 && (j == 3 || j == 6 || j == 7))
+    dst[(uint32_t)j * plane + (uint32_t)ys * nx + (nx - 1)] = v;
+}
+
+// Out of line so that boundary tiles do not raise the register footprint of
+// the interior path.
+template <typename T>
+__device__ __noinline__ void push_boundary9(const CaseDesc *c, T *dst, int x, int y, T f0, T f1,
+                                            T f2, T f3, T f4, T f5, T f6, T f7, T f8) {
+  push_one<T>(*c, dst, x, y, 0, f0);
+  push_one<T>(*c, dst, x, y, 1, f1);
+  push_one<T>(*c, dst, x, y, 2, f2);
+  push_one<T>(*c, dst, x, y, 3, f3);
+  push_one<T>(*c, dst, x, y, 4, f4);
+  push_one<T>(*c, dst, x, y, 5, f5);
+  push_one<T>(*c, dst, x, y, 6, f6);
+  push_one<T>(*c, dst, x, y, 7, f7);
+  push_one<T>(*c, dst, x, y, 8, f8);
 }
 
 template <typename T, int COL>
@@ -237,7 +241,8 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
     }
     ci = lo;
   }
-  const CaseDesc &c = cases[ci];
+  const CaseDesc *cp = cases + ci;
+  const CaseDesc &c = *cp;
   const CaseState *cs = c.state;
   if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
   const int cur = cs->cur;
@@ -248,30 +253,25 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
   const int tx = local % c.tiles_x, ty = local / c.tiles_x;
   const int TX = blockDim.x, TY = blockDim.y * rpt;
   const int nx = c.nx, ny = c.ny;
-  const int64_t plane = c.plane;
+  const uint32_t plane = (uint32_t)c.plane;
   const int x = tx * TX + threadIdx.x;
   const int ybase = ty * TY;
-  // IB force only inside the union of the bodies' force boxes
-  int fb0 = 1 << 30, fb1 = -1, fy0 = 1 << 30, fy1 = -1;
-  for (int b = 0; b < c.nbodies; b++) {
-    const BodyState *bs = c.bodies[b].state;
-    if (bs->box_valid) {
-      fb0 = min(fb0, bs->box[0]); fy0 = min(fy0, bs->box[1]);
-      fb1 = max(fb1, bs->box[2]); fy1 = max(fy1, bs->box[3]);
-    }
-  }
   const int xt0 = tx * TX, xt1 = xt0 + TX - 1, yt1 = ybase + TY - 1;
-  const bool tile_force = !(fb1 < xt0 || fb0 > xt1 || fy1 < ybase || fy0 > yt1);
+  // IB force only inside the union of the bodies' force boxes
+  const bool fvalid = cs->fbox_valid != 0;
+  const int fb0 = cs->fbox[0], fy0 = cs->fbox[1], fb1 = cs->fbox[2], fy1 = cs->fbox[3];
+  const bool tile_force = fvalid && !(fb1 < xt0 || fb0 > xt1 || fy1 < ybase || fy0 > yt1);
   const bool interior = xt0 >= 1 && xt1 <= nx - 3 && ybase >= 1 && yt1 <= ny - 2;
   const T ffx = T(c.fluid_fx), ffy = T(c.fluid_fy);
+  const int dxy = nx;
 
   for (int r = 0; r < rpt; r++) {
     const int y = ybase + threadIdx.y + r * blockDim.y;
     if (x >= nx || y >= ny) continue;
-    const int64_t p = (int64_t)y * nx + x;
+    const uint32_t p = (uint32_t)y * nx + x;
     T f[9];
 #pragma unroll
-    for (int i = 0; i < 9; i++) f[i] = src[i * plane + p];
+    for (int i = 0; i < 9; i++) f[i] = src[(uint32_t)i * plane + p];
     T Fx = ffx, Fy = ffy;
     if (tile_force && x >= fb0 && x <= fb1 && y >= fy0 && y <= fy1) {
       const T a = frc[p], b = frc[plane + p];
@@ -285,10 +285,9 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
     collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
     if (interior) {
 #pragma unroll
-      for (int i = 0; i < 9; i++) dst[i * plane + p + EXI(i) + (int64_t)EYI(i) * nx] = f[i];
+      for (int i = 0; i < 9; i++) dst[(uint32_t)i * plane + p + EXI(i) + EYI(i) * dxy] = f[i];
     } else {
-#pragma unroll
-      for (int i = 0; i < 9; i++) push_boundary<T>(c, dst, x, y, i, f[i]);
+      push_boundary9<T>(cp, dst, x, y, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
     }
   }
 }
