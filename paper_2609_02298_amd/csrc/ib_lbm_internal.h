@@ -102,16 +102,17 @@ struct CaseDesc {
 };
 
 // Workspace of one body, in doubles.  The table part (marker geometry,
-// compact support description) comes first so that it can be cached and
-// copied in bulk; the per-step arrays follow.
+// compact support description, node -> marker lists) comes first so that it
+// can be cached and copied in bulk; the per-step arrays follow.
 //   doubles: X Y Udx Udy (nb each), wx wy (nb*ns each)
 //   ints:    ix0 iy0 (nb each), nidx (nb*ns*ns), ra1 rl1 ra2 (mr each),
-//            off (mr+1), nxy nkc (mn each), S (1)            [padded to even]
+//            off (mr+1), nxy (mn), noff (mn+1), nent (nb*ns*ns), S (1)
+//            [padded to even]
 //   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each)
 //   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), nW nux nuy (mn each)
 __host__ __device__ inline int ws_table_doubles(int nb, int ns) { return nb * (4 + 2 * ns); }
 __host__ __device__ inline int ws_table_ints(int nb, int ns, int mr, int mn) {
-  const int n = nb * (2 + ns * ns) + 4 * mr + 1 + 2 * mn + 1;
+  const int n = nb * (2 + 2 * ns * ns) + 4 * mr + 1 + 2 * mn + 1 + 1;
   return (n + 1) & ~1;
 }
 __host__ __device__ inline int ws_tab_total(int nb, int ns, int mr, int mn) {

@@ -18,11 +18,12 @@
 //      order (wave shuffles, then LDS), and finishes the body update.
 // Steps 2-3 depend only on the body position: for a fixed body they run
 // once and are cached, later steps copy the tables in bulk.
-// Spreading is a gather: each support node sums over the markers of an
-// angular window around it, in marker order, so results are reproducible
-// run to run.  An atomic-scatter variant is kept for comparison.
-// The workspace lives in LDS when it fits, else in a global buffer of the
-// body (the same code reaches both through flat pointers).
+// Spreading is a gather: each support node keeps the list of markers whose
+// stencil covers it (sorted by marker index, built with the tables) and sums
+// over it in that order, so results are reproducible run to run and follow
+// the marker order of the plain definition.  An atomic-scatter variant is
+// kept for comparison.  The workspace lives in LDS when it fits (LDS
+// instantiation), else in a global buffer of the body.
 #include "ib_lbm_internal.h"
 
 namespace iblbm {
@@ -102,10 +103,10 @@ __device__ void block_scan(const int *cnt, int *off, int n, int *wsum) {
 
 struct WsLayout {
   double *X, *Y, *Udx, *Udy, *wx, *wy;                           // table doubles
-  int *ix0, *iy0, *nidx, *ra1, *rl1, *ra2, *off, *nxy, *nkc, *S;  // table ints
+  int *ix0, *iy0, *nidx, *ra1, *rl1, *ra2, *off, *nxy, *noff, *nent, *S;  // table ints
   double *rhoX, *Fx, *Fy, *Ftx, *Fty, *lam, *dlt;                // per-step, markers
   double *nrho, *nux, *nuy, *nW;                                 // per-step, nodes
-  int *lmin, *lmax, *rmin, *rmax, *cnt;  // construction scratch (aliases the node arrays)
+  int *lmin, *lmax, *rmin, *rmax, *cnt, *ncnt, *nfill;  // construction scratch (per-step area)
 };
 
 __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
@@ -117,7 +118,7 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   int *q = (int *)p;
   L.ix0 = q; q += nb; L.iy0 = q; q += nb; L.nidx = q; q += nb * ns * ns;
   L.ra1 = q; q += mr; L.rl1 = q; q += mr; L.ra2 = q; q += mr; L.off = q; q += mr + 1;
-  L.nxy = q; q += mn; L.nkc = q; q += mn; L.S = q;
+  L.nxy = q; q += mn; L.noff = q; q += mn + 1; L.nent = q; q += nb * ns * ns; L.S = q;
   double *d = base + ws_tab_total(nb, ns, mr, mn);
   L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = nullptr;
   if (B.scheme != kDFC) {
@@ -130,26 +131,27 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   L.nux = d; d += mn; L.nuy = d; d += mn;
   int *c = (int *)(base + ws_tab_total(nb, ns, mr, mn) + (B.scheme != kDFC ? 5 * nb : 12 * nb));
   L.lmin = c; c += mr; L.lmax = c; c += mr; L.rmin = c; c += mr; L.rmax = c; c += mr; L.cnt = c;
+  c += mr;
+  L.ncnt = c; c += mn; L.nfill = c;
   return L;
 }
 
-// Gather over the angular marker window of node (x,y): sum_k v_k D_h for two
-// marker arrays at once, in increasing marker order from kc - win.
-__device__ __forceinline__ void gather2(const WsLayout &L, int nb, int ns, int win, int kc, int x,
-                                        int y, const double *va, const double *vb, double &oa,
-                                        double &ob) {
+// Spreading by gather: node j sums v_k D_h(x_j - X_k) over the markers
+// covering it, in increasing marker order.
+__device__ __forceinline__ double node_weight(const WsLayout &L, int ns, int kq) {
+  const int k = kq >> 4, q = kq & 15;
+  return L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
+}
+
+__device__ __forceinline__ void gather2(const WsLayout &L, int ns, int j, const double *va,
+                                        const double *vb, double &oa, double &ob) {
   double a = 0.0, b = 0.0;
-  const bool all = 2 * win + 1 >= nb;
-  const int k0 = all ? 0 : kc - win, k1 = all ? nb - 1 : kc + win;
-  for (int kk = k0; kk <= k1; kk++) {
-    int k = kk;
-    if (k < 0) k += nb; else if (k >= nb) k -= nb;
-    const int jx = x - L.ix0[k], jy = y - L.iy0[k];
-    if ((unsigned)jx < (unsigned)ns && (unsigned)jy < (unsigned)ns) {
-      const double w = L.wx[k * ns + jx] * L.wy[k * ns + jy];
-      a += va[k] * w;
-      b += vb[k] * w;
-    }
+  const int e1 = L.noff[j + 1];
+  for (int e = L.noff[j]; e < e1; e++) {
+    const int kq = L.nent[e], k = kq >> 4;
+    const double w = node_weight(L, ns, kq);
+    a += va[k] * w;
+    b += vb[k] * w;
   }
   oa = a;
   ob = b;
@@ -243,7 +245,6 @@ __device__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout
     __syncthreads();
     return -1;
   }
-  const double inv_dth = 1.0 / B.dtheta;
   for (int j = tid; j < S; j += nth) {
     int lo = 0, hi = B.max_rows - 1;
     while (lo < hi) {
@@ -252,13 +253,8 @@ __device__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout
     }
     const int r = lo, loc = j - L.off[r];
     const int x = loc < L.rl1[r] ? L.ra1[r] + loc : L.ra2[r] + (loc - L.rl1[r]);
-    const int y = ylo + r;
-    L.nxy[j] = x | (y << 16);
-    const float th = atan2f((float)(y - yc), (float)(x - xc));
-    int kc = (int)rintf(th * (float)inv_dth);
-    kc %= nb;
-    if (kc < 0) kc += nb;
-    L.nkc[j] = kc;
+    L.nxy[j] = x | ((ylo + r) << 16);
+    L.ncnt[j] = 0;
   }
   for (int k = tid; k < nb; k += nth) {
     for (int jy = 0; jy < ns; jy++) {
@@ -269,6 +265,30 @@ __device__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout
                                                                   : L.rl1[r] + x - L.ra2[r];
         L.nidx[(k * ns + jy) * ns + jx] = L.off[r] + loc;
       }
+    }
+  }
+  __syncthreads();
+  // node -> marker lists (CSR): count, scan, fill, then sort each short list
+  // by marker index so the gather order does not depend on atomic timing
+  const int nq = ns * ns;
+  for (int e = tid; e < nb * nq; e += nth) atomicAdd(&L.ncnt[L.nidx[e]], 1);
+  __syncthreads();
+  block_scan(L.ncnt, L.noff, S, wsum);
+  for (int j = tid; j < S; j += nth) L.nfill[j] = L.noff[j];
+  __syncthreads();
+  for (int e = tid; e < nb * nq; e += nth) {
+    const int k = e / nq, q = e - k * nq;
+    const int pos = atomicAdd(&L.nfill[L.nidx[e]], 1);
+    L.nent[pos] = (k << 4) | q;
+  }
+  __syncthreads();
+  for (int j = tid; j < S; j += nth) {
+    const int e0 = L.noff[j], e1 = L.noff[j + 1];
+    for (int a = e0 + 1; a < e1; a++) {
+      const int v = L.nent[a];
+      int b = a - 1;
+      while (b >= e0 && L.nent[b] > v) { L.nent[b + 1] = L.nent[b]; b--; }
+      L.nent[b + 1] = v;
     }
   }
   if (tid == 0) L.S[0] = S;
@@ -285,9 +305,9 @@ __device__ __forceinline__ void copy_doubles(double *dst, const double *src, int
   if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
 }
 
-template <typename T>
+template <typename T, bool LDS>
 __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, double *dyn,
-                          int lds_doubles, int spread_mode, double *red, int *ish, double *bsh) {
+                          int spread_mode, double *red, int *ish, double *bsh) {
   const int tid = threadIdx.x, nth = blockDim.x;
   BodyState *bs = B.state;
   const int nb = B.nb, ns = B.ns;
@@ -335,8 +355,8 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
   }
   __syncthreads();
   const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
-  const bool in_lds = lds_doubles >= B.ws_doubles;
-  double *base = in_lds ? dyn : B.ws;
+  constexpr bool in_lds = LDS;
+  double *base = LDS ? dyn : B.ws;
   const WsLayout L = carve(base, B);
   const int ylo = (int)floor(yc - B.radius) - ns;
   const bool fixed = B.motion == kFixed;
@@ -403,9 +423,8 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
       __syncthreads();
       if (spread_mode == 0) {
         for (int j = tid; j < S; j += nth) {
-          const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
           double sx, sy;
-          gather2(L, nb, ns, B.window, L.nkc[j], x, y, L.Fx, L.Fy, sx, sy);
+          gather2(L, ns, j, L.Fx, L.Fy, sx, sy);
           const double h = 1.0 / (2.0 * L.nrho[j]);
           L.nux[j] += sx * ds * h;
           L.nuy[j] += sy * ds * h;
@@ -434,7 +453,7 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double fx, fy;
-        gather2(L, nb, ns, B.window, L.nkc[j], x, y, L.Ftx, L.Fty, fx, fy);
+        gather2(L, ns, j, L.Ftx, L.Fty, fx, fy);
         const uint32_t p = (uint32_t)y * nx + x;
         frc[p] = (T)(fx * ds);
         frc[plane + p] = (T)(fy * ds);
@@ -470,18 +489,8 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     // ---- 4b. DFC
     if (!(fixed && ish[2])) {
       for (int j = tid; j < S; j += nth) {
-        const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double wt = 0.0;
-        const bool all = 2 * B.window + 1 >= nb;
-        const int kc = L.nkc[j];
-        const int k0 = all ? 0 : kc - B.window, k1 = all ? nb - 1 : kc + B.window;
-        for (int kk = k0; kk <= k1; kk++) {
-          int k = kk;
-          if (k < 0) k += nb; else if (k >= nb) k -= nb;
-          const int jx = x - L.ix0[k], jy = y - L.iy0[k];
-          if ((unsigned)jx < (unsigned)ns && (unsigned)jy < (unsigned)ns)
-            wt += L.wx[k * ns + jx] * L.wy[k * ns + jy];
-        }
+        for (int e = L.noff[j]; e < L.noff[j + 1]; e++) wt += node_weight(L, ns, L.nent[e]);
         L.nW[j] = wt;  // W_total(x) of Eq. (17)
       }
       __syncthreads();
@@ -527,19 +536,12 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     if (spread_mode == 0) {
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-        const int kc = L.nkc[j];
         double corr[9];
         for (int i = 0; i < 9; i++) corr[i] = 0.0;
-        const bool all = 2 * B.window + 1 >= nb;
-        const int k0 = all ? 0 : kc - B.window, k1 = all ? nb - 1 : kc + B.window;
-        for (int kk = k0; kk <= k1; kk++) {
-          int k = kk;
-          if (k < 0) k += nb; else if (k >= nb) k -= nb;
-          const int jx = x - L.ix0[k], jy = y - L.iy0[k];
-          if ((unsigned)jx < (unsigned)ns && (unsigned)jy < (unsigned)ns) {
-            const double w = L.wx[k * ns + jx] * L.wy[k * ns + jy];
-            for (int i = 0; i < 9; i++) corr[i] += L.dlt[9 * k + i] * w;
-          }
+        for (int e = L.noff[j]; e < L.noff[j + 1]; e++) {
+          const int kq = L.nent[e], k = kq >> 4;
+          const double w = node_weight(L, ns, kq);
+          for (int i = 0; i < 9; i++) corr[i] += L.dlt[9 * k + i] * w;
         }
         const uint32_t p = (uint32_t)y * nx + x;
         double sm = 0, jxs = 0, jys = 0;
@@ -665,7 +667,13 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
   const int64_t step = cs->step;
   const bool active = step < cs->target && !(cs->flags & kCaseHalted);
   if (!active) return;
-  if (sl.body >= 0) body_step<T>(c, c.bodies[sl.body], step, dyn, lds_doubles, spread_mode, red, ish, bsh);
+  if (sl.body >= 0) {
+    const BodyDesc &B = c.bodies[sl.body];
+    if (lds_doubles >= B.ws_doubles)
+      body_step<T, true>(c, B, step, dyn, spread_mode, red, ish, bsh);
+    else
+      body_step<T, false>(c, B, step, dyn, spread_mode, red, ish, bsh);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();

