@@ -53,10 +53,13 @@ def measured_traffic(workload_key: str):
     return e.get("bytes_per_launch")
 
 
-def run_gpu(case, precision, steps, warmup, graph=0, launch=None):
+def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
     import torch
     import paper_2609_02298_amd as ib
 
+    if launch is None and tune:
+        from paper_2609_02298_amd import autotune
+        launch = autotune.tune(case["nx"], case["ny"], case["collision"], precision)
     sim = ib.Sim(case, precision=precision)
     if launch:
         sim.set_launch(**launch)
@@ -76,7 +79,8 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None):
     sim.timing(False)
     st = sim.forces(0, check=False)
     out = dict(seconds=t1 - t0, lbm_ms=lbm_ms, n_lbm=n_lbm, ibm_ms=ibm_ms, n_ibm=n_ibm,
-               fx=st["fx"], status=st["status"], steps_done=sim.steps_done)
+               fx=st["fx"], status=st["status"], steps_done=sim.steps_done,
+               launch=sim.get_launch())
     sim.close()
     return out
 
@@ -116,6 +120,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--extra", action="store_true", help="also time every scheme/kernel/collision")
     args = ap.parse_args()
 
@@ -139,7 +144,7 @@ def main():
     prec = ib.FP32_SHIFTED if args.precision == "fp32" else ib.FP64
     bpn = 72 if prec == ib.FP32_SHIFTED else 144
 
-    r = run_gpu(case, prec, args.steps, args.warmup, graph=args.graph)
+    r = run_gpu(case, prec, args.steps, args.warmup, graph=args.graph, tune=not args.no_tune)
     mlups = nodes * args.steps / r["seconds"] / 1e6
     lbm_avg_s = r["lbm_ms"] / max(r["n_lbm"], 1) * 1e-3
     achieved = bpn * nodes / lbm_avg_s / 1e9
@@ -168,14 +173,16 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "collide_stream_kernel",
                      "bytes_per_node": bpn,
-                     "avg_launch_us": round(lbm_avg_s * 1e6, 3)},
+                     "avg_launch_us": round(lbm_avg_s * 1e6, 3),
+                     "launch": r["launch"]},
         "ib_pass_avg_us": round(r["ibm_ms"] / max(r["n_ibm"], 1) * 1e3, 3),
         "hbm_fraction_of_step": round(bpn * nodes * args.steps / r["seconds"] / 1e9 / HBM_PEAK_GBS, 4),
         "lattice_bytes": 2 * 9 * nodes * (bpn // 18),
         "mall_resident_note": "2 lattices of this size fit in the 256 MB Infinity Cache",
     }
     if not args.no_fp64 and prec == ib.FP32_SHIFTED:
-        r64 = run_gpu(case, ib.FP64, max(args.steps // 2, 50), args.warmup // 2)
+        r64 = run_gpu(case, ib.FP64, max(args.steps // 2, 50), args.warmup // 2,
+                      tune=not args.no_tune)
         s64 = max(args.steps // 2, 50)
         a64 = 144 * nodes / (r64["lbm_ms"] / max(r64["n_lbm"], 1) * 1e-3) / 1e9
         line["fp64"] = {"value": round(nodes * s64 / r64["seconds"] / 1e6, 2), "unit": "MLUPS",
@@ -190,7 +197,7 @@ def main():
                 for col in ("BGK", "TRT", "CMMRT"):
                     c = ib_cases.unsteady_cylinder(scheme=sch, kernel=ker, collision=col, re=args.re)
                     for pname, p in (("fp32", ib.FP32_SHIFTED), ("fp64", ib.FP64)):
-                        rr = run_gpu(c, p, 100, 10)
+                        rr = run_gpu(c, p, 100, 10, tune=not args.no_tune)
                         combos[f"{sch}/{ker}/{col}/{pname}"] = round(nodes * 100 / rr["seconds"] / 1e6, 1)
         line["combos_mlups"] = combos
     if not args.no_cpu_baseline:

@@ -58,7 +58,7 @@ struct ib_lbm_sim {
   std::vector<HostBody> bodies;
   DevBuf d_bodies, d_case, d_prefix, d_slots, d_tmp;
   int nslots = 0;
-  ib_lbm_launch launch = {64, 4, 2, 1};
+  ib_lbm_launch launch = {128, 2, 1, 1};
   int spread_mode = 0;
   int graph_steps = 0;
   hipGraphExec_t graph_exec = nullptr;
@@ -84,7 +84,7 @@ struct ib_lbm_batch {
   std::vector<Group> groups;
   int nslots = 0;
   int lds_bytes = 0;
-  ib_lbm_launch launch = {64, 4, 2, 1};
+  ib_lbm_launch launch = {128, 2, 1, 1};
   int spread_mode = 0;
   int graph_steps = 0;
   hipGraphExec_t graph_exec = nullptr;
