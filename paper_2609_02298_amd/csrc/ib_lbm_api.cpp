@@ -214,8 +214,8 @@ double host_omega_mdf(double xc, double yc, double R, int nb, int kernel, double
   return 1.0 / (ds * mx);
 }
 
-int ws_doubles_for(int scheme, int nb, int ns, int mr, int mn) {
-  return ws_tab_total(nb, ns, mr, mn) + ws_dyn_doubles(scheme, nb, mn);
+int ws_doubles_for(int scheme, int nb, int ns, int mr, int mn, int pop_bytes) {
+  return ws_tab_total(nb, ns, mr, mn) + ws_dyn_doubles(scheme, nb, mn, pop_bytes);
 }
 
 // LDS bytes for an IB launch: enough for the largest workspace that fits;
@@ -349,7 +349,8 @@ size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_
     // workspace upper estimate (P4), marker tables, history
     const double D = nb / M_PI;
     const int mr = (int)std::ceil(D) + 12, mn = (int)(8 * M_PI * D + 8 * mr + 64);
-    bytes += (size_t)(ws_doubles_for(kDFC, nb, 4, mr, mn) + ws_tab_total(nb, 4, mr, mn) + 2 * mn) * 8 +
+    bytes += (size_t)(ws_doubles_for(kDFC, nb, 4, mr, mn, (int)elem) +
+                      ws_tab_total(nb, 4, mr, mn) + 2 * mn) * 8 +
              (size_t)nb * (8 + 1 + 2) * 8 +
              (size_t)hist * kHistCols * 8 + sizeof(BodyState) + sizeof(BodyDesc);
   }
@@ -536,7 +537,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.max_rows = (int)std::ceil(2 * B.radius) + 2 * B.ns + 4;
   B.max_nodes = maxn + maxn / 10 + 32;
   B.ws_tab = ws_tab_total(nb, B.ns, B.max_rows, B.max_nodes);
-  B.ws_doubles = ws_doubles_for(b->scheme, nb, B.ns, B.max_rows, B.max_nodes);
+  B.pop_bytes = s->cfg.precision == IB_LBM_FP64 ? 8 : 4;
+  B.ws_doubles = ws_doubles_for(b->scheme, nb, B.ns, B.max_rows, B.max_nodes, B.pop_bytes);
   // gather window: a node within s*sqrt(2) of marker k lies within angle
   // 2 asin(s / sqrt(2 R (R - s sqrt 2))) of it
   {

@@ -77,6 +77,7 @@ struct BodyDesc {
   double *tab_cache;    // cached geometry tables of a fixed body (ws_tab doubles)
   double *acc;          // 2 x max_nodes scratch of the atomic-scatter variant
   int32_t ws_tab;       // doubles of the table part of the workspace
+  int32_t pop_bytes;    // bytes of one stored population (8 FP64, 4 FP32 shifted)
   double *markers_out;  // n_b x 8: X Y Udx Udy Fx Fy lambda ds
   double *lambda_cache; // n_b
   double *history;      // hist_cap x kHistCols
@@ -109,7 +110,9 @@ struct CaseDesc {
 //            off (mr+1), nxy (mn), noff (mn+1), nent (nb*ns*ns), S (1)
 //            [padded to even]
 //   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each)
-//   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), nW nux nuy (mn each)
+//   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), nux nuy (mn each),
+//                     then the staged populations (9 mn of T) overlaid by the
+//                     W_total node array while the correction scale is built
 __host__ __device__ inline int ws_table_doubles(int nb, int ns) { return nb * (4 + 2 * ns); }
 __host__ __device__ inline int ws_table_ints(int nb, int ns, int mr, int mn) {
   const int n = nb * (2 + 2 * ns * ns) + 4 * mr + 1 + 2 * mn + 1 + 1;
@@ -118,8 +121,9 @@ __host__ __device__ inline int ws_table_ints(int nb, int ns, int mr, int mn) {
 __host__ __device__ inline int ws_tab_total(int nb, int ns, int mr, int mn) {
   return ws_table_doubles(nb, ns) + ws_table_ints(nb, ns, mr, mn) / 2;
 }
-__host__ __device__ inline int ws_dyn_doubles(int scheme, int nb, int mn) {
-  return scheme == 2 ? nb * 12 + mn * 3 : nb * 5 + mn * 3;
+__host__ __device__ inline int ws_dyn_doubles(int scheme, int nb, int mn, int pop_bytes) {
+  if (scheme == 2) return nb * 12 + (9 * mn * pop_bytes + 7) / 8;
+  return nb * 5 + mn * 3;
 }
 
 // One IB workgroup: the body `body` of case `cas` (body = -1: a case without

@@ -30,7 +30,11 @@ namespace iblbm {
 
 __constant__ int c_exi[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __constant__ int c_eyi[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__constant__ int c_oppi[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// opposite direction, a compile-time function so that unrolled loops index
+// register arrays with constants
+__device__ __forceinline__ constexpr int opp_of(int i) {
+  return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
+}
 __constant__ double c_w[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
@@ -55,7 +59,7 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 // Reduces four values at once: three sums and one max; result valid in all threads.
-__device__ void block_reduce4(double &a, double &b, double &c, double &m, double *red) {
+__device__ __forceinline__ void block_reduce4(double &a, double &b, double &c, double &m, double *red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); m = wave_max(m);
   __syncthreads();
@@ -72,7 +76,7 @@ __device__ void block_reduce4(double &a, double &b, double &c, double &m, double
 // Exclusive prefix sum of cnt[0..n) into off[0..n], off[n] = total.  Each
 // thread sums a contiguous chunk, chunk sums are scanned with wave shuffles
 // and one pass over the wave totals.  wsum holds at least 33 ints.
-__device__ void block_scan(const int *cnt, int *off, int n, int *wsum) {
+__device__ __forceinline__ void block_scan(const int *cnt, int *off, int n, int *wsum) {
   const int nth = blockDim.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int per = (n + nth - 1) / nth;
   const int b0 = min(n, threadIdx.x * per), b1 = min(n, b0 + per);
@@ -105,6 +109,7 @@ struct WsLayout {
   double *X, *Y, *Udx, *Udy, *wx, *wy;                           // table doubles
   int *ix0, *iy0, *nidx, *ra1, *rl1, *ra2, *off, *nxy, *noff, *nent, *S;  // table ints
   double *rhoX, *Fx, *Fy, *Ftx, *Fty, *lam, *dlt;                // per-step, markers
+  void *stage;                                                   // DFC populations
   double *nrho, *nux, *nuy, *nW;                                 // per-step, nodes
   int *lmin, *lmax, *rmin, *rmax, *cnt, *ncnt, *nfill;  // construction scratch (per-step area)
 };
@@ -121,35 +126,71 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   L.nxy = q; q += mn; L.noff = q; q += mn + 1; L.nent = q; q += nb * ns * ns; L.S = q;
   double *d = base + ws_tab_total(nb, ns, mr, mn);
   L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = nullptr;
+  L.stage = nullptr;
   if (B.scheme != kDFC) {
     L.rhoX = d; d += nb; L.Fx = d; d += nb; L.Fy = d; d += nb; L.Ftx = d; d += nb; L.Fty = d; d += nb;
     L.nrho = d; d += mn;
+    L.nux = d; d += mn; L.nuy = d; d += mn;
   } else {
     L.Ftx = d; d += nb; L.Fty = d; d += nb; L.lam = d; d += nb; L.dlt = d; d += 9 * nb;
-    L.nW = d; d += mn;
+    L.nux = L.nuy = nullptr;
+    L.stage = (void *)d;  // 9 x mn populations of the stored type
+    L.nW = d;             // overlays the staging area before it is filled
   }
-  L.nux = d; d += mn; L.nuy = d; d += mn;
-  int *c = (int *)(base + ws_tab_total(nb, ns, mr, mn) + (B.scheme != kDFC ? 5 * nb : 12 * nb));
+  int *c = (int *)(base + ws_tab_total(nb, ns, mr, mn) + (B.scheme == kDFC ? 12 * nb : 5 * nb));
   L.lmin = c; c += mr; L.lmax = c; c += mr; L.rmin = c; c += mr; L.rmax = c; c += mr; L.cnt = c;
   c += mr;
   L.ncnt = c; c += mn; L.nfill = c;
   return L;
 }
 
-// Spreading by gather: node j sums v_k D_h(x_j - X_k) over the markers
-// covering it, in increasing marker order.
-__device__ __forceinline__ double node_weight(const WsLayout &L, int ns, int kq) {
-  const int k = kq >> 4, q = kq & 15;
-  return L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
+// Velocity of the staged (corrected) populations at the support nodes of
+// marker k, interpolated like interp2; `shift` restores w_i rho0.
+template <int NS, typename T>
+__device__ __forceinline__ void interp_stage_velocity(const WsLayout &L, int k, const T *stg, int mn,
+                                                      double shift, double &oa, double &ob) {
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int jy = 0; jy < NS; jy++) {
+    double ra = 0.0, rb = 0.0;
+#pragma unroll
+    for (int jx = 0; jx < NS; jx++) {
+      const int j = L.nidx[(k * NS + jy) * NS + jx];
+      double sm = 0, jxs = 0, jys = 0;
+#pragma unroll
+      for (int i = 0; i < 9; i++) {
+        const double v = (double)stg[i * mn + j] + c_w[i] * shift;
+        sm += v;
+        jxs += v * c_exi[i];
+        jys += v * c_eyi[i];
+      }
+      const double w = L.wx[k * NS + jx];
+      ra += jxs / sm * w;
+      rb += jys / sm * w;
+    }
+    a += ra * L.wy[k * NS + jy];
+    b += rb * L.wy[k * NS + jy];
+  }
+  oa = a;
+  ob = b;
 }
 
-__device__ __forceinline__ void gather2(const WsLayout &L, int ns, int j, const double *va,
+// Spreading by gather: node j sums v_k D_h(x_j - X_k) over the markers
+// covering it, in increasing marker order.
+template <int NS>
+__device__ __forceinline__ double node_weight(const WsLayout &L, int kq) {
+  const int k = kq >> 4, q = kq & 15;
+  return L.wx[k * NS + (q % NS)] * L.wy[k * NS + (q / NS)];
+}
+
+template <int NS>
+__device__ __forceinline__ void gather2(const WsLayout &L, int j, const double *va,
                                         const double *vb, double &oa, double &ob) {
   double a = 0.0, b = 0.0;
   const int e1 = L.noff[j + 1];
   for (int e = L.noff[j]; e < e1; e++) {
     const int kq = L.nent[e], k = kq >> 4;
-    const double w = node_weight(L, ns, kq);
+    const double w = node_weight<NS>(L, kq);
     a += va[k] * w;
     b += vb[k] * w;
   }
@@ -158,29 +199,35 @@ __device__ __forceinline__ void gather2(const WsLayout &L, int ns, int j, const 
 }
 
 // Interpolation of node arrays to marker k (Eq. 7).
-__device__ __forceinline__ double interp1(const WsLayout &L, int ns, int k, const double *nv) {
+template <int NS>
+__device__ __forceinline__ double interp1(const WsLayout &L, int k, const double *nv) {
   double acc = 0.0;
-  for (int jy = 0; jy < ns; jy++) {
+#pragma unroll
+  for (int jy = 0; jy < NS; jy++) {
     double row = 0.0;
-    for (int jx = 0; jx < ns; jx++) row += nv[L.nidx[(k * ns + jy) * ns + jx]] * L.wx[k * ns + jx];
-    acc += row * L.wy[k * ns + jy];
+#pragma unroll
+    for (int jx = 0; jx < NS; jx++) row += nv[L.nidx[(k * NS + jy) * NS + jx]] * L.wx[k * NS + jx];
+    acc += row * L.wy[k * NS + jy];
   }
   return acc;
 }
 
-__device__ __forceinline__ void interp2(const WsLayout &L, int ns, int k, const double *na,
+template <int NS>
+__device__ __forceinline__ void interp2(const WsLayout &L, int k, const double *na,
                                         const double *nb_, double &oa, double &ob) {
   double a = 0.0, b = 0.0;
-  for (int jy = 0; jy < ns; jy++) {
+#pragma unroll
+  for (int jy = 0; jy < NS; jy++) {
     double ra = 0.0, rb = 0.0;
-    for (int jx = 0; jx < ns; jx++) {
-      const int j = L.nidx[(k * ns + jy) * ns + jx];
-      const double w = L.wx[k * ns + jx];
+#pragma unroll
+    for (int jx = 0; jx < NS; jx++) {
+      const int j = L.nidx[(k * NS + jy) * NS + jx];
+      const double w = L.wx[k * NS + jx];
       ra += na[j] * w;
       rb += nb_[j] * w;
     }
-    a += ra * L.wy[k * ns + jy];
-    b += rb * L.wy[k * ns + jy];
+    a += ra * L.wy[k * NS + jy];
+    b += rb * L.wy[k * NS + jy];
   }
   oa = a;
   ob = b;
@@ -188,7 +235,7 @@ __device__ __forceinline__ void interp2(const WsLayout &L, int ns, int k, const 
 
 // Steps 2-3: markers, weights and the compact support.  Returns the node
 // count, or -1 with error flags in ish[0].
-__device__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout &L, double xc,
+__device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout &L, double xc,
                             double yc, double vhx, double vhy, double omh, int ylo, int *ish,
                             int *wsum) {
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -297,20 +344,31 @@ __device__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout
 }
 
 __device__ __forceinline__ void copy_doubles(double *dst, const double *src, int n) {
-  // 16-byte copies (workspace bases are 16-byte aligned)
+  // 16-byte copies, four loads in flight per thread before the stores
+  // (workspace bases are 16-byte aligned)
   const int n2 = n >> 1;
   const double2 *s2 = (const double2 *)src;
   double2 *d2 = (double2 *)dst;
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) d2[i] = s2[i];
+  const int nth = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 3 * nth < n2; i += 4 * nth) {
+    const double2 a = s2[i], b = s2[i + nth], c = s2[i + 2 * nth], d = s2[i + 3 * nth];
+    d2[i] = a;
+    d2[i + nth] = b;
+    d2[i + 2 * nth] = c;
+    d2[i + 3 * nth] = d;
+  }
+  for (; i < n2; i += nth) d2[i] = s2[i];
   if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
 }
 
-template <typename T, bool LDS>
-__device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, double *dyn,
+template <typename T, bool LDS, int NS>
+__device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, double *dyn,
                           int spread_mode, double *red, int *ish, double *bsh) {
   const int tid = threadIdx.x, nth = blockDim.x;
   BodyState *bs = B.state;
-  const int nb = B.nb, ns = B.ns;
+  const int nb = B.nb;
+  constexpr int ns = NS;
   const bool shift = sizeof(T) == 4;
   const double rho0 = c.rho0;
   const int nx = c.nx;
@@ -385,78 +443,116 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
 
   if (B.scheme != kDFC) {
     // ---- 4a. DF (one pass, omega 1) / MDF (N passes, omega_MDF)
-    for (int j = tid; j < S; j += nth) {
-      const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-      const uint32_t p = (uint32_t)y * nx + x;
-      double sm = 0, jx = 0, jy = 0;
-      for (int i = 0; i < 9; i++) {
-        const double v = (double)fpop[i * plane + p] + (shift ? c_w[i] * rho0 : 0.0);
-        sm += v;
-        jx += v * c_exi[i];
-        jy += v * c_eyi[i];
+    // moments of the post-stream populations at the support nodes; the
+    // loads of two nodes per thread are issued before any is used
+    for (int j0 = tid; j0 < S; j0 += 2 * nth) {
+      T v[2][9];
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        const int j = j0 + u * nth;
+        if (j < S) {
+          const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
+          const uint32_t p = (uint32_t)y * nx + x;
+#pragma unroll
+          for (int i = 0; i < 9; i++) v[u][i] = fpop[i * plane + p];
+        }
       }
-      L.nrho[j] = sm;
-      L.nux[j] = jx / sm;
-      L.nuy[j] = jy / sm;
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        const int j = j0 + u * nth;
+        if (j >= S) continue;
+        double sm = 0, jx = 0, jy = 0;
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+          const double w = (double)v[u][i] + (shift ? c_w[i] * rho0 : 0.0);
+          sm += w;
+          jx += w * c_exi[i];
+          jy += w * c_eyi[i];
+        }
+        L.nrho[j] = sm;
+        L.nux[j] = jx / sm;
+        L.nuy[j] = jy / sm;
+      }
     }
     __syncthreads();
-    const int N = B.scheme == kDF ? 1 : B.mdf_iters;
-    const double om = B.scheme == kDF ? 1.0 : B.omega_mdf;
-    for (int k = tid; k < nb; k += nth) {
-      L.rhoX[k] = interp1(L, ns, k, L.nrho);
-      L.Ftx[k] = 0.0;
-      L.Fty[k] = 0.0;
-    }
-    double *accx = B.acc, *accy = B.acc + B.max_nodes;
-    for (int n = 1; n <= N; n++) {
-      for (int k = tid; k < nb; k += nth) {
-        double Ux, Uy;
-        interp2(L, ns, k, L.nux, L.nuy, Ux, Uy);
-        const double ex = L.Udx[k] - Ux, ey = L.Udy[k] - Uy;
-        const double Fx = 2.0 * L.rhoX[k] * ex, Fy = 2.0 * L.rhoX[k] * ey;
-        L.Fx[k] = om * Fx;
-        L.Fy[k] = om * Fy;
-        L.Ftx[k] += om * Fx;
-        L.Fty[k] += om * Fy;
-        if (n == N) resmax = fmax(resmax, sqrt(ex * ex + ey * ey));
-      }
-      __syncthreads();
-      if (spread_mode == 0) {
-        for (int j = tid; j < S; j += nth) {
-          double sx, sy;
-          gather2(L, ns, j, L.Fx, L.Fy, sx, sy);
-          const double h = 1.0 / (2.0 * L.nrho[j]);
-          L.nux[j] += sx * ds * h;
-          L.nuy[j] += sy * ds * h;
-        }
-      } else {
-        for (int j = tid; j < S; j += nth) { accx[j] = 0.0; accy[j] = 0.0; }
-        __syncthreads();
-        for (int k = tid; k < nb; k += nth)
-          for (int q = 0; q < ns * ns; q++) {
-            const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
-            atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.Fx[k] * w);
-            atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.Fy[k] * w);
-          }
-        __syncthreads();
-        for (int j = tid; j < S; j += nth) {
-          const double h = 1.0 / (2.0 * L.nrho[j]);
-          L.nux[j] += accx[j] * ds * h;
-          L.nuy[j] += accy[j] * ds * h;
-        }
-      }
-      __syncthreads();
-    }
-    // Eulerian force f(x) = sum_k F_total D_h ds (Eq. 8) into the force field
     T *frc = (T *)c.force;
+    double *accx = B.acc, *accy = B.acc + B.max_nodes;
+    if (B.scheme == kDF) {
+      // DF, Eq. (11): one interpolation of u*, F_L = 2 rho(X) (U_d - U)
+      for (int k = tid; k < nb; k += nth) {
+        L.rhoX[k] = interp1<NS>(L, k, L.nrho);
+        double Ux, Uy;
+        interp2<NS>(L, k, L.nux, L.nuy, Ux, Uy);
+        L.Ftx[k] = 2.0 * L.rhoX[k] * (L.Udx[k] - Ux);
+        L.Fty[k] = 2.0 * L.rhoX[k] * (L.Udy[k] - Uy);
+      }
+    } else {
+      // MDF, Eq. (12)-(14): N passes of interpolation, force and spreading
+      // back into the node velocities with relaxation omega_MDF; rho(X) is
+      // interpolated once; F_total accumulates omega F^(n).
+      const int N = B.mdf_iters;
+      const double om = B.omega_mdf;
+      for (int k = tid; k < nb; k += nth) {
+        L.rhoX[k] = interp1<NS>(L, k, L.nrho);
+        L.Ftx[k] = 0.0;
+        L.Fty[k] = 0.0;
+      }
+      for (int n = 1; n <= N; n++) {
+        for (int k = tid; k < nb; k += nth) {
+          double Ux, Uy;
+          interp2<NS>(L, k, L.nux, L.nuy, Ux, Uy);
+          const double ex = L.Udx[k] - Ux, ey = L.Udy[k] - Uy;
+          const double Fx = 2.0 * L.rhoX[k] * ex, Fy = 2.0 * L.rhoX[k] * ey;
+          L.Fx[k] = om * Fx;
+          L.Fy[k] = om * Fy;
+          L.Ftx[k] += om * Fx;
+          L.Fty[k] += om * Fy;
+          if (n == N) resmax = fmax(resmax, sqrt(ex * ex + ey * ey));
+        }
+        __syncthreads();
+        if (spread_mode == 0) {
+          for (int j = tid; j < S; j += nth) {
+            double sx, sy;
+            gather2<NS>(L, j, L.Fx, L.Fy, sx, sy);
+            const double h = 1.0 / (2.0 * L.nrho[j]);
+            L.nux[j] += sx * ds * h;
+            L.nuy[j] += sy * ds * h;
+          }
+        } else {
+          for (int j = tid; j < S; j += nth) { accx[j] = 0.0; accy[j] = 0.0; }
+          __syncthreads();
+          for (int k = tid; k < nb; k += nth)
+            for (int q = 0; q < ns * ns; q++) {
+              const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
+              atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.Fx[k] * w);
+              atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.Fy[k] * w);
+            }
+          __syncthreads();
+          for (int j = tid; j < S; j += nth) {
+            const double h = 1.0 / (2.0 * L.nrho[j]);
+            L.nux[j] += accx[j] * ds * h;
+            L.nuy[j] += accy[j] * ds * h;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    // Eulerian force f(x) = sum_k F_total D_h ds (Eq. 8) into the force field;
+    // DF also forms the post-IB node velocity u* + f/(2 rho) for the slip
     if (spread_mode == 0) {
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double fx, fy;
-        gather2(L, ns, j, L.Ftx, L.Fty, fx, fy);
+        gather2<NS>(L, j, L.Ftx, L.Fty, fx, fy);
         const uint32_t p = (uint32_t)y * nx + x;
         frc[p] = (T)(fx * ds);
         frc[plane + p] = (T)(fy * ds);
+        if (B.scheme == kDF) {
+          const double h = 1.0 / (2.0 * L.nrho[j]);
+          L.nux[j] += fx * ds * h;
+          L.nuy[j] += fy * ds * h;
+        }
       }
     } else {
       for (int j = tid; j < S; j += nth) { accx[j] = 0.0; accy[j] = 0.0; }
@@ -473,6 +569,11 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
         const uint32_t p = (uint32_t)y * nx + x;
         frc[p] = (T)(accx[j] * ds);
         frc[plane + p] = (T)(accy[j] * ds);
+        if (B.scheme == kDF) {
+          const double h = 1.0 / (2.0 * L.nrho[j]);
+          L.nux[j] += accx[j] * ds * h;
+          L.nuy[j] += accy[j] * ds * h;
+        }
       }
     }
     // force on the body: -sum_k F_total ds sum_x D_h (Newton's third law),
@@ -490,12 +591,12 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
     if (!(fixed && ish[2])) {
       for (int j = tid; j < S; j += nth) {
         double wt = 0.0;
-        for (int e = L.noff[j]; e < L.noff[j + 1]; e++) wt += node_weight(L, ns, L.nent[e]);
+        for (int e = L.noff[j]; e < L.noff[j + 1]; e++) wt += node_weight<NS>(L, L.nent[e]);
         L.nW[j] = wt;  // W_total(x) of Eq. (17)
       }
       __syncthreads();
       for (int k = tid; k < nb; k += nth) {
-        const double wsum = interp1(L, ns, k, L.nW);
+        const double wsum = interp1<NS>(L, k, L.nW);
         L.lam[k] = 1.0 / (2.0 * rho0 * ds * wsum);
         B.lambda_cache[k] = L.lam[k];
       }
@@ -504,25 +605,60 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
       for (int k = tid; k < nb; k += nth) L.lam[k] = B.lambda_cache[k];
     }
     __syncthreads();
+    // Stage the support populations in LDS (rows of the support are
+    // contiguous in x, so these loads coalesce), one plane per direction.
+    T *stg = (T *)L.stage;
+    const int mn = B.max_nodes;
+    for (int j0 = tid; j0 < S; j0 += 2 * nth) {
+      T v[2][9];
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        const int j = j0 + u * nth;
+        if (j < S) {
+          const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
+          const uint32_t p = (uint32_t)y * nx + x;
+#pragma unroll
+          for (int i = 0; i < 9; i++) v[u][i] = fpop[i * plane + p];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        const int j = j0 + u * nth;
+        if (j < S) {
+#pragma unroll
+          for (int i = 0; i < 9; i++) stg[i * mn + j] = v[u][i];
+        }
+      }
+    }
+    __syncthreads();
     // Eq. (15)-(18), (20): interpolate the stored populations; the bounce-back
     // target minus f* only involves f*_opp - f*_i, the same in f and in g.
     for (int k = tid; k < nb; k += nth) {
       double gi[9];
+#pragma unroll
       for (int i = 0; i < 9; i++) gi[i] = 0.0;
-      for (int jy = 0; jy < ns; jy++) {
-        const int y = L.iy0[k] + jy;
-        for (int jx = 0; jx < ns; jx++) {
-          const int x = L.ix0[k] + jx;
-          const double w = L.wx[k * ns + jx] * L.wy[k * ns + jy];
-          const uint32_t p = (uint32_t)y * nx + x;
-          for (int i = 0; i < 9; i++) gi[i] += (double)fpop[i * plane + p] * w;
+#pragma unroll
+      for (int jy = 0; jy < NS; jy++) {
+        double row[9];
+#pragma unroll
+        for (int i = 0; i < 9; i++) row[i] = 0.0;
+#pragma unroll
+        for (int jx = 0; jx < NS; jx++) {
+          const int j = L.nidx[(k * NS + jy) * NS + jx];
+          const double w = L.wx[k * NS + jx];
+#pragma unroll
+          for (int i = 0; i < 9; i++) row[i] += (double)stg[i * mn + j] * w;
         }
+        const double wy = L.wy[k * NS + jy];
+#pragma unroll
+        for (int i = 0; i < 9; i++) gi[i] += row[i] * wy;
       }
       const double lam = L.lam[k];
       double fsx = 0, fsy = 0;
+#pragma unroll
       for (int i = 0; i < 9; i++) {
         const double eud = c_exi[i] * L.Udx[k] + c_eyi[i] * L.Udy[k];
-        const double d = lam * (gi[c_oppi[i]] - gi[i] + 6.0 * c_w[i] * rho0 * eud);
+        const double d = lam * (gi[opp_of(i)] - gi[i] + 6.0 * c_w[i] * rho0 * eud);
         L.dlt[9 * k + i] = d;
         fsx += c_exi[i] * d;
         fsy += c_eyi[i] * d;
@@ -531,30 +667,28 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
       L.Fty[k] = -ds * fsy;
     }
     __syncthreads();
-    // Eq. (19): f_i(x) <- f*_i(x) + sum_k delta f_i D_h ds, then the
-    // post-correction velocity for the slip diagnostic.
+    // Eq. (19): f_i(x) <- f*_i(x) + sum_k delta f_i D_h ds.  The corrected
+    // populations also replace the staged ones (each node only touches its
+    // own entries) for the slip diagnostic.
     if (spread_mode == 0) {
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double corr[9];
+#pragma unroll
         for (int i = 0; i < 9; i++) corr[i] = 0.0;
         for (int e = L.noff[j]; e < L.noff[j + 1]; e++) {
           const int kq = L.nent[e], k = kq >> 4;
-          const double w = node_weight(L, ns, kq);
+          const double w = node_weight<NS>(L, kq);
+#pragma unroll
           for (int i = 0; i < 9; i++) corr[i] += L.dlt[9 * k + i] * w;
         }
         const uint32_t p = (uint32_t)y * nx + x;
-        double sm = 0, jxs = 0, jys = 0;
+#pragma unroll
         for (int i = 0; i < 9; i++) {
-          const T nv = (T)((double)fpop[i * plane + p] + corr[i] * ds);
+          const T nv = (T)((double)stg[i * mn + j] + corr[i] * ds);
           fpop_w[i * plane + p] = nv;
-          const double v = (double)nv + (shift ? c_w[i] * rho0 : 0.0);
-          sm += v;
-          jxs += v * c_exi[i];
-          jys += v * c_eyi[i];
+          stg[i * mn + j] = nv;
         }
-        L.nux[j] = jxs / sm;
-        L.nuy[j] = jys / sm;
       }
     } else {
       double *accx = B.acc, *accy = B.acc + B.max_nodes;
@@ -571,24 +705,16 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
         for (int j = tid; j < S; j += nth) {
           const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
           const uint32_t p = (uint32_t)y * nx + x;
-          fpop_w[i0 * plane + p] = (T)((double)fpop[i0 * plane + p] + accx[j] * ds);
-          if (i0 + 1 < 9)
-            fpop_w[(i0 + 1) * plane + p] = (T)((double)fpop[(i0 + 1) * plane + p] + accy[j] * ds);
+          const T na = (T)((double)stg[i0 * mn + j] + accx[j] * ds);
+          fpop_w[i0 * plane + p] = na;
+          stg[i0 * mn + j] = na;
+          if (i0 + 1 < 9) {
+            const T nb2 = (T)((double)stg[(i0 + 1) * mn + j] + accy[j] * ds);
+            fpop_w[(i0 + 1) * plane + p] = nb2;
+            stg[(i0 + 1) * mn + j] = nb2;
+          }
         }
         __syncthreads();
-      }
-      for (int j = tid; j < S; j += nth) {
-        const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-        const uint32_t p = (uint32_t)y * nx + x;
-        double sm = 0, jxs = 0, jys = 0;
-        for (int i = 0; i < 9; i++) {
-          const double v = (double)fpop[i * plane + p] + (shift ? c_w[i] * rho0 : 0.0);
-          sm += v;
-          jxs += v * c_exi[i];
-          jys += v * c_eyi[i];
-        }
-        L.nux[j] = jxs / sm;
-        L.nuy[j] = jys / sm;
       }
     }
     for (int k = tid; k < nb; k += nth) {
@@ -602,7 +728,10 @@ __device__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, do
   double slip_sum = 0, slip_max = 0;
   for (int k = tid; k < nb; k += nth) {
     double Ux, Uy;
-    interp2(L, ns, k, L.nux, L.nuy, Ux, Uy);
+    if (B.scheme == kDFC)
+      interp_stage_velocity<NS, T>(L, k, (const T *)L.stage, B.max_nodes, shift ? rho0 : 0.0, Ux, Uy);
+    else
+      interp2<NS>(L, k, L.nux, L.nuy, Ux, Uy);
     const double e = sqrt((Ux - L.Udx[k]) * (Ux - L.Udx[k]) + (Uy - L.Udy[k]) * (Uy - L.Udy[k]));
     slip_sum += e;
     slip_max = fmax(slip_max, e);
@@ -669,61 +798,82 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
   if (!active) return;
   if (sl.body >= 0) {
     const BodyDesc &B = c.bodies[sl.body];
-    if (lds_doubles >= B.ws_doubles)
-      body_step<T, true>(c, B, step, dyn, spread_mode, red, ish, bsh);
-    else
-      body_step<T, false>(c, B, step, dyn, spread_mode, red, ish, bsh);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(&cs->done, 1);
-    if (prev == sl.slots_in_case - 1) {
-      __threadfence();
-      // A body that failed this step (support outside the lattice, work
-      // space too small, non-finite force) stops the case without completing
-      // the step; bodies whose supports could meet within the next step stop
-      // it after completing this one.  The union of the bodies' force boxes
-      // tells the next collide-stream launch where to read the IB force.
-      int bflags = 0, bv = 0, b0 = 1 << 30, b1 = 1 << 30, b2 = -1, b3 = -1;
-      for (int b = 0; b < c.nbodies; b++) {
-        BodyState *st = c.bodies[b].state;
-        bflags |= __hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__hip_atomic_load(&st->box_valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          bv = 1;
-          b0 = min(b0, __hip_atomic_load(&st->box[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          b1 = min(b1, __hip_atomic_load(&st->box[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          b2 = max(b2, __hip_atomic_load(&st->box[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          b3 = max(b3, __hip_atomic_load(&st->box[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        }
-      }
-      bool meet = false;
-      for (int a = 0; a < c.nbodies && !bflags; a++)
-        for (int b = a + 1; b < c.nbodies; b++) {
-          const BodyDesc &A = c.bodies[a], &Bb = c.bodies[b];
-          const double dx = __hip_atomic_load(&A.state->xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
-                            __hip_atomic_load(&Bb.state->xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const double dy = __hip_atomic_load(&A.state->yc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
-                            __hip_atomic_load(&Bb.state->yc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const double lim = A.radius + Bb.radius + A.ns + Bb.ns + 4.0;
-          if (dx * dx + dy * dy <= lim * lim) {
-            meet = true;
-            A.state->flags |= kFlagOverlap;
-          }
-        }
-      cs->done = 0;
-      if (bflags) {
-        cs->flags |= kCaseHalted;
-      } else {
-        cs->fbox[0] = b0; cs->fbox[1] = b1; cs->fbox[2] = b2; cs->fbox[3] = b3;
-        cs->fbox_valid = bv;
-        cs->cur ^= 1;
-        cs->step = step + 1;
-        if (meet) cs->flags |= kCaseHalted;
-      }
-      __threadfence();
+    const bool lds = lds_doubles >= B.ws_doubles;
+    if (B.ns == 2) {
+      if (lds) body_step<T, true, 2>(c, B, step, dyn, spread_mode, red, ish, bsh);
+      else body_step<T, false, 2>(c, B, step, dyn, spread_mode, red, ish, bsh);
+    } else {
+      if (lds) body_step<T, true, 4>(c, B, step, dyn, spread_mode, red, ish, bsh);
+      else body_step<T, false, 4>(c, B, step, dyn, spread_mode, red, ish, bsh);
     }
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (sl.slots_in_case == 1) {
+    // the only workgroup of its case: no other body to wait for
+    const BodyState *st = sl.body >= 0 ? c.bodies[sl.body].state : nullptr;
+    if (st && st->flags) {
+      cs->flags |= kCaseHalted;
+      return;
+    }
+    if (st && st->box_valid) {
+      cs->fbox[0] = st->box[0]; cs->fbox[1] = st->box[1];
+      cs->fbox[2] = st->box[2]; cs->fbox[3] = st->box[3];
+      cs->fbox_valid = 1;
+    } else {
+      cs->fbox_valid = 0;
+    }
+    cs->cur ^= 1;
+    cs->step = step + 1;
+    return;
+  }
+  __threadfence();
+  const int prev = atomicAdd(&cs->done, 1);
+  if (prev != sl.slots_in_case - 1) return;
+  __threadfence();
+  // Last workgroup of its case.  A body that failed this step (support
+  // outside the lattice, work space too small, non-finite force) stops the
+  // case without completing the step; bodies whose supports could meet within
+  // the next step stop it after completing this one.  The union of the
+  // bodies' force boxes tells the next collide-stream launch where to read
+  // the IB force.
+  int bflags = 0, bv = 0, b0 = 1 << 30, b1 = 1 << 30, b2 = -1, b3 = -1;
+  for (int b = 0; b < c.nbodies; b++) {
+    BodyState *st = c.bodies[b].state;
+    bflags |= __hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_load(&st->box_valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      bv = 1;
+      b0 = min(b0, __hip_atomic_load(&st->box[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      b1 = min(b1, __hip_atomic_load(&st->box[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      b2 = max(b2, __hip_atomic_load(&st->box[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      b3 = max(b3, __hip_atomic_load(&st->box[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+  }
+  bool meet = false;
+  for (int a = 0; a < c.nbodies && !bflags; a++)
+    for (int b = a + 1; b < c.nbodies; b++) {
+      const BodyDesc &A = c.bodies[a], &Bb = c.bodies[b];
+      const double dx = __hip_atomic_load(&A.state->xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                        __hip_atomic_load(&Bb.state->xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double dy = __hip_atomic_load(&A.state->yc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                        __hip_atomic_load(&Bb.state->yc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double lim = A.radius + Bb.radius + A.ns + Bb.ns + 4.0;
+      if (dx * dx + dy * dy <= lim * lim) {
+        meet = true;
+        A.state->flags |= kFlagOverlap;
+      }
+    }
+  cs->done = 0;
+  if (bflags) {
+    cs->flags |= kCaseHalted;
+  } else {
+    cs->fbox[0] = b0; cs->fbox[1] = b1; cs->fbox[2] = b2; cs->fbox[3] = b3;
+    cs->fbox_valid = bv;
+    cs->cur ^= 1;
+    cs->step = step + 1;
+    if (meet) cs->flags |= kCaseHalted;
+  }
+  __threadfence();
 }
 
 int ibm_max_lds_bytes() { return kIbmDynLds; }

@@ -283,7 +283,7 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
       }
     }
     collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
-    if (interior) {
+    if (interior || (x >= 1 && x <= nx - 3 && y >= 1 && y <= ny - 2)) {
 #pragma unroll
       for (int i = 0; i < 9; i++) dst[(uint32_t)i * plane + p + EXI(i) + EYI(i) * dxy] = f[i];
     } else {
