@@ -107,6 +107,44 @@ def cpu_baseline(case, target_seconds=12.0):
                        f"oracle, {dt:.1f} s")
 
 
+def serving_leg(precision, launch, n_cases: int, step_scale: int, budget_gb: float,
+                quantum: int, seed: int = 0):
+    """Parameter-sweep serving: the seeded sweep cases (grid widths
+    log-uniform in [128, 2048], aspect 2-4, all 18 scheme/kernel/collision
+    combinations) with step counts divided by `step_scale`, served (a) all
+    arriving at once and (b) by a Poisson process at 1.25x the measured
+    sequential service rate, next to sequential plain solves of the same
+    cases on the same GPU and precision."""
+    import numpy as np
+    import ib_cases
+    from paper_2609_02298_amd import serving
+
+    cases = ib_cases.sweep_cases(n_cases, seed=seed)
+    steps = [max(1, c["steps"] // step_scale) for c in cases]
+    seq = serving.sequential(cases, precision, steps=steps, launch=launch)
+    rate = 1.25 * len(cases) / seq["wall"]
+    # arrival gaps from their own stream so that the cases are the same in
+    # every mode
+    gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, len(cases))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    budget = int(budget_gb * 2**30)
+    burst = serving.serve(cases, precision, steps=steps, hbm_budget=budget, quantum=quantum,
+                          launch=launch)
+    pois = serving.serve(cases, precision, steps=steps, arrivals=arrivals, hbm_budget=budget,
+                         quantum=quantum, launch=launch)
+    nodes = [c["nx"] * c["ny"] for c in cases]
+    return {
+        "workload": f"sweep seed {seed}: {len(cases)} cases, {min(nodes)}-{max(nodes)} nodes, "
+                    f"steps U{{2000..20000}}/{step_scale}",
+        "precision": "fp32-shifted" if precision == 1 else "fp64",
+        "hbm_budget_gb": budget_gb, "quantum": quantum,
+        "node_updates": int(sum(n * k for n, k in zip(nodes, steps))),
+        "burst": serving.summary(cases, burst, seq),
+        "poisson": dict(serving.summary(cases, pois, seq, arrivals=list(arrivals)),
+                        rate_per_s=round(rate, 3)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +160,11 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--extra", action="store_true", help="also time every scheme/kernel/collision")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-cases", type=int, default=256)
+    ap.add_argument("--serve-step-scale", type=int, default=40)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-quantum", type=int, default=128)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -200,6 +243,9 @@ def main():
                         rr = run_gpu(c, p, 100, 10, tune=not args.no_tune)
                         combos[f"{sch}/{ker}/{col}/{pname}"] = round(nodes * 100 / rr["seconds"] / 1e6, 1)
         line["combos_mlups"] = combos
+    if not args.no_serving:
+        line["serving"] = serving_leg(prec, r["launch"], args.serve_cases, args.serve_step_scale,
+                                      args.serve_budget_gb, args.serve_quantum)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)

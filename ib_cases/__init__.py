@@ -165,6 +165,22 @@ def sweep_cases(n_cases: int = 256, seed: int = 0, rate: float | None = None,
     return cases
 
 
+def channel_case(nx: int, ny: int, scheme=DF, kernel=HAT, collision=BGK, re: float = 40.0,
+                 u_max: float = 0.1, steps: int = 100, name: str | None = None) -> dict:
+    """A sweep-style case of any size: channel faces of the fixed-cylinder
+    case (parabolic inlet u_max, zero-gradient outlet, bounce-back walls),
+    body D = ny/10 at (nx/4, ny/2)."""
+    D = ny / 10.0
+    return dict(
+        name=name or f"channel-{nx}x{ny}", nx=nx, ny=ny, collision=collision,
+        tau=tau_from(u_max, D, re), trt_magic=0.25, cm_s_q=1.2, cm_s_eps=1.4, rho0=1.0,
+        bc=(VEL_PARABOLIC, ZERO_GRADIENT, BOUNCE_BACK, BOUNCE_BACK), u_bc=u_max, u_ref=u_max,
+        diameter=D, re=re,
+        bodies=[dict(xc=nx / 4.0, yc=ny / 2.0, diameter=D, n_markers=0, scheme=scheme,
+                     kernel=kernel, mdf_iters=5)],
+        steps=steps)
+
+
 def random_populations(nx: int, ny: int, seed: int, rho0: float = 1.0, amp: float = 0.01,
                        u: tuple = (0.0, 0.0)) -> np.ndarray:
     """Positive random populations [9][ny][nx] near a lattice-weight state:

@@ -233,6 +233,9 @@ ib_lbm_status ib_lbm_batch_detach(ib_lbm_batch *b, ib_lbm_sim *s);
 ib_lbm_status ib_lbm_batch_set_target(ib_lbm_batch *b, ib_lbm_sim *s, int64_t target);
 ib_lbm_status ib_lbm_batch_step(ib_lbm_batch *b, int64_t nsteps);
 ib_lbm_status ib_lbm_batch_set_graph(ib_lbm_batch *b, int32_t steps_per_graph);
+/* Launch shape and spreading variant of the batch's launches (as for a sim). */
+ib_lbm_status ib_lbm_batch_set_launch(ib_lbm_batch *b, const ib_lbm_launch *l);
+ib_lbm_status ib_lbm_batch_set_spread(ib_lbm_batch *b, int32_t mode);
 ib_lbm_status ib_lbm_batch_sync(ib_lbm_batch *b);
 ib_lbm_status ib_lbm_batch_destroy(ib_lbm_batch *b);
 const char *ib_lbm_batch_last_error(const ib_lbm_batch *b);

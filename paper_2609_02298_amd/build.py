@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libib_lbm.so")
-SOURCES = ["lbm_kernels.hip", "ibm_kernels.hip", "ib_lbm_api.cpp"]
+SOURCES = ["lbm_kernels.hip", "ibm_kernels.hip", "ib_lbm_api.cpp", "ib_lbm_server.cpp"]
 ARCH = os.environ.get("IB_LBM_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the generated code
@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
             print(msg, file=sys.stderr)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -1041,6 +1041,27 @@ ib_lbm_status ib_lbm_batch_set_graph(ib_lbm_batch *b, int32_t steps_per_graph) {
   return IB_LBM_OK;
 }
 
+ib_lbm_status ib_lbm_batch_set_launch(ib_lbm_batch *b, const ib_lbm_launch *l) {
+  if (!b) return IB_LBM_E_INVALID;
+  if (b->broken) return IB_LBM_E_STATE;
+  ib_lbm_status st = check_launch(l, &b->err);
+  if (st) return st;
+  b->launch = *l;
+  b->dirty = true;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_batch_set_spread(ib_lbm_batch *b, int32_t mode) {
+  if (!b) return IB_LBM_E_INVALID;
+  if (mode != IB_LBM_SPREAD_GATHER && mode != IB_LBM_SPREAD_ATOMIC) return IB_LBM_E_INVALID;
+  b->spread_mode = mode;
+  if (b->graph_exec) {
+    (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+  }
+  return IB_LBM_OK;
+}
+
 ib_lbm_status ib_lbm_batch_sync(ib_lbm_batch *b) {
   if (!b) return IB_LBM_E_INVALID;
   if (b->broken) return IB_LBM_E_STATE;

@@ -28,10 +28,13 @@ IM_NONE, IM_FENG = 0, 1
 SPREAD_GATHER, SPREAD_ATOMIC = 0, 1
 FLAG_NONFINITE, FLAG_RANGE, FLAG_OVERLAP = 1, 2, 4
 
-STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_DIVERGED",
+PENDING = 1
+MAX_BODIES = 8
+
+STATUS = {1: "PENDING", 0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_DIVERGED",
           -5: "E_RANGE", -6: "E_STATE"}
 
-# Exported symbols declared in include/ib_lbm.h (checked by the CPU tests).
+# Exported symbols declared in include/*.h (checked by the CPU tests).
 EXPORTS = [
     "ib_lbm_abi_version", "ib_lbm_create", "ib_lbm_add_body", "ib_lbm_step", "ib_lbm_forces",
     "ib_lbm_history", "ib_lbm_fields", "ib_lbm_get_populations", "ib_lbm_set_populations",
@@ -41,6 +44,10 @@ EXPORTS = [
     "ib_lbm_timing_read", "ib_lbm_batch_create", "ib_lbm_batch_attach", "ib_lbm_batch_detach",
     "ib_lbm_batch_set_target", "ib_lbm_batch_step", "ib_lbm_batch_set_graph",
     "ib_lbm_batch_sync", "ib_lbm_batch_destroy", "ib_lbm_batch_last_error",
+    "ib_lbm_batch_set_launch", "ib_lbm_batch_set_spread",
+    "ib_lbm_server_create", "ib_lbm_server_submit", "ib_lbm_server_wait",
+    "ib_lbm_server_stats_get", "ib_lbm_server_drain", "ib_lbm_server_destroy",
+    "ib_lbm_server_last_error",
 ]
 
 
@@ -89,6 +96,36 @@ class BodyState(C.Structure):
 class Launch(C.Structure):
     _fields_ = [("block_x", C.c_int32), ("block_y", C.c_int32), ("rows_per_thread", C.c_int32),
                 ("xcd_remap", C.c_int32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("precision", C.c_int32), ("hbm_budget", C.c_uint64),
+                ("max_resident", C.c_int32), ("quantum", C.c_int32), ("graph_steps", C.c_int32),
+                ("spread", C.c_int32), ("launch", Launch), ("stream", C.c_void_p)]
+
+
+class Request(C.Structure):
+    _fields_ = [("lattice", Config), ("n_bodies", C.c_int32), ("bodies", BodyDesc * MAX_BODIES),
+                ("steps", C.c_int64), ("rho", C.POINTER(C.c_double)),
+                ("ux", C.POINTER(C.c_double)), ("uy", C.POINTER(C.c_double))]
+
+
+class Result(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("n_bodies", C.c_int32),
+                ("steps_done", C.c_int64), ("footprint", C.c_uint64), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_finish", C.c_double),
+                ("body", BodyState * MAX_BODIES)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("failed", C.c_int64), ("resident", C.c_int64), ("queued", C.c_int64),
+                ("resident_bytes", C.c_uint64), ("peak_resident_bytes", C.c_uint64),
+                ("peak_resident", C.c_int64), ("node_updates", C.c_int64), ("rounds", C.c_int64),
+                ("busy_seconds", C.c_double), ("now", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -146,6 +183,16 @@ def load_library(path: str = LIB_PATH):
     L.ib_lbm_batch_destroy.argtypes = [vp]
     L.ib_lbm_batch_last_error.restype = C.c_char_p
     L.ib_lbm_batch_last_error.argtypes = [vp]
+    L.ib_lbm_batch_set_launch.argtypes = [vp, C.POINTER(Launch)]
+    L.ib_lbm_batch_set_spread.argtypes = [vp, C.c_int32]
+    L.ib_lbm_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(vp)]
+    L.ib_lbm_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_int64)]
+    L.ib_lbm_server_wait.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(Result)]
+    L.ib_lbm_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+    L.ib_lbm_server_drain.argtypes = [vp]
+    L.ib_lbm_server_destroy.argtypes = [vp]
+    L.ib_lbm_server_last_error.restype = C.c_char_p
+    L.ib_lbm_server_last_error.argtypes = [vp]
     if L.ib_lbm_abi_version() != ABI_VERSION:
         raise ImportError("libib_lbm.so ABI version mismatch")
     _lib = L
@@ -399,12 +446,118 @@ class Batch:
     def set_graph(self, steps_per_graph: int):
         self._check(self.L.ib_lbm_batch_set_graph(self.h, int(steps_per_graph)))
 
+    def set_launch(self, block_x=128, block_y=2, rows_per_thread=1, xcd_remap=1):
+        l = Launch(block_x, block_y, rows_per_thread, xcd_remap)
+        self._check(self.L.ib_lbm_batch_set_launch(self.h, C.byref(l)))
+
+    def set_spread(self, mode: int):
+        self._check(self.L.ib_lbm_batch_set_spread(self.h, int(mode)))
+
     def sync(self):
         self._check(self.L.ib_lbm_batch_sync(self.h))
 
     def close(self):
         if getattr(self, "h", None):
             self.L.ib_lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop with continuous batching (the ABI's ``ib_lbm_server``).
+
+    ``submit`` queues a case and returns its id; ``wait`` returns the result
+    as a dict (body states, times on the server clock, optional final
+    fields).  The worker thread and every HIP call live in the library."""
+
+    def __init__(self, precision: int = FP32_SHIFTED, hbm_budget: int = 0, max_resident: int = 0,
+                 quantum: int = 0, graph_steps: int = 0, spread: int = SPREAD_GATHER,
+                 launch: dict | None = None, stream=None):
+        self.L = load_library()
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available (the library has no CPU path)")
+        torch.cuda.init()
+        c = ServerConfig()
+        c.abi_version = ABI_VERSION
+        c.precision = int(precision)
+        c.hbm_budget = int(hbm_budget)
+        c.max_resident = int(max_resident)
+        c.quantum = int(quantum)
+        c.graph_steps = int(graph_steps)
+        c.spread = int(spread)
+        if launch:
+            c.launch = Launch(launch["block_x"], launch["block_y"], launch["rows_per_thread"],
+                              launch.get("xcd_remap", 1))
+        c.stream = stream
+        self.precision = int(precision)
+        h = C.c_void_p()
+        st = self.L.ib_lbm_server_create(C.byref(c), C.byref(h))
+        if st != 0:
+            raise IbLbmError(st, "server creation failed")
+        self.h = h
+        self._fields = {}
+        self._shape = {}
+
+    def submit(self, case: dict, steps: int, fields: bool = False) -> int:
+        bodies = case.get("bodies", [])
+        if len(bodies) > MAX_BODIES:
+            raise ValueError(f"at most {MAX_BODIES} bodies per request")
+        r = Request()
+        r.lattice = make_config(case, self.precision)
+        r.n_bodies = len(bodies)
+        for i, b in enumerate(bodies):
+            r.bodies[i] = make_body(b)
+        r.steps = int(steps)
+        out = None
+        if fields:
+            ny, nx = int(case["ny"]), int(case["nx"])
+            out = tuple(np.empty((ny, nx)) for _ in range(3))
+            r.rho, r.ux, r.uy = (_dp(a) for a in out)
+        rid = C.c_int64()
+        st = self.L.ib_lbm_server_submit(self.h, C.byref(r), C.byref(rid))
+        if st != 0:
+            raise IbLbmError(st, "submit rejected")
+        if out is not None:
+            self._fields[rid.value] = out
+        return rid.value
+
+    def wait(self, rid: int, timeout: float = -1.0) -> dict | None:
+        res = Result()
+        st = self.L.ib_lbm_server_wait(self.h, int(rid), float(timeout), C.byref(res))
+        if st == PENDING:
+            return None
+        if st != 0:
+            raise IbLbmError(st, "wait failed")
+        d = {n: getattr(res, n) for n, _ in Result._fields_ if n != "body"}
+        d["bodies"] = [res.body[i].as_dict() for i in range(res.n_bodies)]
+        d["latency"] = res.t_finish - res.t_submit
+        f = self._fields.pop(int(rid), None)
+        if f is not None:
+            d["rho"], d["ux"], d["uy"] = f
+        return d
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        st = self.L.ib_lbm_server_stats_get(self.h, C.byref(s))
+        if st != 0:
+            raise IbLbmError(st, "stats failed")
+        return s.as_dict()
+
+    def drain(self):
+        self.L.ib_lbm_server_drain(self.h)
+
+    def last_error(self) -> str:
+        return (self.L.ib_lbm_server_last_error(self.h) or b"").decode()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ib_lbm_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

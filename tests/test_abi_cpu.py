@@ -11,7 +11,8 @@ import paper_2609_02298_amd as ib
 from paper_2609_02298_amd import ib_lbm as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ib_lbm.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def _ensure_built():
@@ -21,9 +22,11 @@ def _ensure_built():
 
 
 def header_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(ib_lbm_\w+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ib_lbm_\w+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_and_binding_agree():
@@ -53,17 +56,20 @@ def test_abi_version_and_footprint_without_device():
     assert f64 > f32
 
 
-@pytest.mark.parametrize("name", ["Config", "BodyDesc", "BodyState", "Launch", "Allocator"])
+@pytest.mark.parametrize("name", ["Config", "BodyDesc", "BodyState", "Launch", "Allocator",
+                                  "ServerConfig", "Request", "Result", "ServerStats"])
 def test_struct_layouts_match_header(name, tmp_path):
     cname = {"Config": "ib_lbm_config", "BodyDesc": "ib_lbm_body_desc",
              "BodyState": "ib_lbm_body_state", "Launch": "ib_lbm_launch",
-             "Allocator": "ib_lbm_allocator"}[name]
+             "Allocator": "ib_lbm_allocator", "ServerConfig": "ib_lbm_server_config",
+             "Request": "ib_lbm_request", "Result": "ib_lbm_result",
+             "ServerStats": "ib_lbm_server_stats"}[name]
     st = getattr(B, name)
     lines = [f'printf("%zu\\n", sizeof({cname}));']
     for fname, _ in st._fields_:
         lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
     src = tmp_path / "layout.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ib_lbm.h"\nint main(){' +
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ib_lbm_server.h"\nint main(){' +
                    "".join(lines) + "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
