@@ -67,18 +67,28 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
         sim.set_graph(graph)
     sim.step(warmup)
     sim.sync()
-    sim.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     sim.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    split, near = sim.overlap()
+    # kernel durations from HIP events in a separate run of unpipelined steps
+    # (the events add host and queue work to every step, so the wall-clock
+    # run above has none; a pipelined collide-stream launch would include its
+    # wait for the IB pass)
+    sim.set_overlap(False)
+    sim.timing(True)
+    sim.step(min(steps, 200))
+    sim.sync()
     lbm_ms, n_lbm = sim.timing_read(0)
     ibm_ms, n_ibm = sim.timing_read(1)
     sim.timing(False)
+    sim.set_overlap(True)
     st = sim.forces(0, check=False)
     out = dict(seconds=t1 - t0, lbm_ms=lbm_ms, n_lbm=n_lbm, ibm_ms=ibm_ms, n_ibm=n_ibm,
+               split=split, near_nodes=near,
                fx=st["fx"], status=st["status"], steps_done=sim.steps_done,
                launch=sim.get_launch())
     sim.close()
@@ -190,7 +200,8 @@ def main():
     r = run_gpu(case, prec, args.steps, args.warmup, graph=args.graph, tune=not args.no_tune)
     mlups = nodes * args.steps / r["seconds"] / 1e6
     lbm_avg_s = r["lbm_ms"] / max(r["n_lbm"], 1) * 1e-3
-    achieved = bpn * nodes / lbm_avg_s / 1e9
+    lbm_nodes = nodes
+    achieved = bpn * lbm_nodes / lbm_avg_s / 1e9
     key = f"{case['name']}-{args.precision}-{args.collision}"
     traffic = measured_traffic(key)
 
@@ -215,9 +226,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "collide_stream_kernel",
-                     "bytes_per_node": bpn,
+                     "bytes_per_node": bpn, "nodes_per_launch": lbm_nodes,
                      "avg_launch_us": round(lbm_avg_s * 1e6, 3),
                      "launch": r["launch"]},
+        "pipelined_steps": {"in_use": r["split"], "nodes_waiting_for_ib": r["near_nodes"]},
         "ib_pass_avg_us": round(r["ibm_ms"] / max(r["n_ibm"], 1) * 1e3, 3),
         "hbm_fraction_of_step": round(bpn * nodes * args.steps / r["seconds"] / 1e9 / HBM_PEAK_GBS, 4),
         "lattice_bytes": 2 * 9 * nodes * (bpn // 18),

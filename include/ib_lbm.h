@@ -216,8 +216,29 @@ ib_lbm_status ib_lbm_set_spread(ib_lbm_sim *s, int32_t mode);
  * replays them; 0 launches kernels directly. */
 ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph);
 
-/* Kernel timing with HIP events on the sim's stream (direct launches only).
- * which: 0 collide-stream, 1 immersed boundary.  Reset with enable. */
+/* Pipelined steps (default on).  For a sim with one body that is fixed or
+ * prescribed, whose supports over the run stay two nodes clear of the faces,
+ * ib_lbm_step runs the collide-stream launches and the IB passes on two
+ * library-owned streams that overlap: the collide-stream of step n+1 starts
+ * while the IB pass of step n is still running, and only its tiles next to
+ * the body (the ones that read what the IB pass writes, or are read by it)
+ * wait for that pass, through device-side counters with a bounded wait
+ * (about 2 s; on expiry the sim halts with IB_LBM_E_STATE from
+ * ib_lbm_forces).  Each ib_lbm_step call first synchronises the sim's
+ * stream, and the sim's stream waits for both streams before the call
+ * returns.  The collide-stream stream leaves one compute unit to the IB
+ * pass.  Results are bitwise the same as unpipelined steps.  Steps replayed
+ * from a graph (ib_lbm_set_graph) are not pipelined.  set_overlap(0/1)
+ * forbids or allows it; get_overlap reports whether the current
+ * configuration uses it (after the first step) and, if near_nodes is not
+ * NULL, the number of nodes in the tiles that wait for the IB pass. */
+ib_lbm_status ib_lbm_set_overlap(ib_lbm_sim *s, int32_t on);
+ib_lbm_status ib_lbm_get_overlap(const ib_lbm_sim *s, int32_t *in_use, int64_t *near_nodes);
+
+/* Kernel timing with HIP events (direct launches only).  which: 0
+ * collide-stream, 1 immersed boundary.  With pipelined steps a collide-stream
+ * launch includes the wait of its tiles next to the body for the previous IB
+ * pass.  Reset with enable. */
 ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on);
 ib_lbm_status ib_lbm_timing_read(ib_lbm_sim *s, int32_t which, double *total_ms, int64_t *launches);
 

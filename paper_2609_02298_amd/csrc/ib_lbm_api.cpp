@@ -35,12 +35,15 @@ struct EventPair {
   hipEvent_t a, b;
 };
 
+// Kernel timing kinds: 0 collide-stream, 1 IB pass.
+constexpr int kTimingKinds = 2;
+
 struct Timing {
   bool on = false;
-  std::vector<EventPair> ev[2];
+  std::vector<EventPair> ev[kTimingKinds];
   std::vector<EventPair> pool;
-  double folded_ms[2] = {0, 0};
-  int64_t folded_n[2] = {0, 0};
+  double folded_ms[kTimingKinds] = {0, 0};
+  int64_t folded_n[kTimingKinds] = {0, 0};
 };
 
 }  // namespace
@@ -67,6 +70,14 @@ struct ib_lbm_sim {
   int64_t host_steps = 0;
   ib_lbm_batch *batch = nullptr;
   int lds_bytes = 0;
+  // Pipelined steps (see plan_split): the tiles of the hold rectangle and
+  // the IB pass run on `iq`, all other tiles on `lq`, ordered by events.
+  bool overlap = true;   // allowed by the caller
+  bool split = false;    // in use for the current tables
+  int32_t hold[4] = {0, 0, 0, 0};
+  hipStream_t lq = nullptr, iq = nullptr;
+  hipEvent_t ev_start = nullptr, ev_lq = nullptr, ev_iq = nullptr, ev_near = nullptr,
+             ev_far = nullptr;
 };
 
 struct ib_lbm_batch {
@@ -238,8 +249,66 @@ ib_lbm_status check_launch(const ib_lbm_launch *l, std::string *err) {
 }
 
 // Device tables of a sim stepped on its own: one case, its IB slots.
+// Decide whether a sim's steps can be pipelined.  The collide-stream of
+// the tiles away from the body (far tiles) does not read what the IB pass
+// writes (its force, or its corrected populations) and is not read by it;
+// only the tiles whose nodes the body's support can occupy, or that push into
+// such nodes (the hold rectangle), are.  So the far tiles of step n run
+// concurrently with the hold tiles and the IB pass of step n.  That needs a
+// single body whose position is known in advance
+// (fixed or prescribed), so that one tile rectangle covers every support of
+// the run widened by two nodes (the pushes and the outlet copy that reach a
+// support node start at most two nodes away), kept two nodes clear of the
+// faces so that no periodic wrap or face rule reaches it from outside.
+ib_lbm_status plan_split(ib_lbm_sim *s) {
+  s->split = false;
+  if (!s->overlap || s->bodies.size() != 1) return IB_LBM_OK;
+  const ib_lbm_body_desc &d = s->bodies[0].d;
+  if (d.motion == IB_LBM_FREE) return IB_LBM_OK;
+  const double ax = d.motion == IB_LBM_PRESCRIBED_SIN ? std::fabs(d.amp[0]) : 0.0;
+  const double ay = d.motion == IB_LBM_PRESCRIBED_SIN ? std::fabs(d.amp[1]) : 0.0;
+  const double r = 0.5 * d.diameter;
+  const int lo = d.kernel == IB_LBM_PESKIN4 ? 1 : 0, hi = d.kernel == IB_LBM_PESKIN4 ? 2 : 1;
+  const double x0 = std::floor(d.xc - ax - r) - lo - 2, y0 = std::floor(d.yc - ay - r) - lo - 2;
+  const double x1 = std::floor(d.xc + ax + r) + hi + 2, y1 = std::floor(d.yc + ay + r) + hi + 2;
+  if (x0 < 2 || y0 < 2 || x1 > s->cd.nx - 3 || y1 > s->cd.ny - 3) return IB_LBM_OK;
+  const int TX = s->launch.block_x, TY = s->launch.block_y * s->launch.rows_per_thread;
+  const int tx0 = (int)x0 / TX, tx1 = (int)x1 / TX, ty0 = (int)y0 / TY, ty1 = (int)y1 / TY;
+  const int nbox = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+  if (nbox >= s->cd.tiles_x * s->cd.tiles_y) return IB_LBM_OK;
+  s->hold[0] = tx0;
+  s->hold[1] = ty0;
+  s->hold[2] = tx1 - tx0 + 1;
+  s->hold[3] = ty1 - ty0 + 1;
+  if (!s->lq) {
+    // The far-tile stream leaves one compute unit per IB workgroup to the
+    // other stream, so that an IB pass never waits for a free unit behind a
+    // full far-tile launch.
+    int dev = 0, ncu = 0;
+    HIPCHK(s, hipGetDevice(&dev));
+    HIPCHK(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+    for (int i = 0; i < ncu - s->nslots; i++) mask[i / 32] |= 1u << (i % 32);
+    if (ncu <= s->nslots ||
+        hipExtStreamCreateWithCUMask(&s->lq, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+      (void)hipGetLastError();
+      s->lq = nullptr;
+      HIPCHK(s, hipStreamCreateWithFlags(&s->lq, hipStreamNonBlocking));
+    }
+  }
+  if (!s->iq) HIPCHK(s, hipStreamCreateWithFlags(&s->iq, hipStreamNonBlocking));
+  if (!s->ev_start) HIPCHK(s, hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming));
+  if (!s->ev_lq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_lq, hipEventDisableTiming));
+  if (!s->ev_iq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_iq, hipEventDisableTiming));
+  if (!s->ev_near) HIPCHK(s, hipEventCreateWithFlags(&s->ev_near, hipEventDisableTiming));
+  if (!s->ev_far) HIPCHK(s, hipEventCreateWithFlags(&s->ev_far, hipEventDisableTiming));
+  s->split = true;
+  return IB_LBM_OK;
+}
+
 ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   if (!s->tables_dirty) return IB_LBM_OK;
+  ib_lbm_status st0;
   std::vector<BodyDesc> bd;
   int maxws = 0;
   for (auto &hb : s->bodies) {
@@ -274,6 +343,7 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   HIPCHK(s, hipMemcpy(s->d_slots.p, slots.data(), slots.size() * sizeof(IbmSlot), hipMemcpyHostToDevice));
   s->nslots = n;
   s->lds_bytes = lds_budget(maxws);
+  if ((st0 = plan_split(s))) return st0;
   s->tables_dirty = false;
   if (s->graph_exec) {
     (void)hipGraphExecDestroy(s->graph_exec);
@@ -294,7 +364,7 @@ EventPair take_pair(Timing &t) {
   return p;
 }
 
-// Enqueue one step of a sim: collide-stream, then the IB pass.
+// Enqueue one step of a sim on `stream`: collide-stream, then the IB pass.
 ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
   const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
@@ -317,6 +387,69 @@ ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
     HIPCHK(s, hipEventRecord(p1.b, stream));
     s->timing.ev[1].push_back(p1);
   }
+  return IB_LBM_OK;
+}
+
+ib_lbm_status read_state(ib_lbm_sim *s, CaseState *cs);
+
+// Enqueue nsteps pipelined steps.  Step n: the hold tiles and then the IB
+// pass on iq, the far tiles on lq.  The far tiles of step n follow the hold
+// tiles of step n-1 (which push into far nodes and whose inputs the far
+// tiles of step n overwrite); the hold tiles of step n follow the far tiles
+// of step n-1 for the same two reasons, and the IB pass of step n-1 by
+// stream order.  Both streams start after the work already on the sim's
+// stream, which then waits for both.
+ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
+  CaseState cs;
+  ib_lbm_status st = read_state(s, &cs);
+  if (st) return st;
+  if (cs.flags & kCaseHalted) return IB_LBM_OK;  // nothing would run
+  LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
+  const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
+  HIPCHK(s, hipEventRecord(s->ev_start, s->stream));
+  HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_start, 0));
+  HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_start, 0));
+  PipeArgs pa{};
+  pa.htx0 = s->hold[0];
+  pa.hty0 = s->hold[1];
+  pa.hntx = s->hold[2];
+  pa.hnty = s->hold[3];
+  const CaseDesc *dc = (const CaseDesc *)s->d_case.p;
+  for (int64_t i = 0; i < nsteps; i++) {
+    pa.cur = cs.cur ^ (int)(i & 1);
+    EventPair p0{}, p1{};
+    // far tiles of step i after the hold tiles of step i-1
+    if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_near, 0));
+    if (timed) {
+      p0 = take_pair(s->timing);
+      HIPCHK(s, hipEventRecord(p0.a, s->lq));
+    }
+    HIPCHK(s, launch_collide_stream_pipe(s->cd.precision, s->cd.collision, dc, ntiles, sh, pa, 0, s->lq));
+    if (timed) {
+      HIPCHK(s, hipEventRecord(p0.b, s->lq));
+      s->timing.ev[0].push_back(p0);
+    }
+    // hold tiles of step i after the far tiles of step i-1 (the wait is
+    // enqueued before ev_far is recorded again for step i)
+    if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_far, 0));
+    HIPCHK(s, hipEventRecord(s->ev_far, s->lq));
+    HIPCHK(s, launch_collide_stream_pipe(s->cd.precision, s->cd.collision, dc, ntiles, sh, pa, 1, s->iq));
+    HIPCHK(s, hipEventRecord(s->ev_near, s->iq));
+    if (timed) {
+      p1 = take_pair(s->timing);
+      HIPCHK(s, hipEventRecord(p1.a, s->iq));
+    }
+    HIPCHK(s, launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, s->nslots, s->lds_bytes,
+                         s->spread_mode, s->iq));
+    if (timed) {
+      HIPCHK(s, hipEventRecord(p1.b, s->iq));
+      s->timing.ev[1].push_back(p1);
+    }
+  }
+  HIPCHK(s, hipEventRecord(s->ev_lq, s->lq));
+  HIPCHK(s, hipEventRecord(s->ev_iq, s->iq));
+  HIPCHK(s, hipStreamWaitEvent(s->stream, s->ev_lq, 0));
+  HIPCHK(s, hipStreamWaitEvent(s->stream, s->ev_iq, 0));
   return IB_LBM_OK;
 }
 
@@ -625,8 +758,12 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
       left -= s->graph_len;
     }
   }
-  for (int64_t i = 0; i < left; i++)
-    if ((st = enqueue_sim_step(s, s->timing.on, s->stream))) return st;
+  if (s->split && left > 0) {
+    if ((st = enqueue_pipelined(s, left, s->timing.on))) return st;
+  } else {
+    for (int64_t i = 0; i < left; i++)
+      if ((st = enqueue_sim_step(s, s->timing.on, s->stream))) return st;
+  }
   s->host_steps += nsteps;
   return IB_LBM_OK;
 }
@@ -788,7 +925,9 @@ ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s) {
   if (s->batch) ib_lbm_batch_detach(s->batch, s);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
-  for (int k = 0; k < 2; k++)
+  if (s->lq) (void)hipStreamSynchronize(s->lq);
+  if (s->iq) (void)hipStreamSynchronize(s->iq);
+  for (int k = 0; k < kTimingKinds; k++)
     for (auto &p : s->timing.ev[k]) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto &p : s->timing.pool) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto &hb : s->bodies) {
@@ -800,6 +939,13 @@ ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s) {
   dev_free(s, &s->d_bodies); dev_free(s, &s->d_case); dev_free(s, &s->d_prefix);
   dev_free(s, &s->d_slots); dev_free(s, &s->d_tmp);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->lq) (void)hipStreamDestroy(s->lq);
+  if (s->iq) (void)hipStreamDestroy(s->iq);
+  if (s->ev_start) (void)hipEventDestroy(s->ev_start);
+  if (s->ev_lq) (void)hipEventDestroy(s->ev_lq);
+  if (s->ev_iq) (void)hipEventDestroy(s->ev_iq);
+  if (s->ev_near) (void)hipEventDestroy(s->ev_near);
+  if (s->ev_far) (void)hipEventDestroy(s->ev_far);
   delete s;
   return IB_LBM_OK;
 }
@@ -830,6 +976,33 @@ ib_lbm_status ib_lbm_set_spread(ib_lbm_sim *s, int32_t mode) {
   return IB_LBM_OK;
 }
 
+ib_lbm_status ib_lbm_set_overlap(ib_lbm_sim *s, int32_t on) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (on != 0 && on != 1) return IB_LBM_E_INVALID;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->overlap = on != 0;
+  s->tables_dirty = true;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_get_overlap(const ib_lbm_sim *s, int32_t *in_use, int64_t *near_nodes) {
+  if (!s || !in_use) return IB_LBM_E_INVALID;
+  *in_use = s->split ? 1 : 0;
+  if (near_nodes) {
+    int64_t n = 0;
+    if (s->split) {
+      const int TX = s->launch.block_x, TY = s->launch.block_y * s->launch.rows_per_thread;
+      const int64_t x0 = (int64_t)s->hold[0] * TX, y0 = (int64_t)s->hold[1] * TY;
+      const int64_t x1 = std::min<int64_t>(x0 + (int64_t)s->hold[2] * TX, s->cd.nx);
+      const int64_t y1 = std::min<int64_t>(y0 + (int64_t)s->hold[3] * TY, s->cd.ny);
+      n = (x1 - x0) * (y1 - y0);
+    }
+    *near_nodes = n;
+  }
+  return IB_LBM_OK;
+}
+
 ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph) {
   ib_lbm_status st = usable(s);
   if (st) return st;
@@ -842,7 +1015,7 @@ ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on) {
   ib_lbm_status st = usable(s);
   if (st) return st;
   HIPCHK(s, hipStreamSynchronize(s->stream));
-  for (int k = 0; k < 2; k++) {
+  for (int k = 0; k < kTimingKinds; k++) {
     for (auto &p : s->timing.ev[k]) s->timing.pool.push_back(p);
     s->timing.ev[k].clear();
     s->timing.folded_ms[k] = 0;
@@ -855,7 +1028,7 @@ ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on) {
 ib_lbm_status ib_lbm_timing_read(ib_lbm_sim *s, int32_t which, double *total_ms, int64_t *launches) {
   ib_lbm_status st = usable(s);
   if (st) return st;
-  if (which < 0 || which > 1 || !total_ms || !launches) return IB_LBM_E_INVALID;
+  if (which < 0 || which >= kTimingKinds || !total_ms || !launches) return IB_LBM_E_INVALID;
   HIPCHK(s, hipStreamSynchronize(s->stream));
   double ms = s->timing.folded_ms[which];
   for (auto &p : s->timing.ev[which]) {

@@ -110,9 +110,10 @@ struct CaseDesc {
 //            off (mr+1), nxy (mn), noff (mn+1), nent (nb*ns*ns), S (1)
 //            [padded to even]
 //   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each)
-//   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), nux nuy (mn each),
-//                     then the staged populations (9 mn of T) overlaid by the
-//                     W_total node array while the correction scale is built
+//   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), then the staged
+//                     populations (9 mn of T), overlaid by the W_total node
+//                     array while the correction scale is built and, at the
+//                     end, by the node velocities of the corrected populations
 __host__ __device__ inline int ws_table_doubles(int nb, int ns) { return nb * (4 + 2 * ns); }
 __host__ __device__ inline int ws_table_ints(int nb, int ns, int mr, int mn) {
   const int n = nb * (2 + 2 * ns * ns) + 4 * mr + 1 + 2 * mn + 1 + 1;
@@ -139,10 +140,22 @@ struct LaunchShape {
   int32_t block_x, block_y, rows_per_thread, xcd_remap;
 };
 
+// Arguments of one pipelined step of a single case: cur, the lattice
+// holding the step's input; the hold rectangle of tiles (htx0, hty0, hntx,
+// hnty).
+struct PipeArgs {
+  int32_t cur;
+  int32_t htx0, hty0, hntx, hnty;
+};
+
 // ---- kernel launchers (defined in the .hip files) ----
 hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
                                  const int32_t *tile_prefix, int ncases, int ntiles,
                                  LaunchShape shape, hipStream_t stream);
+// One part of a pipelined step: near = 1 the hold rectangle, 0 the other tiles.
+hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
+                                      LaunchShape shape, const PipeArgs &pa, int near,
+                                      hipStream_t stream);
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, hipStream_t stream);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);

@@ -59,6 +59,28 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 // Reduces four values at once: three sums and one max; result valid in all threads.
+// Sums a, b, c, d and maxima m1, m2 over the workgroup, each in the same
+// fixed order (wave sums, then the waves in index order).
+__device__ __forceinline__ void block_reduce6(double &a, double &b, double &c, double &d, double &m1,
+                                              double &m2, double *red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d);
+  m1 = wave_max(m1); m2 = wave_max(m2);
+  __syncthreads();
+  if (lane == 0) {
+    red[6 * wv] = a; red[6 * wv + 1] = b; red[6 * wv + 2] = c; red[6 * wv + 3] = d;
+    red[6 * wv + 4] = m1; red[6 * wv + 5] = m2;
+  }
+  __syncthreads();
+  double sa = 0, sb = 0, sc = 0, sd = 0, x1 = -1e300, x2 = -1e300;
+  for (int w = 0; w < nw; w++) {
+    sa += red[6 * w]; sb += red[6 * w + 1]; sc += red[6 * w + 2]; sd += red[6 * w + 3];
+    x1 = fmax(x1, red[6 * w + 4]); x2 = fmax(x2, red[6 * w + 5]);
+  }
+  a = sa; b = sb; c = sc; d = sd; m1 = x1; m2 = x2;
+  __syncthreads();
+}
+
 __device__ __forceinline__ void block_reduce4(double &a, double &b, double &c, double &m, double *red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); m = wave_max(m);
@@ -105,7 +127,11 @@ __device__ __forceinline__ void block_scan(const int *cnt, int *off, int n, int 
   __syncthreads();
 }
 
+// Per-marker tables are stored marker-fastest (entry q of marker k at
+// q * nb + k), so that the 64 lanes of a wave, which handle 64 consecutive
+// markers, read consecutive LDS words and hit distinct banks.
 struct WsLayout {
+  int nb;
   double *X, *Y, *Udx, *Udy, *wx, *wy;                           // table doubles
   int *ix0, *iy0, *nidx, *ra1, *rl1, *ra2, *off, *nxy, *noff, *nent, *S;  // table ints
   double *rhoX, *Fx, *Fy, *Ftx, *Fty, *lam, *dlt;                // per-step, markers
@@ -117,6 +143,7 @@ struct WsLayout {
 __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   const int nb = B.nb, ns = B.ns, mr = B.max_rows, mn = B.max_nodes;
   WsLayout L;
+  L.nb = nb;
   double *p = base;
   L.X = p; p += nb; L.Y = p; p += nb; L.Udx = p; p += nb; L.Udy = p; p += nb;
   L.wx = p; p += nb * ns; L.wy = p; p += nb * ns;
@@ -125,15 +152,17 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   L.ra1 = q; q += mr; L.rl1 = q; q += mr; L.ra2 = q; q += mr; L.off = q; q += mr + 1;
   L.nxy = q; q += mn; L.noff = q; q += mn + 1; L.nent = q; q += nb * ns * ns; L.S = q;
   double *d = base + ws_tab_total(nb, ns, mr, mn);
-  L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = nullptr;
-  L.stage = nullptr;
+  // arrays a scheme does not use alias the start of the per-step area (never
+  // null, so that every pointer provably stays in the workspace's address
+  // space and the LDS instantiation uses LDS instructions)
+  L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = L.nux = L.nuy = d;
+  L.stage = (void *)d;
   if (B.scheme != kDFC) {
     L.rhoX = d; d += nb; L.Fx = d; d += nb; L.Fy = d; d += nb; L.Ftx = d; d += nb; L.Fty = d; d += nb;
     L.nrho = d; d += mn;
     L.nux = d; d += mn; L.nuy = d; d += mn;
   } else {
     L.Ftx = d; d += nb; L.Fty = d; d += nb; L.lam = d; d += nb; L.dlt = d; d += 9 * nb;
-    L.nux = L.nuy = nullptr;
     L.stage = (void *)d;  // 9 x mn populations of the stored type
     L.nW = d;             // overlays the staging area before it is filled
   }
@@ -144,32 +173,55 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   return L;
 }
 
-// Velocity of the staged (corrected) populations at the support nodes of
-// marker k, interpolated like interp2; `shift` restores w_i rho0.
+__device__ __forceinline__ int &NIDX(const WsLayout &L, int k, int q) { return L.nidx[q * L.nb + k]; }
+__device__ __forceinline__ double &WX(const WsLayout &L, int k, int j) { return L.wx[j * L.nb + k]; }
+__device__ __forceinline__ double &WY(const WsLayout &L, int k, int j) { return L.wy[j * L.nb + k]; }
+__device__ __forceinline__ double &DLT(const WsLayout &L, int k, int i) { return L.dlt[i * L.nb + k]; }
+
+// Node velocities of the DFC pass, kept in the population staging area:
+// node j's (ux, uy) as two doubles in slot j of the first planes (the bits of
+// each double split over two planes of floats for the FP32 store), so that
+// a thread writing node j only overwrites values of node j.
+__device__ __forceinline__ void put_u(float *stg, int mn, int j, double ux, double uy) {
+  uint32_t *w = (uint32_t *)stg;
+  const uint64_t bx = (uint64_t)__double_as_longlong(ux), by = (uint64_t)__double_as_longlong(uy);
+  w[j] = (uint32_t)bx;
+  w[mn + j] = (uint32_t)(bx >> 32);
+  w[2 * mn + j] = (uint32_t)by;
+  w[3 * mn + j] = (uint32_t)(by >> 32);
+}
+__device__ __forceinline__ void put_u(double *stg, int mn, int j, double ux, double uy) {
+  stg[j] = ux;
+  stg[mn + j] = uy;
+}
+__device__ __forceinline__ void get_u(const float *stg, int mn, int j, double &ux, double &uy) {
+  const uint32_t *w = (const uint32_t *)stg;
+  ux = __longlong_as_double((long long)(((uint64_t)w[mn + j] << 32) | w[j]));
+  uy = __longlong_as_double((long long)(((uint64_t)w[3 * mn + j] << 32) | w[2 * mn + j]));
+}
+__device__ __forceinline__ void get_u(const double *stg, int mn, int j, double &ux, double &uy) {
+  ux = stg[j];
+  uy = stg[mn + j];
+}
+
+// interp2 of the packed node velocities.
 template <int NS, typename T>
-__device__ __forceinline__ void interp_stage_velocity(const WsLayout &L, int k, const T *stg, int mn,
-                                                      double shift, double &oa, double &ob) {
+__device__ __forceinline__ void interp_packed_u(const WsLayout &L, int k, const T *stg, int mn,
+                                                double &oa, double &ob) {
   double a = 0.0, b = 0.0;
 #pragma unroll
   for (int jy = 0; jy < NS; jy++) {
     double ra = 0.0, rb = 0.0;
 #pragma unroll
     for (int jx = 0; jx < NS; jx++) {
-      const int j = L.nidx[(k * NS + jy) * NS + jx];
-      double sm = 0, jxs = 0, jys = 0;
-#pragma unroll
-      for (int i = 0; i < 9; i++) {
-        const double v = (double)stg[i * mn + j] + c_w[i] * shift;
-        sm += v;
-        jxs += v * c_exi[i];
-        jys += v * c_eyi[i];
-      }
-      const double w = L.wx[k * NS + jx];
-      ra += jxs / sm * w;
-      rb += jys / sm * w;
+      double ux, uy;
+      get_u(stg, mn, NIDX(L, k, jy * NS + jx), ux, uy);
+      const double w = WX(L, k, jx);
+      ra += ux * w;
+      rb += uy * w;
     }
-    a += ra * L.wy[k * NS + jy];
-    b += rb * L.wy[k * NS + jy];
+    a += ra * WY(L, k, jy);
+    b += rb * WY(L, k, jy);
   }
   oa = a;
   ob = b;
@@ -180,20 +232,37 @@ __device__ __forceinline__ void interp_stage_velocity(const WsLayout &L, int k, 
 template <int NS>
 __device__ __forceinline__ double node_weight(const WsLayout &L, int kq) {
   const int k = kq >> 4, q = kq & 15;
-  return L.wx[k * NS + (q % NS)] * L.wy[k * NS + (q / NS)];
+  return WX(L, k, q % NS) * WY(L, k, q / NS);
+}
+
+// Calls f(k, w) for the markers k covering node j, in increasing marker
+// order.  The first U entries are loaded together (a node is covered by at
+// most U markers at unit marker spacing); entries past the node's count
+// repeat its last entry with weight 0, which leaves every sum unchanged.
+// Entries beyond U, at denser marker spacings, follow one by one.
+template <int NS, typename F>
+__device__ __forceinline__ void for_node_entries(const WsLayout &L, int j, F &&f) {
+  constexpr int U = NS == 4 ? 6 : 3;
+  const int e0 = L.noff[j], e1 = L.noff[j + 1];
+  int kq[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) kq[u] = L.nent[min(e0 + u, e1 - 1)];
+#pragma unroll
+  for (int u = 0; u < U; u++) f(kq[u] >> 4, e0 + u < e1 ? node_weight<NS>(L, kq[u]) : 0.0);
+  for (int e = e0 + U; e < e1; e++) {
+    const int q = L.nent[e];
+    f(q >> 4, node_weight<NS>(L, q));
+  }
 }
 
 template <int NS>
 __device__ __forceinline__ void gather2(const WsLayout &L, int j, const double *va,
                                         const double *vb, double &oa, double &ob) {
   double a = 0.0, b = 0.0;
-  const int e1 = L.noff[j + 1];
-  for (int e = L.noff[j]; e < e1; e++) {
-    const int kq = L.nent[e], k = kq >> 4;
-    const double w = node_weight<NS>(L, kq);
+  for_node_entries<NS>(L, j, [&](int k, double w) {
     a += va[k] * w;
     b += vb[k] * w;
-  }
+  });
   oa = a;
   ob = b;
 }
@@ -206,8 +275,8 @@ __device__ __forceinline__ double interp1(const WsLayout &L, int k, const double
   for (int jy = 0; jy < NS; jy++) {
     double row = 0.0;
 #pragma unroll
-    for (int jx = 0; jx < NS; jx++) row += nv[L.nidx[(k * NS + jy) * NS + jx]] * L.wx[k * NS + jx];
-    acc += row * L.wy[k * NS + jy];
+    for (int jx = 0; jx < NS; jx++) row += nv[NIDX(L, k, jy * NS + jx)] * WX(L, k, jx);
+    acc += row * WY(L, k, jy);
   }
   return acc;
 }
@@ -221,13 +290,13 @@ __device__ __forceinline__ void interp2(const WsLayout &L, int k, const double *
     double ra = 0.0, rb = 0.0;
 #pragma unroll
     for (int jx = 0; jx < NS; jx++) {
-      const int j = L.nidx[(k * NS + jy) * NS + jx];
-      const double w = L.wx[k * NS + jx];
+      const int j = NIDX(L, k, jy * NS + jx);
+      const double w = WX(L, k, jx);
       ra += na[j] * w;
       rb += nb_[j] * w;
     }
-    a += ra * L.wy[k * NS + jy];
-    b += rb * L.wy[k * NS + jy];
+    a += ra * WY(L, k, jy);
+    b += rb * WY(L, k, jy);
   }
   oa = a;
   ob = b;
@@ -256,8 +325,8 @@ __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B
     L.iy0[k] = iy0;
     if (ix0 < 0 || iy0 < 0 || ix0 + ns - 1 > nx - 1 || iy0 + ns - 1 > ny - 1) atomicOr(&ish[0], kFlagRange);
     for (int j = 0; j < ns; j++) {
-      L.wx[k * ns + j] = delta1(B.kernel, (double)(ix0 + j) - X);
-      L.wy[k * ns + j] = delta1(B.kernel, (double)(iy0 + j) - Y);
+      WX(L, k, j) = delta1(B.kernel, (double)(ix0 + j) - X);
+      WY(L, k, j) = delta1(B.kernel, (double)(iy0 + j) - Y);
     }
     const bool left = X < xc;
     for (int j = 0; j < ns; j++) {
@@ -310,7 +379,7 @@ __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B
         const int x = L.ix0[k] + jx;
         const int loc = (x >= L.ra1[r] && x < L.ra1[r] + L.rl1[r]) ? x - L.ra1[r]
                                                                   : L.rl1[r] + x - L.ra2[r];
-        L.nidx[(k * ns + jy) * ns + jx] = L.off[r] + loc;
+        NIDX(L, k, jy * ns + jx) = L.off[r] + loc;
       }
     }
   }
@@ -324,7 +393,7 @@ __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B
   for (int j = tid; j < S; j += nth) L.nfill[j] = L.noff[j];
   __syncthreads();
   for (int e = tid; e < nb * nq; e += nth) {
-    const int k = e / nq, q = e - k * nq;
+    const int q = e / nb, k = e - q * nb;  // e = q * nb + k
     const int pos = atomicAdd(&L.nfill[L.nidx[e]], 1);
     L.nent[pos] = (k << 4) | q;
   }
@@ -407,9 +476,14 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     bs->xc = xc; bs->yc = yc;
     bs->vhx = vhx; bs->vhy = vhy; bs->omh = omh;
     bsh[0] = xc; bsh[1] = yc; bsh[2] = vhx; bsh[3] = vhy; bsh[4] = omh;
+    // state the final update needs, kept on chip so that it is not read
+    // back from device memory at the end of the pass
+    bsh[5] = B.motion == kFree ? bs->dimx : 0.0;
+    bsh[6] = B.motion == kFree ? bs->dimy : 0.0;
     ish[0] = 0;
     ish[1] = bs->tables_valid;
     ish[2] = bs->lambda_valid;
+    ish[3] = bs->flags;
   }
   __syncthreads();
   const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
@@ -428,7 +502,13 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   } else {
     S = build_tables(c, B, L, xc, yc, vhx, vhy, omh, ylo, ish, ish + 16);
     if (S < 0) {
-      if (tid == 0) { bs->flags |= ish[0]; bs->box_valid = 0; }
+      if (tid == 0) {
+        const int f = ish[3] | ish[0];
+        bs->flags = f;
+        bs->box_valid = 0;
+        ish[50] = f;
+        ish[51] = 0;
+      }
       return;
     }
     if (fixed) {
@@ -497,6 +577,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         L.Ftx[k] = 0.0;
         L.Fty[k] = 0.0;
       }
+      __syncthreads();
+      // from here on nrho holds ds / (2 rho(x)), the factor of every pass
+      for (int j = tid; j < S; j += nth) L.nrho[j] = ds / (2.0 * L.nrho[j]);
       for (int n = 1; n <= N; n++) {
         for (int k = tid; k < nb; k += nth) {
           double Ux, Uy;
@@ -514,24 +597,22 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
           for (int j = tid; j < S; j += nth) {
             double sx, sy;
             gather2<NS>(L, j, L.Fx, L.Fy, sx, sy);
-            const double h = 1.0 / (2.0 * L.nrho[j]);
-            L.nux[j] += sx * ds * h;
-            L.nuy[j] += sy * ds * h;
+            L.nux[j] += sx * L.nrho[j];
+            L.nuy[j] += sy * L.nrho[j];
           }
         } else {
           for (int j = tid; j < S; j += nth) { accx[j] = 0.0; accy[j] = 0.0; }
           __syncthreads();
           for (int k = tid; k < nb; k += nth)
             for (int q = 0; q < ns * ns; q++) {
-              const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
-              atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.Fx[k] * w);
-              atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.Fy[k] * w);
+              const double w = WX(L, k, q % ns) * WY(L, k, q / ns);
+              atomicAdd(&accx[NIDX(L, k, q)], L.Fx[k] * w);
+              atomicAdd(&accy[NIDX(L, k, q)], L.Fy[k] * w);
             }
           __syncthreads();
           for (int j = tid; j < S; j += nth) {
-            const double h = 1.0 / (2.0 * L.nrho[j]);
-            L.nux[j] += accx[j] * ds * h;
-            L.nuy[j] += accy[j] * ds * h;
+            L.nux[j] += accx[j] * L.nrho[j];
+            L.nuy[j] += accy[j] * L.nrho[j];
           }
         }
         __syncthreads();
@@ -559,9 +640,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       __syncthreads();
       for (int k = tid; k < nb; k += nth)
         for (int q = 0; q < ns * ns; q++) {
-          const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
-          atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.Ftx[k] * w);
-          atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.Fty[k] * w);
+          const double w = WX(L, k, q % ns) * WY(L, k, q / ns);
+          atomicAdd(&accx[NIDX(L, k, q)], L.Ftx[k] * w);
+          atomicAdd(&accy[NIDX(L, k, q)], L.Fty[k] * w);
         }
       __syncthreads();
       for (int j = tid; j < S; j += nth) {
@@ -580,7 +661,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     // torque -sum_k r_k x F_total ds (Sec. 2.7)
     for (int k = tid; k < nb; k += nth) {
       double wsx = 0, wsy = 0;
-      for (int j = 0; j < ns; j++) { wsx += L.wx[k * ns + j]; wsy += L.wy[k * ns + j]; }
+      for (int j = 0; j < ns; j++) { wsx += WX(L, k, j); wsy += WY(L, k, j); }
       const double wsum = wsx * wsy;
       fsum_x -= L.Ftx[k] * ds * wsum;
       fsum_y -= L.Fty[k] * ds * wsum;
@@ -644,12 +725,12 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         for (int i = 0; i < 9; i++) row[i] = 0.0;
 #pragma unroll
         for (int jx = 0; jx < NS; jx++) {
-          const int j = L.nidx[(k * NS + jy) * NS + jx];
-          const double w = L.wx[k * NS + jx];
+          const int j = NIDX(L, k, jy * NS + jx);
+          const double w = WX(L, k, jx);
 #pragma unroll
           for (int i = 0; i < 9; i++) row[i] += (double)stg[i * mn + j] * w;
         }
-        const double wy = L.wy[k * NS + jy];
+        const double wy = WY(L, k, jy);
 #pragma unroll
         for (int i = 0; i < 9; i++) gi[i] += row[i] * wy;
       }
@@ -659,7 +740,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       for (int i = 0; i < 9; i++) {
         const double eud = c_exi[i] * L.Udx[k] + c_eyi[i] * L.Udy[k];
         const double d = lam * (gi[opp_of(i)] - gi[i] + 6.0 * c_w[i] * rho0 * eud);
-        L.dlt[9 * k + i] = d;
+        DLT(L, k, i) = d;
         fsx += c_exi[i] * d;
         fsy += c_eyi[i] * d;
       }
@@ -676,12 +757,10 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         double corr[9];
 #pragma unroll
         for (int i = 0; i < 9; i++) corr[i] = 0.0;
-        for (int e = L.noff[j]; e < L.noff[j + 1]; e++) {
-          const int kq = L.nent[e], k = kq >> 4;
-          const double w = node_weight<NS>(L, kq);
+        for_node_entries<NS>(L, j, [&](int k, double w) {
 #pragma unroll
-          for (int i = 0; i < 9; i++) corr[i] += L.dlt[9 * k + i] * w;
-        }
+          for (int i = 0; i < 9; i++) corr[i] += DLT(L, k, i) * w;
+        });
         const uint32_t p = (uint32_t)y * nx + x;
 #pragma unroll
         for (int i = 0; i < 9; i++) {
@@ -697,9 +776,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         __syncthreads();
         for (int k = tid; k < nb; k += nth)
           for (int q = 0; q < ns * ns; q++) {
-            const double w = L.wx[k * ns + (q % ns)] * L.wy[k * ns + (q / ns)];
-            atomicAdd(&accx[L.nidx[k * ns * ns + q]], L.dlt[9 * k + i0] * w);
-            if (i0 + 1 < 9) atomicAdd(&accy[L.nidx[k * ns * ns + q]], L.dlt[9 * k + i0 + 1] * w);
+            const double w = WX(L, k, q % ns) * WY(L, k, q / ns);
+            atomicAdd(&accx[NIDX(L, k, q)], DLT(L, k, i0) * w);
+            if (i0 + 1 < 9) atomicAdd(&accy[NIDX(L, k, q)], DLT(L, k, i0 + 1) * w);
           }
         __syncthreads();
         for (int j = tid; j < S; j += nth) {
@@ -717,6 +796,19 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         __syncthreads();
       }
     }
+    __syncthreads();
+    // velocity of the corrected populations at every support node
+    for (int j = tid; j < S; j += nth) {
+      double sm = 0, jxs = 0, jys = 0;
+#pragma unroll
+      for (int i = 0; i < 9; i++) {
+        const double v = (double)stg[i * mn + j] + (shift ? c_w[i] * rho0 : 0.0);
+        sm += v;
+        jxs += v * c_exi[i];
+        jys += v * c_eyi[i];
+      }
+      put_u(stg, mn, j, jxs / sm, jys / sm);
+    }
     for (int k = tid; k < nb; k += nth) {
       fsum_x += L.Ftx[k];
       fsum_y += L.Fty[k];
@@ -729,7 +821,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   for (int k = tid; k < nb; k += nth) {
     double Ux, Uy;
     if (B.scheme == kDFC)
-      interp_stage_velocity<NS, T>(L, k, (const T *)L.stage, B.max_nodes, shift ? rho0 : 0.0, Ux, Uy);
+      interp_packed_u<NS, T>(L, k, (const T *)L.stage, B.max_nodes, Ux, Uy);
     else
       interp2<NS>(L, k, L.nux, L.nuy, Ux, Uy);
     const double e = sqrt((Ux - L.Udx[k]) * (Ux - L.Udx[k]) + (Uy - L.Udy[k]) * (Uy - L.Udy[k]));
@@ -740,45 +832,58 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     mo[4] = L.Ftx[k]; mo[5] = L.Fty[k]; mo[6] = B.scheme == kDFC ? L.lam[k] : 0.0; mo[7] = ds;
   }
   double a = fsum_x, b = fsum_y, cq = tq, m = fmax(resmax, 0.0);
-  block_reduce4(a, b, cq, m, red);
-  double s1 = slip_sum, s2 = 0, s3 = 0, s4 = slip_max;
-  block_reduce4(s1, s2, s3, s4, red);
+  double s1 = slip_sum, s4 = slip_max;
+  block_reduce6(a, b, cq, s1, m, s4, red);
   if (tid == 0) {
+    // every value is formed in registers and written once (no read-back of
+    // device memory on this serial tail)
     int flags = 0;
     if (!isfinite(a) || !isfinite(b) || !isfinite(cq) || !isfinite(s1)) flags |= kFlagNonfinite;
+    const double slip_mean = s1 / nb;
+    const double mdf_res = B.scheme == kMDF ? m : 0.0;
+    const int iters = B.scheme == kDFC ? 0 : (B.scheme == kDF ? 1 : B.mdf_iters);
+    int box[4] = {0, 0, -1, -1};
+    const int box_valid = B.scheme == kDFC ? 0 : 1;
+    if (box_valid) {
+      box[0] = max(0, (int)floor(xc - B.radius) - ns);
+      box[1] = max(0, (int)floor(yc - B.radius) - ns);
+      box[2] = min(nx - 1, (int)floor(xc + B.radius) + ns + 1);
+      box[3] = min(c.ny - 1, (int)floor(yc + B.radius) + ns + 1);
+    }
+    double vx = vhx, vy = vhy, om = omh;
+    if (B.motion == kFree) {
+      const double fgx = (B.ms - B.mf) * c.grav_x, fgy = (B.ms - B.mf) * c.grav_y;
+      vx = vhx + (a + fgx + bsh[5]) / (2.0 * B.ms);
+      vy = vhy + (b + fgy + bsh[6]) / (2.0 * B.ms);
+      om = omh + cq / (2.0 * B.Is);
+      if (!isfinite(vx) || !isfinite(vy) || fabs(vx) > 0.5 || fabs(vy) > 0.5) flags |= kFlagNonfinite;
+    } else if (B.motion == kFixed) {
+      vx = 0.0; vy = 0.0; om = 0.0;
+    }
+    flags |= ish[3];
     bs->fhx = a;
     bs->fhy = b;
     bs->torque = cq;
-    bs->slip_mean = s1 / nb;
+    bs->slip_mean = slip_mean;
     bs->slip_max = s4;
-    bs->mdf_res = B.scheme == kMDF ? m : 0.0;
-    bs->mdf_iters_done = B.scheme == kDFC ? 0 : (B.scheme == kDF ? 1 : B.mdf_iters);
-    if (B.scheme == kDFC) {
-      bs->box_valid = 0;
-    } else {
-      bs->box[0] = max(0, (int)floor(xc - B.radius) - ns);
-      bs->box[1] = max(0, (int)floor(yc - B.radius) - ns);
-      bs->box[2] = min(nx - 1, (int)floor(xc + B.radius) + ns + 1);
-      bs->box[3] = min(c.ny - 1, (int)floor(yc + B.radius) + ns + 1);
-      bs->box_valid = 1;
+    bs->mdf_res = mdf_res;
+    bs->mdf_iters_done = iters;
+    bs->box[0] = box[0]; bs->box[1] = box[1]; bs->box[2] = box[2]; bs->box[3] = box[3];
+    bs->box_valid = box_valid;
+    if (B.motion != kPrescribedSin) {
+      bs->vx = vx; bs->vy = vy; bs->om = om;
     }
-    if (B.motion == kFree) {
-      const double fgx = (B.ms - B.mf) * c.grav_x, fgy = (B.ms - B.mf) * c.grav_y;
-      bs->vx = vhx + (a + fgx + bs->dimx) / (2.0 * B.ms);
-      bs->vy = vhy + (b + fgy + bs->dimy) / (2.0 * B.ms);
-      bs->om = omh + cq / (2.0 * B.Is);
-      if (!isfinite(bs->vx) || !isfinite(bs->vy) || fabs(bs->vx) > 0.5 || fabs(bs->vy) > 0.5)
-        flags |= kFlagNonfinite;
-    } else if (B.motion == kFixed) {
-      bs->vx = 0.0; bs->vy = 0.0; bs->om = 0.0;
-    }
-    bs->flags |= flags;
+    bs->flags = flags;
     const int64_t row = step % B.hist_cap;
     double *h = B.history + row * kHistCols;
     h[0] = (double)(step + 1); h[1] = a; h[2] = b; h[3] = cq;
-    h[4] = xc; h[5] = yc; h[6] = bs->vx; h[7] = bs->vy; h[8] = B.motion == kFree ? bs->om : omh;
-    h[9] = bs->slip_mean; h[10] = s4; h[11] = bs->mdf_res;
-    h[12] = bs->mdf_iters_done; h[13] = bs->flags; h[14] = 0; h[15] = 0;
+    h[4] = xc; h[5] = yc; h[6] = vx; h[7] = vy; h[8] = B.motion == kFree ? om : omh;
+    h[9] = slip_mean; h[10] = s4; h[11] = mdf_res;
+    h[12] = iters; h[13] = flags; h[14] = 0; h[15] = 0;
+    // for the case-level update of a single-body case
+    ish[50] = flags;
+    ish[51] = box_valid;
+    ish[52] = box[0]; ish[53] = box[1]; ish[54] = box[2]; ish[55] = box[3];
   }
 }
 
@@ -787,15 +892,19 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
                                                           const IbmSlot *__restrict__ slots,
                                                           int lds_doubles, int spread_mode) {
   extern __shared__ double dyn[];
-  __shared__ double red[4 * (kIbmThreads / 64)];
-  __shared__ int ish[16 + 40];
+  __shared__ double red[6 * (kIbmThreads / 64)];
+  // ish: [0..15] flags and switches, [16..48] scan scratch, [50..55] the
+  // body's final flags, force-box flag and force box
+  __shared__ int ish[56];
   __shared__ double bsh[16];
   const IbmSlot sl = slots[blockIdx.x];
   const CaseDesc &c = cases[sl.cas];
   CaseState *cs = c.state;
   const int64_t step = cs->step;
+  const int cur = cs->cur;
   const bool active = step < cs->target && !(cs->flags & kCaseHalted);
   if (!active) return;
+  if (threadIdx.x == 0) ish[50] = 0;
   if (sl.body >= 0) {
     const BodyDesc &B = c.bodies[sl.body];
     const bool lds = lds_doubles >= B.ws_doubles;
@@ -810,21 +919,21 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
   __syncthreads();
   if (threadIdx.x != 0) return;
   if (sl.slots_in_case == 1) {
-    // the only workgroup of its case: no other body to wait for
-    const BodyState *st = sl.body >= 0 ? c.bodies[sl.body].state : nullptr;
-    if (st && st->flags) {
+    // the only workgroup of its case: no other body to wait for; the body's
+    // flags and force box come from the workgroup's shared memory
+    if (sl.body >= 0 && ish[50]) {
       cs->flags |= kCaseHalted;
-      return;
-    }
-    if (st && st->box_valid) {
-      cs->fbox[0] = st->box[0]; cs->fbox[1] = st->box[1];
-      cs->fbox[2] = st->box[2]; cs->fbox[3] = st->box[3];
-      cs->fbox_valid = 1;
     } else {
-      cs->fbox_valid = 0;
+      if (sl.body >= 0 && ish[51]) {
+        cs->fbox[0] = ish[52]; cs->fbox[1] = ish[53];
+        cs->fbox[2] = ish[54]; cs->fbox[3] = ish[55];
+        cs->fbox_valid = 1;
+      } else {
+        cs->fbox_valid = 0;
+      }
+      cs->cur = cur ^ 1;
+      cs->step = step + 1;
     }
-    cs->cur ^= 1;
-    cs->step = step + 1;
     return;
   }
   __threadfence();

@@ -223,34 +223,17 @@ __device__ __noinline__ void push_boundary9(const CaseDesc *c, T *dst, int x, in
   push_one<T>(*c, dst, x, y, 8, f8);
 }
 
+// Collide and stream one tile (tx, ty) of case c from f[cur] into f[cur^1].
+// `force` allows the IB force of the case's force box to be read (and
+// cleared once applied).
 template <typename T, int COL>
-__global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__restrict__ cases,
-                                                              const int32_t *__restrict__ tile_prefix,
-                                                              int ncases, int ntiles, int rpt,
-                                                              int xcd_remap) {
-  const int nb = gridDim.x;
-  int t = blockIdx.x;
-  if (xcd_remap) t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-  if (t >= ntiles) return;
-  int ci = 0;
-  if (ncases > 1) {
-    int lo = 0, hi = ncases - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    ci = lo;
-  }
-  const CaseDesc *cp = cases + ci;
+__device__ __forceinline__ void collide_stream_tile(const CaseDesc *cp, int tx, int ty, int cur,
+                                                    int rpt, bool force) {
   const CaseDesc &c = *cp;
   const CaseState *cs = c.state;
-  if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
-  const int cur = cs->cur;
   const T *__restrict__ src = (const T *)c.f[cur];
   T *__restrict__ dst = (T *)c.f[cur ^ 1];
   T *__restrict__ frc = (T *)c.force;
-  const int local = t - tile_prefix[ci];
-  const int tx = local % c.tiles_x, ty = local / c.tiles_x;
   const int TX = blockDim.x, TY = blockDim.y * rpt;
   const int nx = c.nx, ny = c.ny;
   const uint32_t plane = (uint32_t)c.plane;
@@ -258,9 +241,12 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
   const int ybase = ty * TY;
   const int xt0 = tx * TX, xt1 = xt0 + TX - 1, yt1 = ybase + TY - 1;
   // IB force only inside the union of the bodies' force boxes
-  const bool fvalid = cs->fbox_valid != 0;
-  const int fb0 = cs->fbox[0], fy0 = cs->fbox[1], fb1 = cs->fbox[2], fy1 = cs->fbox[3];
-  const bool tile_force = fvalid && !(fb1 < xt0 || fb0 > xt1 || fy1 < ybase || fy0 > yt1);
+  int fb0 = 0, fy0 = 0, fb1 = -1, fy1 = -1;
+  bool tile_force = false;
+  if (force && cs->fbox_valid) {
+    fb0 = cs->fbox[0]; fy0 = cs->fbox[1]; fb1 = cs->fbox[2]; fy1 = cs->fbox[3];
+    tile_force = !(fb1 < xt0 || fb0 > xt1 || fy1 < ybase || fy0 > yt1);
+  }
   const bool interior = xt0 >= 1 && xt1 <= nx - 3 && ybase >= 1 && yt1 <= ny - 2;
   const T ffx = T(c.fluid_fx), ffy = T(c.fluid_fy);
   const int dxy = nx;
@@ -292,6 +278,58 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
   }
 }
 
+// Every tile of every case (batches flatten (case, tile) through tile_prefix).
+template <typename T, int COL>
+__global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__restrict__ cases,
+                                                              const int32_t *__restrict__ tile_prefix,
+                                                              int ncases, int ntiles, int rpt,
+                                                              int xcd_remap) {
+  const int nb = gridDim.x;
+  int t = blockIdx.x;
+  if (xcd_remap) t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  if (t >= ntiles) return;
+  int ci = 0;
+  if (ncases > 1) {
+    int lo = 0, hi = ncases - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    ci = lo;
+  }
+  const CaseDesc *cp = cases + ci;
+  const CaseState *cs = cp->state;
+  if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
+  const int local = t - tile_prefix[ci];
+  collide_stream_tile<T, COL>(cp, local % cp->tiles_x, local / cp->tiles_x, cs->cur, rpt, true);
+}
+
+// One part of a pipelined step of a single case (see PipeArgs): the tiles
+// of the hold rectangle (near = 1), which read the IB force and are read by
+// the IB pass, or all other tiles (near = 0), which do neither.  The input
+// lattice `cur` comes from the host: the IB pass of the previous step may
+// still be updating the case state while the far tiles run.
+template <typename T, int COL>
+__global__ __launch_bounds__(1024) void collide_stream_pipe_kernel(const CaseDesc *__restrict__ cases,
+                                                                   int ntiles, int rpt, int xcd_remap,
+                                                                   PipeArgs pa, int near) {
+  const CaseDesc *cp = cases;
+  const CaseState *cs = cp->state;
+  if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
+  const int nb = gridDim.x;
+  int t = blockIdx.x;
+  if (xcd_remap) t = (t & 7) * (nb >> 3) + (t >> 3);
+  if (near) {
+    if (t >= pa.hntx * pa.hnty) return;
+    collide_stream_tile<T, COL>(cp, pa.htx0 + t % pa.hntx, pa.hty0 + t / pa.hntx, pa.cur, rpt, true);
+    return;
+  }
+  if (t >= ntiles) return;
+  const int tx = t % cp->tiles_x, ty = t / cp->tiles_x;
+  if (tx >= pa.htx0 && tx < pa.htx0 + pa.hntx && ty >= pa.hty0 && ty < pa.hty0 + pa.hnty) return;
+  collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, false);
+}
+
 hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
                                  const int32_t *tile_prefix, int ncases, int ntiles,
                                  LaunchShape shape, hipStream_t stream) {
@@ -304,6 +342,31 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
 #define IBL_LAUNCH(T, C)                                                                        \
   hipLaunchKernelGGL((collide_stream_kernel<T, C>), dim3(grid), block, 0, stream, cases,        \
                      tile_prefix, ncases, ntiles, rpt, remap)
+  if (precision == kPrecFP64) {
+    if (collision == kBGK) IBL_LAUNCH(double, kBGK);
+    else if (collision == kTRT) IBL_LAUNCH(double, kTRT);
+    else IBL_LAUNCH(double, kCMMRT);
+  } else {
+    if (collision == kBGK) IBL_LAUNCH(float, kBGK);
+    else if (collision == kTRT) IBL_LAUNCH(float, kTRT);
+    else IBL_LAUNCH(float, kCMMRT);
+  }
+#undef IBL_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
+                                      LaunchShape shape, const PipeArgs &pa, int near,
+                                      hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  int grid = near ? pa.hntx * pa.hnty : ntiles;
+  if (shape.xcd_remap) grid = (grid + 7) / 8 * 8;
+  dim3 block(shape.block_x, shape.block_y);
+  const int rpt = shape.rows_per_thread;
+  const int remap = shape.xcd_remap;
+#define IBL_LAUNCH(T, C)                                                                        \
+  hipLaunchKernelGGL((collide_stream_pipe_kernel<T, C>), dim3(grid), block, 0, stream, cases,   \
+                     ntiles, rpt, remap, pa, near)
   if (precision == kPrecFP64) {
     if (collision == kBGK) IBL_LAUNCH(double, kBGK);
     else if (collision == kTRT) IBL_LAUNCH(double, kTRT);

@@ -41,6 +41,7 @@ EXPORTS = [
     "ib_lbm_force_field", "ib_lbm_markers", "ib_lbm_steps_done", "ib_lbm_sync",
     "ib_lbm_destroy", "ib_lbm_last_error", "ib_lbm_footprint", "ib_lbm_set_launch",
     "ib_lbm_get_launch", "ib_lbm_set_spread", "ib_lbm_set_graph", "ib_lbm_timing_enable",
+    "ib_lbm_set_overlap", "ib_lbm_get_overlap",
     "ib_lbm_timing_read", "ib_lbm_batch_create", "ib_lbm_batch_attach", "ib_lbm_batch_detach",
     "ib_lbm_batch_set_target", "ib_lbm_batch_step", "ib_lbm_batch_set_graph",
     "ib_lbm_batch_sync", "ib_lbm_batch_destroy", "ib_lbm_batch_last_error",
@@ -171,6 +172,8 @@ def load_library(path: str = LIB_PATH):
     L.ib_lbm_get_launch.argtypes = [vp, C.POINTER(Launch)]
     L.ib_lbm_set_spread.argtypes = [vp, C.c_int32]
     L.ib_lbm_set_graph.argtypes = [vp, C.c_int32]
+    L.ib_lbm_set_overlap.argtypes = [vp, C.c_int32]
+    L.ib_lbm_get_overlap.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
     L.ib_lbm_timing_enable.argtypes = [vp, C.c_int32]
     L.ib_lbm_timing_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
     L.ib_lbm_batch_create.argtypes = [vp, C.c_int32, C.POINTER(vp)]
@@ -400,6 +403,16 @@ class Sim:
 
     def set_graph(self, steps_per_graph: int):
         self._check(self.L.ib_lbm_set_graph(self.h, int(steps_per_graph)), self.h)
+
+    def set_overlap(self, on: bool):
+        self._check(self.L.ib_lbm_set_overlap(self.h, 1 if on else 0), self.h)
+
+    def overlap(self) -> tuple[bool, int]:
+        """(split step in use, nodes in the tiles launched before the IB pass)"""
+        v = C.c_int32()
+        n = C.c_int64()
+        self._check(self.L.ib_lbm_get_overlap(self.h, C.byref(v), C.byref(n)), self.h)
+        return bool(v.value), n.value
 
     def timing(self, on: bool):
         self._check(self.L.ib_lbm_timing_enable(self.h, 1 if on else 0), self.h)

@@ -413,3 +413,80 @@ def test_empty_lattice_and_zero_steps():
     sim.step(7)
     ref.step(7)
     assert rel(sim.populations(), ref.populations()) < F64_FIELD
+
+
+# ------------------------------------------------------------- split step
+def _split_case(scheme, kernel, col, motion=ib.FIXED):
+    body = dict(xc=101.37, yc=79.8, diameter=24.0, scheme=scheme, kernel=kernel, mdf_iters=5,
+                motion=motion)
+    if motion == ib.PRESCRIBED_SIN:
+        body.update(amp=(0.0, 4.0), freq=0.01, phase=0.3)
+    return dict(nx=400, ny=160, collision=col, tau=0.62, trt_magic=0.25, cm_s_q=1.2,
+                cm_s_eps=1.4, bc=(ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.VEL_UNIFORM, ib.VEL_UNIFORM),
+                u_bc=0.08, bodies=[body])
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+@pytest.mark.parametrize("scheme,kernel,col,motion", [
+    (ib.DF, ib.HAT, ib.BGK, ib.FIXED), (ib.MDF, ib.PESKIN4, ib.TRT, ib.FIXED),
+    (ib.DFC, ib.PESKIN4, ib.CMMRT, ib.FIXED), (ib.MDF, ib.PESKIN4, ib.TRT, ib.PRESCRIBED_SIN),
+    (ib.DFC, ib.HAT, ib.TRT, ib.PRESCRIBED_SIN)])
+def test_split_step_is_bitwise_the_plain_step(scheme, kernel, col, motion, prec):
+    """Pipelined steps (the collide-stream of step n+1 overlapping the IB
+    pass of step n, with only the tiles next to the body waiting for it)
+    change no bit of the result, with direct launches and mixed with graph
+    replays, over several calls."""
+    say(f"split step scheme={scheme} kernel={kernel} col={col} motion={motion} prec={prec}")
+    case = _split_case(scheme, kernel, col, motion)
+    runs = []
+    for overlap, graph in ((False, 0), (True, 0), (True, 7)):
+        sim = ib.Sim(case, precision=prec)
+        sim.set_launch(64, 1, 1, 1)
+        sim.set_overlap(overlap)
+        if graph:
+            sim.set_graph(graph)
+        for n in (1, 20, 29):
+            sim.step(n)
+        sim.sync()
+        used, near = sim.overlap()
+        assert used == overlap
+        if overlap:
+            assert 0 < near < case["nx"] * case["ny"] // 4
+        runs.append((sim.populations(), sim.forces(0), sim.force()))
+        sim.close()
+    base = runs[0]
+    for pops, st, (fx, fy) in runs[1:]:
+        assert np.array_equal(pops, base[0])
+        for k in ("fx", "fy", "torque", "slip_mean", "xc", "yc"):
+            assert st[k] == base[1][k], k
+        assert np.array_equal(fx, base[2][0]) and np.array_equal(fy, base[2][1])
+
+
+def test_split_step_matches_oracle_and_is_off_for_free_bodies():
+    case = _split_case(ib.MDF, ib.PESKIN4, ib.CMMRT, ib.PRESCRIBED_SIN)
+    sim, ref = make_pair(case)
+    sim.set_launch(64, 2, 1, 1)
+    sim.step(30)
+    ref.step(30)
+    assert sim.overlap()[0]
+    assert rel(sim.populations(), ref.populations()) < F64_FIELD
+    fs, fr = sim.forces(0), ref.body_state(0)
+    assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < F64_DRAG
+    free = ib_cases.sedimentation(pair=False, nx=80, ny=200, diameter=12.0)
+    free["bodies"][0].update(xc=40.0, yc=160.0)
+    s2 = ib.Sim(free, precision=ib.FP64)
+    s2.step(2)
+    assert s2.overlap() == (False, 0)
+    near_face = _split_case(ib.DF, ib.HAT, ib.BGK)
+    near_face["bodies"][0].update(xc=14.0)
+    s3 = ib.Sim(near_face, precision=ib.FP64)
+    s3.step(2)
+    assert s3.overlap() == (False, 0)
+
+
+def test_benchmark_lattice_uses_split_step():
+    case = ib_cases.unsteady_cylinder(scheme="MDF", kernel="P4", collision="TRT", re=100.0)
+    sim = ib.Sim(case, precision=ib.FP32_SHIFTED)
+    sim.step(3)
+    used, near = sim.overlap()
+    assert used and near < case["nx"] * case["ny"] // 50
