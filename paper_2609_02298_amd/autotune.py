@@ -16,7 +16,7 @@ from . import ib_lbm as ib
 
 DEFAULT_CANDIDATES = [
     dict(block_x=bx, block_y=by, rows_per_thread=rpt, xcd_remap=1)
-    for bx, by, rpt in itertools.product((64, 128, 256), (1, 2, 4), (1, 2))
+    for bx, by, rpt in itertools.product((64, 128, 256), (1, 2, 4), (1, 2, 4))
     if bx * by <= 1024
 ]
 

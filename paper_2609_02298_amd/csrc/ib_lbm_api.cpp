@@ -88,9 +88,9 @@ struct ib_lbm_batch {
   bool broken = false;
   std::string err;
   std::vector<ib_lbm_sim *> sims;
-  DevBuf d_cases, d_prefix, d_slots;
+  DevBuf d_cases, d_prefix, d_fprefix, d_slots;
   struct Group {
-    int collision, first, count, ntiles, prefix_off;
+    int collision, first, count, ntiles, prefix_off, nface;
   };
   std::vector<Group> groups;
   int nslots = 0;
@@ -226,7 +226,7 @@ double host_omega_mdf(double xc, double yc, double R, int nb, int kernel, double
 }
 
 int ws_doubles_for(int scheme, int nb, int ns, int mr, int mn, int pop_bytes) {
-  return ws_tab_total(nb, ns, mr, mn) + ws_dyn_doubles(scheme, nb, mn, pop_bytes);
+  return ws_tab_total(nb, ns, mr, mn) + ws_dyn_doubles(scheme, nb, ns, mn, pop_bytes);
 }
 
 // LDS bytes for an IB launch: enough for the largest workspace that fits;
@@ -329,13 +329,14 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   if (!s->d_case.p) {
     ib_lbm_status st = dev_alloc(s, &s->d_case, sizeof(CaseDesc));
     if (st) return st;
-    st = dev_alloc(s, &s->d_prefix, sizeof(int32_t) * 2);
+    st = dev_alloc(s, &s->d_prefix, sizeof(int32_t) * 4);
     if (st) return st;
     st = dev_alloc(s, &s->d_slots, sizeof(IbmSlot) * kMaxBodiesPerCase);
     if (st) return st;
   }
   HIPCHK(s, hipMemcpy(s->d_case.p, &s->cd, sizeof(CaseDesc), hipMemcpyHostToDevice));
-  int32_t pre[2] = {0, s->cd.tiles_x * s->cd.tiles_y};
+  // tile prefix {0, tiles}, then face-node prefix {0, face nodes}
+  int32_t pre[4] = {0, s->cd.tiles_x * s->cd.tiles_y, 0, face_nodes(s->cd.nx, s->cd.ny)};
   HIPCHK(s, hipMemcpy(s->d_prefix.p, pre, sizeof pre, hipMemcpyHostToDevice));
   std::vector<IbmSlot> slots;
   const int n = std::max(1, (int)bd.size());
@@ -378,6 +379,11 @@ ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
   if (timed) {
     HIPCHK(s, hipEventRecord(p0.b, stream));
     s->timing.ev[0].push_back(p0);
+  }
+  HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
+                                        (const int32_t *)s->d_prefix.p + 2, 1,
+                                        face_nodes(s->cd.nx, s->cd.ny), -1, 1, stream));
+  if (timed) {
     p1 = take_pair(s->timing);
     HIPCHK(s, hipEventRecord(p1.a, stream));
   }
@@ -429,6 +435,10 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
       HIPCHK(s, hipEventRecord(p0.b, s->lq));
       s->timing.ev[0].push_back(p0);
     }
+    // face nodes lie outside the hold rectangle's reach (plan_split)
+    HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
+                                          (const int32_t *)s->d_prefix.p + 2, 1,
+                                          face_nodes(s->cd.nx, s->cd.ny), pa.cur, 0, s->lq));
     // hold tiles of step i after the far tiles of step i-1 (the wait is
     // enqueued before ev_far is recorded again for step i)
     if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_far, 0));
@@ -482,7 +492,8 @@ size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_
     // workspace upper estimate (P4), marker tables, history
     const double D = nb / M_PI;
     const int mr = (int)std::ceil(D) + 12, mn = (int)(8 * M_PI * D + 8 * mr + 64);
-    bytes += (size_t)(ws_doubles_for(kDFC, nb, 4, mr, mn, (int)elem) +
+    bytes += (size_t)(std::max(ws_doubles_for(kDFC, nb, 4, mr, mn, (int)elem),
+                               ws_doubles_for(kMDF, nb, 4, mr, mn, (int)elem)) +
                       ws_tab_total(nb, 4, mr, mn) + 2 * mn) * 8 +
              (size_t)nb * (8 + 1 + 2) * 8 +
              (size_t)hist * kHistCols * 8 + sizeof(BodyState) + sizeof(BodyDesc);
@@ -1111,24 +1122,29 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
   std::vector<CaseDesc> cases;
   std::vector<int32_t> prefix;
   std::vector<IbmSlot> slots;
+  std::vector<int32_t> fprefix;
   b->groups.clear();
   int maxws = 0;
   for (int col = 0; col < 3; col++) {
-    ib_lbm_batch::Group g{col, (int)cases.size(), 0, 0, (int)prefix.size()};
-    int tiles = 0;
+    ib_lbm_batch::Group g{col, (int)cases.size(), 0, 0, (int)prefix.size(), 0};
+    int tiles = 0, faces = 0;
     for (auto *s : b->sims) {
       if (s->cd.collision != col) continue;
       CaseDesc c = s->cd;
       fill_case_tiles(&c, b->launch);
       prefix.push_back(tiles);
       tiles += c.tiles_x * c.tiles_y;
+      fprefix.push_back(faces);
+      faces += face_nodes(c.nx, c.ny);
       cases.push_back(c);
       g.count++;
       for (auto &hb : s->bodies)
         if (hb.dev.ws_doubles * 8 <= ibm_max_lds_bytes()) maxws = std::max(maxws, hb.dev.ws_doubles);
     }
     prefix.push_back(tiles);
+    fprefix.push_back(faces);
     g.ntiles = tiles;
+    g.nface = faces;
     if (g.count) b->groups.push_back(g);
   }
   for (int ci = 0; ci < (int)cases.size(); ci++) {
@@ -1152,6 +1168,7 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
   if (!cases.empty()) {
     if ((st = upload(&b->d_cases, cases.data(), cases.size() * sizeof(CaseDesc)))) return st;
     if ((st = upload(&b->d_prefix, prefix.data(), prefix.size() * sizeof(int32_t)))) return st;
+    if ((st = upload(&b->d_fprefix, fprefix.data(), fprefix.size() * sizeof(int32_t)))) return st;
     if ((st = upload(&b->d_slots, slots.data(), slots.size() * sizeof(IbmSlot)))) return st;
   }
   b->nslots = (int)slots.size();
@@ -1166,6 +1183,10 @@ static ib_lbm_status batch_enqueue_step(ib_lbm_batch *b, hipStream_t stream) {
     BHIPCHK(b, launch_collide_stream(b->precision, g.collision, (const CaseDesc *)b->d_cases.p + g.first,
                                      (const int32_t *)b->d_prefix.p + g.prefix_off, g.count, g.ntiles,
                                      sh, stream));
+    BHIPCHK(b, launch_collide_stream_faces(b->precision, g.collision,
+                                           (const CaseDesc *)b->d_cases.p + g.first,
+                                           (const int32_t *)b->d_fprefix.p + g.prefix_off, g.count,
+                                           g.nface, -1, 1, stream));
   }
   BHIPCHK(b, launch_ibm(b->precision, (const CaseDesc *)b->d_cases.p, (const IbmSlot *)b->d_slots.p,
                         b->nslots, b->lds_bytes, b->spread_mode, stream));
@@ -1250,6 +1271,7 @@ ib_lbm_status ib_lbm_batch_destroy(ib_lbm_batch *b) {
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_cases.p) (void)hipFree(b->d_cases.p);
   if (b->d_prefix.p) (void)hipFree(b->d_prefix.p);
+  if (b->d_fprefix.p) (void)hipFree(b->d_fprefix.p);
   if (b->d_slots.p) (void)hipFree(b->d_slots.p);
   delete b;
   return IB_LBM_OK;

@@ -109,7 +109,8 @@ struct CaseDesc {
 //   ints:    ix0 iy0 (nb each), nidx (nb*ns*ns), ra1 rl1 ra2 (mr each),
 //            off (mr+1), nxy (mn), noff (mn+1), nent (nb*ns*ns), S (1)
 //            [padded to even]
-//   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each)
+//   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each),
+//                     ew (nb*ns*ns: the weight of each node -> marker entry)
 //   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), then the staged
 //                     populations (9 mn of T), overlaid by the W_total node
 //                     array while the correction scale is built and, at the
@@ -122,9 +123,9 @@ __host__ __device__ inline int ws_table_ints(int nb, int ns, int mr, int mn) {
 __host__ __device__ inline int ws_tab_total(int nb, int ns, int mr, int mn) {
   return ws_table_doubles(nb, ns) + ws_table_ints(nb, ns, mr, mn) / 2;
 }
-__host__ __device__ inline int ws_dyn_doubles(int scheme, int nb, int mn, int pop_bytes) {
+__host__ __device__ inline int ws_dyn_doubles(int scheme, int nb, int ns, int mn, int pop_bytes) {
   if (scheme == 2) return nb * 12 + (9 * mn * pop_bytes + 7) / 8;
-  return nb * 5 + mn * 3;
+  return nb * 5 + mn * 3 + nb * ns * ns;
 }
 
 // One IB workgroup: the body `body` of case `cas` (body = -1: a case without
@@ -135,6 +136,11 @@ struct IbmSlot {
   int32_t slots_in_case;
   int32_t pad;
 };
+
+// Number of face nodes of an nx x ny lattice: rows y = 0 and ny-1, columns
+// x = 0, nx-2 and nx-1 in between (the nodes with a link that leaves the
+// lattice, and the column the zero-gradient outlet copies from).
+__host__ __device__ inline int face_nodes(int nx, int ny) { return 2 * nx + 3 * (ny - 2); }
 
 struct LaunchShape {
   int32_t block_x, block_y, rows_per_thread, xcd_remap;
@@ -152,6 +158,11 @@ struct PipeArgs {
 hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
                                  const int32_t *tile_prefix, int ncases, int ntiles,
                                  LaunchShape shape, hipStream_t stream);
+// The face nodes (rows 0 and ny-1, columns 0, nx-2, nx-1) with the face
+// closures; cur < 0 takes each case's lattice from its state.
+hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
+                                       const int32_t *face_prefix, int ncases, int nface, int cur,
+                                       int force, hipStream_t stream);
 // One part of a pipelined step: near = 1 the hold rectangle, 0 the other tiles.
 hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
                                       LaunchShape shape, const PipeArgs &pa, int near,

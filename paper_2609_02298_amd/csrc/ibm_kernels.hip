@@ -135,6 +135,7 @@ struct WsLayout {
   double *X, *Y, *Udx, *Udy, *wx, *wy;                           // table doubles
   int *ix0, *iy0, *nidx, *ra1, *rl1, *ra2, *off, *nxy, *noff, *nent, *S;  // table ints
   double *rhoX, *Fx, *Fy, *Ftx, *Fty, *lam, *dlt;                // per-step, markers
+  double *ew;                                                    // per-step, node entries
   void *stage;                                                   // DFC populations
   double *nrho, *nux, *nuy, *nW;                                 // per-step, nodes
   int *lmin, *lmax, *rmin, *rmax, *cnt, *ncnt, *nfill;  // construction scratch (per-step area)
@@ -155,12 +156,13 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   // arrays a scheme does not use alias the start of the per-step area (never
   // null, so that every pointer provably stays in the workspace's address
   // space and the LDS instantiation uses LDS instructions)
-  L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = L.nux = L.nuy = d;
+  L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = L.nux = L.nuy = L.ew = d;
   L.stage = (void *)d;
   if (B.scheme != kDFC) {
     L.rhoX = d; d += nb; L.Fx = d; d += nb; L.Fy = d; d += nb; L.Ftx = d; d += nb; L.Fty = d; d += nb;
     L.nrho = d; d += mn;
     L.nux = d; d += mn; L.nuy = d; d += mn;
+    L.ew = d; d += nb * ns * ns;
   } else {
     L.Ftx = d; d += nb; L.Fty = d; d += nb; L.lam = d; d += nb; L.dlt = d; d += 9 * nb;
     L.stage = (void *)d;  // 9 x mn populations of the stored type
@@ -240,18 +242,26 @@ __device__ __forceinline__ double node_weight(const WsLayout &L, int kq) {
 // most U markers at unit marker spacing); entries past the node's count
 // repeat its last entry with weight 0, which leaves every sum unchanged.
 // Entries beyond U, at denser marker spacings, follow one by one.
-template <int NS, typename F>
+// EW: the entry weights were formed once in L.ew (DF/MDF); otherwise they
+// are formed from the marker weights on the fly.
+template <int NS, bool EW = false, typename F>
 __device__ __forceinline__ void for_node_entries(const WsLayout &L, int j, F &&f) {
   constexpr int U = NS == 4 ? 6 : 3;
   const int e0 = L.noff[j], e1 = L.noff[j + 1];
   int kq[U];
+  double w[U];
 #pragma unroll
-  for (int u = 0; u < U; u++) kq[u] = L.nent[min(e0 + u, e1 - 1)];
+  for (int u = 0; u < U; u++) {
+    const int e = min(e0 + u, e1 - 1);
+    kq[u] = L.nent[e];
+    if (EW) w[u] = L.ew[e];
+  }
 #pragma unroll
-  for (int u = 0; u < U; u++) f(kq[u] >> 4, e0 + u < e1 ? node_weight<NS>(L, kq[u]) : 0.0);
+  for (int u = 0; u < U; u++)
+    f(kq[u] >> 4, e0 + u < e1 ? (EW ? w[u] : node_weight<NS>(L, kq[u])) : 0.0);
   for (int e = e0 + U; e < e1; e++) {
     const int q = L.nent[e];
-    f(q >> 4, node_weight<NS>(L, q));
+    f(q >> 4, EW ? L.ew[e] : node_weight<NS>(L, q));
   }
 }
 
@@ -259,7 +269,7 @@ template <int NS>
 __device__ __forceinline__ void gather2(const WsLayout &L, int j, const double *va,
                                         const double *vb, double &oa, double &ob) {
   double a = 0.0, b = 0.0;
-  for_node_entries<NS>(L, j, [&](int k, double w) {
+  for_node_entries<NS, true>(L, j, [&](int k, double w) {
     a += va[k] * w;
     b += vb[k] * w;
   });
@@ -524,11 +534,13 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   if (B.scheme != kDFC) {
     // ---- 4a. DF (one pass, omega 1) / MDF (N passes, omega_MDF)
     // moments of the post-stream populations at the support nodes; the
-    // loads of two nodes per thread are issued before any is used
-    for (int j0 = tid; j0 < S; j0 += 2 * nth) {
-      T v[2][9];
+    // loads of UM nodes per thread are issued before any is used (one round
+    // trip to device memory covers up to UM * 512 nodes)
+    constexpr int UM = sizeof(T) == 4 ? 3 : 2;
+    for (int j0 = tid; j0 < S; j0 += UM * nth) {
+      T v[UM][9];
 #pragma unroll
-      for (int u = 0; u < 2; u++) {
+      for (int u = 0; u < UM; u++) {
         const int j = j0 + u * nth;
         if (j < S) {
           const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
@@ -538,9 +550,11 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         }
       }
 #pragma unroll
-      for (int u = 0; u < 2; u++) {
+      for (int u = 0; u < UM; u++) {
         const int j = j0 + u * nth;
         if (j >= S) continue;
+        // weights of the node's marker entries, used by every gather below
+        for (int e = L.noff[j]; e < L.noff[j + 1]; e++) L.ew[e] = node_weight<NS>(L, L.nent[e]);
         double sm = 0, jx = 0, jy = 0;
 #pragma unroll
         for (int i = 0; i < 9; i++) {

@@ -207,8 +207,7 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
     dst[(uint32_t)j * plane + (uint32_t)ys * nx + (nx - 1)] = v;
 }
 
-// Out of line so that boundary tiles do not raise the register footprint of
-// the interior path.
+// All nine pushes of a face node.
 template <typename T>
 __device__ __noinline__ void push_boundary9(const CaseDesc *c, T *dst, int x, int y, T f0, T f1,
                                             T f2, T f3, T f4, T f5, T f6, T f7, T f8) {
@@ -223,9 +222,29 @@ __device__ __noinline__ void push_boundary9(const CaseDesc *c, T *dst, int x, in
   push_one<T>(*c, dst, x, y, 8, f8);
 }
 
-// Collide and stream one tile (tx, ty) of case c from f[cur] into f[cur^1].
-// `force` allows the IB force of the case's force box to be read (and
-// cleared once applied).
+// The node's IB force if it lies in the force box (consumed: cleared once
+// read), plus the uniform fluid force.
+template <typename T>
+__device__ __forceinline__ void node_force(T *frc, uint32_t plane, uint32_t p, int x, int y,
+                                           bool in_box, int fb0, int fy0, int fb1, int fy1,
+                                           T &Fx, T &Fy) {
+  if (in_box && x >= fb0 && x <= fb1 && y >= fy0 && y <= fy1) {
+    const T a = frc[p], b = frc[plane + p];
+    if (a != T(0) || b != T(0)) {
+      Fx += a;
+      Fy += b;
+      frc[p] = T(0);
+      frc[plane + p] = T(0);
+    }
+  }
+}
+
+// Collide and stream the inner nodes (1 <= x <= nx-3, 1 <= y <= ny-2) of
+// tile (tx, ty) of case c from f[cur] into f[cur^1]: every link stays inside
+// the lattice, so every push is a plain store.  The other nodes (the face
+// nodes) are left to collide_stream_face_kernel, which keeps the face rules
+// out of this kernel and its register footprint small.  `force` allows the
+// IB force of the case's force box to be read (and cleared once applied).
 template <typename T, int COL>
 __device__ __forceinline__ void collide_stream_tile(const CaseDesc *cp, int tx, int ty, int cur,
                                                     int rpt, bool force) {
@@ -247,38 +266,25 @@ __device__ __forceinline__ void collide_stream_tile(const CaseDesc *cp, int tx, 
     fb0 = cs->fbox[0]; fy0 = cs->fbox[1]; fb1 = cs->fbox[2]; fy1 = cs->fbox[3];
     tile_force = !(fb1 < xt0 || fb0 > xt1 || fy1 < ybase || fy0 > yt1);
   }
-  const bool interior = xt0 >= 1 && xt1 <= nx - 3 && ybase >= 1 && yt1 <= ny - 2;
   const T ffx = T(c.fluid_fx), ffy = T(c.fluid_fy);
-  const int dxy = nx;
-
+  if (x < 1 || x > nx - 3) return;
   for (int r = 0; r < rpt; r++) {
     const int y = ybase + threadIdx.y + r * blockDim.y;
-    if (x >= nx || y >= ny) continue;
+    if (y < 1 || y > ny - 2) continue;
     const uint32_t p = (uint32_t)y * nx + x;
     T f[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) f[i] = src[(uint32_t)i * plane + p];
     T Fx = ffx, Fy = ffy;
-    if (tile_force && x >= fb0 && x <= fb1 && y >= fy0 && y <= fy1) {
-      const T a = frc[p], b = frc[plane + p];
-      if (a != T(0) || b != T(0)) {
-        Fx += a;
-        Fy += b;
-        frc[p] = T(0);
-        frc[plane + p] = T(0);
-      }
-    }
+    node_force<T>(frc, plane, p, x, y, tile_force, fb0, fy0, fb1, fy1, Fx, Fy);
     collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
-    if (interior || (x >= 1 && x <= nx - 3 && y >= 1 && y <= ny - 2)) {
 #pragma unroll
-      for (int i = 0; i < 9; i++) dst[(uint32_t)i * plane + p + EXI(i) + EYI(i) * dxy] = f[i];
-    } else {
-      push_boundary9<T>(cp, dst, x, y, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
-    }
+    for (int i = 0; i < 9; i++) dst[(uint32_t)i * plane + p + EXI(i) + EYI(i) * nx] = f[i];
   }
 }
 
-// Every tile of every case (batches flatten (case, tile) through tile_prefix).
+// Every inner node of every case (batches flatten (case, tile) through
+// tile_prefix).
 template <typename T, int COL>
 __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__restrict__ cases,
                                                               const int32_t *__restrict__ tile_prefix,
@@ -304,6 +310,64 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
   collide_stream_tile<T, COL>(cp, local % cp->tiles_x, local / cp->tiles_x, cs->cur, rpt, true);
 }
 
+// The face nodes of every case (face_prefix flattens (case, face node)), with
+// the face closures.  cur < 0: each case's current lattice from its state;
+// otherwise the lattice given (a pipelined step, whose case state the IB pass
+// may be updating).
+template <typename T, int COL>
+__global__ __launch_bounds__(256) void collide_stream_face_kernel(const CaseDesc *__restrict__ cases,
+                                                                  const int32_t *__restrict__ face_prefix,
+                                                                  int ncases, int nface, int cur_arg,
+                                                                  int force) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nface) return;
+  int ci = 0;
+  if (ncases > 1) {
+    int lo = 0, hi = ncases - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (face_prefix[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    ci = lo;
+  }
+  const CaseDesc *cp = cases + ci;
+  const CaseDesc &c = *cp;
+  const CaseState *cs = c.state;
+  int cur = cur_arg;
+  if (cur < 0) {
+    if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
+    cur = cs->cur;
+  } else if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) {
+    return;
+  }
+  const int nx = c.nx, ny = c.ny;
+  const int m = k - face_prefix[ci];
+  int x, y;
+  if (m < nx) {
+    x = m; y = 0;
+  } else if (m < 2 * nx) {
+    x = m - nx; y = ny - 1;
+  } else {
+    const int q = m - 2 * nx, col = q / (ny - 2);
+    x = col == 0 ? 0 : (col == 1 ? nx - 2 : nx - 1);
+    y = 1 + q % (ny - 2);
+  }
+  const T *__restrict__ src = (const T *)c.f[cur];
+  T *__restrict__ dst = (T *)c.f[cur ^ 1];
+  T *__restrict__ frc = (T *)c.force;
+  const uint32_t plane = (uint32_t)c.plane;
+  const uint32_t p = (uint32_t)y * nx + x;
+  T f[9];
+#pragma unroll
+  for (int i = 0; i < 9; i++) f[i] = src[(uint32_t)i * plane + p];
+  T Fx = T(c.fluid_fx), Fy = T(c.fluid_fy);
+  const bool box = force && cs->fbox_valid;
+  node_force<T>(frc, plane, p, x, y, box, box ? cs->fbox[0] : 0, box ? cs->fbox[1] : 0,
+                box ? cs->fbox[2] : -1, box ? cs->fbox[3] : -1, Fx, Fy);
+  collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
+  push_boundary9<T>(cp, dst, x, y, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
+}
+
 // One part of a pipelined step of a single case (see PipeArgs): the tiles
 // of the hold rectangle (near = 1), which read the IB force and are read by
 // the IB pass, or all other tiles (near = 0), which do neither.  The input
@@ -319,16 +383,30 @@ __global__ __launch_bounds__(1024) void collide_stream_pipe_kernel(const CaseDes
   const int nb = gridDim.x;
   int t = blockIdx.x;
   if (xcd_remap) t = (t & 7) * (nb >> 3) + (t >> 3);
+  int tx, ty;
   if (near) {
     if (t >= pa.hntx * pa.hnty) return;
-    collide_stream_tile<T, COL>(cp, pa.htx0 + t % pa.hntx, pa.hty0 + t / pa.hntx, pa.cur, rpt, true);
-    return;
+    tx = pa.htx0 + t % pa.hntx;
+    ty = pa.hty0 + t / pa.hntx;
+  } else {
+    if (t >= ntiles) return;
+    tx = t % cp->tiles_x;
+    ty = t / cp->tiles_x;
+    if (tx >= pa.htx0 && tx < pa.htx0 + pa.hntx && ty >= pa.hty0 && ty < pa.hty0 + pa.hnty) return;
   }
-  if (t >= ntiles) return;
-  const int tx = t % cp->tiles_x, ty = t / cp->tiles_x;
-  if (tx >= pa.htx0 && tx < pa.htx0 + pa.hntx && ty >= pa.hty0 && ty < pa.hty0 + pa.hnty) return;
-  collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, false);
+  collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, near != 0);
 }
+
+#define IBL_DISPATCH(precision, collision, LAUNCH)                                             \
+  if ((precision) == kPrecFP64) {                                                              \
+    if ((collision) == kBGK) LAUNCH(double, kBGK);                                             \
+    else if ((collision) == kTRT) LAUNCH(double, kTRT);                                        \
+    else LAUNCH(double, kCMMRT);                                                               \
+  } else {                                                                                     \
+    if ((collision) == kBGK) LAUNCH(float, kBGK);                                              \
+    else if ((collision) == kTRT) LAUNCH(float, kTRT);                                         \
+    else LAUNCH(float, kCMMRT);                                                                \
+  }
 
 hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
                                  const int32_t *tile_prefix, int ncases, int ntiles,
@@ -342,15 +420,20 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
 #define IBL_LAUNCH(T, C)                                                                        \
   hipLaunchKernelGGL((collide_stream_kernel<T, C>), dim3(grid), block, 0, stream, cases,        \
                      tile_prefix, ncases, ntiles, rpt, remap)
-  if (precision == kPrecFP64) {
-    if (collision == kBGK) IBL_LAUNCH(double, kBGK);
-    else if (collision == kTRT) IBL_LAUNCH(double, kTRT);
-    else IBL_LAUNCH(double, kCMMRT);
-  } else {
-    if (collision == kBGK) IBL_LAUNCH(float, kBGK);
-    else if (collision == kTRT) IBL_LAUNCH(float, kTRT);
-    else IBL_LAUNCH(float, kCMMRT);
-  }
+  IBL_DISPATCH(precision, collision, IBL_LAUNCH)
+#undef IBL_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
+                                       const int32_t *face_prefix, int ncases, int nface, int cur,
+                                       int force, hipStream_t stream) {
+  if (nface <= 0) return hipSuccess;
+  const int grid = (nface + 255) / 256;
+#define IBL_LAUNCH(T, C)                                                                        \
+  hipLaunchKernelGGL((collide_stream_face_kernel<T, C>), dim3(grid), dim3(256), 0, stream, cases, \
+                     face_prefix, ncases, nface, cur, force)
+  IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
   return hipGetLastError();
 }
@@ -367,18 +450,11 @@ hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDe
 #define IBL_LAUNCH(T, C)                                                                        \
   hipLaunchKernelGGL((collide_stream_pipe_kernel<T, C>), dim3(grid), block, 0, stream, cases,   \
                      ntiles, rpt, remap, pa, near)
-  if (precision == kPrecFP64) {
-    if (collision == kBGK) IBL_LAUNCH(double, kBGK);
-    else if (collision == kTRT) IBL_LAUNCH(double, kTRT);
-    else IBL_LAUNCH(double, kCMMRT);
-  } else {
-    if (collision == kBGK) IBL_LAUNCH(float, kBGK);
-    else if (collision == kTRT) IBL_LAUNCH(float, kTRT);
-    else IBL_LAUNCH(float, kCMMRT);
-  }
+  IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
   return hipGetLastError();
 }
+#undef IBL_DISPATCH
 
 // ------------------------------------------------------------ utilities
 // Equilibrium start state f^eq(rho0, u_init): u_init is the parabolic inlet
