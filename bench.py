@@ -58,6 +58,8 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
     import paper_2609_02298_amd as ib
 
     if launch is None and tune:
+        # the shipped table (written by the autotuner on an MI355X) when it
+        # has this lattice, else tune now
         from paper_2609_02298_amd import autotune
         launch = autotune.tune(case["nx"], case["ny"], case["collision"], precision)
     sim = ib.Sim(case, precision=precision)
@@ -74,20 +76,29 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     split, near = sim.overlap()
-    # kernel durations from HIP events in a separate run of unpipelined steps
-    # (the events add host and queue work to every step, so the wall-clock
-    # run above has none; a pipelined collide-stream launch would include its
-    # wait for the IB pass)
+    # IB pass duration from HIP events around each pass in a separate run of
+    # unpipelined steps (the events add host and queue work to every step, so
+    # the wall-clock run above has none)
     sim.set_overlap(False)
     sim.timing(True)
-    sim.step(min(steps, 200))
+    sim.step(min(steps, 100))
     sim.sync()
-    lbm_ms, n_lbm = sim.timing_read(0)
     ibm_ms, n_ibm = sim.timing_read(1)
     sim.timing(False)
     sim.set_overlap(True)
     st = sim.forces(0, check=False)
+    # collide-stream kernel duration: HIP events around 200 back-to-back
+    # launches on a second sim of the same workload (two steps in, so that
+    # the force box is set), on the stream they are launched on
+    tsim = ib.Sim(case, precision=precision)
+    if launch:
+        tsim.set_launch(**launch)
+    tsim.step(2)
+    lbm_us, inner = tsim.time_collide_stream(200)
+    tsim.close()
+    lbm_ms, n_lbm = lbm_us * 1e-3, 1
     out = dict(seconds=t1 - t0, lbm_ms=lbm_ms, n_lbm=n_lbm, ibm_ms=ibm_ms, n_ibm=n_ibm,
+               inner_nodes=inner,
                split=split, near_nodes=near,
                fx=st["fx"], status=st["status"], steps_done=sim.steps_done,
                launch=sim.get_launch())
@@ -155,6 +166,48 @@ def serving_leg(precision, launch, n_cases: int, step_scale: int, budget_gb: flo
     }
 
 
+def largest_leg(steps32: int = 60, steps64: int = 30):
+    """The largest lattice of the seeded sweep (7175 x 2014, 14.45M nodes,
+    1.04 GB of FP32 populations: well beyond the 256 MB Infinity Cache), with
+    its body, in both precisions: whole-step MLUPS and the collide-stream
+    roofline."""
+    import ib_cases
+    import paper_2609_02298_amd as ib
+
+    cases = ib_cases.sweep_cases(256, seed=0)
+    c = max(cases, key=lambda k: k["nx"] * k["ny"])
+    b = c["bodies"][0]
+    out = {"workload": c["name"], "nx": c["nx"], "ny": c["ny"], "diameter": c["diameter"],
+           "scheme": ["DF", "MDF", "DFC"][b["scheme"]], "kernel": ["hat", "P4"][b["kernel"]],
+           "collision": ["BGK", "TRT", "CMMRT"][c["collision"]]}
+    nodes = c["nx"] * c["ny"]
+    lbm_nodes = (c["nx"] - 3) * (c["ny"] - 2)
+    for pname, p, bpn, steps in (("fp32", ib.FP32_SHIFTED, 72, steps32), ("fp64", ib.FP64, 144, steps64)):
+        r = run_gpu(c, p, steps, 5)
+        avg = r["lbm_ms"] / max(r["n_lbm"], 1) * 1e-3
+        a = bpn * lbm_nodes / avg / 1e9
+        out[pname] = {"value": round(nodes * steps / r["seconds"] / 1e6, 1), "unit": "MLUPS",
+                      "roofline_achieved_GBs": round(a, 1), "roofline_frac": round(a / HBM_PEAK_GBS, 4),
+                      "avg_launch_us": round(avg * 1e6, 2),
+                      "ib_pass_avg_us": round(r["ibm_ms"] / max(r["n_ibm"], 1) * 1e3, 2),
+                      "population_bytes": 2 * 9 * nodes * bpn // 18, "launch": r["launch"]}
+    return out
+
+
+def copy_calibration(mb: float):
+    """One device copy of `mb` MB (read mb, write mb): the reference kernel
+    against which the collide-stream's FETCH_SIZE / WRITE_SIZE counters are
+    scaled."""
+    import torch
+    n = int(mb * 1e6) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return n * 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +228,9 @@ def main():
     ap.add_argument("--serve-step-scale", type=int, default=40)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-quantum", type=int, default=128)
+    ap.add_argument("--no-largest", action="store_true", help="skip the largest-lattice leg")
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -203,7 +259,7 @@ def main():
     # the timed collide-stream launch updates the inner nodes; the face nodes
     # (rows 0 and ny-1, columns 0, nx-2, nx-1) go through a small second
     # launch with the face closures
-    lbm_nodes = (case["nx"] - 3) * (case["ny"] - 2)
+    lbm_nodes = r["inner_nodes"]
     achieved = bpn * lbm_nodes / lbm_avg_s / 1e9
     key = f"{case['name']}-{args.precision}-{args.collision}"
     traffic = measured_traffic(key)
@@ -258,11 +314,15 @@ def main():
                         rr = run_gpu(c, p, 100, 10, tune=not args.no_tune)
                         combos[f"{sch}/{ker}/{col}/{pname}"] = round(nodes * 100 / rr["seconds"] / 1e6, 1)
         line["combos_mlups"] = combos
+    if not args.no_largest:
+        line["largest_lattice"] = largest_leg()
     if not args.no_serving:
         line["serving"] = serving_leg(prec, r["launch"], args.serve_cases, args.serve_step_scale,
                                       args.serve_budget_gb, args.serve_quantum)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case)
+    if args.copy_calibration_mb > 0:
+        line["copy_calibration_bytes"] = copy_calibration(args.copy_calibration_mb)
     print(json.dumps(line), flush=True)
 
 

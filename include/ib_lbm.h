@@ -240,6 +240,16 @@ ib_lbm_status ib_lbm_get_overlap(const ib_lbm_sim *s, int32_t *in_use, int64_t *
  * launch includes the wait of its tiles next to the body for the previous IB
  * pass.  Reset with enable. */
 ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on);
+/* Measurement only: `launches` back-to-back launches of the collide-stream
+ * kernel over the inner nodes (1 <= x <= nx-3, 1 <= y <= ny-2; every link
+ * stays inside the lattice) on the sim's stream, bracketed by two HIP events;
+ * *avg_us receives the average time per launch and *inner_nodes (if not
+ * NULL) the nodes one launch updates.  The sim's populations are advanced by
+ * these launches without face closures or IB passes, so the sim is meant
+ * for the measurement alone (for example a copy of a workload's sim).
+ * Synchronises. */
+ib_lbm_status ib_lbm_time_collide_stream(ib_lbm_sim *s, int32_t launches, double *avg_us,
+                                         int64_t *inner_nodes);
 ib_lbm_status ib_lbm_timing_read(ib_lbm_sim *s, int32_t which, double *total_ms, int64_t *launches);
 
 /* ---- batching: many independent sims stepped by shared launches ----

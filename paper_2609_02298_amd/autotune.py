@@ -3,8 +3,11 @@
 Times candidate tile shapes through the C ABI (HIP events around each
 collide-stream launch on the library's stream) on a body-free lattice of the
 same size, collision model and precision as the workload, and keeps the
-fastest.  Results are cached in memory and, optionally, in a JSON file keyed
-by (precision, collision, nx, ny).
+fastest.  Results are cached in memory and in a JSON table keyed by
+(precision, collision, nx, ny); the table shipped with the package
+(launch_table.json, written on an MI355X by ``python -m
+paper_2609_02298_amd.autotune --write PATH``) is loaded first, so tuned
+workloads start without re-tuning.
 """
 from __future__ import annotations
 
@@ -21,6 +24,7 @@ DEFAULT_CANDIDATES = [
 ]
 
 _cache: dict = {}
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_table.json")
 
 
 def _key(nx, ny, collision, precision):
@@ -58,9 +62,20 @@ def time_shape(nx, ny, collision, precision, shape, steps=40, stream=None) -> fl
     return ms / max(n, 1) * 1e3
 
 
+def lookup(nx, ny, collision, precision):
+    """The tuned shape for this lattice from the shipped table or an earlier
+    tune() in this process, or None."""
+    if not _cache:
+        load_cache(TABLE)
+    e = _cache.get(_key(nx, ny, collision, precision))
+    return dict(e["shape"]) if e else None
+
+
 def tune(nx, ny, collision, precision, candidates=None, steps=40, stream=None) -> dict:
-    """Best launch shape for this lattice (cached)."""
+    """Best launch shape for this lattice (from the table, else timed)."""
     k = _key(nx, ny, collision, precision)
+    if not _cache:
+        load_cache(TABLE)
     if k in _cache:
         return dict(_cache[k]["shape"])
     best = None
@@ -70,3 +85,25 @@ def tune(nx, ny, collision, precision, candidates=None, steps=40, stream=None) -
             best = (t, sh)
     _cache[k] = {"shape": best[1], "us": best[0]}
     return dict(best[1])
+
+
+def _main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the collide-stream launch shape of workloads")
+    ap.add_argument("--write", required=True, help="JSON table to write")
+    ap.add_argument("lattices", nargs="*", default=["2000x800", "4096x4096"],
+                    help="NXxNY entries, tuned for every collision model and precision")
+    args = ap.parse_args(argv)
+    ib.load_library()
+    for spec in args.lattices:
+        nx, ny = (int(v) for v in spec.lower().split("x"))
+        for prec in (ib.FP32_SHIFTED, ib.FP64):
+            for col in (ib.BGK, ib.TRT, ib.CMMRT):
+                sh = tune(nx, ny, col, prec)
+                print(f"{nx}x{ny} precision {prec} collision {col}: {sh} "
+                      f"{_cache[_key(nx, ny, col, prec)]['us']:.1f} us", flush=True)
+    save_cache(args.write)
+
+
+if __name__ == "__main__":
+    _main()

@@ -280,28 +280,6 @@ ib_lbm_status plan_split(ib_lbm_sim *s) {
   s->hold[1] = ty0;
   s->hold[2] = tx1 - tx0 + 1;
   s->hold[3] = ty1 - ty0 + 1;
-  if (!s->lq) {
-    // The far-tile stream leaves one compute unit per IB workgroup to the
-    // other stream, so that an IB pass never waits for a free unit behind a
-    // full far-tile launch.
-    int dev = 0, ncu = 0;
-    HIPCHK(s, hipGetDevice(&dev));
-    HIPCHK(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-    for (int i = 0; i < ncu - s->nslots; i++) mask[i / 32] |= 1u << (i % 32);
-    if (ncu <= s->nslots ||
-        hipExtStreamCreateWithCUMask(&s->lq, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
-      (void)hipGetLastError();
-      s->lq = nullptr;
-      HIPCHK(s, hipStreamCreateWithFlags(&s->lq, hipStreamNonBlocking));
-    }
-  }
-  if (!s->iq) HIPCHK(s, hipStreamCreateWithFlags(&s->iq, hipStreamNonBlocking));
-  if (!s->ev_start) HIPCHK(s, hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming));
-  if (!s->ev_lq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_lq, hipEventDisableTiming));
-  if (!s->ev_iq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_iq, hipEventDisableTiming));
-  if (!s->ev_near) HIPCHK(s, hipEventCreateWithFlags(&s->ev_near, hipEventDisableTiming));
-  if (!s->ev_far) HIPCHK(s, hipEventCreateWithFlags(&s->ev_far, hipEventDisableTiming));
   s->split = true;
   return IB_LBM_OK;
 }
@@ -398,6 +376,34 @@ ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
 
 ib_lbm_status read_state(ib_lbm_sim *s, CaseState *cs);
 
+// The two streams and the events of pipelined steps, created at the first
+// pipelined step (sims stepped through a batch never need them).
+ib_lbm_status ensure_pipe_streams(ib_lbm_sim *s) {
+  if (!s->lq) {
+    // The far-tile stream leaves one compute unit per IB workgroup to the
+    // other stream, so that an IB pass never waits for a free unit behind a
+    // full far-tile launch.
+    int dev = 0, ncu = 0;
+    HIPCHK(s, hipGetDevice(&dev));
+    HIPCHK(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+    for (int i = 0; i < ncu - s->nslots; i++) mask[i / 32] |= 1u << (i % 32);
+    if (ncu <= s->nslots ||
+        hipExtStreamCreateWithCUMask(&s->lq, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+      (void)hipGetLastError();
+      s->lq = nullptr;
+      HIPCHK(s, hipStreamCreateWithFlags(&s->lq, hipStreamNonBlocking));
+    }
+  }
+  if (!s->iq) HIPCHK(s, hipStreamCreateWithFlags(&s->iq, hipStreamNonBlocking));
+  if (!s->ev_start) HIPCHK(s, hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming));
+  if (!s->ev_lq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_lq, hipEventDisableTiming));
+  if (!s->ev_iq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_iq, hipEventDisableTiming));
+  if (!s->ev_near) HIPCHK(s, hipEventCreateWithFlags(&s->ev_near, hipEventDisableTiming));
+  if (!s->ev_far) HIPCHK(s, hipEventCreateWithFlags(&s->ev_far, hipEventDisableTiming));
+  return IB_LBM_OK;
+}
+
 // Enqueue nsteps pipelined steps.  Step n: the hold tiles and then the IB
 // pass on iq, the far tiles on lq.  The far tiles of step n follow the hold
 // tiles of step n-1 (which push into far nodes and whose inputs the far
@@ -410,6 +416,7 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
   ib_lbm_status st = read_state(s, &cs);
   if (st) return st;
   if (cs.flags & kCaseHalted) return IB_LBM_OK;  // nothing would run
+  if ((st = ensure_pipe_streams(s))) return st;
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
   const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
   HIPCHK(s, hipEventRecord(s->ev_start, s->stream));
@@ -1033,6 +1040,38 @@ ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on) {
     s->timing.folded_n[k] = 0;
   }
   s->timing.on = on != 0;
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_time_collide_stream(ib_lbm_sim *s, int32_t launches, double *avg_us,
+                                         int64_t *inner_nodes) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (launches <= 0 || !avg_us) return IB_LBM_E_INVALID;
+  if (s->batch) {
+    set_err(&s->err, "sim is attached to a batch");
+    return IB_LBM_E_STATE;
+  }
+  if ((st = build_sim_tables(s))) return st;
+  s->started = true;
+  LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
+  const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
+  hipEvent_t a, b;
+  HIPCHK(s, hipEventCreate(&a));
+  HIPCHK(s, hipEventCreate(&b));
+  hipError_t e = hipEventRecord(a, s->stream);
+  for (int i = 0; i < launches && e == hipSuccess; i++)
+    e = launch_collide_stream(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
+                              (const int32_t *)s->d_prefix.p, 1, ntiles, sh, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  HIPCHK(s, e);
+  *avg_us = ms * 1e3 / launches;
+  if (inner_nodes) *inner_nodes = (int64_t)(s->cd.nx - 3) * (s->cd.ny - 2);
   return IB_LBM_OK;
 }
 

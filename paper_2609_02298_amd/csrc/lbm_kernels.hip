@@ -209,7 +209,7 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
 
 // All nine pushes of a face node.
 template <typename T>
-__device__ __noinline__ void push_boundary9(const CaseDesc *c, T *dst, int x, int y, T f0, T f1,
+__device__ __forceinline__ void push_boundary9(const CaseDesc *c, T *dst, int x, int y, T f0, T f1,
                                             T f2, T f3, T f4, T f5, T f6, T f7, T f8) {
   push_one<T>(*c, dst, x, y, 0, f0);
   push_one<T>(*c, dst, x, y, 1, f1);

@@ -41,7 +41,7 @@ EXPORTS = [
     "ib_lbm_force_field", "ib_lbm_markers", "ib_lbm_steps_done", "ib_lbm_sync",
     "ib_lbm_destroy", "ib_lbm_last_error", "ib_lbm_footprint", "ib_lbm_set_launch",
     "ib_lbm_get_launch", "ib_lbm_set_spread", "ib_lbm_set_graph", "ib_lbm_timing_enable",
-    "ib_lbm_set_overlap", "ib_lbm_get_overlap",
+    "ib_lbm_set_overlap", "ib_lbm_get_overlap", "ib_lbm_time_collide_stream",
     "ib_lbm_timing_read", "ib_lbm_batch_create", "ib_lbm_batch_attach", "ib_lbm_batch_detach",
     "ib_lbm_batch_set_target", "ib_lbm_batch_step", "ib_lbm_batch_set_graph",
     "ib_lbm_batch_sync", "ib_lbm_batch_destroy", "ib_lbm_batch_last_error",
@@ -173,6 +173,7 @@ def load_library(path: str = LIB_PATH):
     L.ib_lbm_set_spread.argtypes = [vp, C.c_int32]
     L.ib_lbm_set_graph.argtypes = [vp, C.c_int32]
     L.ib_lbm_set_overlap.argtypes = [vp, C.c_int32]
+    L.ib_lbm_time_collide_stream.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
     L.ib_lbm_get_overlap.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
     L.ib_lbm_timing_enable.argtypes = [vp, C.c_int32]
     L.ib_lbm_timing_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
@@ -416,6 +417,16 @@ class Sim:
 
     def timing(self, on: bool):
         self._check(self.L.ib_lbm_timing_enable(self.h, 1 if on else 0), self.h)
+
+    def time_collide_stream(self, launches: int) -> tuple[float, int]:
+        """(average microseconds per collide-stream launch, inner nodes per
+        launch) over back-to-back launches; advances the populations without
+        face closures or IB passes (use a sim made for the measurement)."""
+        us = C.c_double()
+        n = C.c_int64()
+        self._check(self.L.ib_lbm_time_collide_stream(self.h, int(launches), C.byref(us), C.byref(n)),
+                    self.h)
+        return us.value, n.value
 
     def timing_read(self, which: int):
         ms = C.c_double(); n = C.c_int64()
