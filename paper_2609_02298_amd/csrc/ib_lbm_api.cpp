@@ -63,6 +63,7 @@ struct ib_lbm_sim {
   int nslots = 0;
   ib_lbm_launch launch = {128, 2, 1, 1};
   int spread_mode = 0;
+  int nslots_fast = 0;    // the first IB slots, run by the 1024-thread kernel
   int graph_steps = 0;
   hipGraphExec_t graph_exec = nullptr;
   int graph_len = 0;
@@ -90,13 +91,14 @@ struct ib_lbm_batch {
   std::vector<ib_lbm_sim *> sims;
   DevBuf d_cases, d_prefix, d_fprefix, d_slots;
   struct Group {
-    int collision, first, count, ntiles, prefix_off, nface;
+    int collision, first, count, ntiles, prefix_off, nface_blocks;
   };
   std::vector<Group> groups;
   int nslots = 0;
   int lds_bytes = 0;
   ib_lbm_launch launch = {128, 2, 1, 1};
   int spread_mode = 0;
+  int nslots_fast = 0;
   int graph_steps = 0;
   hipGraphExec_t graph_exec = nullptr;
   int graph_len = 0;
@@ -226,7 +228,7 @@ double host_omega_mdf(double xc, double yc, double R, int nb, int kernel, double
 }
 
 int ws_doubles_for(int scheme, int nb, int ns, int mr, int mn, int pop_bytes) {
-  return ws_tab_total(nb, ns, mr, mn) + ws_dyn_doubles(scheme, nb, ns, mn, pop_bytes);
+  return ws_tab_total(scheme, nb, ns, mr, mn) + ws_dyn_doubles(scheme, nb, ns, mn, pop_bytes);
 }
 
 // LDS bytes for an IB launch: enough for the largest workspace that fits;
@@ -284,6 +286,23 @@ ib_lbm_status plan_split(ib_lbm_sim *s) {
   return IB_LBM_OK;
 }
 
+// A body runs on the 1024-thread IB kernel when it is DF/MDF, its workspace
+// fits in LDS and spreading is by gather; the choice depends on the body
+// alone, so a body's results do not depend on its batch-mates.
+bool body_fast(const HostBody &hb, int spread_mode) {
+  return spread_mode == 0 && hb.dev.scheme != kDFC && hb.dev.ws_doubles * 8 <= ibm_max_lds_bytes();
+}
+
+// The IB launches of a step: slots [0, nfast) on the 1024-thread kernel,
+// the rest on the general one (bodies of one case may sit in both; the last
+// of a case's workgroups to finish, in either launch, completes the case).
+hipError_t launch_ibm_slots(int precision, const CaseDesc *cases, const IbmSlot *slots, int nfast, int n,
+                            int lds_bytes, int spread_mode, hipStream_t stream) {
+  hipError_t e = launch_ibm(precision, cases, slots, nfast, lds_bytes, spread_mode, 1, stream);
+  if (e != hipSuccess) return e;
+  return launch_ibm(precision, cases, slots + nfast, n - nfast, lds_bytes, spread_mode, 0, stream);
+}
+
 ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   if (!s->tables_dirty) return IB_LBM_OK;
   ib_lbm_status st0;
@@ -313,12 +332,18 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
     if (st) return st;
   }
   HIPCHK(s, hipMemcpy(s->d_case.p, &s->cd, sizeof(CaseDesc), hipMemcpyHostToDevice));
-  // tile prefix {0, tiles}, then face-node prefix {0, face nodes}
-  int32_t pre[4] = {0, s->cd.tiles_x * s->cd.tiles_y, 0, face_nodes(s->cd.nx, s->cd.ny)};
+  // tile prefix {0, tiles}, then face workgroup prefix {0, face workgroups}
+  int32_t pre[4] = {0, s->cd.tiles_x * s->cd.tiles_y, 0, face_blocks(s->cd.nx, s->cd.ny)};
   HIPCHK(s, hipMemcpy(s->d_prefix.p, pre, sizeof pre, hipMemcpyHostToDevice));
-  std::vector<IbmSlot> slots;
+  std::vector<IbmSlot> slots, rest;
   const int n = std::max(1, (int)bd.size());
-  for (int b = 0; b < n; b++) slots.push_back(IbmSlot{0, bd.empty() ? -1 : b, n, 0});
+  for (int b = 0; b < n; b++) {
+    const IbmSlot sl{0, bd.empty() ? -1 : b, n, 0};
+    if (!bd.empty() && body_fast(s->bodies[b], s->spread_mode)) slots.push_back(sl);
+    else rest.push_back(sl);
+  }
+  s->nslots_fast = (int)slots.size();
+  slots.insert(slots.end(), rest.begin(), rest.end());
   HIPCHK(s, hipMemcpy(s->d_slots.p, slots.data(), slots.size() * sizeof(IbmSlot), hipMemcpyHostToDevice));
   s->nslots = n;
   s->lds_bytes = lds_budget(maxws);
@@ -360,13 +385,13 @@ ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
   }
   HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
                                         (const int32_t *)s->d_prefix.p + 2, 1,
-                                        face_nodes(s->cd.nx, s->cd.ny), -1, 1, stream));
+                                        face_blocks(s->cd.nx, s->cd.ny), -1, 1, stream));
   if (timed) {
     p1 = take_pair(s->timing);
     HIPCHK(s, hipEventRecord(p1.a, stream));
   }
-  HIPCHK(s, launch_ibm(s->cd.precision, (const CaseDesc *)s->d_case.p, (const IbmSlot *)s->d_slots.p,
-                       s->nslots, s->lds_bytes, s->spread_mode, stream));
+  HIPCHK(s, launch_ibm_slots(s->cd.precision, (const CaseDesc *)s->d_case.p, (const IbmSlot *)s->d_slots.p,
+                             s->nslots_fast, s->nslots, s->lds_bytes, s->spread_mode, stream));
   if (timed) {
     HIPCHK(s, hipEventRecord(p1.b, stream));
     s->timing.ev[1].push_back(p1);
@@ -445,7 +470,7 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
     // face nodes lie outside the hold rectangle's reach (plan_split)
     HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
                                           (const int32_t *)s->d_prefix.p + 2, 1,
-                                          face_nodes(s->cd.nx, s->cd.ny), pa.cur, 0, s->lq));
+                                          face_blocks(s->cd.nx, s->cd.ny), pa.cur, 0, s->lq));
     // hold tiles of step i after the far tiles of step i-1 (the wait is
     // enqueued before ev_far is recorded again for step i)
     if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_far, 0));
@@ -456,8 +481,8 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
       p1 = take_pair(s->timing);
       HIPCHK(s, hipEventRecord(p1.a, s->iq));
     }
-    HIPCHK(s, launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, s->nslots, s->lds_bytes,
-                         s->spread_mode, s->iq));
+    HIPCHK(s, launch_ibm_slots(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, s->nslots_fast,
+                               s->nslots, s->lds_bytes, s->spread_mode, s->iq));
     if (timed) {
       HIPCHK(s, hipEventRecord(p1.b, s->iq));
       s->timing.ev[1].push_back(p1);
@@ -501,7 +526,7 @@ size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_
     const int mr = (int)std::ceil(D) + 12, mn = (int)(8 * M_PI * D + 8 * mr + 64);
     bytes += (size_t)(std::max(ws_doubles_for(kDFC, nb, 4, mr, mn, (int)elem),
                                ws_doubles_for(kMDF, nb, 4, mr, mn, (int)elem)) +
-                      ws_tab_total(nb, 4, mr, mn) + 2 * mn) * 8 +
+                      ws_tab_total(kMDF, nb, 4, mr, mn) + 2 * mn) * 8 +
              (size_t)nb * (8 + 1 + 2) * 8 +
              (size_t)hist * kHistCols * 8 + sizeof(BodyState) + sizeof(BodyDesc);
   }
@@ -687,7 +712,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
     }
   B.max_rows = (int)std::ceil(2 * B.radius) + 2 * B.ns + 4;
   B.max_nodes = maxn + maxn / 10 + 32;
-  B.ws_tab = ws_tab_total(nb, B.ns, B.max_rows, B.max_nodes);
+  B.ws_tab = ws_tab_total(b->scheme, nb, B.ns, B.max_rows, B.max_nodes);
+  B.ws_tab_hot = ws_tab_hot(b->scheme, nb, B.ns, B.max_nodes);
   B.pop_bytes = s->cfg.precision == IB_LBM_FP64 ? 8 : 4;
   B.ws_doubles = ws_doubles_for(b->scheme, nb, B.ns, B.max_rows, B.max_nodes, B.pop_bytes);
   // gather window: a node within s*sqrt(2) of marker k lies within angle
@@ -1161,6 +1187,7 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
   std::vector<CaseDesc> cases;
   std::vector<int32_t> prefix;
   std::vector<IbmSlot> slots;
+  std::vector<ib_lbm_sim *> case_sims;  // the sim of each case entry
   std::vector<int32_t> fprefix;
   b->groups.clear();
   int maxws = 0;
@@ -1174,8 +1201,9 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
       prefix.push_back(tiles);
       tiles += c.tiles_x * c.tiles_y;
       fprefix.push_back(faces);
-      faces += face_nodes(c.nx, c.ny);
+      faces += face_blocks(c.nx, c.ny);
       cases.push_back(c);
+      case_sims.push_back(s);
       g.count++;
       for (auto &hb : s->bodies)
         if (hb.dev.ws_doubles * 8 <= ibm_max_lds_bytes()) maxws = std::max(maxws, hb.dev.ws_doubles);
@@ -1183,13 +1211,20 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
     prefix.push_back(tiles);
     fprefix.push_back(faces);
     g.ntiles = tiles;
-    g.nface = faces;
+    g.nface_blocks = faces;
     if (g.count) b->groups.push_back(g);
   }
+  std::vector<IbmSlot> rest;
   for (int ci = 0; ci < (int)cases.size(); ci++) {
     const int n = std::max(1, cases[ci].nbodies);
-    for (int k = 0; k < n; k++) slots.push_back(IbmSlot{ci, cases[ci].nbodies ? k : -1, n, 0});
+    for (int k = 0; k < n; k++) {
+      const IbmSlot sl{ci, cases[ci].nbodies ? k : -1, n, 0};
+      if (cases[ci].nbodies && body_fast(case_sims[ci]->bodies[k], b->spread_mode)) slots.push_back(sl);
+      else rest.push_back(sl);
+    }
   }
+  b->nslots_fast = (int)slots.size();
+  slots.insert(slots.end(), rest.begin(), rest.end());
   auto upload = [&](DevBuf *d, const void *src, size_t bytes) -> ib_lbm_status {
     if (d->bytes < bytes) {
       if (d->p) (void)hipFree(d->p);
@@ -1212,6 +1247,7 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
   }
   b->nslots = (int)slots.size();
   b->lds_bytes = lds_budget(maxws);
+
   b->dirty = false;
   return IB_LBM_OK;
 }
@@ -1225,10 +1261,10 @@ static ib_lbm_status batch_enqueue_step(ib_lbm_batch *b, hipStream_t stream) {
     BHIPCHK(b, launch_collide_stream_faces(b->precision, g.collision,
                                            (const CaseDesc *)b->d_cases.p + g.first,
                                            (const int32_t *)b->d_fprefix.p + g.prefix_off, g.count,
-                                           g.nface, -1, 1, stream));
+                                           g.nface_blocks, -1, 1, stream));
   }
-  BHIPCHK(b, launch_ibm(b->precision, (const CaseDesc *)b->d_cases.p, (const IbmSlot *)b->d_slots.p,
-                        b->nslots, b->lds_bytes, b->spread_mode, stream));
+  BHIPCHK(b, launch_ibm_slots(b->precision, (const CaseDesc *)b->d_cases.p, (const IbmSlot *)b->d_slots.p,
+                              b->nslots_fast, b->nslots, b->lds_bytes, b->spread_mode, stream));
   return IB_LBM_OK;
 }
 

@@ -28,6 +28,7 @@ enum { kCaseHalted = 1 };
 
 constexpr int kMaxBodiesPerCase = 8;
 constexpr int kIbmThreads = 512;
+constexpr int kIbmThreadsFast = 1024;
 constexpr int kHistCols = 16;
 
 // Mutable per-case state, device resident.
@@ -57,7 +58,7 @@ struct BodyState {
   int32_t box_valid;
   int32_t lambda_valid; // DFC cache filled (fixed bodies)
   int32_t tables_valid; // geometry tables cached (fixed bodies)
-  int32_t pad;
+  int32_t tables_full;  // a step needs the whole cached table, not only its hot part
 };
 
 // Constant per-body description plus pointers to the body's device buffers.
@@ -77,6 +78,7 @@ struct BodyDesc {
   double *tab_cache;    // cached geometry tables of a fixed body (ws_tab doubles)
   double *acc;          // 2 x max_nodes scratch of the atomic-scatter variant
   int32_t ws_tab;       // doubles of the table part of the workspace
+  int32_t ws_tab_hot;   // doubles of its hot part (what a DF/MDF step reads)
   int32_t pop_bytes;    // bytes of one stored population (8 FP64, 4 FP32 shifted)
   double *markers_out;  // n_b x 8: X Y Udx Udy Fx Fy lambda ds
   double *lambda_cache; // n_b
@@ -104,28 +106,42 @@ struct CaseDesc {
 
 // Workspace of one body, in doubles.  The table part (marker geometry,
 // compact support description, node -> marker lists) comes first so that it
-// can be cached and copied in bulk; the per-step arrays follow.
+// can be cached and copied in bulk; the per-step arrays follow.  Within the
+// table, what a step reads comes first (the hot part, ws_tab_hot doubles),
+// what only the construction, DFC and nodes with long lists read follows.
 //   doubles: X Y Udx Udy (nb each), wx wy (nb*ns each)
-//   ints:    ix0 iy0 (nb each), nidx (nb*ns*ns), ra1 rl1 ra2 (mr each),
-//            off (mr+1), nxy (mn), noff (mn+1), nent (nb*ns*ns), S (1)
-//            [padded to even]
-//   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each),
-//                     ew (nb*ns*ns: the weight of each node -> marker entry)
+//   ints:    nrow (nb*ns: the first support node of each stencil row), nxy
+//            (mn), ell (DF/MDF only, ell_width(ns)*mn:
+//            the first entries of each node's list, node-fastest), S (1)
+//            [padded to even: the end of the hot part]
+//            ix0 iy0 (nb each), ra1 rl1 ra2 (mr each), off (mr+1),
+//            noff (mn+1), nent (nb*ns*ns) [padded to even]
+//   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each)
 //   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), then the staged
 //                     populations (9 mn of T), overlaid by the W_total node
 //                     array while the correction scale is built and, at the
 //                     end, by the node velocities of the corrected populations
+// Fixed width of the node-fastest copy of the node -> marker lists: a node
+// is covered by at most this many markers at unit marker spacing.
+__host__ __device__ inline int ell_width(int ns) { return ns == 4 ? 6 : 3; }
 __host__ __device__ inline int ws_table_doubles(int nb, int ns) { return nb * (4 + 2 * ns); }
-__host__ __device__ inline int ws_table_ints(int nb, int ns, int mr, int mn) {
-  const int n = nb * (2 + 2 * ns * ns) + 4 * mr + 1 + 2 * mn + 1 + 1;
+__host__ __device__ inline int ws_hot_ints(int scheme, int nb, int ns, int mn) {
+  const int n = nb * ns + mn + (scheme != 2 ? ell_width(ns) * mn : 0) + 1;
   return (n + 1) & ~1;
 }
-__host__ __device__ inline int ws_tab_total(int nb, int ns, int mr, int mn) {
-  return ws_table_doubles(nb, ns) + ws_table_ints(nb, ns, mr, mn) / 2;
+__host__ __device__ inline int ws_table_ints(int scheme, int nb, int ns, int mr, int mn) {
+  const int n = 2 * nb + 4 * mr + 1 + mn + 1 + nb * ns * ns;
+  return ws_hot_ints(scheme, nb, ns, mn) + ((n + 1) & ~1);
+}
+__host__ __device__ inline int ws_tab_hot(int scheme, int nb, int ns, int mn) {
+  return ws_table_doubles(nb, ns) + ws_hot_ints(scheme, nb, ns, mn) / 2;
+}
+__host__ __device__ inline int ws_tab_total(int scheme, int nb, int ns, int mr, int mn) {
+  return ws_table_doubles(nb, ns) + ws_table_ints(scheme, nb, ns, mr, mn) / 2;
 }
 __host__ __device__ inline int ws_dyn_doubles(int scheme, int nb, int ns, int mn, int pop_bytes) {
   if (scheme == 2) return nb * 12 + (9 * mn * pop_bytes + 7) / 8;
-  return nb * 5 + mn * 3 + nb * ns * ns;
+  return nb * 5 + mn * 3;
 }
 
 // One IB workgroup: the body `body` of case `cas` (body = -1: a case without
@@ -141,6 +157,12 @@ struct IbmSlot {
 // x = 0, nx-2 and nx-1 in between (the nodes with a link that leaves the
 // lattice, and the column the zero-gradient outlet copies from).
 __host__ __device__ inline int face_nodes(int nx, int ny) { return 2 * nx + 3 * (ny - 2); }
+// The face launch gives every case whole workgroups of kFaceBlock nodes, so
+// that a workgroup's case (and every read of its description) is uniform.
+constexpr int kFaceBlock = 256;
+__host__ __device__ inline int face_blocks(int nx, int ny) {
+  return (face_nodes(nx, ny) + kFaceBlock - 1) / kFaceBlock;
+}
 
 struct LaunchShape {
   int32_t block_x, block_y, rows_per_thread, xcd_remap;
@@ -159,16 +181,17 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
                                  const int32_t *tile_prefix, int ncases, int ntiles,
                                  LaunchShape shape, hipStream_t stream);
 // The face nodes (rows 0 and ny-1, columns 0, nx-2, nx-1) with the face
-// closures; cur < 0 takes each case's lattice from its state.
+// closures; face_prefix[i] is the first workgroup of case i (face_blocks per
+// case), nblocks the total; cur < 0 takes each case's lattice from its state.
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
-                                       const int32_t *face_prefix, int ncases, int nface, int cur,
+                                       const int32_t *face_prefix, int ncases, int nblocks, int cur,
                                        int force, hipStream_t stream);
 // One part of a pipelined step: near = 1 the hold rectangle, 0 the other tiles.
 hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
                                       LaunchShape shape, const PipeArgs &pa, int near,
                                       hipStream_t stream);
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
-                      int lds_bytes, int spread_mode, hipStream_t stream);
+                      int lds_bytes, int spread_mode, int fast, hipStream_t stream);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
                          hipStream_t stream);

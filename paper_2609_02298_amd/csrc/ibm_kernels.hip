@@ -50,17 +50,42 @@ __device__ __forceinline__ double delta1(int kernel, double r) {
 }
 
 // ---- fixed-order block reductions (wave64 shuffles, then LDS) ----
+// A double moved across lanes by a DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// Wave64 sum and maximum with every lane active: within each row of 16
+// lanes a fixed tree of lane exchanges (pairs, pairs of pairs, half-row
+// mirror, row mirror; each step leaves the same value in both partners, as
+// IEEE addition commutes), then the four row totals in a fixed order.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 __device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-  return v;
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
 // Reduces four values at once: three sums and one max; result valid in all threads.
-// Sums a, b, c, d and maxima m1, m2 over the workgroup, each in the same
-// fixed order (wave sums, then the waves in index order).
+// Sums a, b, c, d and maxima m1, m2 over the workgroup, each in a fixed
+// order: wave totals, then the wave totals (one lane of wave 0 each) by the
+// same wave tree.  The results are valid in the threads of wave 0.
 __device__ __forceinline__ void block_reduce6(double &a, double &b, double &c, double &d, double &m1,
                                               double &m2, double *red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -72,27 +97,16 @@ __device__ __forceinline__ void block_reduce6(double &a, double &b, double &c, d
     red[6 * wv + 4] = m1; red[6 * wv + 5] = m2;
   }
   __syncthreads();
-  double sa = 0, sb = 0, sc = 0, sd = 0, x1 = -1e300, x2 = -1e300;
-  for (int w = 0; w < nw; w++) {
-    sa += red[6 * w]; sb += red[6 * w + 1]; sc += red[6 * w + 2]; sd += red[6 * w + 3];
-    x1 = fmax(x1, red[6 * w + 4]); x2 = fmax(x2, red[6 * w + 5]);
+  if (wv == 0) {
+    const bool in = lane < nw;
+    const double *r = red + 6 * min(lane, nw - 1);
+    a = wave_sum(in ? r[0] : 0.0);
+    b = wave_sum(in ? r[1] : 0.0);
+    c = wave_sum(in ? r[2] : 0.0);
+    d = wave_sum(in ? r[3] : 0.0);
+    m1 = wave_max(in ? r[4] : -1e300);
+    m2 = wave_max(in ? r[5] : -1e300);
   }
-  a = sa; b = sb; c = sc; d = sd; m1 = x1; m2 = x2;
-  __syncthreads();
-}
-
-__device__ __forceinline__ void block_reduce4(double &a, double &b, double &c, double &m, double *red) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); m = wave_max(m);
-  __syncthreads();
-  if (lane == 0) { red[4 * wv] = a; red[4 * wv + 1] = b; red[4 * wv + 2] = c; red[4 * wv + 3] = m; }
-  __syncthreads();
-  double sa = 0, sb = 0, sc = 0, sm = -1e300;
-  for (int w = 0; w < nw; w++) {
-    sa += red[4 * w]; sb += red[4 * w + 1]; sc += red[4 * w + 2]; sm = fmax(sm, red[4 * w + 3]);
-  }
-  a = sa; b = sb; c = sc; m = sm;
-  __syncthreads();
 }
 
 // Exclusive prefix sum of cnt[0..n) into off[0..n], off[n] = total.  Each
@@ -131,11 +145,10 @@ __device__ __forceinline__ void block_scan(const int *cnt, int *off, int n, int 
 // q * nb + k), so that the 64 lanes of a wave, which handle 64 consecutive
 // markers, read consecutive LDS words and hit distinct banks.
 struct WsLayout {
-  int nb;
+  int nb, mn, ns;
   double *X, *Y, *Udx, *Udy, *wx, *wy;                           // table doubles
-  int *ix0, *iy0, *nidx, *ra1, *rl1, *ra2, *off, *nxy, *noff, *nent, *S;  // table ints
+  int *ix0, *iy0, *nrow, *ra1, *rl1, *ra2, *off, *nxy, *noff, *nent, *ell, *S;  // table ints
   double *rhoX, *Fx, *Fy, *Ftx, *Fty, *lam, *dlt;                // per-step, markers
-  double *ew;                                                    // per-step, node entries
   void *stage;                                                   // DFC populations
   double *nrho, *nux, *nuy, *nW;                                 // per-step, nodes
   int *lmin, *lmax, *rmin, *rmax, *cnt, *ncnt, *nfill;  // construction scratch (per-step area)
@@ -145,37 +158,49 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   const int nb = B.nb, ns = B.ns, mr = B.max_rows, mn = B.max_nodes;
   WsLayout L;
   L.nb = nb;
+  L.mn = mn;
+  L.ns = ns;
   double *p = base;
   L.X = p; p += nb; L.Y = p; p += nb; L.Udx = p; p += nb; L.Udy = p; p += nb;
   L.wx = p; p += nb * ns; L.wy = p; p += nb * ns;
   int *q = (int *)p;
-  L.ix0 = q; q += nb; L.iy0 = q; q += nb; L.nidx = q; q += nb * ns * ns;
+  L.nrow = q; q += nb * ns; L.nxy = q; q += mn;
+  L.ell = q; q += B.scheme != kDFC ? ell_width(ns) * mn : 0; L.S = q;
+  q = (int *)(base + ws_tab_hot(B.scheme, nb, ns, mn));
+  L.ix0 = q; q += nb; L.iy0 = q; q += nb;
   L.ra1 = q; q += mr; L.rl1 = q; q += mr; L.ra2 = q; q += mr; L.off = q; q += mr + 1;
-  L.nxy = q; q += mn; L.noff = q; q += mn + 1; L.nent = q; q += nb * ns * ns; L.S = q;
-  double *d = base + ws_tab_total(nb, ns, mr, mn);
+  L.noff = q; q += mn + 1; L.nent = q;
+  double *d = base + ws_tab_total(B.scheme, nb, ns, mr, mn);
   // arrays a scheme does not use alias the start of the per-step area (never
   // null, so that every pointer provably stays in the workspace's address
   // space and the LDS instantiation uses LDS instructions)
-  L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = L.nux = L.nuy = L.ew = d;
+  L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = L.nux = L.nuy = d;
   L.stage = (void *)d;
   if (B.scheme != kDFC) {
     L.rhoX = d; d += nb; L.Fx = d; d += nb; L.Fy = d; d += nb; L.Ftx = d; d += nb; L.Fty = d; d += nb;
     L.nrho = d; d += mn;
     L.nux = d; d += mn; L.nuy = d; d += mn;
-    L.ew = d; d += nb * ns * ns;
   } else {
     L.Ftx = d; d += nb; L.Fty = d; d += nb; L.lam = d; d += nb; L.dlt = d; d += 9 * nb;
     L.stage = (void *)d;  // 9 x mn populations of the stored type
     L.nW = d;             // overlays the staging area before it is filled
   }
-  int *c = (int *)(base + ws_tab_total(nb, ns, mr, mn) + (B.scheme == kDFC ? 12 * nb : 5 * nb));
+  int *c = (int *)(base + ws_tab_total(B.scheme, nb, ns, mr, mn) + (B.scheme == kDFC ? 12 * nb : 5 * nb));
   L.lmin = c; c += mr; L.lmax = c; c += mr; L.rmin = c; c += mr; L.rmax = c; c += mr; L.cnt = c;
   c += mr;
   L.ncnt = c; c += mn; L.nfill = c;
   return L;
 }
 
-__device__ __forceinline__ int &NIDX(const WsLayout &L, int k, int q) { return L.nidx[q * L.nb + k]; }
+// Support node of stencil slot q = jy * ns + jx of marker k.  A marker's
+// stencil row lies in one x-interval of its support row, so its nodes are
+// consecutive in the compact numbering: the table keeps each stencil row's
+// first node (nrow, marker-fastest) and adds jx.
+__device__ __forceinline__ int NROW(const WsLayout &L, int k, int jy) { return L.nrow[jy * L.nb + k]; }
+__device__ __forceinline__ int NIDX(const WsLayout &L, int k, int q) {
+  const int sh = L.ns == 4 ? 2 : 1;
+  return NROW(L, k, q >> sh) + (q & (L.ns - 1));
+}
 __device__ __forceinline__ double &WX(const WsLayout &L, int k, int j) { return L.wx[j * L.nb + k]; }
 __device__ __forceinline__ double &WY(const WsLayout &L, int k, int j) { return L.wy[j * L.nb + k]; }
 __device__ __forceinline__ double &DLT(const WsLayout &L, int k, int i) { return L.dlt[i * L.nb + k]; }
@@ -206,18 +231,35 @@ __device__ __forceinline__ void get_u(const double *stg, int mn, int j, double &
   uy = stg[mn + j];
 }
 
-// interp2 of the packed node velocities.
-template <int NS, typename T>
-__device__ __forceinline__ void interp_packed_u(const WsLayout &L, int k, const T *stg, int mn,
+// Marker loops run LPM lanes per marker (2, or 4 in the 1024-thread kernel
+// with Peskin 4-point): lanes m*LPM .. m*LPM+LPM-1 of a wave share marker
+// k, lane h sums the stencil rows [h NS/LPM, (h+1) NS/LPM) and group_sum
+// adds the partial sums of the group with DPP quad permutations (lanes
+// 0<->1, 2<->3, then 0,1<->2,3 of every quad).  IEEE addition commutes, so
+// every lane of a group holds the same total.  All lanes of a group are
+// always active together (the loops over LPM nb entries step by a block
+// size that is a multiple of LPM).
+template <int LPM>
+__device__ __forceinline__ double group_sum(double v) {
+  if (LPM >= 2) v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+  if (LPM >= 4) v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
+  return v;
+}
+
+// Partial interp2 of the packed node velocities (see group_sum).
+template <int NS, int LPM, typename T>
+__device__ __forceinline__ void interp_packed_u(const WsLayout &L, int k, int h, const T *stg, int mn,
                                                 double &oa, double &ob) {
+  constexpr int R = NS / LPM;
   double a = 0.0, b = 0.0;
 #pragma unroll
-  for (int jy = 0; jy < NS; jy++) {
+  for (int r = 0; r < R; r++) {
+    const int jy = h * R + r;
     double ra = 0.0, rb = 0.0;
 #pragma unroll
     for (int jx = 0; jx < NS; jx++) {
       double ux, uy;
-      get_u(stg, mn, NIDX(L, k, jy * NS + jx), ux, uy);
+      get_u(stg, mn, NROW(L, k, jy) + jx, ux, uy);
       const double w = WX(L, k, jx);
       ra += ux * w;
       rb += uy * w;
@@ -225,8 +267,8 @@ __device__ __forceinline__ void interp_packed_u(const WsLayout &L, int k, const 
     a += ra * WY(L, k, jy);
     b += rb * WY(L, k, jy);
   }
-  oa = a;
-  ob = b;
+  oa = group_sum<LPM>(a);
+  ob = group_sum<LPM>(b);
 }
 
 // Spreading by gather: node j sums v_k D_h(x_j - X_k) over the markers
@@ -237,31 +279,50 @@ __device__ __forceinline__ double node_weight(const WsLayout &L, int kq) {
   return WX(L, k, q % NS) * WY(L, k, q / NS);
 }
 
+// Entries of the node-fastest lists: (marker << 4) | stencil slot, with
+// kEllPad marking a padding slot (it repeats a real entry of the node, or
+// entry 0, and takes weight 0) and kEllMore on the last slot of a node whose
+// list continues in the CSR list (denser marker spacings).
+constexpr int kEllPad = int(0x80000000u);
+constexpr int kEllMore = 0x40000000;
+
 // Calls f(k, w) for the markers k covering node j, in increasing marker
-// order.  The first U entries are loaded together (a node is covered by at
-// most U markers at unit marker spacing); entries past the node's count
-// repeat its last entry with weight 0, which leaves every sum unchanged.
-// Entries beyond U, at denser marker spacings, follow one by one.
-// EW: the entry weights were formed once in L.ew (DF/MDF); otherwise they
-// are formed from the marker weights on the fly.
-template <int NS, bool EW = false, typename F>
+// order: the fixed-width slots first (one load each, at consecutive
+// addresses for consecutive nodes; padding adds w = 0, which leaves every
+// sum unchanged), then, rarely, the rest of the CSR list.
+template <int NS, typename F>
 __device__ __forceinline__ void for_node_entries(const WsLayout &L, int j, F &&f) {
+  constexpr int U = NS == 4 ? 6 : 3;
+  int kq[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) kq[u] = L.ell[u * L.mn + j];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int v = kq[u] & ~(kEllPad | kEllMore);
+    const double w = node_weight<NS>(L, v);
+    f(v >> 4, kq[u] < 0 ? 0.0 : w);
+  }
+  if (kq[U - 1] & kEllMore) {
+    for (int e = L.noff[j] + U; e < L.noff[j + 1]; e++) {
+      const int q = L.nent[e];
+      f(q >> 4, node_weight<NS>(L, q));
+    }
+  }
+}
+
+// The same from the CSR list alone (DFC), the weights formed on the fly.
+template <int NS, typename F>
+__device__ __forceinline__ void for_node_entries_csr(const WsLayout &L, int j, F &&f) {
   constexpr int U = NS == 4 ? 6 : 3;
   const int e0 = L.noff[j], e1 = L.noff[j + 1];
   int kq[U];
-  double w[U];
 #pragma unroll
-  for (int u = 0; u < U; u++) {
-    const int e = min(e0 + u, e1 - 1);
-    kq[u] = L.nent[e];
-    if (EW) w[u] = L.ew[e];
-  }
+  for (int u = 0; u < U; u++) kq[u] = L.nent[min(e0 + u, e1 - 1)];
 #pragma unroll
-  for (int u = 0; u < U; u++)
-    f(kq[u] >> 4, e0 + u < e1 ? (EW ? w[u] : node_weight<NS>(L, kq[u])) : 0.0);
+  for (int u = 0; u < U; u++) f(kq[u] >> 4, e0 + u < e1 ? node_weight<NS>(L, kq[u]) : 0.0);
   for (int e = e0 + U; e < e1; e++) {
     const int q = L.nent[e];
-    f(q >> 4, EW ? L.ew[e] : node_weight<NS>(L, q));
+    f(q >> 4, node_weight<NS>(L, q));
   }
 }
 
@@ -269,7 +330,7 @@ template <int NS>
 __device__ __forceinline__ void gather2(const WsLayout &L, int j, const double *va,
                                         const double *vb, double &oa, double &ob) {
   double a = 0.0, b = 0.0;
-  for_node_entries<NS, true>(L, j, [&](int k, double w) {
+  for_node_entries<NS>(L, j, [&](int k, double w) {
     a += va[k] * w;
     b += vb[k] * w;
   });
@@ -277,30 +338,37 @@ __device__ __forceinline__ void gather2(const WsLayout &L, int j, const double *
   ob = b;
 }
 
-// Interpolation of node arrays to marker k (Eq. 7).
-template <int NS>
-__device__ __forceinline__ double interp1(const WsLayout &L, int k, const double *nv) {
+// Interpolation of node arrays to marker k (Eq. 7): rows in x weighted by
+// w_x, then by w_y; lane h of the marker's group takes NS / LPM of the rows
+// (see group_sum).
+template <int NS, int LPM>
+__device__ __forceinline__ double interp1(const WsLayout &L, int k, int h, const double *nv) {
+  constexpr int R = NS / LPM;
   double acc = 0.0;
 #pragma unroll
-  for (int jy = 0; jy < NS; jy++) {
+  for (int r = 0; r < R; r++) {
+    const int jy = h * R + r;
     double row = 0.0;
+    const int j0 = NROW(L, k, jy);
 #pragma unroll
-    for (int jx = 0; jx < NS; jx++) row += nv[NIDX(L, k, jy * NS + jx)] * WX(L, k, jx);
+    for (int jx = 0; jx < NS; jx++) row += nv[j0 + jx] * WX(L, k, jx);
     acc += row * WY(L, k, jy);
   }
-  return acc;
+  return group_sum<LPM>(acc);
 }
 
-template <int NS>
-__device__ __forceinline__ void interp2(const WsLayout &L, int k, const double *na,
+template <int NS, int LPM>
+__device__ __forceinline__ void interp2(const WsLayout &L, int k, int h, const double *na,
                                         const double *nb_, double &oa, double &ob) {
+  constexpr int R = NS / LPM;
   double a = 0.0, b = 0.0;
 #pragma unroll
-  for (int jy = 0; jy < NS; jy++) {
+  for (int r = 0; r < R; r++) {
+    const int jy = h * R + r;
     double ra = 0.0, rb = 0.0;
 #pragma unroll
     for (int jx = 0; jx < NS; jx++) {
-      const int j = NIDX(L, k, jy * NS + jx);
+      const int j = NROW(L, k, jy) + jx;
       const double w = WX(L, k, jx);
       ra += na[j] * w;
       rb += nb_[j] * w;
@@ -308,8 +376,8 @@ __device__ __forceinline__ void interp2(const WsLayout &L, int k, const double *
     a += ra * WY(L, k, jy);
     b += rb * WY(L, k, jy);
   }
-  oa = a;
-  ob = b;
+  oa = group_sum<LPM>(a);
+  ob = group_sum<LPM>(b);
 }
 
 // Steps 2-3: markers, weights and the compact support.  Returns the node
@@ -385,29 +453,30 @@ __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B
   for (int k = tid; k < nb; k += nth) {
     for (int jy = 0; jy < ns; jy++) {
       const int r = L.iy0[k] + jy - ylo;
-      for (int jx = 0; jx < ns; jx++) {
-        const int x = L.ix0[k] + jx;
-        const int loc = (x >= L.ra1[r] && x < L.ra1[r] + L.rl1[r]) ? x - L.ra1[r]
-                                                                  : L.rl1[r] + x - L.ra2[r];
-        NIDX(L, k, jy * ns + jx) = L.off[r] + loc;
-      }
+      const int x = L.ix0[k];
+      const int loc = (x >= L.ra1[r] && x < L.ra1[r] + L.rl1[r]) ? x - L.ra1[r] : L.rl1[r] + x - L.ra2[r];
+      L.nrow[jy * nb + k] = L.off[r] + loc;
     }
   }
   __syncthreads();
   // node -> marker lists (CSR): count, scan, fill, then sort each short list
   // by marker index so the gather order does not depend on atomic timing
   const int nq = ns * ns;
-  for (int e = tid; e < nb * nq; e += nth) atomicAdd(&L.ncnt[L.nidx[e]], 1);
+  for (int e = tid; e < nb * nq; e += nth) {
+    const int q = e / nb, k = e - q * nb;  // e = q * nb + k
+    atomicAdd(&L.ncnt[NIDX(L, k, q)], 1);
+  }
   __syncthreads();
   block_scan(L.ncnt, L.noff, S, wsum);
   for (int j = tid; j < S; j += nth) L.nfill[j] = L.noff[j];
   __syncthreads();
   for (int e = tid; e < nb * nq; e += nth) {
     const int q = e / nb, k = e - q * nb;  // e = q * nb + k
-    const int pos = atomicAdd(&L.nfill[L.nidx[e]], 1);
+    const int pos = atomicAdd(&L.nfill[NIDX(L, k, q)], 1);
     L.nent[pos] = (k << 4) | q;
   }
   __syncthreads();
+  const int uw = ell_width(ns), mn = B.max_nodes;
   for (int j = tid; j < S; j += nth) {
     const int e0 = L.noff[j], e1 = L.noff[j + 1];
     for (int a = e0 + 1; a < e1; a++) {
@@ -416,6 +485,14 @@ __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B
       while (b >= e0 && L.nent[b] > v) { L.nent[b + 1] = L.nent[b]; b--; }
       L.nent[b + 1] = v;
     }
+    // the node-fastest copy of the first entries (DF/MDF)
+    const int cnt = e1 - e0;
+    for (int u = 0; u < (B.scheme != kDFC ? uw : 0); u++) {
+      int v = u < cnt ? L.nent[e0 + u] : ((cnt > 0 ? L.nent[e1 - 1] : 0) | kEllPad);
+      if (u == uw - 1 && cnt > uw) v |= kEllMore;
+      L.ell[u * mn + j] = v;
+    }
+    if (cnt > uw) atomicOr(&ish[5], 1);
   }
   if (tid == 0) L.S[0] = S;
   __syncthreads();
@@ -441,9 +518,14 @@ __device__ __forceinline__ void copy_doubles(double *dst, const double *src, int
   if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
 }
 
-template <typename T, bool LDS, int NS>
-__device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, double *dyn,
-                          int spread_mode, double *red, int *ish, double *bsh) {
+// FAST: the 1024-thread instance for DF/MDF bodies with an LDS workspace
+// and gather spreading (no DFC or atomic-scatter code, so that it fits 128
+// VGPRs); marker loops then run one lane per stencil row.
+template <typename T, bool LDS, int NS, bool FAST>
+__device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, int cur,
+                                          double *dyn, int spread_mode, double *red, int *ish,
+                                          double *bsh) {
+  constexpr int LPM = FAST ? NS : 2;
   const int tid = threadIdx.x, nth = blockDim.x;
   BodyState *bs = B.state;
   const int nb = B.nb;
@@ -452,6 +534,10 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   const double rho0 = c.rho0;
   const int nx = c.nx;
   const uint32_t plane = (uint32_t)c.plane;
+  // post-stream populations of this step (the IB pass runs after the
+  // collide-stream into lattice cur ^ 1)
+  const T *fpop = (const T *)c.f[cur ^ 1];
+  T *fpop_w = (T *)c.f[cur ^ 1];
 
   // ---- 1. kinematics for t_{n+1}
   if (tid == 0) {
@@ -494,6 +580,8 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     ish[1] = bs->tables_valid;
     ish[2] = bs->lambda_valid;
     ish[3] = bs->flags;
+    ish[4] = bs->tables_full;
+    ish[5] = 0;  // set by build_tables when a node's list outgrows its fixed-width copy
   }
   __syncthreads();
   const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
@@ -506,7 +594,8 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   // ---- 2-3. tables: cached for fixed bodies
   int S;
   if (fixed && ish[1]) {
-    if (in_lds) copy_doubles(base, B.tab_cache, B.ws_tab);
+    // a DF/MDF step without long node lists reads only the hot part
+    if (in_lds) copy_doubles(base, B.tab_cache, ish[4] ? B.ws_tab : B.ws_tab_hot);
     __syncthreads();
     S = L.S[0];
   } else {
@@ -523,20 +612,21 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     }
     if (fixed) {
       if (in_lds) copy_doubles(B.tab_cache, base, B.ws_tab);
-      if (tid == 0) bs->tables_valid = 1;
+      if (tid == 0) {
+        bs->tables_full = (B.scheme == kDFC || ish[5]) ? 1 : 0;
+        bs->tables_valid = 1;
+      }
     }
   }
-  const T *fpop = (const T *)c.f[c.state->cur ^ 1];
-  T *fpop_w = (T *)c.f[c.state->cur ^ 1];
   const double ds = B.ds;
   double fsum_x = 0, fsum_y = 0, tq = 0, resmax = 0;
 
-  if (B.scheme != kDFC) {
+  if (FAST || B.scheme != kDFC) {
     // ---- 4a. DF (one pass, omega 1) / MDF (N passes, omega_MDF)
     // moments of the post-stream populations at the support nodes; the
     // loads of UM nodes per thread are issued before any is used (one round
     // trip to device memory covers up to UM * 512 nodes)
-    constexpr int UM = sizeof(T) == 4 ? 3 : 2;
+    constexpr int UM = FAST ? 1 : (sizeof(T) == 4 ? 3 : 2);
     for (int j0 = tid; j0 < S; j0 += UM * nth) {
       T v[UM][9];
 #pragma unroll
@@ -553,8 +643,6 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       for (int u = 0; u < UM; u++) {
         const int j = j0 + u * nth;
         if (j >= S) continue;
-        // weights of the node's marker entries, used by every gather below
-        for (int e = L.noff[j]; e < L.noff[j + 1]; e++) L.ew[e] = node_weight<NS>(L, L.nent[e]);
         double sm = 0, jx = 0, jy = 0;
 #pragma unroll
         for (int i = 0; i < 9; i++) {
@@ -573,12 +661,16 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     double *accx = B.acc, *accy = B.acc + B.max_nodes;
     if (B.scheme == kDF) {
       // DF, Eq. (11): one interpolation of u*, F_L = 2 rho(X) (U_d - U)
-      for (int k = tid; k < nb; k += nth) {
-        L.rhoX[k] = interp1<NS>(L, k, L.nrho);
+      for (int kk = tid; kk < LPM * nb; kk += nth) {
+        const int k = kk / LPM, h = kk % LPM;
+        const double rX = interp1<NS, LPM>(L, k, h, L.nrho);
         double Ux, Uy;
-        interp2<NS>(L, k, L.nux, L.nuy, Ux, Uy);
-        L.Ftx[k] = 2.0 * L.rhoX[k] * (L.Udx[k] - Ux);
-        L.Fty[k] = 2.0 * L.rhoX[k] * (L.Udy[k] - Uy);
+        interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
+        if (h == 0) {
+          L.rhoX[k] = rX;
+          L.Ftx[k] = 2.0 * rX * (L.Udx[k] - Ux);
+          L.Fty[k] = 2.0 * rX * (L.Udy[k] - Uy);
+        }
       }
     } else {
       // MDF, Eq. (12)-(14): N passes of interpolation, force and spreading
@@ -586,28 +678,38 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       // interpolated once; F_total accumulates omega F^(n).
       const int N = B.mdf_iters;
       const double om = B.omega_mdf;
-      for (int k = tid; k < nb; k += nth) {
-        L.rhoX[k] = interp1<NS>(L, k, L.nrho);
-        L.Ftx[k] = 0.0;
-        L.Fty[k] = 0.0;
+      for (int kk = tid; kk < LPM * nb; kk += nth) {
+        const int k = kk / LPM, h = kk % LPM;
+        const double rX = interp1<NS, LPM>(L, k, h, L.nrho);
+        if (h == 0) {
+          L.rhoX[k] = rX;
+          L.Ftx[k] = 0.0;
+          L.Fty[k] = 0.0;
+        }
       }
       __syncthreads();
       // from here on nrho holds ds / (2 rho(x)), the factor of every pass
       for (int j = tid; j < S; j += nth) L.nrho[j] = ds / (2.0 * L.nrho[j]);
       for (int n = 1; n <= N; n++) {
-        for (int k = tid; k < nb; k += nth) {
+        for (int kk = tid; kk < LPM * nb; kk += nth) {
+          const int k = kk / LPM, h = kk % LPM;
+          // the marker's own operands are loaded ahead of the node gathers
+          const double udx = L.Udx[k], udy = L.Udy[k], rX = L.rhoX[k];
+          const double ftx = L.Ftx[k], fty = L.Fty[k];
           double Ux, Uy;
-          interp2<NS>(L, k, L.nux, L.nuy, Ux, Uy);
-          const double ex = L.Udx[k] - Ux, ey = L.Udy[k] - Uy;
-          const double Fx = 2.0 * L.rhoX[k] * ex, Fy = 2.0 * L.rhoX[k] * ey;
-          L.Fx[k] = om * Fx;
-          L.Fy[k] = om * Fy;
-          L.Ftx[k] += om * Fx;
-          L.Fty[k] += om * Fy;
-          if (n == N) resmax = fmax(resmax, sqrt(ex * ex + ey * ey));
+          interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
+          if (h == 0) {
+            const double ex = udx - Ux, ey = udy - Uy;
+            const double Fx = 2.0 * rX * ex, Fy = 2.0 * rX * ey;
+            L.Fx[k] = om * Fx;
+            L.Fy[k] = om * Fy;
+            L.Ftx[k] = ftx + om * Fx;
+            L.Fty[k] = fty + om * Fy;
+            if (n == N) resmax = fmax(resmax, sqrt(ex * ex + ey * ey));
+          }
         }
         __syncthreads();
-        if (spread_mode == 0) {
+        if (FAST || spread_mode == 0) {
           for (int j = tid; j < S; j += nth) {
             double sx, sy;
             gather2<NS>(L, j, L.Fx, L.Fy, sx, sy);
@@ -635,7 +737,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     __syncthreads();
     // Eulerian force f(x) = sum_k F_total D_h ds (Eq. 8) into the force field;
     // DF also forms the post-IB node velocity u* + f/(2 rho) for the slip
-    if (spread_mode == 0) {
+    if (FAST || spread_mode == 0) {
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double fx, fy;
@@ -681,7 +783,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       fsum_y -= L.Fty[k] * ds * wsum;
       tq -= ((L.X[k] - xc) * L.Fty[k] - (L.Y[k] - yc) * L.Ftx[k]) * ds;
     }
-  } else {
+  } else if constexpr (!FAST) {
     // ---- 4b. DFC
     if (!(fixed && ish[2])) {
       for (int j = tid; j < S; j += nth) {
@@ -690,10 +792,13 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         L.nW[j] = wt;  // W_total(x) of Eq. (17)
       }
       __syncthreads();
-      for (int k = tid; k < nb; k += nth) {
-        const double wsum = interp1<NS>(L, k, L.nW);
-        L.lam[k] = 1.0 / (2.0 * rho0 * ds * wsum);
-        B.lambda_cache[k] = L.lam[k];
+      for (int kk = tid; kk < LPM * nb; kk += nth) {
+        const int k = kk / LPM, h = kk % LPM;
+        const double wsum = interp1<NS, LPM>(L, k, h, L.nW);
+        if (h == 0) {
+          L.lam[k] = 1.0 / (2.0 * rho0 * ds * wsum);
+          B.lambda_cache[k] = L.lam[k];
+        }
       }
       if (fixed && tid == 0) bs->lambda_valid = 1;
     } else {
@@ -728,18 +833,20 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     __syncthreads();
     // Eq. (15)-(18), (20): interpolate the stored populations; the bounce-back
     // target minus f* only involves f*_opp - f*_i, the same in f and in g.
-    for (int k = tid; k < nb; k += nth) {
+    for (int kk = tid; kk < LPM * nb; kk += nth) {
+      const int k = kk / LPM, h = kk % LPM;
       double gi[9];
 #pragma unroll
       for (int i = 0; i < 9; i++) gi[i] = 0.0;
 #pragma unroll
-      for (int jy = 0; jy < NS; jy++) {
+      for (int r = 0; r < NS / LPM; r++) {
+        const int jy = h * (NS / LPM) + r;
         double row[9];
 #pragma unroll
         for (int i = 0; i < 9; i++) row[i] = 0.0;
 #pragma unroll
         for (int jx = 0; jx < NS; jx++) {
-          const int j = NIDX(L, k, jy * NS + jx);
+          const int j = NROW(L, k, jy) + jx;
           const double w = WX(L, k, jx);
 #pragma unroll
           for (int i = 0; i < 9; i++) row[i] += (double)stg[i * mn + j] * w;
@@ -748,6 +855,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
 #pragma unroll
         for (int i = 0; i < 9; i++) gi[i] += row[i] * wy;
       }
+#pragma unroll
+      for (int i = 0; i < 9; i++) gi[i] = group_sum<LPM>(gi[i]);
+      if (h) continue;
       const double lam = L.lam[k];
       double fsx = 0, fsy = 0;
 #pragma unroll
@@ -771,7 +881,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         double corr[9];
 #pragma unroll
         for (int i = 0; i < 9; i++) corr[i] = 0.0;
-        for_node_entries<NS>(L, j, [&](int k, double w) {
+        for_node_entries_csr<NS>(L, j, [&](int k, double w) {
 #pragma unroll
           for (int i = 0; i < 9; i++) corr[i] += DLT(L, k, i) * w;
         });
@@ -832,18 +942,38 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   __syncthreads();
   // ---- 5. slip with the post-IB velocity, reductions, body update
   double slip_sum = 0, slip_max = 0;
-  for (int k = tid; k < nb; k += nth) {
+  for (int kk = tid; kk < LPM * nb; kk += nth) {
+    const int k = kk / LPM, h = kk % LPM;
     double Ux, Uy;
-    if (B.scheme == kDFC)
-      interp_packed_u<NS, T>(L, k, (const T *)L.stage, B.max_nodes, Ux, Uy);
+    if (!FAST && B.scheme == kDFC)
+      interp_packed_u<NS, LPM, T>(L, k, h, (const T *)L.stage, B.max_nodes, Ux, Uy);
     else
-      interp2<NS>(L, k, L.nux, L.nuy, Ux, Uy);
-    const double e = sqrt((Ux - L.Udx[k]) * (Ux - L.Udx[k]) + (Uy - L.Udy[k]) * (Uy - L.Udy[k]));
-    slip_sum += e;
-    slip_max = fmax(slip_max, e);
+      interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
+    // the marker's output row (X Y Udx Udy Fx Fy lambda ds), split over
+    // the lanes of its group
     double *mo = B.markers_out + 8 * k;
-    mo[0] = L.X[k]; mo[1] = L.Y[k]; mo[2] = L.Udx[k]; mo[3] = L.Udy[k];
-    mo[4] = L.Ftx[k]; mo[5] = L.Fty[k]; mo[6] = B.scheme == kDFC ? L.lam[k] : 0.0; mo[7] = ds;
+    if (h == 0) {
+      const double e = sqrt((Ux - L.Udx[k]) * (Ux - L.Udx[k]) + (Uy - L.Udy[k]) * (Uy - L.Udy[k]));
+      slip_sum += e;
+      slip_max = fmax(slip_max, e);
+    }
+    if (LPM == 2) {
+      if (h == 0) {
+        mo[0] = L.X[k]; mo[1] = L.Y[k]; mo[2] = L.Udx[k]; mo[3] = L.Udy[k];
+      } else {
+        mo[4] = L.Ftx[k]; mo[5] = L.Fty[k]; mo[6] = (!FAST && B.scheme == kDFC) ? L.lam[k] : 0.0; mo[7] = ds;
+      }
+    } else {
+      if (h == 0) {
+        mo[0] = L.X[k]; mo[1] = L.Y[k];
+      } else if (h == 1) {
+        mo[2] = L.Udx[k]; mo[3] = L.Udy[k];
+      } else if (h == 2) {
+        mo[4] = L.Ftx[k]; mo[5] = L.Fty[k];
+      } else {
+        mo[6] = (!FAST && B.scheme == kDFC) ? L.lam[k] : 0.0; mo[7] = ds;
+      }
+    }
   }
   double a = fsum_x, b = fsum_y, cq = tq, m = fmax(resmax, 0.0);
   double s1 = slip_sum, s4 = slip_max;
@@ -901,12 +1031,15 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__restrict__ cases,
-                                                          const IbmSlot *__restrict__ slots,
-                                                          int lds_doubles, int spread_mode) {
+// One workgroup per IB slot: kIbmThreads threads, or kIbmThreadsFast for
+// the FAST instance (every body of the launch DF/MDF, in LDS, gather
+// spreading; see body_step).
+template <typename T, bool FAST>
+__global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kernel(
+    const CaseDesc *__restrict__ cases, const IbmSlot *__restrict__ slots, int lds_doubles,
+    int spread_mode) {
   extern __shared__ double dyn[];
-  __shared__ double red[6 * (kIbmThreads / 64)];
+  __shared__ double red[6 * ((FAST ? kIbmThreadsFast : kIbmThreads) / 64)];
   // ish: [0..15] flags and switches, [16..48] scan scratch, [50..55] the
   // body's final flags, force-box flag and force box
   __shared__ int ish[56];
@@ -922,12 +1055,15 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
   if (sl.body >= 0) {
     const BodyDesc &B = c.bodies[sl.body];
     const bool lds = lds_doubles >= B.ws_doubles;
-    if (B.ns == 2) {
-      if (lds) body_step<T, true, 2>(c, B, step, dyn, spread_mode, red, ish, bsh);
-      else body_step<T, false, 2>(c, B, step, dyn, spread_mode, red, ish, bsh);
+    if constexpr (FAST) {
+      if (B.ns == 2) body_step<T, true, 2, true>(c, B, step, cur, dyn, spread_mode, red, ish, bsh);
+      else body_step<T, true, 4, true>(c, B, step, cur, dyn, spread_mode, red, ish, bsh);
+    } else if (B.ns == 2) {
+      if (lds) body_step<T, true, 2, false>(c, B, step, cur, dyn, spread_mode, red, ish, bsh);
+      else body_step<T, false, 2, false>(c, B, step, cur, dyn, spread_mode, red, ish, bsh);
     } else {
-      if (lds) body_step<T, true, 4>(c, B, step, dyn, spread_mode, red, ish, bsh);
-      else body_step<T, false, 4>(c, B, step, dyn, spread_mode, red, ish, bsh);
+      if (lds) body_step<T, true, 4, false>(c, B, step, cur, dyn, spread_mode, red, ish, bsh);
+      else body_step<T, false, 4, false>(c, B, step, cur, dyn, spread_mode, red, ish, bsh);
     }
   }
   __syncthreads();
@@ -1002,24 +1138,37 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_kernel(const CaseDesc *__rest
 int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
-                      int lds_bytes, int spread_mode, hipStream_t stream) {
+                      int lds_bytes, int spread_mode, int fast, hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
   static bool configured = false;
   if (!configured) {
     // allow the large dynamic LDS workspace (gfx950 has 160 KB per CU)
-    (void)hipFuncSetAttribute((const void *)ibm_kernel<double>,
+    (void)hipFuncSetAttribute((const void *)ibm_kernel<double, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
-    (void)hipFuncSetAttribute((const void *)ibm_kernel<float>,
+    (void)hipFuncSetAttribute((const void *)ibm_kernel<float, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)ibm_kernel<double, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)ibm_kernel<float, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
     configured = true;
   }
   const int lds_doubles = lds_bytes / 8;
-  if (precision == kPrecFP64)
-    hipLaunchKernelGGL(ibm_kernel<double>, dim3(nslots), dim3(kIbmThreads), lds_bytes, stream,
-                       cases, slots, lds_doubles, spread_mode);
-  else
-    hipLaunchKernelGGL(ibm_kernel<float>, dim3(nslots), dim3(kIbmThreads), lds_bytes, stream,
-                       cases, slots, lds_doubles, spread_mode);
+  if (precision == kPrecFP64) {
+    if (fast)
+      hipLaunchKernelGGL((ibm_kernel<double, true>), dim3(nslots), dim3(kIbmThreadsFast), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode);
+    else
+      hipLaunchKernelGGL((ibm_kernel<double, false>), dim3(nslots), dim3(kIbmThreads), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode);
+  } else {
+    if (fast)
+      hipLaunchKernelGGL((ibm_kernel<float, true>), dim3(nslots), dim3(kIbmThreadsFast), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode);
+    else
+      hipLaunchKernelGGL((ibm_kernel<float, false>), dim3(nslots), dim3(kIbmThreads), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode);
+  }
   return hipGetLastError();
 }
 

@@ -283,6 +283,57 @@ __device__ __forceinline__ void collide_stream_tile(const CaseDesc *cp, int tx, 
   }
 }
 
+// The hold-rectangle tiles of a pipelined step (a few dozen workgroups on
+// the step's critical path, so latency rather than bandwidth): every row's
+// populations and IB force are loaded before any is used, and before the
+// case's halt flag is known.  The force is read at every node: outside the
+// force box it is zero (each step's collide-stream consumes the box of the
+// previous IB pass), so the result is that of collide_stream_tile.
+template <typename T, int COL, int RPT>
+__device__ __forceinline__ void collide_stream_tile_near(const CaseDesc *cp, int tx, int ty, int cur) {
+  const CaseDesc &c = *cp;
+  const CaseState *cs = c.state;
+  const T *__restrict__ src = (const T *)c.f[cur];
+  T *__restrict__ dst = (T *)c.f[cur ^ 1];
+  T *__restrict__ frc = (T *)c.force;
+  const int TX = blockDim.x, TY = blockDim.y * RPT;
+  const int nx = c.nx, ny = c.ny;
+  const uint32_t plane = (uint32_t)c.plane;
+  const int x = tx * TX + threadIdx.x;
+  const int ybase = ty * TY;
+  if (x < 1 || x > nx - 3) return;
+  T f[RPT][9], fa[RPT], fb[RPT];
+  bool ok[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; r++) {
+    const int y = ybase + threadIdx.y + r * blockDim.y;
+    ok[r] = y >= 1 && y <= ny - 2;
+    const uint32_t p = (uint32_t)(ok[r] ? y : 1) * nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; i++) f[r][i] = src[(uint32_t)i * plane + p];
+    fa[r] = frc[p];
+    fb[r] = frc[plane + p];
+  }
+  if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
+  const T ffx = T(c.fluid_fx), ffy = T(c.fluid_fy);
+#pragma unroll
+  for (int r = 0; r < RPT; r++) {
+    if (!ok[r]) continue;
+    const int y = ybase + threadIdx.y + r * blockDim.y;
+    const uint32_t p = (uint32_t)y * nx + x;
+    T Fx = ffx, Fy = ffy;
+    if (fa[r] != T(0) || fb[r] != T(0)) {
+      Fx += fa[r];
+      Fy += fb[r];
+      frc[p] = T(0);
+      frc[plane + p] = T(0);
+    }
+    collide<T, sizeof(T) == 4, COL>(f[r], Fx, Fy, c);
+#pragma unroll
+    for (int i = 0; i < 9; i++) dst[(uint32_t)i * plane + p + EXI(i) + EYI(i) * nx] = f[r][i];
+  }
+}
+
 // Every inner node of every case (batches flatten (case, tile) through
 // tile_prefix).
 template <typename T, int COL>
@@ -310,38 +361,33 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
   collide_stream_tile<T, COL>(cp, local % cp->tiles_x, local / cp->tiles_x, cs->cur, rpt, true);
 }
 
-// The face nodes of every case (face_prefix flattens (case, face node)), with
+// The face nodes of every case, kFaceBlock per workgroup (face_prefix[i] is
+// the first workgroup of case i, so the case is uniform in a workgroup), with
 // the face closures.  cur < 0: each case's current lattice from its state;
 // otherwise the lattice given (a pipelined step, whose case state the IB pass
 // may be updating).
 template <typename T, int COL>
-__global__ __launch_bounds__(256) void collide_stream_face_kernel(const CaseDesc *__restrict__ cases,
+__global__ __launch_bounds__(kFaceBlock) void collide_stream_face_kernel(const CaseDesc *__restrict__ cases,
                                                                   const int32_t *__restrict__ face_prefix,
-                                                                  int ncases, int nface, int cur_arg,
+                                                                  int ncases, int nblocks, int cur_arg,
                                                                   int force) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nface) return;
+  const int blk = blockIdx.x;
+  if (blk >= nblocks) return;
   int ci = 0;
   if (ncases > 1) {
     int lo = 0, hi = ncases - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (face_prefix[mid] <= k) lo = mid; else hi = mid - 1;
+      if (face_prefix[mid] <= blk) lo = mid; else hi = mid - 1;
     }
     ci = lo;
   }
   const CaseDesc *cp = cases + ci;
   const CaseDesc &c = *cp;
   const CaseState *cs = c.state;
-  int cur = cur_arg;
-  if (cur < 0) {
-    if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
-    cur = cs->cur;
-  } else if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) {
-    return;
-  }
+  const int m = (blk - face_prefix[ci]) * kFaceBlock + (int)threadIdx.x;
+  if (m >= face_nodes(c.nx, c.ny)) return;
   const int nx = c.nx, ny = c.ny;
-  const int m = k - face_prefix[ci];
   int x, y;
   if (m < nx) {
     x = m; y = 0;
@@ -352,14 +398,36 @@ __global__ __launch_bounds__(256) void collide_stream_face_kernel(const CaseDesc
     x = col == 0 ? 0 : (col == 1 ? nx - 2 : nx - 1);
     y = 1 + q % (ny - 2);
   }
-  const T *__restrict__ src = (const T *)c.f[cur];
-  T *__restrict__ dst = (T *)c.f[cur ^ 1];
-  T *__restrict__ frc = (T *)c.force;
   const uint32_t plane = (uint32_t)c.plane;
   const uint32_t p = (uint32_t)y * nx + x;
+  // The populations are loaded before the case state is known (a latency
+  // chain on a small launch): from the given lattice, or from both lattices
+  // when the state names it.
   T f[9];
+  int cur = cur_arg;
+  if (cur >= 0) {
+    const T *__restrict__ src = (const T *)c.f[cur];
 #pragma unroll
-  for (int i = 0; i < 9; i++) f[i] = src[(uint32_t)i * plane + p];
+    for (int i = 0; i < 9; i++) f[i] = src[(uint32_t)i * plane + p];
+    if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
+  } else {
+    const T *__restrict__ s0 = (const T *)c.f[0];
+    const T *__restrict__ s1 = (const T *)c.f[1];
+    T g[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+      f[i] = s0[(uint32_t)i * plane + p];
+      g[i] = s1[(uint32_t)i * plane + p];
+    }
+    if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
+    cur = cs->cur;
+    if (cur) {
+#pragma unroll
+      for (int i = 0; i < 9; i++) f[i] = g[i];
+    }
+  }
+  T *__restrict__ dst = (T *)c.f[cur ^ 1];
+  T *__restrict__ frc = (T *)c.force;
   T Fx = T(c.fluid_fx), Fy = T(c.fluid_fy);
   const bool box = force && cs->fbox_valid;
   node_force<T>(frc, plane, p, x, y, box, box ? cs->fbox[0] : 0, box ? cs->fbox[1] : 0,
@@ -369,32 +437,39 @@ __global__ __launch_bounds__(256) void collide_stream_face_kernel(const CaseDesc
 }
 
 // One part of a pipelined step of a single case (see PipeArgs): the tiles
-// of the hold rectangle (near = 1), which read the IB force and are read by
-// the IB pass, or all other tiles (near = 0), which do neither.  The input
-// lattice `cur` comes from the host: the IB pass of the previous step may
-// still be updating the case state while the far tiles run.
-template <typename T, int COL>
+// of the hold rectangle (NEAR), which read the IB force and are read by the
+// IB pass, or all other tiles, which do neither (force = 0, passed at run
+// time, which keeps this instance's register allocation that of the plain
+// kernel).  The input lattice `cur` comes from the host: the IB pass of the
+// previous step may still be updating the case state while the far tiles
+// run.
+template <typename T, int COL, bool NEAR>
 __global__ __launch_bounds__(1024) void collide_stream_pipe_kernel(const CaseDesc *__restrict__ cases,
                                                                    int ntiles, int rpt, int xcd_remap,
-                                                                   PipeArgs pa, int near) {
+                                                                   PipeArgs pa, int force) {
   const CaseDesc *cp = cases;
   const CaseState *cs = cp->state;
-  if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
   const int nb = gridDim.x;
   int t = blockIdx.x;
   if (xcd_remap) t = (t & 7) * (nb >> 3) + (t >> 3);
-  int tx, ty;
-  if (near) {
+  if (NEAR) {
     if (t >= pa.hntx * pa.hnty) return;
-    tx = pa.htx0 + t % pa.hntx;
-    ty = pa.hty0 + t / pa.hntx;
-  } else {
-    if (t >= ntiles) return;
-    tx = t % cp->tiles_x;
-    ty = t / cp->tiles_x;
-    if (tx >= pa.htx0 && tx < pa.htx0 + pa.hntx && ty >= pa.hty0 && ty < pa.hty0 + pa.hnty) return;
+    const int tx = pa.htx0 + t % pa.hntx, ty = pa.hty0 + t / pa.hntx;
+    if (rpt == 1) {
+      collide_stream_tile_near<T, COL, 1>(cp, tx, ty, pa.cur);
+    } else if (rpt == 2) {
+      collide_stream_tile_near<T, COL, 2>(cp, tx, ty, pa.cur);
+    } else {
+      if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
+      collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, true);
+    }
+    return;
   }
-  collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, near != 0);
+  if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
+  if (t >= ntiles) return;
+  const int tx = t % cp->tiles_x, ty = t / cp->tiles_x;
+  if (tx >= pa.htx0 && tx < pa.htx0 + pa.hntx && ty >= pa.hty0 && ty < pa.hty0 + pa.hnty) return;
+  collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, force != 0);
 }
 
 #define IBL_DISPATCH(precision, collision, LAUNCH)                                             \
@@ -426,13 +501,12 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
 }
 
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
-                                       const int32_t *face_prefix, int ncases, int nface, int cur,
+                                       const int32_t *face_prefix, int ncases, int nblocks, int cur,
                                        int force, hipStream_t stream) {
-  if (nface <= 0) return hipSuccess;
-  const int grid = (nface + 255) / 256;
-#define IBL_LAUNCH(T, C)                                                                        \
-  hipLaunchKernelGGL((collide_stream_face_kernel<T, C>), dim3(grid), dim3(256), 0, stream, cases, \
-                     face_prefix, ncases, nface, cur, force)
+  if (nblocks <= 0) return hipSuccess;
+#define IBL_LAUNCH(T, C)                                                                   \
+  hipLaunchKernelGGL((collide_stream_face_kernel<T, C>), dim3(nblocks), dim3(kFaceBlock), 0, \
+                     stream, cases, face_prefix, ncases, nblocks, cur, force)
   IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
   return hipGetLastError();
@@ -448,8 +522,12 @@ hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDe
   const int rpt = shape.rows_per_thread;
   const int remap = shape.xcd_remap;
 #define IBL_LAUNCH(T, C)                                                                        \
-  hipLaunchKernelGGL((collide_stream_pipe_kernel<T, C>), dim3(grid), block, 0, stream, cases,   \
-                     ntiles, rpt, remap, pa, near)
+  if (near)                                                                                     \
+    hipLaunchKernelGGL((collide_stream_pipe_kernel<T, C, true>), dim3(grid), block, 0, stream,  \
+                       cases, ntiles, rpt, remap, pa, 1);                                       \
+  else                                                                                          \
+    hipLaunchKernelGGL((collide_stream_pipe_kernel<T, C, false>), dim3(grid), block, 0, stream, \
+                       cases, ntiles, rpt, remap, pa, 0)
   IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
   return hipGetLastError();

@@ -512,3 +512,18 @@ def test_benchmark_lattice_uses_split_step():
     sim.step(3)
     used, near = sim.overlap()
     assert used and near < case["nx"] * case["ny"] // 25
+
+
+def test_time_collide_stream_counts_inner_nodes():
+    """The measurement entry point times back-to-back launches of the inner
+    collide-stream and reports the inner node count (columns 1..nx-3, rows
+    1..ny-2) that the roofline divides by."""
+    case = dict(nx=130, ny=40, collision=ib.TRT, tau=0.8, bc=(ib.PERIODIC,) * 4)
+    say("time_collide_stream 130x40")
+    sim = ib.Sim(case, precision=ib.FP32_SHIFTED)
+    try:
+        us, n = sim.time_collide_stream(8)
+    finally:
+        sim.close()
+    assert n == 127 * 38
+    assert 0.0 < us < 1e5
