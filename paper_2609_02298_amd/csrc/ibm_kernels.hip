@@ -675,30 +675,22 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     } else {
       // MDF, Eq. (12)-(14): N passes of interpolation, force and spreading
       // back into the node velocities with relaxation omega_MDF; rho(X) is
-      // interpolated once; F_total accumulates omega F^(n).
+      // interpolated once, in the first pass; F_total accumulates omega F^(n).
+      // After the first pass's interpolation nrho holds ds / (2 rho(x)), the
+      // factor of every pass (each node's thread converts its own entry).
       const int N = B.mdf_iters;
       const double om = B.omega_mdf;
-      for (int kk = tid; kk < LPM * nb; kk += nth) {
-        const int k = kk / LPM, h = kk % LPM;
-        const double rX = interp1<NS, LPM>(L, k, h, L.nrho);
-        if (h == 0) {
-          L.rhoX[k] = rX;
-          L.Ftx[k] = 0.0;
-          L.Fty[k] = 0.0;
-        }
-      }
-      __syncthreads();
-      // from here on nrho holds ds / (2 rho(x)), the factor of every pass
-      for (int j = tid; j < S; j += nth) L.nrho[j] = ds / (2.0 * L.nrho[j]);
       for (int n = 1; n <= N; n++) {
         for (int kk = tid; kk < LPM * nb; kk += nth) {
           const int k = kk / LPM, h = kk % LPM;
           // the marker's own operands are loaded ahead of the node gathers
-          const double udx = L.Udx[k], udy = L.Udy[k], rX = L.rhoX[k];
-          const double ftx = L.Ftx[k], fty = L.Fty[k];
+          const double udx = L.Udx[k], udy = L.Udy[k];
+          const double rX = n == 1 ? interp1<NS, LPM>(L, k, h, L.nrho) : L.rhoX[k];
+          const double ftx = n == 1 ? 0.0 : L.Ftx[k], fty = n == 1 ? 0.0 : L.Fty[k];
           double Ux, Uy;
           interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
           if (h == 0) {
+            if (n == 1) L.rhoX[k] = rX;
             const double ex = udx - Ux, ey = udy - Uy;
             const double Fx = 2.0 * rX * ex, Fy = 2.0 * rX * ey;
             L.Fx[k] = om * Fx;
@@ -709,6 +701,8 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
           }
         }
         __syncthreads();
+        if (n == 1)
+          for (int j = tid; j < S; j += nth) L.nrho[j] = ds / (2.0 * L.nrho[j]);
         if (FAST || spread_mode == 0) {
           for (int j = tid; j < S; j += nth) {
             double sx, sy;
