@@ -363,8 +363,10 @@ EventPair take_pair(Timing &t) {
     return p;
   }
   EventPair p;
-  (void)hipEventCreate(&p.a);
-  (void)hipEventCreate(&p.b);
+  // timing events around device work: a device-scope release keeps the
+  // cache writeback of a system-scope release out of the measured span
+  (void)hipEventCreateWithFlags(&p.a, hipEventReleaseToDevice);
+  (void)hipEventCreateWithFlags(&p.b, hipEventReleaseToDevice);
   return p;
 }
 
@@ -421,11 +423,15 @@ ib_lbm_status ensure_pipe_streams(ib_lbm_sim *s) {
     }
   }
   if (!s->iq) HIPCHK(s, hipStreamCreateWithFlags(&s->iq, hipStreamNonBlocking));
-  if (!s->ev_start) HIPCHK(s, hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming));
-  if (!s->ev_lq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_lq, hipEventDisableTiming));
-  if (!s->ev_iq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_iq, hipEventDisableTiming));
-  if (!s->ev_near) HIPCHK(s, hipEventCreateWithFlags(&s->ev_near, hipEventDisableTiming));
-  if (!s->ev_far) HIPCHK(s, hipEventCreateWithFlags(&s->ev_far, hipEventDisableTiming));
+  // the events only order work between streams of this device: a
+  // device-scope release suffices (the default system-scope release writes
+  // back and invalidates the caches at every record)
+  const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;
+  if (!s->ev_start) HIPCHK(s, hipEventCreateWithFlags(&s->ev_start, evf));
+  if (!s->ev_lq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_lq, evf));
+  if (!s->ev_iq) HIPCHK(s, hipEventCreateWithFlags(&s->ev_iq, evf));
+  if (!s->ev_near) HIPCHK(s, hipEventCreateWithFlags(&s->ev_near, evf));
+  if (!s->ev_far) HIPCHK(s, hipEventCreateWithFlags(&s->ev_far, evf));
   return IB_LBM_OK;
 }
 
