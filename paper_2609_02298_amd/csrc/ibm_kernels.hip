@@ -499,14 +499,16 @@ __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B
   return S;
 }
 
-__device__ __forceinline__ void copy_doubles(double *dst, const double *src, int n) {
-  // 16-byte copies, four loads in flight per thread before the stores
-  // (workspace bases are 16-byte aligned)
+// Copies n doubles with the threads from `first` on (16-byte copies, four
+// loads in flight per thread before the stores; workspace bases are 16-byte
+// aligned).
+__device__ __forceinline__ void copy_doubles(double *dst, const double *src, int n, int first = 0) {
   const int n2 = n >> 1;
   const double2 *s2 = (const double2 *)src;
   double2 *d2 = (double2 *)dst;
-  const int nth = blockDim.x;
-  int i = threadIdx.x;
+  const int nth = blockDim.x - first;
+  int i = (int)threadIdx.x - first;
+  if (i < 0) return;
   for (; i + 3 * nth < n2; i += 4 * nth) {
     const double2 a = s2[i], b = s2[i + nth], c = s2[i + 2 * nth], d = s2[i + 3 * nth];
     d2[i] = a;
@@ -515,7 +517,7 @@ __device__ __forceinline__ void copy_doubles(double *dst, const double *src, int
     d2[i + 3 * nth] = d;
   }
   for (; i < n2; i += nth) d2[i] = s2[i];
-  if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
+  if ((n & 1) && (int)threadIdx.x == first) dst[n - 1] = src[n - 1];
 }
 
 // FAST: the 1024-thread instance for DF/MDF bodies with an LDS workspace
@@ -538,6 +540,14 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   // collide-stream into lattice cur ^ 1)
   const T *fpop = (const T *)c.f[cur ^ 1];
   T *fpop_w = (T *)c.f[cur ^ 1];
+
+  // A fixed body of the 1024-thread instance copies the hot part of its
+  // cached tables with waves 1.. while thread 0 advances the kinematics
+  // (wave 0 issues no copy loads for its kinematics loads to queue behind).
+  // Before the cache is first filled this copies stale words, which the
+  // table build below overwrites (the barrier after the kinematics orders
+  // the two).
+  if (FAST && B.motion == kFixed) copy_doubles(dyn, B.tab_cache, B.ws_tab_hot, 64);
 
   // ---- 1. kinematics for t_{n+1}
   if (tid == 0) {
@@ -594,8 +604,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   // ---- 2-3. tables: cached for fixed bodies
   int S;
   if (fixed && ish[1]) {
-    // a DF/MDF step without long node lists reads only the hot part
-    if (in_lds) copy_doubles(base, B.tab_cache, ish[4] ? B.ws_tab : B.ws_tab_hot);
+    // a DF/MDF step without long node lists reads only the hot part (already
+    // copied by the 1024-thread instance)
+    if (in_lds && (ish[4] || !FAST)) copy_doubles(base, B.tab_cache, ish[4] ? B.ws_tab : B.ws_tab_hot);
     __syncthreads();
     S = L.S[0];
   } else {
