@@ -91,7 +91,7 @@ __device__ __forceinline__ void block_reduce6(double &a, double &b, double &c, d
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d);
   m1 = wave_max(m1); m2 = wave_max(m2);
-  __syncthreads();
+  // (red is used once per pass, so nothing earlier needs a barrier here)
   if (lane == 0) {
     red[6 * wv] = a; red[6 * wv + 1] = b; red[6 * wv + 2] = c; red[6 * wv + 3] = d;
     red[6 * wv + 4] = m1; red[6 * wv + 5] = m2;
@@ -593,6 +593,22 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     ish[4] = bs->tables_full;
     ish[5] = 0;  // set by build_tables when a node's list outgrows its fixed-width copy
   }
+  if (tid == 64) {
+    // what the end of the pass needs from the descriptors, staged on chip
+    // beside the kinematics (the pass's stores to device memory would
+    // otherwise make the serial tail load them again)
+    ish[10] = B.scheme == kDFC ? 0 : 1;
+    ish[11] = B.scheme == kDFC ? 0 : (B.scheme == kDF ? 1 : B.mdf_iters);
+    ish[12] = B.motion;
+    ish[13] = B.scheme;
+    ish[14] = c.ny;
+    bsh[7] = __longlong_as_double((long long)(B.history + (step % B.hist_cap) * kHistCols));
+    bsh[8] = B.ms;
+    bsh[9] = (B.ms - B.mf) * c.grav_x;
+    bsh[10] = (B.ms - B.mf) * c.grav_y;
+    bsh[11] = B.Is;
+    bsh[12] = B.radius;
+  }
   __syncthreads();
   const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
   constexpr bool in_lds = LDS;
@@ -985,28 +1001,29 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   block_reduce6(a, b, cq, s1, m, s4, red);
   if (tid == 0) {
     // every value is formed in registers and written once (no read-back of
-    // device memory on this serial tail)
+    // device memory on this serial tail; the descriptor values come from
+    // the on-chip copy made with the kinematics)
+    const int motion = ish[12], scheme = ish[13], iters = ish[11], box_valid = ish[10];
     int flags = 0;
     if (!isfinite(a) || !isfinite(b) || !isfinite(cq) || !isfinite(s1)) flags |= kFlagNonfinite;
     const double slip_mean = s1 / nb;
-    const double mdf_res = B.scheme == kMDF ? m : 0.0;
-    const int iters = B.scheme == kDFC ? 0 : (B.scheme == kDF ? 1 : B.mdf_iters);
+    const double mdf_res = scheme == kMDF ? m : 0.0;
     int box[4] = {0, 0, -1, -1};
-    const int box_valid = B.scheme == kDFC ? 0 : 1;
     if (box_valid) {
-      box[0] = max(0, (int)floor(xc - B.radius) - ns);
-      box[1] = max(0, (int)floor(yc - B.radius) - ns);
-      box[2] = min(nx - 1, (int)floor(xc + B.radius) + ns + 1);
-      box[3] = min(c.ny - 1, (int)floor(yc + B.radius) + ns + 1);
+      const double r = bsh[12];
+      box[0] = max(0, (int)floor(xc - r) - ns);
+      box[1] = max(0, (int)floor(yc - r) - ns);
+      box[2] = min(nx - 1, (int)floor(xc + r) + ns + 1);
+      box[3] = min(ish[14] - 1, (int)floor(yc + r) + ns + 1);
     }
     double vx = vhx, vy = vhy, om = omh;
-    if (B.motion == kFree) {
-      const double fgx = (B.ms - B.mf) * c.grav_x, fgy = (B.ms - B.mf) * c.grav_y;
-      vx = vhx + (a + fgx + bsh[5]) / (2.0 * B.ms);
-      vy = vhy + (b + fgy + bsh[6]) / (2.0 * B.ms);
-      om = omh + cq / (2.0 * B.Is);
+    if (motion == kFree) {
+      const double ms = bsh[8];
+      vx = vhx + (a + bsh[9] + bsh[5]) / (2.0 * ms);
+      vy = vhy + (b + bsh[10] + bsh[6]) / (2.0 * ms);
+      om = omh + cq / (2.0 * bsh[11]);
       if (!isfinite(vx) || !isfinite(vy) || fabs(vx) > 0.5 || fabs(vy) > 0.5) flags |= kFlagNonfinite;
-    } else if (B.motion == kFixed) {
+    } else if (motion == kFixed) {
       vx = 0.0; vy = 0.0; om = 0.0;
     }
     flags |= ish[3];
@@ -1019,14 +1036,13 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     bs->mdf_iters_done = iters;
     bs->box[0] = box[0]; bs->box[1] = box[1]; bs->box[2] = box[2]; bs->box[3] = box[3];
     bs->box_valid = box_valid;
-    if (B.motion != kPrescribedSin) {
+    if (motion != kPrescribedSin) {
       bs->vx = vx; bs->vy = vy; bs->om = om;
     }
     bs->flags = flags;
-    const int64_t row = step % B.hist_cap;
-    double *h = B.history + row * kHistCols;
+    double *h = (double *)__double_as_longlong(bsh[7]);
     h[0] = (double)(step + 1); h[1] = a; h[2] = b; h[3] = cq;
-    h[4] = xc; h[5] = yc; h[6] = vx; h[7] = vy; h[8] = B.motion == kFree ? om : omh;
+    h[4] = xc; h[5] = yc; h[6] = vx; h[7] = vy; h[8] = motion == kFree ? om : omh;
     h[9] = slip_mean; h[10] = s4; h[11] = mdf_res;
     h[12] = iters; h[13] = flags; h[14] = 0; h[15] = 0;
     // for the case-level update of a single-body case
