@@ -57,7 +57,8 @@ struct ib_lbm_sim {
   bool tables_dirty = true;
   std::string err;
   CaseDesc cd;  // host copy
-  DevBuf f0, f1, force, state;
+  DevBuf f0, f1, force, state, ticket;
+  uint32_t ibm_seq = 0;  // launches of the replicated IB pass (ticket sequence)
   std::vector<HostBody> bodies;
   DevBuf d_bodies, d_case, d_prefix, d_slots, d_tmp;
   int nslots = 0;
@@ -298,9 +299,10 @@ bool body_fast(const HostBody &hb, int spread_mode) {
 // of a case's workgroups to finish, in either launch, completes the case).
 hipError_t launch_ibm_slots(int precision, const CaseDesc *cases, const IbmSlot *slots, int nfast, int n,
                             int lds_bytes, int spread_mode, hipStream_t stream) {
-  hipError_t e = launch_ibm(precision, cases, slots, nfast, lds_bytes, spread_mode, 1, stream);
+  hipError_t e = launch_ibm(precision, cases, slots, nfast, lds_bytes, spread_mode, 1, 1, 0, nullptr, stream);
   if (e != hipSuccess) return e;
-  return launch_ibm(precision, cases, slots + nfast, n - nfast, lds_bytes, spread_mode, 0, stream);
+  return launch_ibm(precision, cases, slots + nfast, n - nfast, lds_bytes, spread_mode, 0, 1, 0, nullptr,
+                    stream);
 }
 
 ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
@@ -423,6 +425,13 @@ ib_lbm_status ensure_pipe_streams(ib_lbm_sim *s) {
     }
   }
   if (!s->iq) HIPCHK(s, hipStreamCreateWithFlags(&s->iq, hipStreamNonBlocking));
+  if (!s->ticket.p) {
+    // the replicated IB workgroup's ticket, advanced once per launch
+    ib_lbm_status st = dev_alloc(s, &s->ticket, 256);
+    if (st) return st;
+    HIPCHK(s, hipMemset(s->ticket.p, 0, 256));
+    s->ibm_seq = 0;
+  }
   // the events only order work between streams of this device: a
   // device-scope release suffices (the default system-scope release writes
   // back and invalidates the caches at every record)
@@ -487,8 +496,10 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
       p1 = take_pair(s->timing);
       HIPCHK(s, hipEventRecord(p1.a, s->iq));
     }
-    HIPCHK(s, launch_ibm_slots(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, s->nslots_fast,
-                               s->nslots, s->lds_bytes, s->spread_mode, s->iq));
+    // one copy of the single body's IB workgroup per XCD; the first to start
+    // runs the pass (the far tiles on the other stream fill the chip)
+    HIPCHK(s, launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, 1, s->lds_bytes,
+                         s->spread_mode, s->nslots_fast, 8, ++s->ibm_seq, (uint32_t *)s->ticket.p, s->iq));
     if (timed) {
       HIPCHK(s, hipEventRecord(p1.b, s->iq));
       s->timing.ev[1].push_back(p1);
@@ -986,6 +997,7 @@ ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s) {
     dev_free(s, &hb.lambda); dev_free(s, &hb.history); dev_free(s, &hb.state);
   }
   dev_free(s, &s->f0); dev_free(s, &s->f1); dev_free(s, &s->force); dev_free(s, &s->state);
+  dev_free(s, &s->ticket);
   dev_free(s, &s->d_bodies); dev_free(s, &s->d_case); dev_free(s, &s->d_prefix);
   dev_free(s, &s->d_slots); dev_free(s, &s->d_tmp);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);

@@ -190,8 +190,12 @@ hipError_t launch_collide_stream_faces(int precision, int collision, const CaseD
 hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
                                       LaunchShape shape, const PipeArgs &pa, int near,
                                       hipStream_t stream);
+// IB launch over nslots slots; replicas > 1 (with a per-slot ticket and
+// the launch's sequence number, see ibm_kernel) lets the first-started copy
+// of each slot run it.
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
-                      int lds_bytes, int spread_mode, int fast, hipStream_t stream);
+                      int lds_bytes, int spread_mode, int fast, int replicas, uint32_t seq,
+                      uint32_t *ticket, hipStream_t stream);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
                          hipStream_t stream);

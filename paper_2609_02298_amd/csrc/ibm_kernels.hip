@@ -1054,23 +1054,35 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
 
 // One workgroup per IB slot: kIbmThreads threads, or kIbmThreadsFast for
 // the FAST instance (every body of the launch DF/MDF, in LDS, gather
-// spreading; see body_step).
+// spreading; see body_step).  With replicas > 1 each slot is launched that
+// many times (one workgroup per XCD for replicas = 8) and the first of them
+// to start takes the slot: it moves ticket[slot] from seq - 1 to seq, the
+// others leave at once.  A pass that shares the chip with a large launch on
+// another stream then starts on whichever XCD frees a compute unit first.
 template <typename T, bool FAST>
 __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kernel(
     const CaseDesc *__restrict__ cases, const IbmSlot *__restrict__ slots, int lds_doubles,
-    int spread_mode) {
+    int spread_mode, int replicas, uint32_t seq, uint32_t *ticket) {
   extern __shared__ double dyn[];
   __shared__ double red[6 * ((FAST ? kIbmThreadsFast : kIbmThreads) / 64)];
   // ish: [0..15] flags and switches, [16..48] scan scratch, [50..55] the
   // body's final flags, force-box flag and force box
   __shared__ int ish[56];
   __shared__ double bsh[16];
-  const IbmSlot sl = slots[blockIdx.x];
+  const int slot = replicas > 1 ? (int)blockIdx.x / replicas : (int)blockIdx.x;
+  // the ticket is taken by a thread of wave 1 while all threads read the
+  // slot and the case state; nothing is written before the outcome is known
+  if (replicas > 1 && threadIdx.x == 64) ish[49] = atomicCAS(&ticket[slot], seq - 1u, seq) == seq - 1u;
+  const IbmSlot sl = slots[slot];
   const CaseDesc &c = cases[sl.cas];
   CaseState *cs = c.state;
   const int64_t step = cs->step;
   const int cur = cs->cur;
   const bool active = step < cs->target && !(cs->flags & kCaseHalted);
+  if (replicas > 1) {
+    __syncthreads();
+    if (!ish[49]) return;
+  }
   if (!active) return;
   if (threadIdx.x == 0) ish[50] = 0;
   if (sl.body >= 0) {
@@ -1159,7 +1171,8 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
 int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
-                      int lds_bytes, int spread_mode, int fast, hipStream_t stream) {
+                      int lds_bytes, int spread_mode, int fast, int replicas, uint32_t seq,
+                      uint32_t *ticket, hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
   static bool configured = false;
   if (!configured) {
@@ -1175,20 +1188,22 @@ hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots
     configured = true;
   }
   const int lds_doubles = lds_bytes / 8;
+  if (replicas < 1) replicas = 1;
+  const int grid = nslots * replicas;
   if (precision == kPrecFP64) {
     if (fast)
-      hipLaunchKernelGGL((ibm_kernel<double, true>), dim3(nslots), dim3(kIbmThreadsFast), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode);
+      hipLaunchKernelGGL((ibm_kernel<double, true>), dim3(grid), dim3(kIbmThreadsFast), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
     else
-      hipLaunchKernelGGL((ibm_kernel<double, false>), dim3(nslots), dim3(kIbmThreads), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode);
+      hipLaunchKernelGGL((ibm_kernel<double, false>), dim3(grid), dim3(kIbmThreads), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
   } else {
     if (fast)
-      hipLaunchKernelGGL((ibm_kernel<float, true>), dim3(nslots), dim3(kIbmThreadsFast), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode);
+      hipLaunchKernelGGL((ibm_kernel<float, true>), dim3(grid), dim3(kIbmThreadsFast), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
     else
-      hipLaunchKernelGGL((ibm_kernel<float, false>), dim3(nslots), dim3(kIbmThreads), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode);
+      hipLaunchKernelGGL((ibm_kernel<float, false>), dim3(grid), dim3(kIbmThreads), lds_bytes,
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
   }
   return hipGetLastError();
 }

@@ -527,3 +527,27 @@ def test_time_collide_stream_counts_inner_nodes():
         sim.close()
     assert n == 127 * 38
     assert 0.0 < us < 1e5
+
+
+def test_split_step_over_many_calls_is_the_plain_step():
+    """Pipelined steps issued over many small calls (each IB launch of a
+    pipelined step is replicated once per XCD and the first copy to start
+    runs it, through a ticket advanced once per launch) give the plain
+    steps' result bit for bit."""
+    say("split step over 40 calls")
+    case = _split_case(ib.MDF, ib.PESKIN4, ib.TRT)
+    runs = []
+    for overlap in (False, True):
+        sim = ib.Sim(case, precision=ib.FP32_SHIFTED)
+        sim.set_launch(64, 1, 1, 1)
+        sim.set_overlap(overlap)
+        for n in [1, 2, 3] * 13 + [1]:
+            sim.step(n)
+        sim.sync()
+        assert sim.steps_done == 79
+        assert sim.overlap()[0] == overlap
+        runs.append((sim.populations(), sim.forces(0)))
+        sim.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for k in ("fx", "fy", "torque", "slip_mean"):
+        assert runs[0][1][k] == runs[1][1][k], k
