@@ -31,10 +31,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
 def kernel_source_hash() -> str:
+    """Hash of what the collide-stream kernels are built from: their source
+    and the shared definitions (structs, helpers) ahead of the launcher
+    declarations in the internal header."""
+    csrc = os.path.join(ROOT, "paper_2609_02298_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "ib_lbm_internal.h"):
-        with open(os.path.join(ROOT, "paper_2609_02298_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "lbm_kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "ib_lbm_internal.h"), "rb") as fh:
+        head = fh.read()
+    h.update(head.split(b"// ---- kernel launchers")[0])
     return h.hexdigest()[:16]
 
 
