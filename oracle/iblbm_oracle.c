@@ -360,6 +360,8 @@ void or_destroy(or_sim *s) {
 int or_add_body(or_sim *s, const or_body_desc *d) {
   if (s->nbody >= OR_MAX_BODIES || d->diameter <= 0) return -1;
   if (s->nbody > 0 && s->body[0].d.scheme != d->scheme) return -1;
+  if (d->scheme == OR_MDF && (d->mdf_iters < 1 || (d->mdf_tol > 0.0 && (d->mdf_nmin < 1 || d->mdf_nmin > d->mdf_iters))))
+    return -1;
   or_body *b = &s->body[s->nbody];
   memset(b, 0, sizeof(*b));
   b->d = *d;
@@ -640,52 +642,66 @@ static void ibm_df(or_sim *s) {
   }
 }
 
-/* Multi-direct forcing, Eq. (12)-(14): N Richardson passes with relaxation
- * omega_MDF; F_total = sum_n omega F^(n); the Eulerian force is the spread
- * of F_total.  rho(X_k) is interpolated once per step. */
+/* Multi-direct forcing, Eq. (12)-(14).  Pass n interpolates U^(n) from the
+ * node velocities u^(n-1), forms F^(n) = 2 rho(X_k) (U_d - U^(n)) and adds
+ * omega/(2 rho) spread(F^(n)) to the node velocities; F_total = sum_n omega
+ * F^(n), and the Eulerian force is the spread of F_total.  rho(X_k) is
+ * interpolated once per step.  The bodies iterate one after the other: no
+ * node lies in the supports of two bodies (the library refuses such bodies),
+ * so a body's passes change only its own nodes and the order of the bodies
+ * does not matter.
+ *
+ * Fixed form (mdf_tol <= 0): mdf_iters passes.  Adaptive form (mdf_tol > 0,
+ * Sec. 2.5.2 and App. A.2): the residual r_n = max_k |U_d - U^(n)(X_k)| is
+ * measured before pass n is applied, and the iteration ends there, without
+ * pass n, once at least mdf_nmin passes are done and r_n < mdf_tol, or when
+ * r_n > 1.5 r_{n-1} (divergence guard); it applies at most mdf_iters passes.
+ * Reading: the guard holds from the second interpolation on, also before
+ * mdf_nmin passes are done.  The reported residual is that of the last
+ * interpolation, the count that of the passes applied. */
 static void ibm_mdf(or_sim *s) {
   int n = s->n;
   double *rho = s->tmpa, *ux = s->tmpb, *uy = s->tmpc;
   post_stream_moments(s, rho, ux, uy);
   double *sx = calloc(n, sizeof(double)), *sy = calloc(n, sizeof(double));
-  int nmax = 0;
   for (int b = 0; b < s->nbody; b++) {
     or_body *B = &s->body[b];
-    for (int k = 0; k < B->nb; k++) B->Fx[k] = B->Fy[k] = 0.0;
-    if (B->d.mdf_iters > nmax) nmax = B->d.mdf_iters;
-  }
-  double **rX = calloc(s->nbody, sizeof(double *));
-  for (int b = 0; b < s->nbody; b++) {
-    or_body *B = &s->body[b];
-    rX[b] = calloc(B->nb, sizeof(double));
-    for (int k = 0; k < B->nb; k++) rX[b][k] = interp(s, B->d.kernel, rho, B->X[k], B->Y[k]);
-  }
-  for (int it = 1; it <= nmax; it++) {
-    for (int p = 0; p < n; p++) sx[p] = sy[p] = 0.0;
-    for (int b = 0; b < s->nbody; b++) {
-      or_body *B = &s->body[b];
-      if (it > B->d.mdf_iters) continue;
+    double *ex = B->mdfU, *ey = B->mdfU + B->nb;
+    double *rX = calloc(B->nb, sizeof(double));
+    for (int k = 0; k < B->nb; k++) {
+      B->Fx[k] = B->Fy[k] = 0.0;
+      rX[k] = interp(s, B->d.kernel, rho, B->X[k], B->Y[k]);
+    }
+    const int adaptive = B->d.mdf_tol > 0.0;
+    double rprev = 0.0;
+    B->mdf_iters_done = 0;
+    for (int it = 1; it <= B->d.mdf_iters; it++) {
       double res = 0.0;
       for (int k = 0; k < B->nb; k++) {
-        double Ux = interp(s, B->d.kernel, ux, B->X[k], B->Y[k]);
-        double Uy = interp(s, B->d.kernel, uy, B->X[k], B->Y[k]);
-        double ex = B->Udx[k] - Ux, ey = B->Udy[k] - Uy;
-        double r = sqrt(ex * ex + ey * ey);
+        ex[k] = B->Udx[k] - interp(s, B->d.kernel, ux, B->X[k], B->Y[k]);
+        ey[k] = B->Udy[k] - interp(s, B->d.kernel, uy, B->X[k], B->Y[k]);
+        double r = sqrt(ex[k] * ex[k] + ey[k] * ey[k]);
         res = r > res ? r : res;
-        double Fnx = 2.0 * rX[b][k] * ex, Fny = 2.0 * rX[b][k] * ey;
+      }
+      B->mdf_res = res;
+      if (adaptive && ((it > B->d.mdf_nmin && res < B->d.mdf_tol) || (it > 1 && res > 1.5 * rprev)))
+        break;
+      rprev = res;
+      for (int p = 0; p < n; p++) sx[p] = sy[p] = 0.0;
+      for (int k = 0; k < B->nb; k++) {
+        double Fnx = 2.0 * rX[k] * ex[k], Fny = 2.0 * rX[k] * ey[k];
         B->Fx[k] += B->omega_mdf * Fnx;
         B->Fy[k] += B->omega_mdf * Fny;
-        /* omega is folded into the spread so each body keeps its own */
         spread_add(s, B->d.kernel, sx, B->omega_mdf * Fnx, B->X[k], B->Y[k], B->ds);
         spread_add(s, B->d.kernel, sy, B->omega_mdf * Fny, B->X[k], B->Y[k], B->ds);
       }
-      B->mdf_res = res;
+      for (int p = 0; p < n; p++) {
+        ux[p] += sx[p] / (2.0 * rho[p]);
+        uy[p] += sy[p] / (2.0 * rho[p]);
+      }
       B->mdf_iters_done = it;
     }
-    for (int p = 0; p < n; p++) {
-      ux[p] += sx[p] / (2.0 * rho[p]);
-      uy[p] += sy[p] / (2.0 * rho[p]);
-    }
+    free(rX);
   }
   for (int p = 0; p < n; p++) s->Fx[p] = s->Fy[p] = 0.0;
   for (int b = 0; b < s->nbody; b++) {
@@ -694,9 +710,7 @@ static void ibm_mdf(or_sim *s) {
       spread_add(s, B->d.kernel, s->Fx, B->Fx[k], B->X[k], B->Y[k], B->ds);
       spread_add(s, B->d.kernel, s->Fy, B->Fy[k], B->X[k], B->Y[k], B->ds);
     }
-    free(rX[b]);
   }
-  free(rX);
   free(sx);
   free(sy);
 }

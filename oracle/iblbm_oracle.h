@@ -53,6 +53,9 @@ typedef struct {
   int32_t internal_mass;
   double amp[2], freq, phase;
   double density_ratio;
+  int32_t mdf_nmin;        /* adaptive MDF: fewest passes before the tolerance stop */
+  int32_t pad1;
+  double mdf_tol;          /* > 0: adaptive MDF (Sec. 2.5.2, App. A.2); <= 0: mdf_iters passes */
 } or_body_desc;
 
 typedef struct or_sim or_sim;

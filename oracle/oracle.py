@@ -46,7 +46,8 @@ class _Body(C.Structure):
                 ("n_markers", C.c_int32), ("scheme", C.c_int32), ("kernel", C.c_int32),
                 ("mdf_iters", C.c_int32), ("mdf_omega", C.c_double), ("motion", C.c_int32),
                 ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
-                ("phase", C.c_double), ("density_ratio", C.c_double)]
+                ("phase", C.c_double), ("density_ratio", C.c_double),
+                ("mdf_nmin", C.c_int32), ("pad1", C.c_int32), ("mdf_tol", C.c_double)]
 
 
 _lib = None
@@ -128,6 +129,8 @@ def make_body(b: dict) -> _Body:
     d.freq = float(b.get("freq", 0.0))
     d.phase = float(b.get("phase", 0.0))
     d.density_ratio = float(b.get("density_ratio", 1.0))
+    d.mdf_nmin = int(b.get("mdf_nmin", 1))
+    d.mdf_tol = float(b.get("mdf_tol", 0.0))
     return d
 
 

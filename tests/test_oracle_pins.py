@@ -435,6 +435,90 @@ def test_mdf_reduces_residual_and_slip(kernel):
     assert res[5]["mdf_residual"] < res[1]["mdf_residual"]
 
 
+# ------------------------------------------ adaptive MDF (Sec. 2.5.2, App. A.2)
+def _adaptive_single_marker(factor, nmin, nmax, tol, u0=0.05, ds=0.35):
+    """One P4 marker in a uniform stream u0 (rho = 1) with U_d = 0 and MDF
+    relaxation omega = (1 - factor)/a, where a = (3/8)^2 ds is the single
+    entry of A.  Pass n then sees U^(n) = u0 factor^(n-1) exactly, so the
+    residual r_n = |u0| |factor|^(n-1) is known in closed form."""
+    a = (3 / 8) ** 2 * ds
+    om = (1 - factor) / a
+    s = _uniform_box(24, 22, u0)
+    D = ds / math.pi
+    s.add_body(dict(xc=10.3 - D / 2, yc=9.71, diameter=D, n_markers=1, scheme=MDF,
+                    kernel=PESKIN4, mdf_iters=nmax, mdf_nmin=nmin, mdf_tol=tol, mdf_omega=om))
+    s.step(1)
+    return s.body_state(0), s.markers(0)[0], om
+
+
+# (factor, N_min, N_max, tol) -> (passes applied, residual of the last
+# interpolation), worked out by hand from r_n = 0.05 |factor|^(n-1):
+ADAPTIVE_CASES = [
+    # r_9 = 1.95e-4, r_10 = 9.77e-5 < 1e-4: stops before pass 10
+    ((0.5, 5, 20, 1e-4), (9, 0.05 / 2 ** 9)),
+    # r_1 = 0.05 is already below 0.1, but N_min = 5 passes come first
+    ((0.5, 5, 20, 0.1), (5, 0.05 / 2 ** 5)),
+    # the N_max cap: r_7 = 7.8e-4 is still above the tolerance
+    ((0.5, 5, 7, 1e-4), (7, 0.05 / 2 ** 6)),
+    # |factor| = 1: the residual stays at 0.05, no guard, N_max passes
+    ((-1.0, 5, 12, 1e-4), (12, 0.05)),
+    # growth 2 > 1.5: the divergence guard ends the iteration after one pass
+    ((-2.0, 5, 20, 1e-4), (1, 0.1)),
+    # growth 1.4 < 1.5: no guard, the residual grows to the cap
+    ((-1.4, 5, 6, 1e-4), (6, 0.05 * 1.4 ** 5)),
+]
+
+
+@pytest.mark.parametrize("case,expect", ADAPTIVE_CASES)
+def test_adaptive_mdf_single_marker_closed_form(case, expect):
+    """Stopping rules of the adaptive MDF on the closed form: the tolerance
+    stop after at least N_min passes, the N_max cap and the r_n > 1.5 r_(n-1)
+    guard; F_total = sum_n omega F^(n) and the post-IB slip u0 factor^N."""
+    factor, nmin, nmax, tol = case
+    npass, res = expect
+    st, m, om = _adaptive_single_marker(factor, nmin, nmax, tol)
+    u0 = 0.05
+    assert st["mdf_iters"] == npass
+    assert abs(st["mdf_residual"] - res) < 1e-12 * res
+    ftot = -2.0 * om * u0 * sum(factor ** n for n in range(npass))
+    assert abs(m[4] - ftot) < 1e-12 * 2.0 * om * u0
+    assert abs(m[5]) < 1e-12 * 2.0 * om * u0
+    slip = u0 * abs(factor) ** npass
+    assert abs(st["slip_mean"] - slip) < 1e-12 * u0
+
+
+@pytest.mark.parametrize("kernel", [HAT, PESKIN4])
+def test_adaptive_mdf_reduces_to_fixed_passes(kernel):
+    """A tolerance nothing can miss ends every step after exactly N_min
+    passes, and one nothing can meet runs N_max passes (no guard fires on
+    this contracting case): both reproduce the fixed form bit for bit."""
+    cfg, body = _cyl_case(MDF, kernel, motion=PRESCRIBED_SIN, amp=(0.0, 1.5), freq=0.01)
+    for adaptive, fixed_n, stop in ((dict(mdf_nmin=3, mdf_iters=20, mdf_tol=1e300), 3, True),
+                                    (dict(mdf_nmin=2, mdf_iters=9, mdf_tol=1e-300), 9, False)):
+        a = oracle.OracleSim(cfg); a.add_body(dict(body, **adaptive))
+        b = oracle.OracleSim(cfg); b.add_body(dict(body, mdf_iters=fixed_n))
+        c = oracle.OracleSim(cfg); c.add_body(dict(body, mdf_iters=fixed_n + 1))
+        a.step(1); b.step(1); c.step(1)
+        # a tolerance stop reports the residual measured after the last
+        # pass (the interpolation a further pass would start from); the cap
+        # reports the one measured before it, as the fixed form does
+        ref = c if stop else b
+        assert a.body_state(0)["mdf_residual"] == ref.body_state(0)["mdf_residual"]
+        for _ in range(4):
+            assert a.body_state(0)["mdf_iters"] == fixed_n
+            a.step(1); b.step(1)
+        np.testing.assert_array_equal(a.populations(), b.populations())
+        np.testing.assert_array_equal(np.stack(a.force()), np.stack(b.force()))
+
+
+def test_adaptive_mdf_rejects_bad_bounds():
+    cfg, body = _cyl_case(MDF, PESKIN4)
+    for bad in (dict(mdf_nmin=0, mdf_iters=5, mdf_tol=1e-4), dict(mdf_nmin=6, mdf_iters=5, mdf_tol=1e-4)):
+        s = oracle.OracleSim(cfg)
+        with pytest.raises(Exception):
+            s.add_body(dict(body, **bad))
+
+
 # ------------------------------------------------------------ Eq. (15)-(20)
 def _golden_lambda():
     rows = {}
