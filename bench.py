@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -81,6 +83,8 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
     sim.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # MDF passes applied in each timed step (history column 12)
+    passes = sim.history(0, warmup + 1, steps)[:, 12] if steps else np.zeros(0)
     split, near = sim.overlap()
     # IB pass duration from HIP events around each pass in a separate run of
     # unpipelined steps (the events add host and queue work to every step, so
@@ -107,6 +111,9 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
                inner_nodes=inner,
                split=split, near_nodes=near,
                fx=st["fx"], status=st["status"], steps_done=sim.steps_done,
+               passes_mean=float(passes.mean()) if len(passes) else 0.0,
+               passes_min=int(passes.min()) if len(passes) else 0,
+               passes_max=int(passes.max()) if len(passes) else 0,
                launch=sim.get_launch())
     sim.close()
     return out
@@ -235,6 +242,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-quantum", type=int, default=128)
     ap.add_argument("--no-largest", action="store_true", help="skip the largest-lattice leg")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive-MDF leg (N in [5, 20], tolerance 1e-4)")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -310,6 +319,22 @@ def main():
                         "roofline_frac": round(a64 / HBM_PEAK_GBS, 4),
                         "avg_launch_us": round(r64["lbm_ms"] / max(r64["n_lbm"], 1) * 1e3, 3),
                         "ib_pass_avg_us": round(r64["ibm_ms"] / max(r64["n_ibm"], 1) * 1e3, 3)}
+    if not args.no_adaptive and prec == ib.FP32_SHIFTED:
+        # the paper's adaptive MDF on the same lattice and body: between 5
+        # and 20 passes per step, as the slip residual decides
+        ca = ib_cases.unsteady_cylinder(scheme="MDF", kernel=args.kernel,
+                                        collision=args.collision, re=args.re)
+        ca["bodies"][0].update(ib_cases.ADAPTIVE_MDF)
+        sa = max(args.steps // 2, 50)
+        ra = run_gpu(ca, prec, sa, args.warmup // 2, tune=not args.no_tune)
+        line["adaptive_mdf"] = {
+            "value": round(nodes * sa / ra["seconds"] / 1e6, 2), "unit": "MLUPS",
+            "steps": sa, "bounds": [ib_cases.ADAPTIVE_MDF["mdf_nmin"], ib_cases.ADAPTIVE_MDF["mdf_iters"]],
+            "tolerance": ib_cases.ADAPTIVE_MDF["mdf_tol"],
+            "passes_mean": round(ra["passes_mean"], 2),
+            "passes_min": ra["passes_min"], "passes_max": ra["passes_max"],
+            "ib_pass_avg_us": round(ra["ibm_ms"] / max(ra["n_ibm"], 1) * 1e3, 3)}
+        line["mdf_passes_per_step"] = r["passes_mean"]
     if args.extra:
         combos = {}
         for sch in ("DF", "MDF", "DFC"):

@@ -14,7 +14,8 @@ Body dicts: xc, yc, diameter, n_markers (0 -> round(pi D)), scheme (0 DF,
 1 MDF, 2 DFC), kernel (0 hat, 1 Peskin 4-point), mdf_iters, mdf_omega
 (<= 0 -> 1/||A||_inf), motion (0 fixed, 1 prescribed sine, 2 free),
 internal_mass (0 none, 1 Feng explicit history), amp, freq, phase,
-density_ratio.
+density_ratio, mdf_nmin and mdf_tol (mdf_tol > 0 selects the adaptive MDF
+with at least mdf_nmin and at most mdf_iters passes).
 
 The parameter rules come from the paper: tau = 1/2 + 3 nu (App. A.1),
 Re = U D / nu (Sec. 2.6), N_b = round(pi D) markers of spacing pi D / N_b
@@ -41,6 +42,11 @@ COLLISIONS = {"BGK": BGK, "TRT": TRT, "CMMRT": CMMRT}
 # oscillation frequency of the oscillating-cylinder workload.  The paper does
 # not print a Re = 100 value; 0.165 is the commonly reported one.
 ST0_RE100 = 0.165
+
+
+# The adaptive MDF of the paper's runs (Sec. 2.5.2, App. A.2): N in [5, 20],
+# L-infinity slip-residual tolerance 1e-4.
+ADAPTIVE_MDF = dict(mdf_nmin=5, mdf_iters=20, mdf_tol=1e-4)
 
 
 def tau_from(u_ref: float, diameter: float, re: float) -> float:

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define IB_LBM_ABI_VERSION 1u
+#define IB_LBM_ABI_VERSION 2u
 
 typedef enum {
   IB_LBM_OK = 0,
@@ -104,8 +104,15 @@ typedef struct {
 
 /* A rigid circular body (Sec. 2.3-2.7).  n_markers = 0 -> round(pi D)
  * evenly spaced markers (Table I), arc spacing ds = pi D / n_markers.
- * MDF: mdf_iters passes (Eq. 12-14) with relaxation mdf_omega, or
- * 1/||A||_inf computed once here when mdf_omega <= 0 (Sec. 2.5.2).
+ * MDF: passes of Eq. 12-14 with relaxation mdf_omega, or 1/||A||_inf
+ * computed once here when mdf_omega <= 0 (Sec. 2.5.2).  mdf_tol <= 0: exactly
+ * mdf_iters passes.  mdf_tol > 0: the adaptive form of Sec. 2.5.2 / App. A.2.
+ * Before pass n the residual r_n = max_k |U_d - U^(n)(X_k)| is measured, and
+ * the iteration ends there, without pass n, once at least mdf_nmin passes
+ * are done and r_n < mdf_tol, or when r_n > 1.5 r_(n-1) (divergence guard,
+ * from n = 2); it applies at most mdf_iters passes (the paper's runs:
+ * mdf_nmin 5, mdf_iters 20, mdf_tol 1e-4).  Each body decides on its own
+ * residual.  IB_LBM_E_INVALID unless 1 <= mdf_nmin <= mdf_iters.
  * PRESCRIBED_SIN: X_c(t) = X_c0 + amp sin(2 pi freq t + phase).
  * FREE: density_ratio rho_s/rho0, internal_mass selects scheme (A) or the
  * Feng explicit-history correction (App. A.5).  All bodies of one sim use
@@ -121,12 +128,16 @@ typedef struct {
   int32_t internal_mass;
   double amp[2], freq, phase;
   double density_ratio;
+  int32_t mdf_nmin; /* adaptive MDF: fewest passes before the tolerance stop */
+  double mdf_tol;   /* > 0 selects the adaptive MDF; <= 0 the fixed form */
 } ib_lbm_body_desc;
 
 /* State of a body after the last completed step.  Forces are on the body
  * (Newton's third law for DF/MDF).  slip_* are |interp(u) - U_d| over the
- * markers with the post-IB velocity; mdf_residual is max_k |U_d - U^(N)| of
- * the last MDF pass. */
+ * markers with the post-IB velocity; mdf_residual is max_k |U_d - U| of the
+ * last MDF interpolation of the step (before the last pass applied, or,
+ * after an adaptive stop, the one that ended the iteration); mdf_iters is
+ * the number of passes applied. */
 typedef struct {
   int64_t step;
   double fx, fy, torque;

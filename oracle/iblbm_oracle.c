@@ -43,6 +43,8 @@ typedef struct {
   double *Fx, *Fy;  /* DF/MDF: F_L^total per marker; DFC: F_s per marker */
   double *lambda;   /* DFC */
   double *mdfU;     /* scratch */
+  double *mdf_r;    /* MDF residual of each interpolation of the last step */
+  int mdf_nr;       /* number of interpolations of the last step */
   /* rigid-body state */
   double xc0, yc0;
   double xc, yc, vx, vy, vpx, vpy, om;
@@ -350,7 +352,7 @@ void or_destroy(or_sim *s) {
   for (int b = 0; b < s->nbody; b++) {
     or_body *B = &s->body[b];
     free(B->X); free(B->Y); free(B->Udx); free(B->Udy);
-    free(B->Fx); free(B->Fy); free(B->lambda); free(B->mdfU);
+    free(B->Fx); free(B->Fy); free(B->lambda); free(B->mdfU); free(B->mdf_r);
   }
   free(s->f); free(s->fc); free(s->Fx); free(s->Fy);
   free(s->tmpa); free(s->tmpb); free(s->tmpc);
@@ -360,7 +362,7 @@ void or_destroy(or_sim *s) {
 int or_add_body(or_sim *s, const or_body_desc *d) {
   if (s->nbody >= OR_MAX_BODIES || d->diameter <= 0) return -1;
   if (s->nbody > 0 && s->body[0].d.scheme != d->scheme) return -1;
-  if (d->scheme == OR_MDF && (d->mdf_iters < 1 || (d->mdf_tol > 0.0 && (d->mdf_nmin < 1 || d->mdf_nmin > d->mdf_iters))))
+  if (d->scheme == OR_MDF && (d->mdf_iters < 1 || d->mdf_iters > 1000 || (d->mdf_tol > 0.0 && (d->mdf_nmin < 1 || d->mdf_nmin > d->mdf_iters))))
     return -1;
   or_body *b = &s->body[s->nbody];
   memset(b, 0, sizeof(*b));
@@ -372,6 +374,7 @@ int or_add_body(or_sim *s, const or_body_desc *d) {
   b->X = calloc(nb, 8); b->Y = calloc(nb, 8); b->Udx = calloc(nb, 8); b->Udy = calloc(nb, 8);
   b->Fx = calloc(nb, 8); b->Fy = calloc(nb, 8); b->lambda = calloc(nb, 8);
   b->mdfU = calloc(2 * nb, 8);
+  b->mdf_r = calloc(d->mdf_iters > 0 ? (size_t)d->mdf_iters : 1, 8);
   b->xc0 = b->xc = d->xc;
   b->yc0 = b->yc = d->yc;
   double rs = d->density_ratio * s->c.rho0, area = M_PI * b->radius * b->radius;
@@ -395,6 +398,11 @@ int or_add_body(or_sim *s, const or_body_desc *d) {
 }
 
 double or_body_omega(const or_sim *s, int b) { return s->body[b].omega_mdf; }
+int or_mdf_residuals(const or_sim *s, int b, double *out) {
+  const or_body *B = &s->body[b];
+  for (int i = 0; i < B->mdf_nr; i++) out[i] = B->mdf_r[i];
+  return B->mdf_nr;
+}
 int64_t or_steps_done(const or_sim *s) { return s->step; }
 
 /* ------------------------------------------------------------------ */
@@ -675,6 +683,7 @@ static void ibm_mdf(or_sim *s) {
     const int adaptive = B->d.mdf_tol > 0.0;
     double rprev = 0.0;
     B->mdf_iters_done = 0;
+    B->mdf_nr = 0;
     for (int it = 1; it <= B->d.mdf_iters; it++) {
       double res = 0.0;
       for (int k = 0; k < B->nb; k++) {
@@ -684,6 +693,7 @@ static void ibm_mdf(or_sim *s) {
         res = r > res ? r : res;
       }
       B->mdf_res = res;
+      B->mdf_r[B->mdf_nr++] = res;
       if (adaptive && ((it > B->d.mdf_nmin && res < B->d.mdf_tol) || (it > 1 && res > 1.5 * rprev)))
         break;
       rprev = res;

@@ -78,6 +78,9 @@ int or_body_state(const or_sim *s, int b, double *out);
 /* per marker 8 values: X Y Udx Udy Fx Fy lambda ds */
 int or_markers(const or_sim *s, int b, double *out);
 double or_body_omega(const or_sim *s, int b);
+/* MDF residual r_n of each interpolation of the last step (out holds
+ * mdf_iters doubles); returns their number. */
+int or_mdf_residuals(const or_sim *s, int b, double *out);
 
 /* unit-level pieces used by the pins */
 double or_phi(int kernel, double r);

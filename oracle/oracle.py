@@ -75,6 +75,8 @@ def lib():
         L.or_markers.argtypes = [C.c_void_p, C.c_int, dp]
         L.or_body_omega.restype = C.c_double
         L.or_body_omega.argtypes = [C.c_void_p, C.c_int]
+        L.or_mdf_residuals.restype = C.c_int
+        L.or_mdf_residuals.argtypes = [C.c_void_p, C.c_int, dp]
         L.or_phi.restype = C.c_double
         L.or_phi.argtypes = [C.c_int, C.c_double]
         L.or_equilibrium.argtypes = [C.c_double, C.c_double, C.c_double, dp]
@@ -210,6 +212,12 @@ class OracleSim:
 
     def mdf_omega(self, b: int = 0) -> float:
         return lib().or_body_omega(self.h, b)
+
+    def mdf_residuals(self, b: int = 0) -> np.ndarray:
+        """MDF residual r_n of every interpolation of the last step."""
+        out = np.zeros(1024)
+        n = lib().or_mdf_residuals(self.h, b, out.ctypes.data_as(C.POINTER(C.c_double)))
+        return out[:n].copy()
 
 
 def phi(kernel: int, r: float) -> float:

@@ -648,6 +648,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   if (!(b->diameter > 0) || b->scheme < IB_LBM_DF || b->scheme > IB_LBM_DFC || b->kernel < 0 ||
       b->kernel > 1 || b->motion < 0 || b->motion > 2 || b->n_markers < 0 ||
       (b->scheme == IB_LBM_MDF && (b->mdf_iters < 1 || b->mdf_iters > 1000)) ||
+      (b->scheme == IB_LBM_MDF && b->mdf_tol > 0 &&
+       (b->mdf_nmin < 1 || b->mdf_nmin > b->mdf_iters)) ||
       (b->motion == IB_LBM_FREE && !(b->density_ratio > 0))) {
     set_err(&s->err, "invalid body description");
     return IB_LBM_E_INVALID;
@@ -669,6 +671,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.scheme = b->scheme;
   B.kernel = b->kernel;
   B.mdf_iters = b->scheme == IB_LBM_MDF ? b->mdf_iters : 1;
+  B.mdf_tol = b->scheme == IB_LBM_MDF && b->mdf_tol > 0 ? b->mdf_tol : 0.0;
+  B.mdf_nmin = B.mdf_tol > 0 ? b->mdf_nmin : B.mdf_iters;
   B.motion = b->motion;
   B.internal_mass = b->internal_mass;
   B.ns = b->kernel == IB_LBM_HAT ? 2 : 4;

@@ -80,6 +80,8 @@ struct BodyDesc {
   int32_t ws_tab;       // doubles of the table part of the workspace
   int32_t ws_tab_hot;   // doubles of its hot part (what a DF/MDF step reads)
   int32_t pop_bytes;    // bytes of one stored population (8 FP64, 4 FP32 shifted)
+  int32_t mdf_nmin;     // adaptive MDF: fewest passes before the tolerance stop
+  double mdf_tol;       // > 0: adaptive MDF with this tolerance; else mdf_iters passes
   double *markers_out;  // n_b x 8: X Y Udx Udy Fx Fy lambda ds
   double *lambda_cache; // n_b
   double *history;      // hist_cap x kHistCols

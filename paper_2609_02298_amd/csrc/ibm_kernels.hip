@@ -82,7 +82,6 @@ __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_f64<0x140>(v));
   return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
-// Reduces four values at once: three sums and one max; result valid in all threads.
 // Sums a, b, c, d and maxima m1, m2 over the workgroup, each in a fixed
 // order: wave totals, then the wave totals (one lane of wave 0 each) by the
 // same wave tree.  The results are valid in the threads of wave 0.
@@ -705,15 +704,25 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       // interpolated once, in the first pass; F_total accumulates omega F^(n).
       // After the first pass's interpolation nrho holds ds / (2 rho(x)), the
       // factor of every pass (each node's thread converts its own entry).
+      // Adaptive form (tolerance > 0, Sec. 2.5.2 / App. A.2): the residual
+      // r_n = max_k |U_d - U^(n)| is reduced over the workgroup before pass n
+      // is applied; the iteration ends there, without pass n, after at least
+      // nmin passes once r_n < tol, or when r_n > 1.5 r_(n-1).  F_total then
+      // takes omega F^(n) only once the pass is kept.
       const int N = B.mdf_iters;
       const double om = B.omega_mdf;
+      const double tol = B.mdf_tol;
+      const bool adapt = tol > 0.0;
+      double rprev = 0.0;
       for (int n = 1; n <= N; n++) {
+        double rloc = 0.0;
         for (int kk = tid; kk < LPM * nb; kk += nth) {
           const int k = kk / LPM, h = kk % LPM;
           // the marker's own operands are loaded ahead of the node gathers
           const double udx = L.Udx[k], udy = L.Udy[k];
           const double rX = n == 1 ? interp1<NS, LPM>(L, k, h, L.nrho) : L.rhoX[k];
-          const double ftx = n == 1 ? 0.0 : L.Ftx[k], fty = n == 1 ? 0.0 : L.Fty[k];
+          const bool acc = n > 1 && !adapt;
+          const double ftx = acc ? L.Ftx[k] : 0.0, fty = acc ? L.Fty[k] : 0.0;
           double Ux, Uy;
           interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
           if (h == 0) {
@@ -722,12 +731,32 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
             const double Fx = 2.0 * rX * ex, Fy = 2.0 * rX * ey;
             L.Fx[k] = om * Fx;
             L.Fy[k] = om * Fy;
-            L.Ftx[k] = ftx + om * Fx;
-            L.Fty[k] = fty + om * Fy;
-            if (n == N) resmax = fmax(resmax, sqrt(ex * ex + ey * ey));
+            if (!adapt) {
+              L.Ftx[k] = ftx + om * Fx;
+              L.Fty[k] = fty + om * Fy;
+            }
+            rloc = fmax(rloc, sqrt(ex * ex + ey * ey));
           }
         }
+        if (!adapt && n == N) resmax = rloc;
+        if (adapt) {
+          rloc = wave_max(rloc);
+          if ((tid & 63) == 0) red[tid >> 6] = rloc;
+        }
         __syncthreads();
+        if (adapt) {
+          // every thread takes the same decision from the same partials
+          double rn = red[0];
+          for (int w = 1; w < (nth >> 6); w++) rn = fmax(rn, red[w]);
+          resmax = rn;
+          if ((n > B.mdf_nmin && rn < tol) || (n > 1 && rn > 1.5 * rprev)) break;
+          rprev = rn;
+          if (tid == 0) ish[11] = n;
+          for (int k = tid; k < nb; k += nth) {
+            L.Ftx[k] = (n == 1 ? 0.0 : L.Ftx[k]) + L.Fx[k];
+            L.Fty[k] = (n == 1 ? 0.0 : L.Fty[k]) + L.Fy[k];
+          }
+        }
         if (n == 1)
           for (int j = tid; j < S; j += nth) L.nrho[j] = ds / (2.0 * L.nrho[j]);
         if (FAST || spread_mode == 0) {

@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libib_lbm.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 FP64, FP32_SHIFTED = 0, 1
 BGK, TRT, CMMRT = 0, 1, 2
@@ -79,7 +79,8 @@ class BodyDesc(C.Structure):
                 ("n_markers", C.c_int32), ("scheme", C.c_int32), ("kernel", C.c_int32),
                 ("mdf_iters", C.c_int32), ("mdf_omega", C.c_double), ("motion", C.c_int32),
                 ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
-                ("phase", C.c_double), ("density_ratio", C.c_double)]
+                ("phase", C.c_double), ("density_ratio", C.c_double),
+                ("mdf_nmin", C.c_int32), ("mdf_tol", C.c_double)]
 
 
 class BodyState(C.Structure):
@@ -281,6 +282,8 @@ def make_body(b: dict) -> BodyDesc:
     d.freq = float(b.get("freq", 0.0))
     d.phase = float(b.get("phase", 0.0))
     d.density_ratio = float(b.get("density_ratio", 1.0))
+    d.mdf_nmin = int(b.get("mdf_nmin", 1))
+    d.mdf_tol = float(b.get("mdf_tol", 0.0))
     return d
 
 

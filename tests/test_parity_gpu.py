@@ -321,6 +321,121 @@ def test_sedimentation_full_size_window(pair):
         assert abs(fs["vy"] - fr["vy"]) < 1e-10 * abs(fr["vy"])
 
 
+# ------------------------------------------ adaptive MDF (Sec. 2.5.2, App. A.2)
+def decision_margin(rs, nmin, tol):
+    """Smallest relative distance of the oracle's residuals r_n from the
+    thresholds that its stop decisions compared them with (the tolerance
+    after nmin passes, 1.5 r_(n-1) from the second interpolation on)."""
+    m = math.inf
+    for n in range(1, len(rs) + 1):
+        if n > nmin:
+            m = min(m, abs(rs[n - 1] - tol) / tol)
+        if n > 1:
+            m = min(m, abs(rs[n - 1] - 1.5 * rs[n - 2]) / (1.5 * rs[n - 2]))
+    return m
+
+
+ADAPTIVE_GPU = [(ib.HAT, 1e-3, ib.PRESCRIBED_SIN, ib.SPREAD_GATHER),
+                (ib.PESKIN4, 1e-4, ib.PRESCRIBED_SIN, ib.SPREAD_GATHER),
+                (ib.PESKIN4, 1e-4, ib.FIXED, ib.SPREAD_GATHER),
+                (ib.PESKIN4, 1e-4, ib.PRESCRIBED_SIN, ib.SPREAD_ATOMIC)]
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+@pytest.mark.parametrize("kernel,tol,motion,spread", ADAPTIVE_GPU)
+def test_adaptive_mdf(kernel, tol, motion, spread, prec):
+    """Adaptive MDF (N in [5, 20]) step by step against the oracle: the pass
+    count of every step, its last residual, the forces and the fields.  The
+    stop decisions are taken in FP64 on both sides; these seeded cases keep
+    each of the oracle's residuals at least 1e-4 (relative) away from the
+    threshold it was compared with (asserted), ten times further than the
+    FP32 store moves them (the residuals agree to 1e-5), so the counts must
+    agree exactly."""
+    say(f"adaptive MDF kernel={kernel} tol={tol} motion={motion} spread={spread} prec={prec}")
+    case = body_case(ib.MDF, kernel, ib.TRT, mdf_iters=20, mdf_nmin=5, mdf_tol=tol,
+                     motion=motion, amp=(0.0, 3.2), freq=0.004)
+    sim, ref = make_pair(case, prec)
+    sim.set_spread(spread)
+    f64 = prec == ib.FP64
+    counts, rerr = [], 0.0
+    for _ in range(40):
+        sim.step(1)
+        ref.step(1)
+        fs, fr = sim.forces(0), ref.body_state(0)
+        assert decision_margin(ref.mdf_residuals(0), 5, tol) > (1e-9 if f64 else 1e-4)
+        assert fs["mdf_iters"] == fr["mdf_iters"]
+        counts.append(fs["mdf_iters"])
+        rerr = max(rerr, abs(fs["mdf_residual"] - fr["mdf_residual"]) / fr["mdf_residual"])
+        assert rerr < (1e-10 if f64 else 1e-5)
+        assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < (F64_DRAG if f64 else F32_DRAG)
+    say(f"  pass counts {counts}; residual max rel err {rerr:.2e}")
+    assert len(set(counts)) > 1 or counts[0] == 20
+    if f64:
+        assert rel(sim.populations(), ref.populations()) < F64_FIELD
+        gx, gy = sim.force()
+        rx, ry = ref.force()
+        assert rel(np.stack([gx, gy]), np.stack([rx, ry])) < F64_FIELD
+    else:
+        assert compare_fields(sim, ref, None) < F32_FIELD
+    h = sim.history(0, 1, 40)
+    np.testing.assert_array_equal(h[:, 12], counts)
+
+
+def test_adaptive_mdf_single_marker_closed_form_gpu():
+    """The closed form of the single-marker iteration (r_n = |u0| |factor|^(n-1))
+    on the GPU: pass counts, residual and F_total for the tolerance stop,
+    the N_min floor, the N_max cap and the divergence guard."""
+    u0, ds = 0.05, 0.35
+    a = (3 / 8) ** 2 * ds
+    feq = oracle.equilibrium(1.0, u0, 0.0)
+    cases = [((0.5, 5, 20, 1e-4), (9, 0.05 / 2 ** 9)), ((0.5, 5, 20, 0.1), (5, 0.05 / 2 ** 5)),
+             ((0.5, 5, 7, 1e-4), (7, 0.05 / 2 ** 6)), ((-1.0, 5, 12, 1e-4), (12, 0.05)),
+             ((-2.0, 5, 20, 1e-4), (1, 0.1)), ((-1.4, 5, 6, 1e-4), (6, 0.05 * 1.4 ** 5))]
+    for (factor, nmin, nmax, tol), (npass, res) in cases:
+        say(f"single marker factor={factor} nmin={nmin} nmax={nmax} tol={tol}")
+        om = (1 - factor) / a
+        D = ds / math.pi
+        case = dict(nx=24, ny=22, collision=ib.BGK, tau=0.8, bc=(ib.PERIODIC,) * 4,
+                    bodies=[dict(xc=10.3 - D / 2, yc=9.71, diameter=D, n_markers=1, scheme=ib.MDF,
+                                 kernel=ib.PESKIN4, mdf_iters=nmax, mdf_nmin=nmin, mdf_tol=tol,
+                                 mdf_omega=om)])
+        sim = ib.Sim(case)
+        f = np.zeros((9, 22, 24))
+        f[:] = feq[:, None, None]
+        sim.set_populations(f)
+        sim.step(1)
+        st, m = sim.forces(0), sim.markers(0)[0]
+        assert st["mdf_iters"] == npass
+        assert abs(st["mdf_residual"] - res) < 1e-12 * res
+        ftot = -2.0 * om * u0 * sum(factor ** n for n in range(npass))
+        assert abs(m[4] - ftot) < 1e-12 * 2.0 * om * u0
+        assert abs(st["slip_mean"] - u0 * abs(factor) ** npass) < 1e-12 * u0
+
+
+def test_adaptive_mdf_full_size_window():
+    """2000x800, D = 80, MDF P4 TRT with the paper's adaptive bounds, FP64,
+    through the split (pipelined) step of this lattice."""
+    say("2000x800 adaptive MDF window")
+    case = ib_cases.unsteady_cylinder(scheme="MDF", kernel="P4", collision="TRT", re=100.0)
+    case["bodies"][0].update(ib_cases.ADAPTIVE_MDF)
+    sim, ref = make_pair(case)
+    for _ in range(4):
+        sim.step(1)
+        ref.step(1)
+        fs, fr = sim.forces(0), ref.body_state(0)
+        assert decision_margin(ref.mdf_residuals(0), 5, 1e-4) > 1e-6
+        assert fs["mdf_iters"] == fr["mdf_iters"]
+        assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < F64_DRAG
+    assert rel(sim.populations(), ref.populations()) < F64_FIELD
+
+
+def test_adaptive_mdf_bounds_are_checked():
+    for bad in (dict(mdf_nmin=0, mdf_iters=5, mdf_tol=1e-4), dict(mdf_nmin=6, mdf_iters=5, mdf_tol=1e-4)):
+        case = body_case(ib.MDF, ib.PESKIN4, ib.TRT, **bad)
+        with pytest.raises(ib.IbLbmError):
+            ib.Sim(case)
+
+
 # ------------------------------------------------------------- properties
 def test_run_to_run_bitwise_and_gather_vs_atomic():
     case = body_case(ib.MDF, ib.PESKIN4, ib.CMMRT)
