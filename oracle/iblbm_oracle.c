@@ -874,6 +874,84 @@ void or_fields(const or_sim *s, double *rho, double *ux, double *uy) {
   }
 }
 
+/* Boundary-fidelity diagnostics (Sec. 2.8) and the marker profiles of
+ * Sec. 4.2, on the current Eulerian field u = (sum_i f_i e_i + F/2)/rho.
+ * Readings: the field is sampled at the markers by bilinear interpolation
+ * (the hat kernel, Eq. 9), a probe distinct from the scheme's own kernel;
+ * velocities are taken relative to the body's rigid motion U_b(x) = v +
+ * Omega x (x - X_c) with the velocities reported for the body after the
+ * step (zero for a fixed body); n_k = (X_k - X_c)/R.
+ *   sum[0..1] slip mean / max: |u(X_k) - U_b(X_k)| / u_ref
+ *   sum[2]    leakage flux sum_k rho(X_k) (u - U_b).n_k ds / (u_ref pi D)
+ *   sum[3..5] internal residual: mean / max of |u - U_b| / u_ref over the
+ *             nodes with |x - X_c| < R - kappa, and their count
+ *   sum[6]    mean pressure deviation (rho(X_k) - rho0) c_s^2
+ *   sum[7]    mean marker force magnitude |F_k| (F_L of DF/MDF, F_s of DFC)
+ *   pm[6k..]  slip_k, dp_k, |F_k|, rho(X_k), normal and tangential
+ *             relative velocity / u_ref */
+int or_diagnostics(const or_sim *s, int b, int kappa, double u_ref, double *sum, double *pm) {
+  if (b < 0 || b >= s->nbody || kappa < 0 || !(u_ref > 0)) return -1;
+  const or_body *B = &s->body[b];
+  const int n = s->n, nx = s->c.nx, ny = s->c.ny;
+  double *rho = malloc(sizeof(double) * n), *ux = malloc(sizeof(double) * n),
+         *uy = malloc(sizeof(double) * n);
+  or_fields(s, rho, ux, uy);
+  const double xc = B->xc, yc = B->yc, R = B->radius;
+  const double vx = B->d.motion == OR_FREE ? B->vx : B->vhx;
+  const double vy = B->d.motion == OR_FREE ? B->vy : B->vhy;
+  const double om = B->d.motion == OR_FREE ? B->om : B->omh;
+  const double cs2 = 1.0 / 3.0;
+  double slip_sum = 0, slip_max = 0, flux = 0, dp_sum = 0, f_sum = 0;
+  for (int k = 0; k < B->nb; k++) {
+    const double X = B->X[k], Y = B->Y[k];
+    const double rk = interp(s, OR_HAT, rho, X, Y);
+    const double dx = interp(s, OR_HAT, ux, X, Y) - (vx - om * (Y - yc));
+    const double dy = interp(s, OR_HAT, uy, X, Y) - (vy + om * (X - xc));
+    const double nxk = (X - xc) / R, nyk = (Y - yc) / R;
+    const double slip = sqrt(dx * dx + dy * dy) / u_ref;
+    const double dp = (rk - s->c.rho0) * cs2;
+    const double fm = sqrt(B->Fx[k] * B->Fx[k] + B->Fy[k] * B->Fy[k]);
+    slip_sum += slip;
+    slip_max = slip > slip_max ? slip : slip_max;
+    flux += rk * (dx * nxk + dy * nyk) * B->ds;
+    dp_sum += dp;
+    f_sum += fm;
+    if (pm) {
+      double *o = pm + 6 * k;
+      o[0] = slip;
+      o[1] = dp;
+      o[2] = fm;
+      o[3] = rk;
+      o[4] = (dx * nxk + dy * nyk) / u_ref;
+      o[5] = (-dx * nyk + dy * nxk) / u_ref;
+    }
+  }
+  double in_sum = 0, in_max = 0;
+  long in_n = 0;
+  const double Ri = R - kappa;
+  for (int y = 0; y < ny && Ri > 0; y++)
+    for (int x = 0; x < nx; x++) {
+      const double rx = x - xc, ry = y - yc;
+      if (rx * rx + ry * ry >= Ri * Ri) continue;
+      const int p = y * nx + x;
+      const double dx = ux[p] - (vx - om * ry), dy = uy[p] - (vy + om * rx);
+      const double m = sqrt(dx * dx + dy * dy) / u_ref;
+      in_sum += m;
+      in_max = m > in_max ? m : in_max;
+      in_n++;
+    }
+  sum[0] = slip_sum / B->nb;
+  sum[1] = slip_max;
+  sum[2] = flux / (u_ref * M_PI * B->d.diameter);
+  sum[3] = in_n ? in_sum / in_n : 0.0;
+  sum[4] = in_max;
+  sum[5] = (double)in_n;
+  sum[6] = dp_sum / B->nb;
+  sum[7] = f_sum / B->nb;
+  free(rho); free(ux); free(uy);
+  return 0;
+}
+
 int or_body_state(const or_sim *s, int b, double *out) {
   if (b < 0 || b >= s->nbody) return -1;
   const or_body *B = &s->body[b];

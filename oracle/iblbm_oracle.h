@@ -81,6 +81,9 @@ double or_body_omega(const or_sim *s, int b);
 /* MDF residual r_n of each interpolation of the last step (out holds
  * mdf_iters doubles); returns their number. */
 int or_mdf_residuals(const or_sim *s, int b, double *out);
+/* Boundary-fidelity diagnostics of body b on the current field (Sec. 2.8,
+ * Sec. 4.2): sum[8] and, when pm is not NULL, 6 values per marker. */
+int or_diagnostics(const or_sim *s, int b, int kappa, double u_ref, double *sum, double *pm);
 
 /* unit-level pieces used by the pins */
 double or_phi(int kernel, double r);

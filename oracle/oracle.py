@@ -77,6 +77,8 @@ def lib():
         L.or_body_omega.argtypes = [C.c_void_p, C.c_int]
         L.or_mdf_residuals.restype = C.c_int
         L.or_mdf_residuals.argtypes = [C.c_void_p, C.c_int, dp]
+        L.or_diagnostics.restype = C.c_int
+        L.or_diagnostics.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, dp, dp]
         L.or_phi.restype = C.c_double
         L.or_phi.argtypes = [C.c_int, C.c_double]
         L.or_equilibrium.argtypes = [C.c_double, C.c_double, C.c_double, dp]
@@ -212,6 +214,19 @@ class OracleSim:
 
     def mdf_omega(self, b: int = 0) -> float:
         return lib().or_body_omega(self.h, b)
+
+    def diagnostics(self, b: int = 0, kappa: int = 2, u_ref: float = 1.0):
+        """Boundary-fidelity diagnostics (summary dict, per-marker n_b x 6)."""
+        sm = np.zeros(8)
+        nb = self.markers(b).shape[0]
+        pm = np.zeros((nb, 6))
+        dpp = C.POINTER(C.c_double)
+        if lib().or_diagnostics(self.h, b, int(kappa), float(u_ref), sm.ctypes.data_as(dpp),
+                                pm.ctypes.data_as(dpp)) != 0:
+            raise ValueError("or_diagnostics: invalid arguments")
+        keys = ["slip_mean", "slip_max", "phi_leak", "u_inside_mean", "u_inside_max",
+                "n_inside", "dp_mean", "force_mean"]
+        return dict(zip(keys, sm.tolist())), pm
 
     def mdf_residuals(self, b: int = 0) -> np.ndarray:
         """MDF residual r_n of every interpolation of the last step."""

@@ -519,6 +519,104 @@ def test_adaptive_mdf_rejects_bad_bounds():
             s.add_body(dict(body, **bad))
 
 
+# ------------------------------------------- boundary diagnostics (Sec. 2.8)
+def _field_box(nx, ny, rho_fn, u_fn, body):
+    """Periodic box whose populations are f^eq(rho(x), u(x)) at every node, so
+    that the Eulerian field is exactly rho(x), u(x); one fixed body, no step."""
+    s = oracle.OracleSim(_box(BGK, nx, ny, (PERIODIC,) * 4, tau=0.8))
+    s.add_body(body)
+    f = np.zeros((9, ny, nx))
+    for y in range(ny):
+        for x in range(nx):
+            ux, uy = u_fn(x, y)
+            f[:, y, x] = oracle.equilibrium(rho_fn(x, y), ux, uy)
+    s.set_populations(f)
+    return s
+
+
+DIAG_BODY = dict(xc=24.3, yc=23.8, diameter=16.0, n_markers=50, scheme=DF, kernel=PESKIN4)
+
+
+def _inside(nx, ny, xc, yc, r_in):
+    ys, xs = np.mgrid[0:ny, 0:nx]
+    r = np.hypot(xs - xc, ys - yc)
+    return r[r < r_in]
+
+
+@pytest.mark.parametrize("kappa", [0, 2])
+def test_diagnostics_radial_source_closed_form(kappa):
+    """u = c (x - X_c): the bilinear probe is exact on a linear field, so every
+    marker sees |u| = c R along n_k, the leakage flux is c R / u_ref exactly
+    (N_b ds = pi D), and the interior mean is c <r> over the nodes inside
+    R - kappa."""
+    c, uref, (xc, yc, D) = 2e-3, 0.05, (24.3, 23.8, 16.0)
+    s = _field_box(48, 48, lambda x, y: 1.0, lambda x, y: (c * (x - xc), c * (y - yc)), DIAG_BODY)
+    sm, pm = s.diagnostics(0, kappa=kappa, u_ref=uref)
+    R = D / 2
+    assert abs(sm["phi_leak"] - c * R / uref) < 1e-13
+    np.testing.assert_allclose(pm[:, 0], c * R / uref, rtol=1e-12)
+    np.testing.assert_allclose(pm[:, 4], c * R / uref, rtol=1e-12)
+    assert np.abs(pm[:, 5]).max() < 1e-13
+    assert abs(sm["slip_max"] - c * R / uref) < 1e-13
+    r = _inside(48, 48, xc, yc, R - kappa)
+    assert sm["n_inside"] == len(r)
+    assert abs(sm["u_inside_mean"] - c * r.mean() / uref) < 1e-13
+    assert abs(sm["u_inside_max"] - c * r.max() / uref) < 1e-13
+    assert np.abs(pm[:, 1]).max() < 1e-15
+
+
+def test_diagnostics_rigid_rotation_has_no_leakage():
+    """u = Omega x (x - X_c): tangential everywhere, so no normal velocity
+    and no leakage; the marker slip is Omega R, the interior mean Omega <r>."""
+    Om, uref, (xc, yc, D) = 4e-3, 0.05, (24.3, 23.8, 16.0)
+    s = _field_box(48, 48, lambda x, y: 1.0, lambda x, y: (-Om * (y - yc), Om * (x - xc)),
+                   DIAG_BODY)
+    sm, pm = s.diagnostics(0, kappa=2, u_ref=uref)
+    R = D / 2
+    assert abs(sm["phi_leak"]) < 1e-14
+    assert np.abs(pm[:, 4]).max() < 1e-13
+    np.testing.assert_allclose(pm[:, 5], Om * R / uref, rtol=1e-12)
+    np.testing.assert_allclose(pm[:, 0], Om * R / uref, rtol=1e-12)
+    r = _inside(48, 48, xc, yc, R - 2)
+    assert abs(sm["u_inside_mean"] - Om * r.mean() / uref) < 1e-13
+
+
+def test_diagnostics_pressure_probe_is_bilinear():
+    """rho = 1 + eps (x - X_c)^2: bilinear sampling of a quadratic adds
+    w (1 - w) (w the marker's fractional x offset) to (X_k - X_c)^2, which a
+    Peskin 4-point probe would not; dp_k = (rho(X_k) - 1)/3 (Sec. 4.2)."""
+    eps, (xc, yc) = 1e-4, (24.3, 23.8)
+    s = _field_box(48, 48, lambda x, y: 1.0 + eps * (x - xc) ** 2, lambda x, y: (0.0, 0.0),
+                   DIAG_BODY)
+    sm, pm = s.diagnostics(0, kappa=2, u_ref=0.05)
+    X = s.markers(0)[:, 0]
+    w = X - np.floor(X)
+    dp = eps * ((X - xc) ** 2 + w * (1 - w)) / 3.0
+    # (a Peskin 4-point probe adds 0.51-0.54 in place of w (1 - w), which
+    # moves dp_k by about 1e-5)
+    np.testing.assert_allclose(pm[:, 1], dp, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(pm[:, 3], 1.0 + 3.0 * dp, rtol=0, atol=1e-15)
+    assert abs(sm["dp_mean"] - dp.mean()) < 1e-15
+    assert sm["slip_max"] == 0.0 and sm["u_inside_mean"] == 0.0
+
+
+def test_diagnostics_uniform_stream_and_force_column():
+    """A uniform stream: every marker slips by u0, the net flux through the
+    closed boundary vanishes; after one DF step the force column is |F_L,k|."""
+    u0, uref = 0.04, 0.05
+    s = _field_box(48, 48, lambda x, y: 1.0, lambda x, y: (u0, 0.0), DIAG_BODY)
+    sm, pm = s.diagnostics(0, kappa=2, u_ref=uref)
+    np.testing.assert_allclose(pm[:, 0], u0 / uref, rtol=1e-12)
+    assert abs(sm["phi_leak"]) < 1e-14
+    th = np.arctan2(s.markers(0)[:, 1] - 23.8, s.markers(0)[:, 0] - 24.3)
+    np.testing.assert_allclose(pm[:, 4], u0 * np.cos(th) / uref, rtol=0, atol=1e-13)
+    s.step(1)
+    sm, pm = s.diagnostics(0, kappa=2, u_ref=uref)
+    m = s.markers(0)
+    np.testing.assert_allclose(pm[:, 2], np.hypot(m[:, 4], m[:, 5]), rtol=1e-15)
+    assert abs(sm["force_mean"] - np.hypot(m[:, 4], m[:, 5]).mean()) < 1e-15
+
+
 # ------------------------------------------------------------ Eq. (15)-(20)
 def _golden_lambda():
     rows = {}
