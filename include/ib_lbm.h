@@ -207,6 +207,30 @@ ib_lbm_status ib_lbm_force_field(ib_lbm_sim *s, double *fx, double *fy);
  * *n_markers. */
 ib_lbm_status ib_lbm_markers(ib_lbm_sim *s, int32_t body_id, double *out, int32_t *n_markers);
 
+/* Boundary-fidelity diagnostics of body_id on the current state (Sec. 2.8,
+ * and the marker-resolved profiles of Sec. 4.2), computed on the device and
+ * returned to the host (synchronises).  The Eulerian field is u = (sum_i f_i
+ * e_i + F/2)/rho with the pending IB force, as ib_lbm_fields returns it; it
+ * is sampled at the markers by bilinear interpolation (hat weights of the
+ * 2 x 2 surrounding nodes), a probe distinct from the scheme's own kernel.
+ * Velocities are taken relative to the body's rigid motion U_b(x) = v +
+ * omega x (x - X_c), with v, omega as ib_lbm_forces reports them (zero for a
+ * fixed body); n_k = (X_k - X_c)/R; velocities are divided by u_ref (> 0,
+ * U_inf of the paper); kappa >= 0 buffer cells are excluded inside the
+ * solid (the paper uses 2).
+ *   summary[8] (host): slip mean and max of |u(X_k) - U_b(X_k)|/u_ref;
+ *     leakage flux sum_k rho(X_k) (u - U_b).n_k ds / (u_ref pi D); internal
+ *     residual mean and max of |u - U_b|/u_ref over the nodes with
+ *     |x - X_c| < R - kappa, and their count; mean (rho(X_k) - rho0)/3; mean
+ *     marker force magnitude |F_k| (F_L for DF/MDF, F_s for DFC).
+ *   per_marker (host, n_markers x 6, or NULL): slip_k, dp_k = (rho(X_k) -
+ *     rho0)/3, |F_k|, rho(X_k), normal and tangential (u - U_b)/u_ref.
+ * IB_LBM_E_STATE before the first completed step; IB_LBM_E_DIVERGED when the
+ * body's position or velocity is not finite.  A marker whose 2 x 2 stencil
+ * is not inside the lattice yields NaN. */
+ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, double u_ref,
+                                 double *summary, double *per_marker);
+
 /* Completed steps (synchronises). */
 ib_lbm_status ib_lbm_steps_done(ib_lbm_sim *s, int64_t *steps);
 ib_lbm_status ib_lbm_sync(ib_lbm_sim *s);

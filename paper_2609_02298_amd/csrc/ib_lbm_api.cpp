@@ -968,6 +968,39 @@ ib_lbm_status ib_lbm_markers(ib_lbm_sim *s, int32_t body_id, double *out, int32_
   return IB_LBM_OK;
 }
 
+ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, double u_ref,
+                                 double *summary, double *per_marker) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!summary || body_id < 0 || body_id >= (int)s->bodies.size() || kappa < 0 || !(u_ref > 0))
+    return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  if (cs.step < 1) {
+    set_err(&s->err, "diagnostics need a completed step");
+    return IB_LBM_E_STATE;
+  }
+  const HostBody &hb = s->bodies[body_id];
+  BodyState b;
+  HIPCHK(s, hipMemcpy(&b, hb.state.p, sizeof b, hipMemcpyDeviceToHost));
+  const bool freeb = hb.d.motion == IB_LBM_FREE;
+  const double vx = freeb ? b.vx : b.vhx, vy = freeb ? b.vy : b.vhy, om = freeb ? b.om : b.omh;
+  if (!std::isfinite(b.xc) || !std::isfinite(b.yc) || !std::isfinite(vx) || !std::isfinite(vy) ||
+      !std::isfinite(om)) {
+    set_err(&s->err, "body %d has a non-finite position or velocity", body_id);
+    return IB_LBM_E_DIVERGED;
+  }
+  const int nb = hb.dev.nb;
+  if ((st = ensure_tmp(s, (size_t)(8 + 6 * nb) * 8))) return st;
+  double *d = (double *)s->d_tmp.p;
+  HIPCHK(s, launch_diagnostics(s->cd, cs.cur, (const double *)hb.markers.p, nb, b.xc, b.yc, vx, vy,
+                               om, hb.dev.radius, hb.dev.ds, kappa, u_ref, d, d + 8, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemcpy(summary, d, 8 * 8, hipMemcpyDeviceToHost));
+  if (per_marker) HIPCHK(s, hipMemcpy(per_marker, d + 8, (size_t)nb * 6 * 8, hipMemcpyDeviceToHost));
+  return IB_LBM_OK;
+}
+
 ib_lbm_status ib_lbm_steps_done(ib_lbm_sim *s, int64_t *steps) {
   ib_lbm_status st = usable(s);
   if (st) return st;

@@ -204,6 +204,10 @@ hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, do
 hipError_t launch_export(const CaseDesc &c, int buf, double *out, hipStream_t stream);
 hipError_t launch_import(const CaseDesc &c, int buf, const double *in, hipStream_t stream);
 hipError_t launch_force_export(const CaseDesc &c, double *fx, double *fy, hipStream_t stream);
+hipError_t launch_diagnostics(const CaseDesc &c, int buf, const double *markers, int nb, double xc,
+                              double yc, double vx, double vy, double om, double radius,
+                              double ds, int kappa, double u_ref, double *out, double *pm,
+                              hipStream_t stream);
 int ibm_max_lds_bytes();
 
 }  // namespace iblbm

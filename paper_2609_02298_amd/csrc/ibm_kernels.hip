@@ -1197,6 +1197,149 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
   __threadfence();
 }
 
+// ---- boundary-fidelity diagnostics (Sec. 2.8, marker profiles of Sec. 4.2)
+// Density and velocity at node p with the pending IB force (Eq. 4).
+template <typename T>
+__device__ __forceinline__ void node_moments(const CaseDesc &c, const T *f, const T *frc, uint32_t p,
+                                             double &rho, double &ux, double &uy) {
+  const bool shift = sizeof(T) == 4;
+  const uint32_t plane = (uint32_t)c.plane;
+  double s = 0, jx = 0, jy = 0;
+#pragma unroll
+  for (int i = 0; i < 9; i++) {
+    const double v = (double)f[i * plane + p] + (shift ? c_w[i] * c.rho0 : 0.0);
+    s += v;
+    jx += v * c_exi[i];
+    jy += v * c_eyi[i];
+  }
+  const double Fx = (double)frc[p] + c.fluid_fx, Fy = (double)frc[plane + p] + c.fluid_fy;
+  rho = s;
+  ux = (jx + 0.5 * Fx) / s;
+  uy = (jy + 0.5 * Fy) / s;
+}
+
+// One workgroup per call.  Markers: the field sampled bilinearly (the hat
+// weights of the 2 x 2 nodes around X_k), relative to the rigid motion
+// U_b(x) = v + om x (x - X_c); interior: nodes with |x - X_c| < R - kappa.
+// Sums and maxima are reduced in a fixed order (wave trees, then the waves
+// in index order); out[8] as the C entry point documents, pm[6 k ..] per
+// marker.
+constexpr int kDiagThreads = 256;
+template <typename T>
+__global__ void __launch_bounds__(kDiagThreads)
+diag_kernel(CaseDesc c, int buf, const double *mk, int nb, double xc, double yc, double vx,
+            double vy, double om, double radius, double diameter, double ds, int kappa,
+            double u_ref, double *out, double *pm) {
+  __shared__ double red[8 * (kDiagThreads / 64)];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const T *f = (const T *)c.f[buf];
+  const T *frc = (const T *)c.force;
+  const int nx = c.nx;
+  double s_slip = 0, m_slip = 0, s_flux = 0, s_dp = 0, s_f = 0;
+  for (int k = tid; k < nb; k += nth) {
+    const double *m = mk + 8 * k;
+    const double X = m[0], Y = m[1];
+    // the 2 x 2 stencil must lie in the lattice (false for NaN positions);
+    // a marker outside gives NaN and no loads
+    if (!(X >= 0.0 && Y >= 0.0 && X < (double)(nx - 1) && Y < (double)(c.ny - 1))) {
+      const double nan = __builtin_nan("");
+      s_slip += nan;
+      s_flux += nan;
+      if (pm)
+        for (int i = 0; i < 6; i++) pm[6 * k + i] = nan;
+      continue;
+    }
+    const int x0 = (int)floor(X), y0 = (int)floor(Y);
+    double rk = 0, uxk = 0, uyk = 0;
+    for (int jy = 0; jy < 2; jy++)
+      for (int jx = 0; jx < 2; jx++) {
+        const double w = delta1(kHat, (double)(x0 + jx) - X) * delta1(kHat, (double)(y0 + jy) - Y);
+        double r, u, v;
+        node_moments<T>(c, f, frc, (uint32_t)(y0 + jy) * nx + (x0 + jx), r, u, v);
+        rk += r * w;
+        uxk += u * w;
+        uyk += v * w;
+      }
+    const double dx = uxk - (vx - om * (Y - yc)), dy = uyk - (vy + om * (X - xc));
+    const double nxk = (X - xc) / radius, nyk = (Y - yc) / radius;
+    const double slip = sqrt(dx * dx + dy * dy) / u_ref;
+    const double dp = (rk - c.rho0) * (1.0 / 3.0);
+    const double fm = sqrt(m[4] * m[4] + m[5] * m[5]);
+    s_slip += slip;
+    m_slip = fmax(m_slip, slip);
+    s_flux += rk * (dx * nxk + dy * nyk) * ds;
+    s_dp += dp;
+    s_f += fm;
+    if (pm) {
+      double *o = pm + 6 * k;
+      o[0] = slip;
+      o[1] = dp;
+      o[2] = fm;
+      o[3] = rk;
+      o[4] = (dx * nxk + dy * nyk) / u_ref;
+      o[5] = (-dx * nyk + dy * nxk) / u_ref;
+    }
+  }
+  double s_in = 0, m_in = 0, n_in = 0;
+  const double ri = radius - kappa;
+  if (ri > 0) {
+    const int bx0 = max(0, (int)ceil(xc - ri)), bx1 = min(nx - 1, (int)floor(xc + ri));
+    const int by0 = max(0, (int)ceil(yc - ri)), by1 = min(c.ny - 1, (int)floor(yc + ri));
+    const int bw = bx1 - bx0 + 1, bh = by1 - by0 + 1;
+    const int nq = bw > 0 && bh > 0 ? bw * bh : 0;
+    for (int q = tid; q < nq; q += nth) {
+      const int x = bx0 + q % bw, y = by0 + q / bw;
+      const double rx = x - xc, ry = y - yc;
+      if (rx * rx + ry * ry >= ri * ri) continue;
+      double r, u, v;
+      node_moments<T>(c, f, frc, (uint32_t)y * nx + x, r, u, v);
+      const double dx = u - (vx - om * ry), dy = v - (vy + om * rx);
+      const double mg = sqrt(dx * dx + dy * dy) / u_ref;
+      s_in += mg;
+      m_in = fmax(m_in, mg);
+      n_in += 1.0;
+    }
+  }
+  double v8[8] = {s_slip, m_slip, s_flux, s_in, m_in, n_in, s_dp, s_f};
+  const int lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const bool mx = i == 1 || i == 4;
+    v8[i] = mx ? wave_max(v8[i]) : wave_sum(v8[i]);
+    if (lane == 0) red[8 * wv + i] = v8[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t[8];
+    for (int i = 0; i < 8; i++) {
+      t[i] = red[i];
+      for (int w = 1; w < nw; w++)
+        t[i] = (i == 1 || i == 4) ? fmax(t[i], red[8 * w + i]) : t[i] + red[8 * w + i];
+    }
+    out[0] = t[0] / nb;
+    out[1] = t[1];
+    out[2] = t[2] / (u_ref * M_PI * diameter);
+    out[3] = t[5] > 0 ? t[3] / t[5] : 0.0;
+    out[4] = t[4];
+    out[5] = t[5];
+    out[6] = t[6] / nb;
+    out[7] = t[7] / nb;
+  }
+}
+
+hipError_t launch_diagnostics(const CaseDesc &c, int buf, const double *markers, int nb, double xc,
+                              double yc, double vx, double vy, double om, double radius,
+                              double ds, int kappa, double u_ref, double *out, double *pm,
+                              hipStream_t stream) {
+  if (c.precision == kPrecFP64)
+    hipLaunchKernelGGL(diag_kernel<double>, dim3(1), dim3(kDiagThreads), 0, stream, c, buf, markers,
+                       nb, xc, yc, vx, vy, om, radius, 2.0 * radius, ds, kappa, u_ref, out, pm);
+  else
+    hipLaunchKernelGGL(diag_kernel<float>, dim3(1), dim3(kDiagThreads), 0, stream, c, buf, markers,
+                       nb, xc, yc, vx, vy, om, radius, 2.0 * radius, ds, kappa, u_ref, out, pm);
+  return hipGetLastError();
+}
+
 int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,

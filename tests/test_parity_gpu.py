@@ -436,6 +436,63 @@ def test_adaptive_mdf_bounds_are_checked():
             ib.Sim(case)
 
 
+# --------------------------------- boundary diagnostics (Sec. 2.8, Sec. 4.2)
+DIAG_GPU = [(ib.DF, ib.HAT, ib.FIXED), (ib.MDF, ib.PESKIN4, ib.PRESCRIBED_SIN),
+            (ib.DFC, ib.PESKIN4, ib.FIXED), (ib.DFC, ib.HAT, ib.FREE)]
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+@pytest.mark.parametrize("scheme,kernel,motion", DIAG_GPU)
+def test_diagnostics_match_oracle(scheme, kernel, motion, prec):
+    """Slip, leakage flux, internal residual (kappa 0 and 2) and the marker
+    profiles on the device against the oracle after 30 steps.  Velocity
+    quantities are divided by u_ref, so they are held to the field tolerance
+    times max|u|/u_ref; the pressure deviation in FP32 to 1e-7, above the
+    density error of the FP32 store (nine populations of at most 0.1 rounded
+    to 2^-24 relative: 5e-8 in rho, 2e-8 in rho/3)."""
+    say(f"diagnostics scheme={scheme} kernel={kernel} motion={motion} prec={prec}")
+    case = body_case(scheme, kernel, ib.TRT, motion=motion, amp=(0.0, 3.2), freq=0.004,
+                     density_ratio=3.0)
+    sim, ref = make_pair(case, prec)
+    sim.step(30)
+    ref.step(30)
+    uref = 0.06
+    _, rx, ry = ref.fields()
+    umax = float(np.hypot(rx, ry).max())
+    f64 = prec == ib.FP64
+    tv = (F64_FIELD if f64 else F32_FIELD) * umax / uref
+    tdp = 1e-15 if f64 else 1e-7
+    for kappa in (0, 2):
+        gs, gp = sim.diagnostics(0, kappa, uref)
+        rs, rp = ref.diagnostics(0, kappa, uref)
+        say(f"  kappa={kappa} slip {gs['slip_mean']:.4e} leak {gs['phi_leak']:.3e} "
+            f"inside {gs['u_inside_mean']:.4e} n {gs['n_inside']:.0f}")
+        assert gs["n_inside"] == rs["n_inside"] and gs["n_inside"] > 0
+        for k in ("slip_mean", "slip_max", "phi_leak", "u_inside_mean", "u_inside_max"):
+            assert abs(gs[k] - rs[k]) < tv, k
+        assert abs(gs["dp_mean"] - rs["dp_mean"]) < tdp
+        assert abs(gs["force_mean"] - rs["force_mean"]) < (1e-11 if f64 else F32_DRAG) * rs["force_mean"]
+        np.testing.assert_allclose(gp[:, [0, 4, 5]], rp[:, [0, 4, 5]], rtol=0, atol=tv)
+        np.testing.assert_allclose(gp[:, 1], rp[:, 1], rtol=0, atol=tdp)
+        np.testing.assert_allclose(gp[:, 3], rp[:, 3], rtol=0, atol=3 * tdp)
+        np.testing.assert_allclose(gp[:, 2], rp[:, 2], rtol=1e-11 if f64 else F32_DRAG,
+                                   atol=1e-11 * rp[:, 2].max())
+
+
+def test_diagnostics_state_and_arguments():
+    case = body_case(ib.DF, ib.HAT, ib.BGK)
+    sim = ib.Sim(case)
+    with pytest.raises(ib.IbLbmError):
+        sim.diagnostics(0, 2, 0.06)  # no step completed yet
+    sim.step(1)
+    for kappa, uref in ((-1, 0.06), (2, 0.0)):
+        with pytest.raises(ib.IbLbmError):
+            sim.diagnostics(0, kappa, uref)
+    # a buffer wider than the radius leaves no interior node
+    sm, _ = sim.diagnostics(0, 9, 0.06)
+    assert sm["n_inside"] == 0 and sm["u_inside_mean"] == 0.0
+
+
 # ------------------------------------------------------------- properties
 def test_run_to_run_bitwise_and_gather_vs_atomic():
     case = body_case(ib.MDF, ib.PESKIN4, ib.CMMRT)
