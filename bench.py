@@ -97,6 +97,13 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
     sim.timing(False)
     sim.set_overlap(True)
     st = sim.forces(0, check=False)
+    # boundary-fidelity diagnostics of the body (Sec. 2.8) on the final
+    # state: host wall clock of the whole call (launch, wait, copy back)
+    dts = []
+    for _ in range(5):
+        td = time.perf_counter()
+        diag, _ = sim.diagnostics(0, 2, case.get("u_ref", 0.1))
+        dts.append(time.perf_counter() - td)
     # collide-stream kernel duration: HIP events around 200 back-to-back
     # launches on a second sim of the same workload (two steps in, so that
     # the force box is set), on the stream they are launched on
@@ -111,6 +118,7 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True):
                inner_nodes=inner,
                split=split, near_nodes=near,
                fx=st["fx"], status=st["status"], steps_done=sim.steps_done,
+               diag=diag, diag_ms=float(np.median(dts)) * 1e3,
                passes_mean=float(passes.mean()) if len(passes) else 0.0,
                passes_min=int(passes.min()) if len(passes) else 0,
                passes_max=int(passes.max()) if len(passes) else 0,
@@ -308,6 +316,8 @@ def main():
         "hbm_fraction_of_step": round(bpn * nodes * args.steps / r["seconds"] / 1e9 / HBM_PEAK_GBS, 4),
         "lattice_bytes": 2 * 9 * nodes * (bpn // 18),
         "mall_resident_note": "2 lattices of this size fit in the 256 MB Infinity Cache",
+        "diagnostics": {"call_ms": round(r["diag_ms"], 3), "kappa": 2,
+                        **{k: round(v, 6) for k, v in r["diag"].items()}},
     }
     if not args.no_fp64 and prec == ib.FP32_SHIFTED:
         r64 = run_gpu(case, ib.FP64, max(args.steps // 2, 50), args.warmup // 2,

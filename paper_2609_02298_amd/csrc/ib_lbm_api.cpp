@@ -882,9 +882,13 @@ ib_lbm_status ib_lbm_history(ib_lbm_sim *s, int32_t body_id, int64_t first, int6
     return IB_LBM_E_RANGE;
   }
   const double *h = (const double *)s->bodies[body_id].history.p;
-  for (int64_t i = 0; i < count; i++) {
+  // the rows lie in the ring in at most two runs (before and after the wrap)
+  for (int64_t i = 0; i < count;) {
     const int64_t row = (first - 1 + i) % cap;
-    HIPCHK(s, hipMemcpy(out + i * kHistCols, h + row * kHistCols, kHistCols * 8, hipMemcpyDeviceToHost));
+    const int64_t run = std::min<int64_t>(count - i, cap - row);
+    HIPCHK(s, hipMemcpy(out + i * kHistCols, h + row * kHistCols, (size_t)run * kHistCols * 8,
+                        hipMemcpyDeviceToHost));
+    i += run;
   }
   return IB_LBM_OK;
 }

@@ -560,6 +560,20 @@ def test_history_matches_forces():
         assert h[i, 0] == i + 1
         assert h[i, 1] == r["fx"] and h[i, 2] == r["fy"] and h[i, 3] == r["torque"]
 
+    # a ring of 7 rows read across its wrap (rows 9..15 sit at 1..6 and 0)
+    w = ib.Sim(case, history_capacity=7)
+    rows = []
+    for _ in range(15):
+        w.step(1)
+        rows.append(w.forces(0))
+    h = w.history(0, 9, 7)
+    for i in range(7):
+        assert h[i, 0] == 9 + i and h[i, 1] == rows[8 + i]["fx"]
+    h = w.history(0, 13, 2)
+    assert list(h[:, 0]) == [13, 14]
+    with pytest.raises(ib.IbLbmError):
+        w.history(0, 8, 2)  # row 8 has been overwritten
+
 
 # ------------------------------------------------------------- edge cases
 def test_invalid_configurations_are_rejected():
