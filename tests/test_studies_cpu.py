@@ -1,0 +1,51 @@
+"""Host-side statistics of the paper-scale studies (no GPU): drag / lift
+coefficients and Strouhal numbers of force histories with known answers."""
+import math
+
+import numpy as np
+import pytest
+
+import ib_cases
+from paper_2609_02298_amd.studies import flow_statistics
+
+
+def test_statistics_of_a_pure_shedding_signal():
+    """F_x constant, F_y a sinusoid of an integer number of periods: mean
+    C_d, rms lift A/sqrt(2), amplitude A, and both Strouhal estimates equal
+    f D / u (the FFT exactly, as f N is an integer)."""
+    u, D, n = 0.1, 40.0, 20000
+    f = 0.005  # 100 periods in the window
+    t = np.arange(n)
+    q = 0.5 * u * u * D
+    fx = np.full(n, 1.35 * q)
+    fy = 0.33 * q * np.sin(2 * math.pi * f * t + 0.3)
+    s = flow_statistics(fx, fy, u, D)
+    assert abs(s["cd_mean"] - 1.35) < 1e-12
+    assert abs(s["cl_rms"] - 0.33 / math.sqrt(2)) < 1e-9
+    # sampled 200 times a period, the extremes miss the peak by at most
+    # 1 - cos(pi / 200) = 1.2e-4 relative
+    assert abs(s["cl_amp"] - 0.33) < 1.3e-4 * 0.33
+    assert abs(s["st_fft"] - f * D / u) < 1e-12
+    assert abs(s["st_zero"] - f * D / u) < 1e-6 * f * D / u
+
+
+def test_statistics_of_a_steady_wake():
+    u, D = 0.1, 40.0
+    q = 0.5 * u * u * D
+    s = flow_statistics(np.full(500, 2.08 * q), np.zeros(500), u, D)
+    assert abs(s["cd_mean"] - 2.08) < 1e-12
+    assert s["st_fft"] is None and s["st_zero"] is None and s["cl_rms"] == 0.0
+
+
+@pytest.mark.parametrize("re,nx,ny,D,nb,tau", [(20, 2001, 1601, 40.0, 188, 1.1),
+                                                (100, 2001, 1601, 40.0, 188, 0.62),
+                                                (200, 3001, 2401, 60.0, 283, 0.59)])
+def test_paper_fixed_cylinder_parameters(re, nx, ny, D, nb, tau):
+    """Table I: grid, diameter, marker count at spacing 2/3, tau = 1/2 + 3 nu
+    (0.59 at Re = 200, as printed), cylinder at (0.4 L_x, 0.5 L_y)."""
+    c = ib_cases.paper_fixed_cylinder(re)
+    b = c["bodies"][0]
+    assert (c["nx"], c["ny"], c["diameter"], b["n_markers"]) == (nx, ny, D, nb)
+    assert abs(c["tau"] - tau) < 1e-12
+    assert b["xc"] == 0.4 * (nx - 1) and b["yc"] == 0.5 * (ny - 1)
+    assert b["mdf_tol"] == 1e-4 and (b["mdf_nmin"], b["mdf_iters"]) == (5, 20)
