@@ -118,6 +118,34 @@ def paper_fixed_cylinder(re: float, scheme="MDF", kernel="P4", collision="BGK",
         diameter=D, bodies=[body], steps=steps, average_from=avg0, re=re)
 
 
+def paper_inline_oscillation(scheme="MDF", kernel="P4", collision="BGK",
+                             adaptive: bool = True) -> dict:
+    """The in-line oscillating cylinder of Sec. 2.9.2 / Table I: L_x x L_y =
+    1.5 x 1.0 at D = 80 (2401 x 1601 nodes), cylinder centred, x_c(t) =
+    -A sin(2 pi f0 t) with KC = U_max / (f0 D) = 5, A = KC D / (2 pi),
+    U_max = 0.1 (period T = KC D / U_max = 4000 steps), Re = U_max D / nu =
+    100 (nu = 0.08, tau = 0.74), quiescent fluid, zero-gradient faces on all
+    four sides, marker spacing 2/3 (377 markers); 40,000 steps (10 periods),
+    statistics over the last 8 (steps from 8,000)."""
+    umax, D, kc, re = 0.1, 80.0, 5.0, 100.0
+    nx, ny = 2401, 1601
+    f0 = umax / (kc * D)
+    sch = SCHEMES[scheme] if isinstance(scheme, str) else scheme
+    ker = KERNELS[kernel] if isinstance(kernel, str) else kernel
+    col = COLLISIONS[collision] if isinstance(collision, str) else collision
+    body = dict(xc=0.5 * (nx - 1), yc=0.5 * (ny - 1), diameter=D,
+                n_markers=int(round(math.pi * D / (2.0 / 3.0))), scheme=sch, kernel=ker,
+                mdf_iters=5, motion=PRESCRIBED_SIN, amp=(-kc * D / (2.0 * math.pi), 0.0),
+                freq=f0, phase=0.0)
+    if sch == MDF and adaptive:
+        body.update(ADAPTIVE_MDF)
+    return dict(
+        name=f"paper-inline-oscillation-{nx}x{ny}-KC5", nx=nx, ny=ny, collision=col,
+        tau=tau_from(umax, D, re), trt_magic=0.25, cm_s_q=1.2, cm_s_eps=1.4, rho0=1.0,
+        bc=(ZERO_GRADIENT,) * 4, u_bc=0.0, u_ref=umax, diameter=D, bodies=[body],
+        steps=40000, average_from=8001, period=int(round(1.0 / f0)), re=re)
+
+
 def oscillating_cylinder(steps=60000, nx=1200, ny=600, diameter=40.0) -> dict:
     """Transversely oscillating cylinder: 1200x600, D = 40, Re = 100,
     y(t) = A sin(2 pi f t), A = 0.2 D, f = 0.8 St0 u_inf / D; MDF (k=5), P4,

@@ -57,7 +57,8 @@ typedef enum {
 enum { IB_LBM_FP64 = 0, IB_LBM_FP32_SHIFTED = 1 };
 enum { IB_LBM_BGK = 0, IB_LBM_TRT = 1, IB_LBM_CMMRT = 2 };
 /* Face closures.  PERIODIC must be set on both faces of an axis; the
- * zero-gradient face is supported on the east face only. */
+ * zero-gradient face copies the entering populations from the nodes one
+ * step inside (any face; Sec. 2.9). */
 enum { IB_LBM_PERIODIC = 0, IB_LBM_BOUNCE_BACK = 1, IB_LBM_VEL_PARABOLIC = 2,
        IB_LBM_VEL_UNIFORM = 3, IB_LBM_ZERO_GRADIENT = 4 };
 enum { IB_LBM_DF = 0, IB_LBM_MDF = 1, IB_LBM_DFC = 2 };

@@ -575,9 +575,7 @@ ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out) {
   if ((cfg->bc[0] == IB_LBM_PERIODIC) != (cfg->bc[1] == IB_LBM_PERIODIC) ||
       (cfg->bc[2] == IB_LBM_PERIODIC) != (cfg->bc[3] == IB_LBM_PERIODIC))
     return fail(IB_LBM_E_INVALID, "periodic faces must come in pairs");
-  if (cfg->bc[0] == IB_LBM_ZERO_GRADIENT || cfg->bc[2] == IB_LBM_ZERO_GRADIENT ||
-      cfg->bc[3] == IB_LBM_ZERO_GRADIENT)
-    return fail(IB_LBM_E_INVALID, "zero-gradient closure only on the east face");
+
   if (cfg->bc[2] == IB_LBM_VEL_PARABOLIC || cfg->bc[3] == IB_LBM_VEL_PARABOLIC)
     return fail(IB_LBM_E_INVALID, "parabolic profile only on the west or east face");
   if (cfg->collision == IB_LBM_TRT && !(cfg->trt_magic > 0.0))

@@ -159,14 +159,18 @@ __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c
 __device__ __forceinline__ bool is_vel(int b) { return b == kVelParabolic || b == kVelUniform; }
 
 // Push population i of node (x,y) with value v, applying the face closures:
-//   periodic faces wrap; a link leaving through the zero-gradient east face
-//   is dropped (the entering populations of the east column are written as
-//   copies of the column nx-2, see the duplicate store below); a link
-//   leaving through a wall returns as opp(i) at the node (half-way
-//   bounce-back); through a velocity face it returns as
-//   opp(i) - 6 w_i rho0 (e_i . u_w), u_w evaluated at the link mid-point.  A
-//   link leaving through a wall and a velocity face is a wall link; among
-//   velocity faces the first of W, E, S, N is used.
+//   periodic faces wrap; a link leaving through a zero-gradient face is
+//   dropped, and the populations entering a zero-gradient face are copies of
+//   those one node inside (column 1 for W, nx-2 for E, row 1 for S, ny-2 for
+//   N), written as duplicate stores of the pushes that land there (every
+//   such push comes from a face node); a corner of two zero-gradient faces
+//   takes its diagonal population from the diagonal inner node, which is
+//   what copying the columns and then the rows gives.  A link leaving
+//   through a wall returns as opp(i) at the node (half-way bounce-back);
+//   through a velocity face it returns as opp(i) - 6 w_i rho0 (e_i . u_w),
+//   u_w evaluated at the link mid-point.  A link leaving through a wall and
+//   a velocity face is a wall link; among velocity faces the first of W, E,
+//   S, N is used.
 template <typename T>
 __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
   const int nx = c.nx, ny = c.ny;
@@ -179,7 +183,9 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
   if (cn && c.bc[kFaceN] == kPeriodic) { yd -= ny; cn = false; }
   int j = i, xs = xd, ys = yd;
   if (cw || ce || cs || cn) {
-    if (ce && c.bc[kFaceE] == kZeroGradient) return;
+    if ((cw && c.bc[kFaceW] == kZeroGradient) || (ce && c.bc[kFaceE] == kZeroGradient) ||
+        (cs && c.bc[kFaceS] == kZeroGradient) || (cn && c.bc[kFaceN] == kZeroGradient))
+      return;
     j = OPPI(i);
     xs = x;
     ys = y;
@@ -202,9 +208,18 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
       v = v - T(6) * wgt<T>(i) * T(c.rho0) * (T(c_ex[i]) * uw);
     }
   }
-  dst[(uint32_t)j * plane + (uint32_t)ys * nx + xs] = v;
-  if (c.bc[kFaceE] == kZeroGradient && xs == nx - 2 && (j == 3 || j == 6 || j == 7))
-    dst[(uint32_t)j * plane + (uint32_t)ys * nx + (nx - 1)] = v;
+  T *d = dst + (uint32_t)j * plane;
+  d[(uint32_t)ys * nx + xs] = v;
+  // zero-gradient copies: the column (W / E) and row (S / N) this value is
+  // copied to, and their corner when both apply
+  int xc = -1, yc = -1;
+  if (c.bc[kFaceW] == kZeroGradient && xs == 1 && c_ex[j] > 0) xc = 0;
+  if (c.bc[kFaceE] == kZeroGradient && xs == nx - 2 && c_ex[j] < 0) xc = nx - 1;
+  if (c.bc[kFaceS] == kZeroGradient && ys == 1 && c_ey[j] > 0) yc = 0;
+  if (c.bc[kFaceN] == kZeroGradient && ys == ny - 2 && c_ey[j] < 0) yc = ny - 1;
+  if (xc >= 0) d[(uint32_t)ys * nx + xc] = v;
+  if (yc >= 0) d[(uint32_t)yc * nx + xs] = v;
+  if (xc >= 0 && yc >= 0) d[(uint32_t)yc * nx + xc] = v;
 }
 
 // All nine pushes of a face node.

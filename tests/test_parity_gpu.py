@@ -73,18 +73,27 @@ def test_periodic_box(col, prec):
     assert sim.steps_done == 40
 
 
+FACE_SETS = {
+    "periodic": ((ib.PERIODIC,) * 4, 0.0),
+    "channel": ((ib.VEL_PARABOLIC, ib.ZERO_GRADIENT, ib.BOUNCE_BACK, ib.BOUNCE_BACK), 0.05),
+    "farfield": ((ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.VEL_UNIFORM, ib.VEL_UNIFORM), 0.08),
+    "box": ((ib.BOUNCE_BACK,) * 4, 0.0),
+    # zero-gradient on every face (the open boundaries of the in-line
+    # oscillating cylinder, Sec. 2.9.2), and mixed with a wall and a
+    # velocity face so that every kind of corner meets one
+    "open": ((ib.ZERO_GRADIENT,) * 4, 0.0),
+    "open-mixed": ((ib.ZERO_GRADIENT, ib.ZERO_GRADIENT, ib.BOUNCE_BACK, ib.VEL_UNIFORM), 0.04),
+    "inflow-open": ((ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.ZERO_GRADIENT, ib.ZERO_GRADIENT), 0.06),
+}
+
+
 @pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
 @pytest.mark.parametrize("col", [ib.BGK, ib.TRT, ib.CMMRT])
-@pytest.mark.parametrize("faces", ["channel", "farfield", "box"])
+@pytest.mark.parametrize("faces", ["channel", "farfield", "box", "open", "open-mixed", "inflow-open"])
 def test_faces(col, prec, faces):
     """Every face closure on a ragged lattice (not a multiple of the tile)."""
     say(f"faces {faces} col={col} prec={prec}")
-    if faces == "channel":
-        bc, u = (ib.VEL_PARABOLIC, ib.ZERO_GRADIENT, ib.BOUNCE_BACK, ib.BOUNCE_BACK), 0.05
-    elif faces == "farfield":
-        bc, u = (ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.VEL_UNIFORM, ib.VEL_UNIFORM), 0.08
-    else:
-        bc, u = (ib.BOUNCE_BACK,) * 4, 0.0
+    bc, u = FACE_SETS[faces]
     case = dict(nx=77, ny=41, collision=col, tau=0.66, bc=bc, u_bc=u)
     u0 = (u * 0.5, 0.0) if u > 0 else (0.05, 0.03)  # closed box: sloshing start
     pops = ib_cases.random_populations(77, 41, 2, amp=0.01, u=u0)
@@ -97,15 +106,12 @@ def test_faces(col, prec, faces):
 
 
 @pytest.mark.parametrize("col", [ib.BGK, ib.TRT, ib.CMMRT])
-@pytest.mark.parametrize("faces", ["periodic", "channel", "farfield", "box"])
+@pytest.mark.parametrize("faces", ["periodic", "channel", "farfield", "box", "open", "open-mixed"])
 def test_faces_even_width_fp32(col, faces):
     """FP32 on a wider lattice (several tiles in x and y, inner nodes and
     face nodes in separate launches), every face closure."""
     say(f"even width fp32 {faces} col={col}")
-    bc, u = {"periodic": ((ib.PERIODIC,) * 4, 0.0),
-             "channel": ((ib.VEL_PARABOLIC, ib.ZERO_GRADIENT, ib.BOUNCE_BACK, ib.BOUNCE_BACK), 0.05),
-             "farfield": ((ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.VEL_UNIFORM, ib.VEL_UNIFORM), 0.08),
-             "box": ((ib.BOUNCE_BACK,) * 4, 0.0)}[faces]
+    bc, u = FACE_SETS[faces]
     nx, ny = 390, 46
     case = dict(nx=nx, ny=ny, collision=col, tau=0.66, bc=bc, u_bc=u,
                 fluid_force=(2e-6, -1e-6) if faces == "periodic" else (0.0, 0.0))
@@ -296,6 +302,26 @@ def test_unsteady_cylinder_full_size_window(scheme, kernel, col, steps):
     assert rel(sim.populations(), ref.populations()) < F64_FIELD
     fs, fr = sim.forces(0), ref.body_state(0)
     assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < F64_DRAG
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+def test_inline_oscillation_open_faces(prec):
+    """A body oscillating in x in a quiescent fluid with zero-gradient faces on
+    all four sides (the in-line case of Sec. 2.9.2, reduced): fields, drag
+    and position against the oracle."""
+    say(f"in-line oscillation, open faces, prec={prec}")
+    case = dict(nx=150, ny=100, collision=ib.BGK, tau=0.74, bc=(ib.ZERO_GRADIENT,) * 4,
+                bodies=[dict(xc=74.6, yc=49.7, diameter=16.0, scheme=ib.MDF, kernel=ib.PESKIN4,
+                             mdf_iters=5, motion=ib.PRESCRIBED_SIN,
+                             amp=(-5 * 16 / (2 * math.pi), 0.0), freq=0.1 / 80.0)])
+    sim, ref = make_pair(case, prec)
+    for _ in range(4):
+        sim.step(30)
+        ref.step(30)
+        fs, fr = sim.forces(0), ref.body_state(0)
+        assert abs(fs["xc"] - fr["xc"]) < 1e-12
+        assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < (F64_DRAG if prec == ib.FP64 else F32_DRAG)
+    assert compare_fields(sim, ref, None) < (F64_FIELD if prec == ib.FP64 else F32_FIELD)
 
 
 def test_oscillating_cylinder_full_size_window():
@@ -579,7 +605,8 @@ def test_history_matches_forces():
 def test_invalid_configurations_are_rejected():
     base = dict(nx=40, ny=30, tau=0.8, bc=(ib.PERIODIC,) * 4)
     for bad in (dict(base, tau=0.5), dict(base, bc=(ib.PERIODIC, ib.BOUNCE_BACK, 0, 0)),
-                dict(base, bc=(ib.ZERO_GRADIENT, ib.ZERO_GRADIENT, 1, 1)), dict(base, nx=2)):
+                dict(base, bc=(ib.PERIODIC, ib.PERIODIC, ib.VEL_PARABOLIC, 1)),
+                dict(base, bc=(ib.ZERO_GRADIENT, 7, 1, 1)), dict(base, nx=2)):
         with pytest.raises(ib.IbLbmError):
             ib.Sim(bad)
 

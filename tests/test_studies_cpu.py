@@ -49,3 +49,29 @@ def test_paper_fixed_cylinder_parameters(re, nx, ny, D, nb, tau):
     assert abs(c["tau"] - tau) < 1e-12
     assert b["xc"] == 0.4 * (nx - 1) and b["yc"] == 0.5 * (ny - 1)
     assert b["mdf_tol"] == 1e-4 and (b["mdf_nmin"], b["mdf_iters"]) == (5, 20)
+
+
+def test_peak_drag_of_a_periodic_force():
+    """|C_d| peaks of a known periodic force: each period's maximum, their
+    mean, and the window maximum."""
+    from paper_2609_02298_amd.studies import peak_drag
+    u, D, T = 0.1, 80.0, 4000
+    t = np.arange(4 * T)
+    q = 0.5 * u * u * D
+    amp = np.repeat([2.0, 2.1, 2.05, 2.15], T)
+    fx = q * amp * np.sin(2 * math.pi * t / T)
+    p = peak_drag(fx, u, D, T)
+    assert p["periods"] == 4
+    assert abs(p["cd_peak"] - 2.075) < 1e-9 and abs(p["cd_max"] - 2.15) < 1e-9
+
+
+def test_paper_inline_oscillation_parameters():
+    """Sec. 2.9.2 / Table I: KC = 5, Re = 100, T = 4000, tau = 0.74, 2401 x
+    1601, D = 80, open faces, A = KC D / (2 pi)."""
+    c = ib_cases.paper_inline_oscillation()
+    b = c["bodies"][0]
+    assert (c["nx"], c["ny"], c["diameter"], c["period"]) == (2401, 1601, 80.0, 4000)
+    assert abs(c["tau"] - 0.74) < 1e-12 and c["bc"] == (ib_cases.ZERO_GRADIENT,) * 4
+    assert abs(b["amp"][0] + 5 * 80 / (2 * math.pi)) < 1e-12 and b["freq"] == 1 / 4000
+    # velocity amplitude 2 pi f0 A = U_max
+    assert abs(2 * math.pi * b["freq"] * abs(b["amp"][0]) - 0.1) < 1e-15
