@@ -18,6 +18,6 @@ from .oracle import (  # noqa: F401
     body_half_kick,
     body_full_kick,
     BGK, TRT, CMMRT,
-    PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM, ZERO_GRADIENT,
+    PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM, ZERO_GRADIENT, ZOU_HE,
     DF, MDF, DFC, HAT, PESKIN4, FIXED, PRESCRIBED_SIN, FREE, IM_NONE, IM_FENG,
 )

@@ -563,6 +563,67 @@ static void stream_all(or_sim *s) {
   }
 }
 
+/* No-slip walls with the on-node velocity closure of Zou and He at zero wall
+ * velocity (the walls of Sec. 2.9.3-2.9.4).  The wall nodes are the face
+ * nodes themselves; after streaming, the populations that would have come
+ * from outside are rebuilt from the known ones so that the node has zero
+ * momentum: the normal one by bounce-back of its opposite, the two diagonal
+ * ones by bounce-back corrected with half the tangential imbalance of the
+ * known axial pair (for the south wall f2 = f4, f5 = f7 - (f1 - f3)/2,
+ * f6 = f8 + (f1 - f3)/2; the other walls by symmetry).  A corner of two such
+ * walls has five unknowns: the three pointing into the fluid are bounce-back
+ * of their opposites and the two buried diagonals share what the density of
+ * the diagonal inner node leaves (reading: the paper does not give the
+ * corner rule; this is the usual one).  Links that leave through these faces
+ * were dropped by the streaming. */
+static void zou_he_walls(or_sim *s) {
+  int nx = s->c.nx, ny = s->c.ny, n = s->n;
+  const int *bc = s->c.bc;
+  double *f = s->f;
+#define F(i, x, y) f[(size_t)(i) * n + (size_t)(y) * nx + (x)]
+  for (int y = 0; y < ny; y++)
+    for (int x = 0; x < nx; x++) {
+      int w = x == 0 && bc[0] == OR_ZOU_HE, e = x == nx - 1 && bc[1] == OR_ZOU_HE;
+      int so = y == 0 && bc[2] == OR_ZOU_HE, no = y == ny - 1 && bc[3] == OR_ZOU_HE;
+      if ((w || e) && (so || no)) {
+        /* corner: i_in are the axial and diagonal populations pointing into
+         * the fluid, a and b the buried diagonals */
+        int sx = w ? 1 : -1, sy = so ? 1 : -1;
+        int ix = sx > 0 ? 1 : 3, iy = sy > 0 ? 2 : 4;
+        int id = -1, ia = -1, ib = -1;
+        for (int i = 5; i < 9; i++) {
+          if (EX[i] == sx && EY[i] == sy) id = i;
+          else if (EX[i] == -sx && EY[i] == sy) ia = i;
+          else if (EX[i] == sx && EY[i] == -sy) ib = i;
+        }
+        F(ix, x, y) = F(OPP[ix], x, y);
+        F(iy, x, y) = F(OPP[iy], x, y);
+        F(id, x, y) = F(OPP[id], x, y);
+        double rc = 0.0;
+        for (int i = 0; i < 9; i++) rc += F(i, x + sx, y + sy);
+        double known = 0.0;
+        for (int i = 0; i < 9; i++)
+          if (i != ia && i != ib) known += F(i, x, y);
+        F(ia, x, y) = F(ib, x, y) = 0.5 * (rc - known);
+      } else if (so || no) {
+        int in = so ? 2 : 4;               /* normal population into the fluid */
+        int d1 = so ? 5 : 8, d2 = so ? 6 : 7; /* diagonals into the fluid, +x and -x */
+        double t = 0.5 * (F(1, x, y) - F(3, x, y));
+        F(in, x, y) = F(OPP[in], x, y);
+        F(d1, x, y) = F(OPP[d1], x, y) - t;
+        F(d2, x, y) = F(OPP[d2], x, y) + t;
+      } else if (w || e) {
+        int in = w ? 1 : 3;
+        int d1 = w ? 5 : 6, d2 = w ? 8 : 7;   /* diagonals into the fluid, +y and -y */
+        double t = 0.5 * (F(2, x, y) - F(4, x, y));
+        F(in, x, y) = F(OPP[in], x, y);
+        F(d1, x, y) = F(OPP[d1], x, y) - t;
+        F(d2, x, y) = F(OPP[d2], x, y) + t;
+      }
+    }
+#undef F
+}
+
 /* ------------------------------------------------------------------ */
 /* Interpolation of a scalar field to (X,Y), Eq. (7). */
 static double interp_nx(int nx, int kernel, const double *field, double X, double Y) {
@@ -840,6 +901,7 @@ int or_step(or_sim *s, int64_t nsteps) {
       }
     collide_all(s);
     stream_all(s);
+    zou_he_walls(s);
     if (s->nbody > 0) {
       int scheme = s->body[0].d.scheme;
       if (scheme == OR_DF) ibm_df(s);

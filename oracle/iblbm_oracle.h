@@ -22,7 +22,7 @@ extern "C" {
 
 enum { OR_BGK = 0, OR_TRT = 1, OR_CMMRT = 2 };
 enum { OR_PERIODIC = 0, OR_BOUNCE_BACK = 1, OR_VEL_PARABOLIC = 2, OR_VEL_UNIFORM = 3,
-       OR_ZERO_GRADIENT = 4 };
+       OR_ZERO_GRADIENT = 4, OR_ZOU_HE = 5 };
 enum { OR_DF = 0, OR_MDF = 1, OR_DFC = 2 };
 enum { OR_HAT = 0, OR_PESKIN4 = 1 };
 enum { OR_FIXED = 0, OR_PRESCRIBED_SIN = 1, OR_FREE = 2 };

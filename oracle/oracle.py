@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "iblbm_oracle.c")
 _LIB = os.path.join(_HERE, "libiblbm_oracle.so")
 
 BGK, TRT, CMMRT = 0, 1, 2
-PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM, ZERO_GRADIENT = 0, 1, 2, 3, 4
+PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM, ZERO_GRADIENT, ZOU_HE = 0, 1, 2, 3, 4, 5
 DF, MDF, DFC = 0, 1, 2
 HAT, PESKIN4 = 0, 1
 FIXED, PRESCRIBED_SIN, FREE = 0, 1, 2

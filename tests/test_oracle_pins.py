@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from oracle import (BGK, TRT, CMMRT, PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM,
-                    ZERO_GRADIENT, DF, MDF, DFC, HAT, PESKIN4, FIXED, PRESCRIBED_SIN, IM_NONE,
+                    ZERO_GRADIENT, ZOU_HE, DF, MDF, DFC, HAT, PESKIN4, FIXED, PRESCRIBED_SIN, IM_NONE,
                     IM_FENG)
 from ib_cases import random_populations
 
@@ -251,6 +251,63 @@ def test_uniform_stream_is_fixed_point_of_faces():
         np.testing.assert_allclose(s.populations(), f0, rtol=0, atol=1e-15)
         _, ux, uy = s.fields()
         assert np.abs(ux - u).max() < 1e-14 and np.abs(uy).max() < 1e-15
+
+
+@pytest.mark.parametrize("faces", ["box", "channel"])
+def test_zou_he_walls_have_zero_momentum(faces):
+    """After every step each Zou-He wall node carries no momentum (sum_i f_i
+    e_i = 0, the rest-wall condition), and a corner the density of its
+    diagonal inner node."""
+    bc = (ZOU_HE,) * 4 if faces == "box" else (PERIODIC, PERIODIC, ZOU_HE, ZOU_HE)
+    nx, ny = 13, 9
+    s = oracle.OracleSim(_box(TRT, nx, ny, bc, tau=0.8))
+    s.set_populations(random_populations(nx, ny, 3, amp=0.01, u=(0.03, -0.02)))
+    wall = np.zeros((ny, nx), bool)
+    wall[0, :] = wall[-1, :] = True
+    if faces == "box":
+        wall[:, 0] = wall[:, -1] = True
+    for _ in range(3):
+        s.step(1)
+        f = s.populations()
+        jx = (f * EX[:, None, None]).sum(0)
+        jy = (f * EY[:, None, None]).sum(0)
+        assert np.abs(jx[wall]).max() < 1e-16 and np.abs(jy[wall]).max() < 1e-16
+        assert np.abs(jx[~wall]).max() > 1e-4  # the fluid itself moves
+        if faces == "box":
+            rho = f.sum(0)
+            for (y, x), (yi, xi) in (((0, 0), (1, 1)), ((0, -1), (1, -2)), ((-1, 0), (-2, 1)),
+                                     ((-1, -1), (-2, -2))):
+                assert abs(rho[y, x] - rho[yi, xi]) < 1e-15
+
+
+def test_zou_he_rest_state_is_a_fixed_point():
+    nx, ny = 13, 9
+    s = oracle.OracleSim(_box(CMMRT, nx, ny, (ZOU_HE,) * 4, tau=0.8))
+    f0 = np.zeros((9, ny, nx))
+    f0[:] = oracle.equilibrium(1.0, 0.0, 0.0)[:, None, None]
+    s.set_populations(f0)
+    s.step(50)
+    assert np.abs(s.populations() - f0).max() < 1e-15
+
+
+@pytest.mark.parametrize("ny", [11, 21])
+def test_zou_he_body_force_channel_closed_form(ny):
+    """Body-force channel between Zou-He walls on nodes y = 0 and y = H =
+    ny - 1: the steady profile is the parabola F y (H - y) / (2 nu) plus a
+    uniform F/(2 rho): the closure zeroes sum_i f_i e_i at the wall, so the
+    half-force velocity there is F/2 (an error 4 nu / H^2 relative to the
+    centre line, second order in the spacing)."""
+    F, tau = 1e-6, 0.8
+    nu = (tau - 0.5) / 3.0
+    H = ny - 1
+    s = oracle.OracleSim(_box(BGK, 4, ny, (PERIODIC, PERIODIC, ZOU_HE, ZOU_HE), tau=tau,
+                              fluid_force=(F, 0.0)))
+    s.step(int(8 * H * H / nu))
+    _, ux, uy = s.fields()
+    y = np.arange(ny)
+    exact = F / (2 * nu) * y * (H - y) + F / 2
+    np.testing.assert_allclose(ux, np.broadcast_to(exact[:, None], ux.shape), rtol=1e-9, atol=0)
+    assert np.abs(uy).max() < 1e-15
 
 
 def test_zero_gradient_copy_and_bounce_back_rules():
