@@ -164,12 +164,13 @@ def oscillating_cylinder(steps=60000, nx=1200, ny=600, diameter=40.0) -> dict:
 
 
 def sedimentation(pair: bool = False, steps=200000, nx=400, ny=2000, diameter=20.0,
-                  internal_mass=IM_FENG) -> dict:
+                  internal_mass=IM_FENG, walls=ZOU_HE) -> dict:
     """Sedimenting disk(s) in a closed 400x2000 box, D = 20, nu = 0.02
     (tau = 0.56), g from Ar = (rho_r - 1) g D^3 / nu^2 = 1000 at rho_r = 1.5,
-    gravity -y; DFC + P4, CM-MRT, Feng explicit internal-mass correction.
-    The pair: heavy (1.5) leading at (199, 1760), light (1.1) trailing at
-    (201, 1800)."""
+    gravity -y; DFC + P4, CM-MRT, Feng explicit internal-mass correction;
+    no-slip walls with the Zou-He closure as in the paper (Sec. 2.9.3), or
+    half-way bounce-back (walls=BOUNCE_BACK).  The pair: heavy (1.5) leading
+    at (199, 1760), light (1.1) trailing at (201, 1800)."""
     nu = 0.02
     g = 1000.0 * nu * nu / (0.5 * diameter ** 3)
     if pair:
@@ -186,7 +187,7 @@ def sedimentation(pair: bool = False, steps=200000, nx=400, ny=2000, diameter=20
     return dict(
         name=f"sedimentation-{'pair' if pair else 'single'}-{nx}x{ny}", nx=nx, ny=ny,
         collision=CMMRT, tau=0.5 + 3.0 * nu, cm_s_q=1.2, cm_s_eps=1.4, rho0=1.0,
-        bc=(BOUNCE_BACK,) * 4, u_bc=0.0, gravity=(0.0, -g), u_ref=math.sqrt(0.5 * g * diameter),
+        bc=(walls,) * 4, u_bc=0.0, gravity=(0.0, -g), u_ref=math.sqrt(0.5 * g * diameter),
         diameter=diameter, bodies=bodies, steps=steps)
 
 

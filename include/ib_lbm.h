@@ -58,9 +58,14 @@ enum { IB_LBM_FP64 = 0, IB_LBM_FP32_SHIFTED = 1 };
 enum { IB_LBM_BGK = 0, IB_LBM_TRT = 1, IB_LBM_CMMRT = 2 };
 /* Face closures.  PERIODIC must be set on both faces of an axis; the
  * zero-gradient face copies the entering populations from the nodes one
- * step inside (any face; Sec. 2.9). */
+ * step inside (any face; Sec. 2.9).  BOUNCE_BACK is a half-way wall (half a
+ * spacing outside the face nodes); ZOU_HE is an on-node wall at rest with
+ * the closure of Zou and He (the walls of Sec. 2.9.3-2.9.4): the face nodes
+ * are wall nodes whose momentum sum_i f_i e_i is zero after every step.
+ * ZOU_HE combines only with ZOU_HE or PERIODIC faces, and such a sim cannot
+ * join a batch. */
 enum { IB_LBM_PERIODIC = 0, IB_LBM_BOUNCE_BACK = 1, IB_LBM_VEL_PARABOLIC = 2,
-       IB_LBM_VEL_UNIFORM = 3, IB_LBM_ZERO_GRADIENT = 4 };
+       IB_LBM_VEL_UNIFORM = 3, IB_LBM_ZERO_GRADIENT = 4, IB_LBM_ZOU_HE = 5 };
 enum { IB_LBM_DF = 0, IB_LBM_MDF = 1, IB_LBM_DFC = 2 };
 enum { IB_LBM_HAT = 0, IB_LBM_PESKIN4 = 1 };
 enum { IB_LBM_FIXED = 0, IB_LBM_PRESCRIBED_SIN = 1, IB_LBM_FREE = 2 };

@@ -372,6 +372,10 @@ EventPair take_pair(Timing &t) {
   return p;
 }
 
+static bool has_zou_he(const CaseDesc &c) {
+  return c.bc[0] == kZouHe || c.bc[1] == kZouHe || c.bc[2] == kZouHe || c.bc[3] == kZouHe;
+}
+
 // Enqueue one step of a sim on `stream`: collide-stream, then the IB pass.
 ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
@@ -390,6 +394,9 @@ ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
   HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
                                         (const int32_t *)s->d_prefix.p + 2, 1,
                                         face_blocks(s->cd.nx, s->cd.ny), -1, 1, stream));
+  if (has_zou_he(s->cd))
+    HIPCHK(s, launch_zou_he(s->cd.precision, (const CaseDesc *)s->d_case.p, s->cd.nx, s->cd.ny, -1,
+                            stream));
   if (timed) {
     p1 = take_pair(s->timing);
     HIPCHK(s, hipEventRecord(p1.a, stream));
@@ -486,6 +493,8 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
     HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
                                           (const int32_t *)s->d_prefix.p + 2, 1,
                                           face_blocks(s->cd.nx, s->cd.ny), pa.cur, 0, s->lq));
+    if (has_zou_he(s->cd))
+      HIPCHK(s, launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, pa.cur, s->lq));
     // hold tiles of step i after the far tiles of step i-1 (the wait is
     // enqueued before ev_far is recorded again for step i)
     if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_far, 0));
@@ -570,8 +579,17 @@ ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out) {
   if (cfg->collision < IB_LBM_BGK || cfg->collision > IB_LBM_CMMRT)
     return fail(IB_LBM_E_INVALID, "unknown collision");
   for (int f = 0; f < 4; f++)
-    if (cfg->bc[f] < IB_LBM_PERIODIC || cfg->bc[f] > IB_LBM_ZERO_GRADIENT)
+    if (cfg->bc[f] < IB_LBM_PERIODIC || cfg->bc[f] > IB_LBM_ZOU_HE)
       return fail(IB_LBM_E_INVALID, "unknown face closure");
+  {
+    bool zh = false, other = false;
+    for (int f = 0; f < 4; f++) {
+      zh |= cfg->bc[f] == IB_LBM_ZOU_HE;
+      other |= cfg->bc[f] != IB_LBM_ZOU_HE && cfg->bc[f] != IB_LBM_PERIODIC;
+    }
+    if (zh && other)
+      return fail(IB_LBM_E_INVALID, "Zou-He walls combine only with other Zou-He walls or periodic faces");
+  }
   if ((cfg->bc[0] == IB_LBM_PERIODIC) != (cfg->bc[1] == IB_LBM_PERIODIC) ||
       (cfg->bc[2] == IB_LBM_PERIODIC) != (cfg->bc[3] == IB_LBM_PERIODIC))
     return fail(IB_LBM_E_INVALID, "periodic faces must come in pairs");
@@ -1203,6 +1221,10 @@ ib_lbm_status ib_lbm_batch_attach(ib_lbm_batch *b, ib_lbm_sim *s) {
   }
   if (s->cd.precision != b->precision || s->stream != b->stream) {
     set_err(&b->err, "sim precision or stream differs from the batch");
+    return IB_LBM_E_INVALID;
+  }
+  if (has_zou_he(s->cd)) {
+    set_err(&b->err, "sims with Zou-He walls are stepped on their own, not in a batch");
     return IB_LBM_E_INVALID;
   }
   ib_lbm_status st = build_sim_tables(s);

@@ -14,7 +14,8 @@ namespace iblbm {
 
 enum { kPrecFP64 = 0, kPrecFP32 = 1 };
 enum { kBGK = 0, kTRT = 1, kCMMRT = 2 };
-enum { kPeriodic = 0, kBounceBack = 1, kVelParabolic = 2, kVelUniform = 3, kZeroGradient = 4 };
+enum { kPeriodic = 0, kBounceBack = 1, kVelParabolic = 2, kVelUniform = 3, kZeroGradient = 4,
+       kZouHe = 5 };
 enum { kFaceW = 0, kFaceE = 1, kFaceS = 2, kFaceN = 3 };
 enum { kDF = 0, kMDF = 1, kDFC = 2 };
 enum { kHat = 0, kPeskin4 = 1 };
@@ -198,6 +199,7 @@ hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDe
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t seq,
                       uint32_t *ticket, hipStream_t stream);
+hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
                          hipStream_t stream);

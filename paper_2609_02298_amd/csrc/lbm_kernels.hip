@@ -159,8 +159,9 @@ __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c
 __device__ __forceinline__ bool is_vel(int b) { return b == kVelParabolic || b == kVelUniform; }
 
 // Push population i of node (x,y) with value v, applying the face closures:
-//   periodic faces wrap; a link leaving through a zero-gradient face is
-//   dropped, and the populations entering a zero-gradient face are copies of
+//   periodic faces wrap; a link leaving through a zero-gradient or a Zou-He
+//   face is dropped (zou_he_kernel rebuilds the populations a Zou-He wall
+//   node is missing), and the populations entering a zero-gradient face are copies of
 //   those one node inside (column 1 for W, nx-2 for E, row 1 for S, ny-2 for
 //   N), written as duplicate stores of the pushes that land there (every
 //   such push comes from a face node); a corner of two zero-gradient faces
@@ -183,8 +184,8 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
   if (cn && c.bc[kFaceN] == kPeriodic) { yd -= ny; cn = false; }
   int j = i, xs = xd, ys = yd;
   if (cw || ce || cs || cn) {
-    if ((cw && c.bc[kFaceW] == kZeroGradient) || (ce && c.bc[kFaceE] == kZeroGradient) ||
-        (cs && c.bc[kFaceS] == kZeroGradient) || (cn && c.bc[kFaceN] == kZeroGradient))
+    if ((cw && c.bc[kFaceW] >= kZeroGradient) || (ce && c.bc[kFaceE] >= kZeroGradient) ||
+        (cs && c.bc[kFaceS] >= kZeroGradient) || (cn && c.bc[kFaceN] >= kZeroGradient))
       return;
     j = OPPI(i);
     xs = x;
@@ -449,6 +450,99 @@ __global__ __launch_bounds__(kFaceBlock) void collide_stream_face_kernel(const C
                 box ? cs->fbox[2] : -1, box ? cs->fbox[3] : -1, Fx, Fy);
   collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
   push_boundary9<T>(cp, dst, x, y, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
+}
+
+// No-slip walls with the on-node closure of Zou and He at zero wall
+// velocity, applied to the wall nodes after the step's streaming is
+// complete (the pushes of inner and face nodes have all landed).  The
+// populations that would have come from outside are rebuilt so that the
+// node has no momentum: the normal one as its opposite, the two diagonals
+// as their opposites corrected by half the tangential imbalance of the
+// axial pair.  A corner of two such walls bounces the three populations
+// pointing into the fluid and shares between the two buried diagonals what
+// the density of the diagonal inner node leaves.  The relations pair
+// populations of equal weight, so they hold unchanged for the shifted FP32
+// store (g = f - w rho0).  Links leaving through these faces were dropped
+// by push_one.  One thread per perimeter node: rows 0 and ny-1, then
+// columns 0 and nx-1 between them.
+template <typename T>
+__global__ __launch_bounds__(256) void zou_he_kernel(const CaseDesc *__restrict__ cp, int cur_arg) {
+  const CaseDesc &c = *cp;
+  const CaseState *cs = c.state;
+  const int nx = c.nx, ny = c.ny;
+  const int m = blockIdx.x * blockDim.x + (int)threadIdx.x;
+  if (m >= 2 * nx + 2 * (ny - 2)) return;
+  int x, y;
+  if (m < 2 * nx) {
+    x = m % nx;
+    y = m < nx ? 0 : ny - 1;
+  } else {
+    const int q = m - 2 * nx;
+    x = q < ny - 2 ? 0 : nx - 1;
+    y = 1 + q % (ny - 2);
+  }
+  const bool w = x == 0 && c.bc[kFaceW] == kZouHe, e = x == nx - 1 && c.bc[kFaceE] == kZouHe;
+  const bool so = y == 0 && c.bc[kFaceS] == kZouHe, no = y == ny - 1 && c.bc[kFaceN] == kZouHe;
+  if (!(w || e || so || no)) return;
+  int cur = cur_arg;
+  if (cur < 0) {
+    if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
+    cur = cs->cur;
+  } else if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) {
+    return;
+  }
+  T *__restrict__ f = (T *)c.f[cur ^ 1];
+  const uint32_t plane = (uint32_t)c.plane;
+  const uint32_t p = (uint32_t)y * nx + x;
+  T v[9];
+#pragma unroll
+  for (int i = 0; i < 9; i++) v[i] = f[i * plane + p];
+  if ((w || e) && (so || no)) {
+    const int sx = w ? 1 : -1, sy = so ? 1 : -1;
+    const int ix = sx > 0 ? 1 : 3, iy = sy > 0 ? 2 : 4;
+    // diagonal into the fluid, and the two buried ones
+    const int id = sx > 0 ? (sy > 0 ? 5 : 8) : (sy > 0 ? 6 : 7);
+    const int ia = sx > 0 ? (sy > 0 ? 6 : 7) : (sy > 0 ? 5 : 8);  // (-sx, sy)
+    const int ib = sx > 0 ? (sy > 0 ? 8 : 5) : (sy > 0 ? 7 : 6);  // (sx, -sy)
+    v[ix] = v[OPPI(ix)];
+    v[iy] = v[OPPI(iy)];
+    v[id] = v[OPPI(id)];
+    const uint32_t pc = (uint32_t)(y + sy) * nx + (x + sx);
+    double rc = 0.0, known = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+      rc += (double)f[i * plane + pc];
+      if (i != ia && i != ib) known += (double)v[i];
+    }
+    const T b = T(0.5 * (rc - known));
+    f[ix * plane + p] = v[ix];
+    f[iy * plane + p] = v[iy];
+    f[id * plane + p] = v[id];
+    f[ia * plane + p] = b;
+    f[ib * plane + p] = b;
+  } else if (so || no) {
+    const int in = so ? 2 : 4, d1 = so ? 5 : 8, d2 = so ? 6 : 7;
+    const T t = T(0.5) * (v[1] - v[3]);
+    f[in * plane + p] = v[OPPI(in)];
+    f[d1 * plane + p] = v[OPPI(d1)] - t;
+    f[d2 * plane + p] = v[OPPI(d2)] + t;
+  } else {
+    const int in = w ? 1 : 3, d1 = w ? 5 : 6, d2 = w ? 8 : 7;
+    const T t = T(0.5) * (v[2] - v[4]);
+    f[in * plane + p] = v[OPPI(in)];
+    f[d1 * plane + p] = v[OPPI(d1)] - t;
+    f[d2 * plane + p] = v[OPPI(d2)] + t;
+  }
+}
+
+hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream) {
+  const int n = 2 * nx + 2 * (ny - 2);
+  const int blocks = (n + 255) / 256;
+  if (precision == kPrecFP64)
+    hipLaunchKernelGGL(zou_he_kernel<double>, dim3(blocks), dim3(256), 0, stream, c, cur);
+  else
+    hipLaunchKernelGGL(zou_he_kernel<float>, dim3(blocks), dim3(256), 0, stream, c, cur);
+  return hipGetLastError();
 }
 
 // One part of a pipelined step of a single case (see PipeArgs): the tiles

@@ -84,12 +84,16 @@ FACE_SETS = {
     "open": ((ib.ZERO_GRADIENT,) * 4, 0.0),
     "open-mixed": ((ib.ZERO_GRADIENT, ib.ZERO_GRADIENT, ib.BOUNCE_BACK, ib.VEL_UNIFORM), 0.04),
     "inflow-open": ((ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.ZERO_GRADIENT, ib.ZERO_GRADIENT), 0.06),
+    # on-node Zou-He walls: a closed box (all four corners) and a channel
+    "zh-box": ((ib.ZOU_HE,) * 4, 0.0),
+    "zh-channel": ((ib.PERIODIC, ib.PERIODIC, ib.ZOU_HE, ib.ZOU_HE), 0.0),
 }
 
 
 @pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
 @pytest.mark.parametrize("col", [ib.BGK, ib.TRT, ib.CMMRT])
-@pytest.mark.parametrize("faces", ["channel", "farfield", "box", "open", "open-mixed", "inflow-open"])
+@pytest.mark.parametrize("faces", ["channel", "farfield", "box", "open", "open-mixed", "inflow-open",
+                                   "zh-box", "zh-channel"])
 def test_faces(col, prec, faces):
     """Every face closure on a ragged lattice (not a multiple of the tile)."""
     say(f"faces {faces} col={col} prec={prec}")
@@ -106,7 +110,8 @@ def test_faces(col, prec, faces):
 
 
 @pytest.mark.parametrize("col", [ib.BGK, ib.TRT, ib.CMMRT])
-@pytest.mark.parametrize("faces", ["periodic", "channel", "farfield", "box", "open", "open-mixed"])
+@pytest.mark.parametrize("faces", ["periodic", "channel", "farfield", "box", "open", "open-mixed",
+                                   "zh-box", "zh-channel"])
 def test_faces_even_width_fp32(col, faces):
     """FP32 on a wider lattice (several tiles in x and y, inner nodes and
     face nodes in separate launches), every face closure."""
@@ -114,7 +119,7 @@ def test_faces_even_width_fp32(col, faces):
     bc, u = FACE_SETS[faces]
     nx, ny = 390, 46
     case = dict(nx=nx, ny=ny, collision=col, tau=0.66, bc=bc, u_bc=u,
-                fluid_force=(2e-6, -1e-6) if faces == "periodic" else (0.0, 0.0))
+                fluid_force=(2e-6, -1e-6) if faces in ("periodic", "zh-channel") else (0.0, 0.0))
     u0 = (u * 0.5, 0.0) if u > 0 else (0.05, 0.03)
     pops = ib_cases.random_populations(nx, ny, 5, amp=0.01, u=u0)
     sim, ref = make_pair(case, ib.FP32_SHIFTED, pops)
@@ -695,6 +700,46 @@ def test_split_step_is_bitwise_the_plain_step(scheme, kernel, col, motion, prec)
         for k in ("fx", "fy", "torque", "slip_mean", "xc", "yc"):
             assert st[k] == base[1][k], k
         assert np.array_equal(fx, base[2][0]) and np.array_equal(fy, base[2][1])
+
+
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+def test_split_step_with_zou_he_walls(prec):
+    """A body in a force-driven channel between Zou-He walls: the wall pass
+    runs after the face nodes in both the plain and the pipelined step; the
+    two are bitwise equal and match the oracle."""
+    say(f"split step, Zou-He channel, prec={prec}")
+    case = _split_case(ib.MDF, ib.PESKIN4, ib.TRT)
+    case.update(bc=(ib.PERIODIC, ib.PERIODIC, ib.ZOU_HE, ib.ZOU_HE), u_bc=0.0,
+                fluid_force=(4e-6, 0.0))
+    runs = []
+    for overlap in (False, True):
+        sim = ib.Sim(case, precision=prec)
+        sim.set_launch(64, 1, 1, 1)
+        sim.set_overlap(overlap)
+        sim.step(1)
+        sim.step(24)
+        assert sim.overlap()[0] == overlap
+        runs.append((sim.populations(), sim.forces(0)))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    ref = oracle.OracleSim(case)
+    ref.add_body(case["bodies"][0])
+    ref.step(25)
+    fs, fr = runs[1][1], ref.body_state(0)
+    f64 = prec == ib.FP64
+    assert abs(fs["fx"] - fr["fx"]) / abs(fr["fx"]) < (F64_DRAG if f64 else F32_DRAG)
+    if f64:
+        assert rel(runs[1][0], ref.populations()) < F64_FIELD
+
+
+def test_zou_he_sims_stay_out_of_batches():
+    case = dict(nx=40, ny=30, tau=0.8, bc=(ib.ZOU_HE,) * 4)
+    b = ib.Batch(precision=ib.FP64)
+    s = ib.Sim(case)
+    with pytest.raises(ib.IbLbmError):
+        b.attach(s)
+    for bad in ((ib.ZOU_HE, ib.ZOU_HE, ib.BOUNCE_BACK, ib.ZOU_HE), (ib.ZOU_HE, 6, 5, 5)):
+        with pytest.raises(ib.IbLbmError):
+            ib.Sim(dict(case, bc=bad))
 
 
 def test_split_step_matches_oracle_and_is_off_for_free_bodies():
