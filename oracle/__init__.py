@@ -17,7 +17,9 @@ from .oracle import (  # noqa: F401
     dfc_lambda,
     body_half_kick,
     body_full_kick,
+    body_euler,
     BGK, TRT, CMMRT,
     PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM, ZERO_GRADIENT, ZOU_HE,
     DF, MDF, DFC, HAT, PESKIN4, FIXED, PRESCRIBED_SIN, FREE, IM_NONE, IM_FENG,
+    VERLET, EULER_A1,
 )

@@ -49,6 +49,7 @@ typedef struct {
   double xc0, yc0;
   double xc, yc, vx, vy, vpx, vpy, om;
   double vhx, vhy, omh;
+  double omp;       /* Omega^(n-1) (Euler-explicit update) */
   double fhx, fhy, torque;
   double dimx, dimy;
   double ms, mf, Is;
@@ -433,6 +434,31 @@ void or_body_full_kick(double ms, double mf, double Is, const double *g, double 
   st[6] += st[9] / (2.0 * Is);
 }
 
+/* Euler-explicit update of Eq. (A1), the integrator of the paper's
+ * wake-interaction cross-check: v^(n+1) = (1 + r) v^n - r v^(n-1) +
+ * (F_hydro^n + F_g)/m_s with r = m_f/m_s (= rho_f/rho_s) for the Feng form
+ * and r = 0 without it; the rotation carries the internal angular-momentum
+ * increment the same way, Omega^(n+1) = (1 + r) Omega^n - r Omega^(n-1) +
+ * T^n/I_s (reading: the increment is that of the rigid interior,
+ * I_f (Omega^n - Omega^(n-1)) with I_f/I_s = r); X^(n+1) = X^n + v^(n+1)
+ * (reading).  st: 0 x 1 y 2 vx 3 vy 4 vpx 5 vpy 6 om 7 Fhx 8 Fhy 9 T
+ * 10 Omega^(n-1); on return 2,3,6 hold the new velocities, 4,5,10 the old. */
+void or_body_euler(double ms, double mf, double Is, int internal_mass, const double *g, double *st) {
+  const double r = internal_mass == OR_IM_FENG ? mf / ms : 0.0;
+  const double Fgx = (ms - mf) * g[0], Fgy = (ms - mf) * g[1];
+  const double vx = (1.0 + r) * st[2] - r * st[4] + (st[7] + Fgx) / ms;
+  const double vy = (1.0 + r) * st[3] - r * st[5] + (st[8] + Fgy) / ms;
+  const double om = (1.0 + r) * st[6] - r * st[10] + st[9] / Is;
+  st[4] = st[2];
+  st[5] = st[3];
+  st[10] = st[6];
+  st[2] = vx;
+  st[3] = vy;
+  st[6] = om;
+  st[0] += vx;
+  st[1] += vy;
+}
+
 static void body_pre(or_sim *s, or_body *b, int64_t n) {
   double t1 = (double)(n + 1);
   if (b->d.motion == OR_FIXED) {
@@ -447,6 +473,14 @@ static void body_pre(or_sim *s, or_body *b, int64_t n) {
     b->vx = b->vhx;
     b->vy = b->vhy;
     b->omh = 0.0;
+  } else if (b->d.integrator == OR_EULER_A1) {
+    double st[12] = {b->xc, b->yc, b->vx, b->vy, b->vpx, b->vpy, b->om,
+                     b->fhx, b->fhy, b->torque, b->omp, 0};
+    or_body_euler(b->ms, b->mf, b->Is, b->d.internal_mass, s->c.gravity, st);
+    b->xc = st[0]; b->yc = st[1];
+    b->vx = b->vhx = st[2]; b->vy = b->vhy = st[3]; b->om = b->omh = st[6];
+    b->vpx = st[4]; b->vpy = st[5]; b->omp = st[10];
+    b->dimx = b->dimy = 0.0;
   } else {
     double st[12] = {b->xc, b->yc, b->vx, b->vy, b->vpx, b->vpy, b->om,
                      b->fhx, b->fhy, b->torque, 0, 0};
@@ -466,7 +500,7 @@ static void body_pre(or_sim *s, or_body *b, int64_t n) {
 }
 
 static void body_post(or_sim *s, or_body *b) {
-  if (b->d.motion != OR_FREE) return;
+  if (b->d.motion != OR_FREE || b->d.integrator == OR_EULER_A1) return;
   double st[12] = {b->xc, b->yc, b->vhx, b->vhy, b->vpx, b->vpy, b->omh,
                    b->fhx, b->fhy, b->torque, b->dimx, b->dimy};
   or_body_full_kick(b->ms, b->mf, b->Is, s->c.gravity, st);

@@ -27,6 +27,7 @@ enum { OR_DF = 0, OR_MDF = 1, OR_DFC = 2 };
 enum { OR_HAT = 0, OR_PESKIN4 = 1 };
 enum { OR_FIXED = 0, OR_PRESCRIBED_SIN = 1, OR_FREE = 2 };
 enum { OR_IM_NONE = 0, OR_IM_FENG = 1 };
+enum { OR_VERLET = 0, OR_EULER_A1 = 1 };
 
 typedef struct {
   int32_t nx, ny;
@@ -56,6 +57,8 @@ typedef struct {
   int32_t mdf_nmin;        /* adaptive MDF: fewest passes before the tolerance stop */
   int32_t pad1;
   double mdf_tol;          /* > 0: adaptive MDF (Sec. 2.5.2, App. A.2); <= 0: mdf_iters passes */
+  int32_t integrator;      /* free bodies: OR_VERLET (Eq. 23) or OR_EULER_A1 (Eq. A1) */
+  int32_t pad2;
 } or_body_desc;
 
 typedef struct or_sim or_sim;
@@ -78,6 +81,9 @@ int or_body_state(const or_sim *s, int b, double *out);
 /* per marker 8 values: X Y Udx Udy Fx Fy lambda ds */
 int or_markers(const or_sim *s, int b, double *out);
 double or_body_omega(const or_sim *s, int b);
+/* Euler-explicit rigid-body step of Eq. (A1); st as for the Verlet kicks
+ * with st[10] = Omega^(n-1). */
+void or_body_euler(double ms, double mf, double Is, int internal_mass, const double *g, double *st);
 /* MDF residual r_n of each interpolation of the last step (out holds
  * mdf_iters doubles); returns their number. */
 int or_mdf_residuals(const or_sim *s, int b, double *out);

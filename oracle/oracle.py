@@ -22,6 +22,7 @@ DF, MDF, DFC = 0, 1, 2
 HAT, PESKIN4 = 0, 1
 FIXED, PRESCRIBED_SIN, FREE = 0, 1, 2
 IM_NONE, IM_FENG = 0, 1
+VERLET, EULER_A1 = 0, 1
 
 
 def build_oracle(force: bool = True) -> str:
@@ -47,7 +48,8 @@ class _Body(C.Structure):
                 ("mdf_iters", C.c_int32), ("mdf_omega", C.c_double), ("motion", C.c_int32),
                 ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
                 ("phase", C.c_double), ("density_ratio", C.c_double),
-                ("mdf_nmin", C.c_int32), ("pad1", C.c_int32), ("mdf_tol", C.c_double)]
+                ("mdf_nmin", C.c_int32), ("pad1", C.c_int32), ("mdf_tol", C.c_double),
+                ("integrator", C.c_int32), ("pad2", C.c_int32)]
 
 
 _lib = None
@@ -89,6 +91,7 @@ def lib():
         L.or_dense_A.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, dp]
         L.or_dfc_lambda.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, dp]
         L.or_body_half_kick.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, dp, dp]
+        L.or_body_euler.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, dp, dp]
         L.or_body_full_kick.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
         _lib = L
     return _lib
@@ -135,6 +138,7 @@ def make_body(b: dict) -> _Body:
     d.density_ratio = float(b.get("density_ratio", 1.0))
     d.mdf_nmin = int(b.get("mdf_nmin", 1))
     d.mdf_tol = float(b.get("mdf_tol", 0.0))
+    d.integrator = int(b.get("integrator", VERLET))
     return d
 
 
@@ -283,3 +287,8 @@ def body_half_kick(ms, mf, Is, internal_mass, g, st: np.ndarray):
 def body_full_kick(ms, mf, Is, g, st: np.ndarray):
     gv = np.ascontiguousarray(g, np.float64)
     lib().or_body_full_kick(ms, mf, Is, _dp(gv), _dp(st))
+
+
+def body_euler(ms, mf, Is, internal_mass, g, st: np.ndarray):
+    gv = np.ascontiguousarray(g, np.float64)
+    lib().or_body_euler(ms, mf, Is, internal_mass, _dp(gv), _dp(st))

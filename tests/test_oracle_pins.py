@@ -797,6 +797,57 @@ def test_free_fall_internal_mass_converges_to_g():
         assert abs(hist[n + 1] - ((1 + r) * hist[n] - r * vm1 + (ms - mf) * g[1] / ms)) < 1e-15
 
 
+def test_euler_a1_free_fall_closed_forms():
+    """Euler-explicit update of Eq. (A1) with no hydrodynamic force.  Without
+    internal mass: v^n = n a, X^n = a n (n+1)/2 (a = F_g/m_s, the position
+    advanced with the new velocity).  With it (r = m_f/m_s): the velocity
+    increments obey d_n = r d_(n-1) + a, so d_n = a (1 - r^(n+1))/(1 - r),
+    whose limit is F_g/(m_s - m_f) = g; a constant torque likewise drives
+    the spin-up rate to T/(I_s - I_f)."""
+    ms, mf, Is, g = 3.0, 2.0, 5.0, np.array([4e-4, -1e-3])
+    a = (ms - mf) * g / ms
+    st = np.zeros(12); st[1] = 100.0
+    for n in range(1, 40):
+        oracle.body_euler(ms, mf, Is, IM_NONE, g, st)
+        assert np.abs(st[2:4] - n * a).max() < 1e-15
+        assert abs(st[0] - a[0] * n * (n + 1) / 2) < 1e-13
+        assert abs(st[1] - (100.0 + a[1] * n * (n + 1) / 2)) < 1e-12
+    r = mf / ms
+    T = 0.3
+    st = np.zeros(12); st[9] = T
+    v = np.zeros(2); om = 0.0
+    for n in range(60):
+        oracle.body_euler(ms, mf, Is, IM_FENG, g, st)
+        d = a * (1 - r ** (n + 1)) / (1 - r)
+        v = v + d
+        om = om + T / Is * (1 - r ** (n + 1)) / (1 - r)
+        assert np.abs(st[2:4] - v).max() < 1e-14
+        assert abs(st[6] - om) < 1e-13
+        assert np.abs(st[4:6] - (v - d)).max() < 1e-14  # previous velocity kept
+    np.testing.assert_allclose(st[2:4] - st[4:6], g, rtol=1e-9)
+    # I_f / I_s = m_f / m_s = r for the disk and its fictitious fluid
+    assert abs((st[6] - st[10]) - T / (Is * (1 - r))) < 1e-9
+
+
+def test_euler_a1_body_in_fluid_uses_new_velocity():
+    """In a sim the Euler-explicit body moves by its new velocity each step
+    and reports it; the marker velocities are that rigid motion."""
+    cfg = dict(nx=64, ny=48, collision=BGK, tau=0.8, bc=(PERIODIC,) * 4, gravity=(0.0, -2e-5))
+    s = oracle.OracleSim(cfg)
+    s.add_body(dict(xc=30.3, yc=24.2, diameter=10.0, scheme=DF, kernel=PESKIN4, motion=oracle.FREE,
+                    density_ratio=2.0, internal_mass=IM_FENG, integrator=oracle.EULER_A1))
+    prev = s.body_state(0)
+    for _ in range(5):
+        s.step(1)
+        st = s.body_state(0)
+        assert abs(st["yc"] - (prev["yc"] + st["vy"])) < 1e-14
+        m = s.markers(0)
+        rx, ry = m[:, 0] - st["xc"], m[:, 1] - st["yc"]
+        np.testing.assert_allclose(m[:, 2], st["vx"] - st["omega"] * ry, atol=1e-15)
+        np.testing.assert_allclose(m[:, 3], st["vy"] + st["omega"] * rx, atol=1e-15)
+        prev = st
+
+
 def test_torque_only_rotation():
     ms, mf, Is = 3.0, 2.0, 5.0
     st = np.zeros(12); st[9] = 0.2
