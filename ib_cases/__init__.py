@@ -33,6 +33,7 @@ DF, MDF, DFC = 0, 1, 2
 HAT, PESKIN4 = 0, 1
 FIXED, PRESCRIBED_SIN, FREE = 0, 1, 2
 IM_NONE, IM_FENG = 0, 1
+VERLET, EULER_A1 = 0, 1
 
 SCHEMES = {"DF": DF, "MDF": MDF, "DFC": DFC}
 KERNELS = {"hat": HAT, "P4": PESKIN4}

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define IB_LBM_ABI_VERSION 2u
+#define IB_LBM_ABI_VERSION 3u
 
 typedef enum {
   IB_LBM_OK = 0,
@@ -70,6 +70,7 @@ enum { IB_LBM_DF = 0, IB_LBM_MDF = 1, IB_LBM_DFC = 2 };
 enum { IB_LBM_HAT = 0, IB_LBM_PESKIN4 = 1 };
 enum { IB_LBM_FIXED = 0, IB_LBM_PRESCRIBED_SIN = 1, IB_LBM_FREE = 2 };
 enum { IB_LBM_IM_NONE = 0, IB_LBM_IM_FENG = 1 };
+enum { IB_LBM_VERLET = 0, IB_LBM_EULER_A1 = 1 };
 enum { IB_LBM_SPREAD_GATHER = 0, IB_LBM_SPREAD_ATOMIC = 1 };
 
 /* Body flags reported in ib_lbm_body_state.flags */
@@ -121,8 +122,13 @@ typedef struct {
  * residual.  IB_LBM_E_INVALID unless 1 <= mdf_nmin <= mdf_iters.
  * PRESCRIBED_SIN: X_c(t) = X_c0 + amp sin(2 pi freq t + phase).
  * FREE: density_ratio rho_s/rho0, internal_mass selects scheme (A) or the
- * Feng explicit-history correction (App. A.5).  All bodies of one sim use
- * the same scheme. */
+ * Feng explicit-history correction (App. A.5).  integrator: the
+ * Velocity-Verlet update of Eq. 23 (half-kick and drift before the step,
+ * full kick after it), or the Euler-explicit update of Eq. A1 before the
+ * step, v^(n+1) = (1 + r) v^n - r v^(n-1) + (F_hydro^n + F_g)/m_s with r =
+ * rho0/rho_s (0 without internal mass), the rotation likewise with the
+ * rigid interior's angular-momentum increment, X^(n+1) = X^n + v^(n+1).
+ * All bodies of one sim use the same scheme. */
 typedef struct {
   double xc, yc, diameter;
   int32_t n_markers;
@@ -136,6 +142,7 @@ typedef struct {
   double density_ratio;
   int32_t mdf_nmin; /* adaptive MDF: fewest passes before the tolerance stop */
   double mdf_tol;   /* > 0 selects the adaptive MDF; <= 0 the fixed form */
+  int32_t integrator; /* FREE bodies: IB_LBM_VERLET | IB_LBM_EULER_A1 */
 } ib_lbm_body_desc;
 
 /* State of a body after the last completed step.  Forces are on the body

@@ -666,7 +666,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
       (b->scheme == IB_LBM_MDF && (b->mdf_iters < 1 || b->mdf_iters > 1000)) ||
       (b->scheme == IB_LBM_MDF && b->mdf_tol > 0 &&
        (b->mdf_nmin < 1 || b->mdf_nmin > b->mdf_iters)) ||
-      (b->motion == IB_LBM_FREE && !(b->density_ratio > 0))) {
+      (b->motion == IB_LBM_FREE && !(b->density_ratio > 0)) ||
+      (b->integrator != IB_LBM_VERLET && b->integrator != IB_LBM_EULER_A1)) {
     set_err(&s->err, "invalid body description");
     return IB_LBM_E_INVALID;
   }
@@ -691,6 +692,7 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.mdf_nmin = B.mdf_tol > 0 ? b->mdf_nmin : B.mdf_iters;
   B.motion = b->motion;
   B.internal_mass = b->internal_mass;
+  B.integrator = b->integrator;
   B.ns = b->kernel == IB_LBM_HAT ? 2 : 4;
   B.radius = 0.5 * b->diameter;
   B.ds = M_PI * b->diameter / nb;

@@ -14,6 +14,7 @@ namespace iblbm {
 
 enum { kPrecFP64 = 0, kPrecFP32 = 1 };
 enum { kBGK = 0, kTRT = 1, kCMMRT = 2 };
+enum { kVerlet = 0, kEulerA1 = 1 };
 enum { kPeriodic = 0, kBounceBack = 1, kVelParabolic = 2, kVelUniform = 3, kZeroGradient = 4,
        kZouHe = 5 };
 enum { kFaceW = 0, kFaceE = 1, kFaceS = 2, kFaceN = 3 };
@@ -49,6 +50,7 @@ struct BodyState {
   double vx, vy;        // velocity v^n
   double vpx, vpy;      // v^(n-1)
   double om;            // angular velocity
+  double omp;           // Omega^(n-1) (Euler-explicit update)
   double vhx, vhy, omh; // half-step values used for U_d in the last step
   double fhx, fhy, torque;
   double dimx, dimy;    // internal-mass force held over the step
@@ -66,6 +68,8 @@ struct BodyState {
 struct BodyDesc {
   int32_t nb, scheme, kernel, mdf_iters;
   int32_t motion, internal_mass;
+  int32_t integrator;   // free bodies: kVerlet (Eq. 23) or kEulerA1 (Eq. A1)
+  int32_t pad_integrator;
   int32_t ns;           // support width: 2 (hat) or 4 (P4)
   int32_t window;       // half width of the angular marker window of the gather
   int32_t max_rows, max_nodes;

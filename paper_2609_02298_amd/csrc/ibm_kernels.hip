@@ -561,6 +561,24 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       vhy = B.amp[1] * 2.0 * M_PI * B.freq * cn;
       bs->vx = vhx;
       bs->vy = vhy;
+    } else if (B.motion == kFree && B.integrator == kEulerA1) {
+      // Euler-explicit update of Eq. (A1) from the force of the last step:
+      // v^(n+1) = (1 + r) v^n - r v^(n-1) + (F^n + F_g)/m_s with r = m_f/m_s
+      // (0 without internal mass); the rotation with the rigid interior's
+      // angular-momentum increment; the position by the new velocity.
+      const double r = B.internal_mass == kImFeng ? B.mf / B.ms : 0.0;
+      const double fgx = (B.ms - B.mf) * c.grav_x;
+      const double fgy = (B.ms - B.mf) * c.grav_y;
+      vhx = (1.0 + r) * bs->vx - r * bs->vpx + (bs->fhx + fgx) / B.ms;
+      vhy = (1.0 + r) * bs->vy - r * bs->vpy + (bs->fhy + fgy) / B.ms;
+      omh = (1.0 + r) * bs->om - r * bs->omp + bs->torque / B.Is;
+      bs->vpx = bs->vx;
+      bs->vpy = bs->vy;
+      bs->omp = bs->om;
+      bs->dimx = 0.0;
+      bs->dimy = 0.0;
+      xc += vhx;
+      yc += vhy;
     } else if (B.motion == kFree) {
       // Eq. (23) first half-kick and drift, with the internal-mass force of
       // Eq. (A3) held over the step and the net gravity of Eq. (22).
@@ -601,6 +619,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     ish[12] = B.motion;
     ish[13] = B.scheme;
     ish[14] = c.ny;
+    ish[15] = B.integrator;
     bsh[7] = __longlong_as_double((long long)(B.history + (step % B.hist_cap) * kHistCols));
     bsh[8] = B.ms;
     bsh[9] = (B.ms - B.mf) * c.grav_x;
@@ -1046,7 +1065,11 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       box[3] = min(ish[14] - 1, (int)floor(yc + r) + ns + 1);
     }
     double vx = vhx, vy = vhy, om = omh;
-    if (motion == kFree) {
+    if (motion == kFree && ish[15] == kEulerA1) {
+      // the Euler-explicit velocity was set before the step; the new force
+      // enters the next one
+      if (!isfinite(vx) || !isfinite(vy) || fabs(vx) > 0.5 || fabs(vy) > 0.5) flags |= kFlagNonfinite;
+    } else if (motion == kFree) {
       const double ms = bsh[8];
       vx = vhx + (a + bsh[9] + bsh[5]) / (2.0 * ms);
       vy = vhy + (b + bsh[10] + bsh[6]) / (2.0 * ms);

@@ -223,8 +223,10 @@ def test_prescribed_oscillation(prec):
 @pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
 @pytest.mark.parametrize("pair", [False, True])
 @pytest.mark.parametrize("im", [ib.IM_NONE, ib.IM_FENG])
-def test_free_bodies(prec, pair, im):
-    """Free disks settling in a closed box (Eq. 21-23, A3).
+@pytest.mark.parametrize("integ", [ib.VERLET, ib.EULER_A1])
+def test_free_bodies(prec, pair, im, integ):
+    """Free disks settling in a closed box (Eq. 21-23, A3), with the
+    Velocity-Verlet or the Euler-explicit (Eq. A1) update.
 
     The heavy disk (density ratio 1.5) is compared at the stated
     tolerances over 80 steps.  The light disk of the pair (ratio 1.1) is
@@ -235,8 +237,10 @@ def test_free_bodies(prec, pair, im):
     populations, differs by 3.5e-10 after 80 steps).  It is compared at
     the stated tolerance over the first 12 steps, and over 80 steps within
     1e-6 (FP64) / 1e-2 (FP32 shifted) relative."""
-    say(f"free bodies pair={pair} im={im} prec={prec}")
+    say(f"free bodies pair={pair} im={im} integrator={integ} prec={prec}")
     case = ib_cases.sedimentation(pair=pair, nx=80, ny=200, diameter=12.0, internal_mass=im)
+    for b in case["bodies"]:
+        b["integrator"] = integ
     case["gravity"] = (0.0, -1e-4)
     if pair:
         case["bodies"][0].update(xc=39.0, yc=140.0)
