@@ -147,6 +147,33 @@ def paper_inline_oscillation(scheme="MDF", kernel="P4", collision="BGK",
         steps=40000, average_from=8001, period=int(round(1.0 / f0)), re=re)
 
 
+def paper_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator=VERLET,
+                           internal_mass=IM_FENG, steps=60000) -> dict:
+    """The two-particle wake-interaction channel of Sec. 2.9.4: Omega =
+    [0, 10] x [-1, 1] on 4001 x 801 nodes (spacing 0.0025), d = 0.2 (D = 80),
+    heavy particle (density ratio 1.5) at (0.8, -0.13) and light one (1.25)
+    at (1.2, 0.13), gravity g = 2.156e-4 along +x, tau = 0.59, no-slip
+    Zou-He walls on all four sides (Sec. 2.9.3); marker spacing 2/3
+    (reading; 377 markers).  The reference baseline of Table V is DF,
+    Peskin 4-point, Velocity-Verlet with the explicit-history correction."""
+    nx, ny, h, D = 4001, 801, 0.0025, 80.0
+    sch = SCHEMES[scheme] if isinstance(scheme, str) else scheme
+    ker = KERNELS[kernel] if isinstance(kernel, str) else kernel
+    col = COLLISIONS[collision] if isinstance(collision, str) else collision
+    nb = int(round(math.pi * D / (2.0 / 3.0)))
+
+    def body(x, y, ratio):
+        return dict(xc=x / h, yc=(y + 1.0) / h, diameter=D, n_markers=nb, scheme=sch, kernel=ker,
+                    mdf_iters=5, motion=FREE, density_ratio=ratio, internal_mass=internal_mass,
+                    integrator=integrator)
+    tau = 0.59
+    return dict(
+        name=f"paper-wake-interaction-{nx}x{ny}", nx=nx, ny=ny, collision=col, tau=tau,
+        trt_magic=0.25, cm_s_q=1.2, cm_s_eps=1.4, rho0=1.0, bc=(ZOU_HE,) * 4, u_bc=0.0,
+        gravity=(2.156e-4, 0.0), diameter=D, nu=(tau - 0.5) / 3.0,
+        bodies=[body(0.8, -0.13, 1.5), body(1.2, 0.13, 1.25)], steps=steps)
+
+
 def oscillating_cylinder(steps=60000, nx=1200, ny=600, diameter=40.0) -> dict:
     """Transversely oscillating cylinder: 1200x600, D = 40, Re = 100,
     y(t) = A sin(2 pi f t), A = 0.2 D, f = 0.8 St0 u_inf / D; MDF (k=5), P4,

@@ -7,6 +7,11 @@ Table B.8 (largest |C_d| of each period after the first two, averaged), of
 the body's whole IB force and of the outer fluid's force alone (the IB
 force less the inertia of the fluid inside the cylinder).
 
+``python -m paper_2609_02298_amd.studies wake-interaction [--integrator verlet
+euler] [--internal-mass feng none]`` runs the two-particle channel of Sec.
+2.9.4 and reports each particle's peak Re_f = |v| D / nu (Table V), the
+minimum gap and the overtaking step.
+
 ``python -m paper_2609_02298_amd.studies fixed-cylinder [--re 20 40 100 200]
 [--scheme DF MDF DFC] [--kernel hat P4] [--precision fp64|fp32]`` runs the
 fixed cylinder of Sec. 2.9.1 / Table I (2001 x 1601, D = 40 for Re <= 100;
@@ -179,6 +184,55 @@ def run_inline_oscillation(scheme: str, kernel: str, collision: str = "BGK",
     return out
 
 
+def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="verlet",
+                         internal_mass="feng", precision="fp64", log=sys.stderr) -> dict:
+    """Two particles settling along +x (Sec. 2.9.4) until a support reaches
+    the end wall or the step budget is spent: the peak Reynolds number of
+    each on the fluid-density basis Re_f = |v| D / nu (the quantity of
+    Table V), the minimum surface gap over D and its step, and the step at
+    which the heavy particle passes the light one."""
+    import ib_cases
+    from . import ib_lbm as ib
+
+    case = ib_cases.paper_wake_interaction(
+        scheme=scheme, kernel=kernel, collision=collision,
+        integrator=ib.EULER_A1 if integrator == "euler" else ib.VERLET,
+        internal_mass=ib.IM_FENG if internal_mass == "feng" else ib.IM_NONE)
+    prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
+    nsteps = case["steps"]
+    sim = ib.Sim(case, precision=prec, history_capacity=nsteps)
+    t0 = time.perf_counter()
+    done, status = 0, 0
+    while done < nsteps:
+        sim.step(min(5000, nsteps - done))
+        sim.sync()
+        done = sim.steps_done
+        st = [sim.forces(b, check=False) for b in range(2)]
+        status = max(abs(x["status"]) for x in st)
+        print(f"  {case['name']} {scheme}/{kernel}/{collision}/{integrator}/{internal_mass} "
+              f"{precision}: {done} steps, x = {st[0]['xc']:.1f} / {st[1]['xc']:.1f}, "
+              f"{time.perf_counter() - t0:.1f} s", file=log, flush=True)
+        if status:
+            break
+    wall = time.perf_counter() - t0
+    n = sim.steps_done
+    hh, hl = sim.history(0, 1, n), sim.history(1, 1, n)
+    D, nu = case["diameter"], case["nu"]
+    re_h = np.hypot(hh[:, 6], hh[:, 7]) * D / nu
+    re_l = np.hypot(hl[:, 6], hl[:, 7]) * D / nu
+    gap = np.hypot(hh[:, 4] - hl[:, 4], hh[:, 5] - hl[:, 5]) / D - 1.0
+    passed = np.nonzero(hh[:, 4] > hl[:, 4])[0]
+    out = {"case": case["name"], "scheme": scheme, "kernel": kernel, "collision": collision,
+           "integrator": integrator, "internal_mass": internal_mass, "precision": precision,
+           "steps": int(n), "stopped_by": "wall" if status else "step budget",
+           "re_f_max_heavy": float(re_h.max()), "re_f_max_light": float(re_l.max()),
+           "min_gap_over_d": float(gap.min()), "min_gap_step": int(gap.argmin()) + 1,
+           "overtake_step": int(passed[0]) + 1 if len(passed) else None,
+           "mlups": case["nx"] * case["ny"] * n / wall / 1e6, "seconds": wall}
+    sim.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="study", required=True)
@@ -195,11 +249,25 @@ def main(argv=None):
     oc.add_argument("--kernel", nargs="+", default=["hat", "P4"])
     oc.add_argument("--collision", default="BGK")
     oc.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    wi = sub.add_parser("wake-interaction", help="Sec. 2.9.4 two-particle wake interaction")
+    wi.add_argument("--scheme", default="DF")
+    wi.add_argument("--kernel", default="P4")
+    wi.add_argument("--collision", default="BGK")
+    wi.add_argument("--integrator", nargs="+", default=["verlet"], choices=["verlet", "euler"])
+    wi.add_argument("--internal-mass", nargs="+", default=["feng", "none"], choices=["feng", "none"])
+    wi.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     args = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         print("studies: no HIP device", file=sys.stderr)
         return 1
+    if args.study == "wake-interaction":
+        for integ in args.integrator:
+            for im in args.internal_mass:
+                r = run_wake_interaction(args.scheme, args.kernel, args.collision, integ, im,
+                                         args.precision)
+                print(json.dumps(r), flush=True)
+        return 0
     if args.study == "inline-oscillation":
         for kernel in args.kernel:
             for scheme in args.scheme:

@@ -75,3 +75,17 @@ def test_paper_inline_oscillation_parameters():
     assert abs(b["amp"][0] + 5 * 80 / (2 * math.pi)) < 1e-12 and b["freq"] == 1 / 4000
     # velocity amplitude 2 pi f0 A = U_max
     assert abs(2 * math.pi * b["freq"] * abs(b["amp"][0]) - 0.1) < 1e-15
+
+
+def test_paper_wake_interaction_parameters():
+    """Sec. 2.9.4: 4001 x 801 over [0, 10] x [-1, 1] (spacing 0.0025), D = 80,
+    heavy 1.5 at (0.8, -0.13), light 1.25 at (1.2, 0.13), gravity +x,
+    tau = 0.59, Zou-He walls."""
+    c = ib_cases.paper_wake_interaction()
+    h, l = c["bodies"]
+    assert (c["nx"], c["ny"], c["diameter"], c["tau"]) == (4001, 801, 80.0, 0.59)
+    np.testing.assert_allclose([h["xc"], h["yc"], l["xc"], l["yc"]], [320, 348, 480, 452],
+                               rtol=0, atol=1e-9)
+    assert (h["density_ratio"], l["density_ratio"]) == (1.5, 1.25)
+    assert c["gravity"] == (2.156e-4, 0.0) and c["bc"] == (ib_cases.ZOU_HE,) * 4
+    assert abs(c["nu"] - 0.03) < 1e-15
