@@ -93,6 +93,7 @@ struct ib_lbm_batch {
   DevBuf d_cases, d_prefix, d_fprefix, d_slots;
   struct Group {
     int collision, first, count, ntiles, prefix_off, nface_blocks;
+    int general_zg;  // some case has a zero-gradient face other than the east one
   };
   std::vector<Group> groups;
   int nslots = 0;
@@ -372,6 +373,12 @@ EventPair take_pair(Timing &t) {
   return p;
 }
 
+// Zero-gradient faces other than the east one need the general copy rules
+// of the face kernel.
+static bool general_zero_gradient(const CaseDesc &c) {
+  return c.bc[0] == kZeroGradient || c.bc[2] == kZeroGradient || c.bc[3] == kZeroGradient;
+}
+
 static bool has_zou_he(const CaseDesc &c) {
   return c.bc[0] == kZouHe || c.bc[1] == kZouHe || c.bc[2] == kZouHe || c.bc[3] == kZouHe;
 }
@@ -393,7 +400,8 @@ ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
   }
   HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
                                         (const int32_t *)s->d_prefix.p + 2, 1,
-                                        face_blocks(s->cd.nx, s->cd.ny), -1, 1, stream));
+                                        face_blocks(s->cd.nx, s->cd.ny), -1, 1,
+                                        general_zero_gradient(s->cd), stream));
   if (has_zou_he(s->cd))
     HIPCHK(s, launch_zou_he(s->cd.precision, (const CaseDesc *)s->d_case.p, s->cd.nx, s->cd.ny, -1,
                             stream));
@@ -492,7 +500,8 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
     // face nodes lie outside the hold rectangle's reach (plan_split)
     HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
                                           (const int32_t *)s->d_prefix.p + 2, 1,
-                                          face_blocks(s->cd.nx, s->cd.ny), pa.cur, 0, s->lq));
+                                          face_blocks(s->cd.nx, s->cd.ny), pa.cur, 0,
+                                          general_zero_gradient(s->cd), s->lq));
     if (has_zou_he(s->cd))
       HIPCHK(s, launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, pa.cur, s->lq));
     // hold tiles of step i after the far tiles of step i-1 (the wait is
@@ -1273,7 +1282,7 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
   b->groups.clear();
   int maxws = 0;
   for (int col = 0; col < 3; col++) {
-    ib_lbm_batch::Group g{col, (int)cases.size(), 0, 0, (int)prefix.size(), 0};
+    ib_lbm_batch::Group g{col, (int)cases.size(), 0, 0, (int)prefix.size(), 0, 0};
     int tiles = 0, faces = 0;
     for (auto *s : b->sims) {
       if (s->cd.collision != col) continue;
@@ -1286,6 +1295,7 @@ static ib_lbm_status batch_tables(ib_lbm_batch *b) {
       cases.push_back(c);
       case_sims.push_back(s);
       g.count++;
+      g.general_zg |= general_zero_gradient(c) ? 1 : 0;
       for (auto &hb : s->bodies)
         if (hb.dev.ws_doubles * 8 <= ibm_max_lds_bytes()) maxws = std::max(maxws, hb.dev.ws_doubles);
     }
@@ -1342,7 +1352,7 @@ static ib_lbm_status batch_enqueue_step(ib_lbm_batch *b, hipStream_t stream) {
     BHIPCHK(b, launch_collide_stream_faces(b->precision, g.collision,
                                            (const CaseDesc *)b->d_cases.p + g.first,
                                            (const int32_t *)b->d_fprefix.p + g.prefix_off, g.count,
-                                           g.nface_blocks, -1, 1, stream));
+                                           g.nface_blocks, -1, 1, g.general_zg, stream));
   }
   BHIPCHK(b, launch_ibm_slots(b->precision, (const CaseDesc *)b->d_cases.p, (const IbmSlot *)b->d_slots.p,
                               b->nslots_fast, b->nslots, b->lds_bytes, b->spread_mode, stream));

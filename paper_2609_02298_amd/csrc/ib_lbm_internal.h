@@ -192,7 +192,7 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
 // case), nblocks the total; cur < 0 takes each case's lattice from its state.
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
                                        const int32_t *face_prefix, int ncases, int nblocks, int cur,
-                                       int force, hipStream_t stream);
+                                       int force, int general_zg, hipStream_t stream);
 // One part of a pipelined step: near = 1 the hold rectangle, 0 the other tiles.
 hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
                                       LaunchShape shape, const PipeArgs &pa, int near,

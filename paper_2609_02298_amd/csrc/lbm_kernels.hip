@@ -159,9 +159,8 @@ __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c
 __device__ __forceinline__ bool is_vel(int b) { return b == kVelParabolic || b == kVelUniform; }
 
 // Push population i of node (x,y) with value v, applying the face closures:
-//   periodic faces wrap; a link leaving through a zero-gradient or a Zou-He
-//   face is dropped (zou_he_kernel rebuilds the populations a Zou-He wall
-//   node is missing), and the populations entering a zero-gradient face are copies of
+//   periodic faces wrap; a link leaving through a zero-gradient face is
+//   dropped, and the populations entering a zero-gradient face are copies of
 //   those one node inside (column 1 for W, nx-2 for E, row 1 for S, ny-2 for
 //   N), written as duplicate stores of the pushes that land there (every
 //   such push comes from a face node); a corner of two zero-gradient faces
@@ -171,8 +170,13 @@ __device__ __forceinline__ bool is_vel(int b) { return b == kVelParabolic || b =
 //   through a velocity face it returns as opp(i) - 6 w_i rho0 (e_i . u_w),
 //   u_w evaluated at the link mid-point.  A link leaving through a wall and
 //   a velocity face is a wall link; among velocity faces the first of W, E,
-//   S, N is used.
-template <typename T>
+//   S, N is used.  A link leaving through a Zou-He face is dropped (it is
+//   neither a wall nor a velocity face here); zou_he_kernel rebuilds what
+//   the wall node is missing.  GZG: zero-gradient faces other than the east
+//   one are present (the general copy rules); otherwise only the east face
+//   can be zero-gradient, the usual outflow, which keeps the common case's
+//   code short.
+template <typename T, bool GZG>
 __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
   const int nx = c.nx, ny = c.ny;
   const uint32_t plane = (uint32_t)c.plane;
@@ -184,9 +188,13 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
   if (cn && c.bc[kFaceN] == kPeriodic) { yd -= ny; cn = false; }
   int j = i, xs = xd, ys = yd;
   if (cw || ce || cs || cn) {
-    if ((cw && c.bc[kFaceW] >= kZeroGradient) || (ce && c.bc[kFaceE] >= kZeroGradient) ||
-        (cs && c.bc[kFaceS] >= kZeroGradient) || (cn && c.bc[kFaceN] >= kZeroGradient))
-      return;
+    if (GZG) {
+      if ((cw && c.bc[kFaceW] == kZeroGradient) || (ce && c.bc[kFaceE] == kZeroGradient) ||
+          (cs && c.bc[kFaceS] == kZeroGradient) || (cn && c.bc[kFaceN] == kZeroGradient))
+        return;
+    } else {
+      if (ce && c.bc[kFaceE] == kZeroGradient) return;
+    }
     j = OPPI(i);
     xs = x;
     ys = y;
@@ -209,33 +217,41 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
       v = v - T(6) * wgt<T>(i) * T(c.rho0) * (T(c_ex[i]) * uw);
     }
   }
+  if (!GZG) {
+    dst[(uint32_t)j * plane + (uint32_t)ys * nx + xs] = v;
+    if (c.bc[kFaceE] == kZeroGradient && xs == nx - 2 && (j == 3 || j == 6 || j == 7))
+      dst[(uint32_t)j * plane + (uint32_t)ys * nx + (nx - 1)] = v;
+    return;
+  }
   T *d = dst + (uint32_t)j * plane;
   d[(uint32_t)ys * nx + xs] = v;
-  // zero-gradient copies: the column (W / E) and row (S / N) this value is
-  // copied to, and their corner when both apply
+  // the column (W / E) and row (S / N) this value is copied to, and their
+  // corner when both apply
   int xc = -1, yc = -1;
   if (c.bc[kFaceW] == kZeroGradient && xs == 1 && c_ex[j] > 0) xc = 0;
   if (c.bc[kFaceE] == kZeroGradient && xs == nx - 2 && c_ex[j] < 0) xc = nx - 1;
   if (c.bc[kFaceS] == kZeroGradient && ys == 1 && c_ey[j] > 0) yc = 0;
   if (c.bc[kFaceN] == kZeroGradient && ys == ny - 2 && c_ey[j] < 0) yc = ny - 1;
   if (xc >= 0) d[(uint32_t)ys * nx + xc] = v;
-  if (yc >= 0) d[(uint32_t)yc * nx + xs] = v;
-  if (xc >= 0 && yc >= 0) d[(uint32_t)yc * nx + xc] = v;
+  if (yc >= 0) {
+    d[(uint32_t)yc * nx + xs] = v;
+    if (xc >= 0) d[(uint32_t)yc * nx + xc] = v;
+  }
 }
 
 // All nine pushes of a face node.
-template <typename T>
+template <typename T, bool GZG>
 __device__ __forceinline__ void push_boundary9(const CaseDesc *c, T *dst, int x, int y, T f0, T f1,
                                             T f2, T f3, T f4, T f5, T f6, T f7, T f8) {
-  push_one<T>(*c, dst, x, y, 0, f0);
-  push_one<T>(*c, dst, x, y, 1, f1);
-  push_one<T>(*c, dst, x, y, 2, f2);
-  push_one<T>(*c, dst, x, y, 3, f3);
-  push_one<T>(*c, dst, x, y, 4, f4);
-  push_one<T>(*c, dst, x, y, 5, f5);
-  push_one<T>(*c, dst, x, y, 6, f6);
-  push_one<T>(*c, dst, x, y, 7, f7);
-  push_one<T>(*c, dst, x, y, 8, f8);
+  push_one<T, GZG>(*c, dst, x, y, 0, f0);
+  push_one<T, GZG>(*c, dst, x, y, 1, f1);
+  push_one<T, GZG>(*c, dst, x, y, 2, f2);
+  push_one<T, GZG>(*c, dst, x, y, 3, f3);
+  push_one<T, GZG>(*c, dst, x, y, 4, f4);
+  push_one<T, GZG>(*c, dst, x, y, 5, f5);
+  push_one<T, GZG>(*c, dst, x, y, 6, f6);
+  push_one<T, GZG>(*c, dst, x, y, 7, f7);
+  push_one<T, GZG>(*c, dst, x, y, 8, f8);
 }
 
 // The node's IB force if it lies in the force box (consumed: cleared once
@@ -382,7 +398,7 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
 // the face closures.  cur < 0: each case's current lattice from its state;
 // otherwise the lattice given (a pipelined step, whose case state the IB pass
 // may be updating).
-template <typename T, int COL>
+template <typename T, int COL, bool GZG>
 __global__ __launch_bounds__(kFaceBlock) void collide_stream_face_kernel(const CaseDesc *__restrict__ cases,
                                                                   const int32_t *__restrict__ face_prefix,
                                                                   int ncases, int nblocks, int cur_arg,
@@ -449,7 +465,7 @@ __global__ __launch_bounds__(kFaceBlock) void collide_stream_face_kernel(const C
   node_force<T>(frc, plane, p, x, y, box, box ? cs->fbox[0] : 0, box ? cs->fbox[1] : 0,
                 box ? cs->fbox[2] : -1, box ? cs->fbox[3] : -1, Fx, Fy);
   collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
-  push_boundary9<T>(cp, dst, x, y, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
+  push_boundary9<T, GZG>(cp, dst, x, y, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8]);
 }
 
 // No-slip walls with the on-node closure of Zou and He at zero wall
@@ -611,11 +627,15 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
 
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
                                        const int32_t *face_prefix, int ncases, int nblocks, int cur,
-                                       int force, hipStream_t stream) {
+                                       int force, int general_zg, hipStream_t stream) {
   if (nblocks <= 0) return hipSuccess;
-#define IBL_LAUNCH(T, C)                                                                   \
-  hipLaunchKernelGGL((collide_stream_face_kernel<T, C>), dim3(nblocks), dim3(kFaceBlock), 0, \
-                     stream, cases, face_prefix, ncases, nblocks, cur, force)
+#define IBL_LAUNCH(T, C)                                                                         \
+  if (general_zg)                                                                                \
+    hipLaunchKernelGGL((collide_stream_face_kernel<T, C, true>), dim3(nblocks), dim3(kFaceBlock), \
+                       0, stream, cases, face_prefix, ncases, nblocks, cur, force);              \
+  else                                                                                           \
+    hipLaunchKernelGGL((collide_stream_face_kernel<T, C, false>), dim3(nblocks), dim3(kFaceBlock), \
+                       0, stream, cases, face_prefix, ncases, nblocks, cur, force)
   IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
   return hipGetLastError();
