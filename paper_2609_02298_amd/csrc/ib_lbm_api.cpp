@@ -764,6 +764,23 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.ws_tab_hot = ws_tab_hot(b->scheme, nb, B.ns, B.max_nodes);
   B.pop_bytes = s->cfg.precision == IB_LBM_FP64 ? 8 : 4;
   B.ws_doubles = ws_doubles_for(b->scheme, nb, B.ns, B.max_rows, B.max_nodes, B.pop_bytes);
+  // MDF passes in marker space (the 1024-thread instance): markers k and l
+  // can share a stencil node only if they are less than ns apart in x and
+  // in y, so less than ns sqrt 2 apart; on the circle of radius R that
+  // bounds |l - k| by (n_b / pi) asin(ns sqrt 2 / (2 R)).  Used when the
+  // band is narrow and the workspace with it still fits in LDS.
+  B.mdf_band = 0;
+  if (b->scheme == IB_LBM_MDF && B.ns * std::sqrt(2.0) < 2.0 * B.radius) {
+    const int w = (int)std::floor(nb / M_PI * std::asin(B.ns * std::sqrt(2.0) / (2.0 * B.radius))) + 1;
+    // U at the markers is new space; the band (its half, B being
+    // symmetric) overlays the two node-velocity arrays
+    const int extra = 2 * nb;
+    if (w <= 12 && 2 * w + 1 < nb && nb * (w + 1) <= 2 * B.max_nodes &&
+        (B.ws_doubles + extra) * 8 <= ibm_max_lds_bytes()) {
+      B.mdf_band = w;
+      B.ws_doubles += extra;
+    }
+  }
   // gather window: a node within s*sqrt(2) of marker k lies within angle
   // 2 asin(s / sqrt(2 R (R - s sqrt 2))) of it
   {

@@ -69,7 +69,7 @@ struct BodyDesc {
   int32_t nb, scheme, kernel, mdf_iters;
   int32_t motion, internal_mass;
   int32_t integrator;   // free bodies: kVerlet (Eq. 23) or kEulerA1 (Eq. A1)
-  int32_t pad_integrator;
+  int32_t mdf_band;     // > 0: MDF passes in marker space with this band half-width
   int32_t ns;           // support width: 2 (hat) or 4 (P4)
   int32_t window;       // half width of the angular marker window of the gather
   int32_t max_rows, max_nodes;

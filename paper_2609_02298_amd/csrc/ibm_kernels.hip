@@ -150,6 +150,8 @@ struct WsLayout {
   double *rhoX, *Fx, *Fy, *Ftx, *Fty, *lam, *dlt;                // per-step, markers
   void *stage;                                                   // DFC populations
   double *nrho, *nux, *nuy, *nW;                                 // per-step, nodes
+  double *Ux, *Uy, *Bm;  // marker-space MDF: velocities at the markers, band matrix
+  int bw;                // its half-width (0: the passes run on the support nodes)
   int *lmin, *lmax, *rmin, *rmax, *cnt, *ncnt, *nfill;  // construction scratch (per-step area)
 };
 
@@ -174,11 +176,18 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   // null, so that every pointer provably stays in the workspace's address
   // space and the LDS instantiation uses LDS instructions)
   L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = L.nux = L.nuy = d;
+  L.Ux = L.Uy = L.Bm = d;
+  L.bw = 0;
   L.stage = (void *)d;
   if (B.scheme != kDFC) {
     L.rhoX = d; d += nb; L.Fx = d; d += nb; L.Fy = d; d += nb; L.Ftx = d; d += nb; L.Fty = d; d += nb;
     L.nrho = d; d += mn;
     L.nux = d; d += mn; L.nuy = d; d += mn;
+    L.bw = B.mdf_band;
+    L.Ux = d; d += B.mdf_band > 0 ? nb : 0; L.Uy = d; d += B.mdf_band > 0 ? nb : 0;
+    // the band overlays the node velocities, which the marker-space passes
+    // no longer need once U^(1) is interpolated
+    L.Bm = L.nux;
   } else {
     L.Ftx = d; d += nb; L.Fty = d; d += nb; L.lam = d; d += nb; L.dlt = d; d += 9 * nb;
     L.stage = (void *)d;  // 9 x mn populations of the stored type
@@ -717,6 +726,122 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
           L.Fty[k] = 2.0 * rX * (L.Udy[k] - Uy);
         }
       }
+    } else if (FAST && L.bw > 0) {
+      // MDF, Eq. (12)-(14), in marker space.  Interpolating the updated node
+      // velocities of Eq. (14) gives U^(n+1) = U^(n) + omega B F^(n) with
+      // B_kl = sum_x D_h(x - X_k) D_h(x - X_l) ds / (2 rho(x)), the same
+      // iteration up to rounding.  B couples only markers whose stencils
+      // share a node, so it is a band of half-width bw around the diagonal
+      // (marker indices wrap around the circle); it is built once per step
+      // and each pass is a short dot product per marker instead of an
+      // interpolation and a spreading over the support nodes.  The node
+      // velocities are not updated; the velocity after the passes, which the
+      // slip needs, is U at the markers.
+      const int N = B.mdf_iters;
+      const double om = B.omega_mdf;
+      const double tol = B.mdf_tol;
+      const bool adapt = tol > 0.0;
+      const int bw = L.bw;
+      // U^(1) and rho(X) from the force-free post-stream moments
+      for (int kk = tid; kk < LPM * nb; kk += nth) {
+        const int k = kk / LPM, h = kk % LPM;
+        const double rX = interp1<NS, LPM>(L, k, h, L.nrho);
+        double Ux, Uy;
+        interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
+        if (h == 0) {
+          L.rhoX[k] = rX;
+          L.Ux[k] = Ux;
+          L.Uy[k] = Uy;
+        }
+      }
+      __syncthreads();
+      for (int j = tid; j < S; j += nth) L.nrho[j] = ds / (2.0 * L.nrho[j]);
+      __syncthreads();
+      // B: one thread per (k, l = k + d), 0 <= d <= bw, over the nodes the
+      // two stencils share (stencil origins from the node coordinates),
+      // rows outer and columns inner.  B is symmetric: row k keeps its
+      // entries d = 0..bw, and B_(k, k-d) is read as entry d of row k - d.
+      // It overlays the node velocities, read for the last time above.
+      for (int t = tid; t < nb * (bw + 1); t += nth) {
+        const int k = t / (bw + 1), dd = t - k * (bw + 1);
+        const int l = k + dd < nb ? k + dd : k + dd - nb;
+        const int xyk = L.nxy[NROW(L, k, 0)], xyl = L.nxy[NROW(L, l, 0)];
+        const int dx = (xyl & 0xffff) - (xyk & 0xffff), dy = (xyl >> 16) - (xyk >> 16);
+        double b = 0.0;
+        if (dx > -ns && dx < ns && dy > -ns && dy < ns) {
+#pragma unroll
+          for (int jy = 0; jy < ns; jy++) {
+            const int ly = jy - dy;
+            if (ly < 0 || ly >= ns) continue;
+            const int r0 = NROW(L, k, jy);
+            double row = 0.0;
+#pragma unroll
+            for (int jx = 0; jx < ns; jx++) {
+              const int lx = jx - dx;
+              if (lx < 0 || lx >= ns) continue;
+              row += WX(L, k, jx) * WX(L, l, lx) * L.nrho[r0 + jx];
+            }
+            b += WY(L, k, jy) * WY(L, l, ly) * row;
+          }
+        }
+        L.Bm[k * (bw + 1) + dd] = b;
+      }
+      __syncthreads();
+      double rprev = 0.0;
+      for (int n = 1; n <= N; n++) {
+        // F^(n) = 2 rho(X) (U_d - U^(n)), relaxed: omega F^(n)
+        double rloc = 0.0;
+        for (int k = tid; k < nb; k += nth) {
+          const double ex = L.Udx[k] - L.Ux[k], ey = L.Udy[k] - L.Uy[k];
+          const double rX = L.rhoX[k];
+          const double Fx = 2.0 * rX * ex, Fy = 2.0 * rX * ey;
+          L.Fx[k] = om * Fx;
+          L.Fy[k] = om * Fy;
+          if (!adapt) {
+            L.Ftx[k] = (n == 1 ? 0.0 : L.Ftx[k]) + om * Fx;
+            L.Fty[k] = (n == 1 ? 0.0 : L.Fty[k]) + om * Fy;
+          }
+          rloc = fmax(rloc, sqrt(ex * ex + ey * ey));
+        }
+        if (!adapt && n == N) resmax = rloc;
+        if (adapt) {
+          rloc = wave_max(rloc);
+          if ((tid & 63) == 0) red[tid >> 6] = rloc;
+        }
+        __syncthreads();
+        if (adapt) {
+          double rn = red[0];
+          for (int w = 1; w < (nth >> 6); w++) rn = fmax(rn, red[w]);
+          resmax = rn;
+          if ((n > B.mdf_nmin && rn < tol) || (n > 1 && rn > 1.5 * rprev)) break;
+          rprev = rn;
+          if (tid == 0) ish[11] = n;
+          for (int k = tid; k < nb; k += nth) {
+            L.Ftx[k] = (n == 1 ? 0.0 : L.Ftx[k]) + L.Fx[k];
+            L.Fty[k] = (n == 1 ? 0.0 : L.Fty[k]) + L.Fy[k];
+          }
+        }
+        // U^(n+1) = U^(n) + B (omega F^(n)), the band split over the lanes
+        for (int kk = tid; kk < LPM * nb; kk += nth) {
+          const int k = kk / LPM, h = kk % LPM;
+          double sx = 0.0, sy = 0.0;
+          for (int d = h - bw; d <= bw; d += LPM) {
+            int l = k + d;
+            l = l < 0 ? l + nb : (l >= nb ? l - nb : l);
+            // B_(k,l) is entry |d| of the earlier row in circular order
+            const double bkl = d >= 0 ? L.Bm[k * (bw + 1) + d] : L.Bm[l * (bw + 1) - d];
+            sx += bkl * L.Fx[l];
+            sy += bkl * L.Fy[l];
+          }
+          sx = group_sum<LPM>(sx);
+          sy = group_sum<LPM>(sy);
+          if (h == 0) {
+            L.Ux[k] += sx;
+            L.Uy[k] += sy;
+          }
+        }
+        __syncthreads();
+      }
     } else {
       // MDF, Eq. (12)-(14): N passes of interpolation, force and spreading
       // back into the node velocities with relaxation omega_MDF; rho(X) is
@@ -1014,10 +1139,14 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   for (int kk = tid; kk < LPM * nb; kk += nth) {
     const int k = kk / LPM, h = kk % LPM;
     double Ux, Uy;
-    if (!FAST && B.scheme == kDFC)
+    if (!FAST && B.scheme == kDFC) {
       interp_packed_u<NS, LPM, T>(L, k, h, (const T *)L.stage, B.max_nodes, Ux, Uy);
-    else
+    } else if (FAST && L.bw > 0 && B.scheme == kMDF) {
+      Ux = L.Ux[k];  // the marker-space passes end with the post-IB velocity
+      Uy = L.Uy[k];
+    } else {
       interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
+    }
     // the marker's output row (X Y Udx Udy Fx Fy lambda ds), split over
     // the lanes of its group
     double *mo = B.markers_out + 8 * k;
