@@ -559,8 +559,9 @@ size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_
     // workspace upper estimate (P4), marker tables, history
     const double D = nb / M_PI;
     const int mr = (int)std::ceil(D) + 12, mn = (int)(8 * M_PI * D + 8 * mr + 64);
+    // (the MDF workspace may carry the marker-space velocities, 2 n_b)
     bytes += (size_t)(std::max(ws_doubles_for(kDFC, nb, 4, mr, mn, (int)elem),
-                               ws_doubles_for(kMDF, nb, 4, mr, mn, (int)elem)) +
+                               ws_doubles_for(kMDF, nb, 4, mr, mn, (int)elem) + 2 * nb) +
                       ws_tab_total(kMDF, nb, 4, mr, mn) + 2 * mn) * 8 +
              (size_t)nb * (8 + 1 + 2) * 8 +
              (size_t)hist * kHistCols * 8 + sizeof(BodyState) + sizeof(BodyDesc);
