@@ -7,6 +7,10 @@ Table B.8 (largest |C_d| of each period after the first two, averaged), of
 the body's whole IB force and of the outer fluid's force alone (the IB
 force less the inertia of the fluid inside the cylinder).
 
+``python -m paper_2609_02298_amd.studies settling [--density-ratio 1.5 1.1 1.01]``
+runs the single-particle sedimentation of Sec. 2.9.3 (1281 x 3841, Zou-He
+walls) and reports the largest settling speed over u_g (Table IV).
+
 ``python -m paper_2609_02298_amd.studies wake-interaction [--integrator verlet
 euler] [--internal-mass feng none]`` runs the two-particle channel of Sec.
 2.9.4 and reports each particle's peak Re_f = |v| D / nu (Table V), the
@@ -184,6 +188,58 @@ def run_inline_oscillation(scheme: str, kernel: str, collision: str = "BGK",
     return out
 
 
+def stop_reason(status: int) -> str:
+    """What ended a free-body run: the step budget, a support reaching a wall
+    or another body's support (range status), or a non-finite force."""
+    if status == 0:
+        return "step budget"
+    if status == -5:
+        return "wall or contact"
+    if status == -4:
+        return "diverged"
+    return f"status {status}"
+
+
+def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str = "BGK",
+                 precision: str = "fp64", log=sys.stderr) -> dict:
+    """One particle settling in the closed channel (Sec. 2.9.3) until its
+    support reaches the bottom wall or the step budget is spent: the largest
+    settling speed over u_g (the quantity of Table IV) and the step it
+    occurs at."""
+    import ib_cases
+    from . import ib_lbm as ib
+
+    case = ib_cases.paper_settling(density_ratio, scheme=scheme, kernel=kernel, collision=collision)
+    prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
+    nsteps = case["steps"]
+    sim = ib.Sim(case, precision=prec, history_capacity=nsteps)
+    t0 = time.perf_counter()
+    done, status = 0, 0
+    while done < nsteps:
+        sim.step(min(10000, nsteps - done))
+        sim.sync()
+        done = sim.steps_done
+        st = sim.forces(0, check=False)
+        status = st["status"]
+        print(f"  {case['name']} {scheme}/{kernel}/{collision} {precision}: {done} steps, "
+              f"y = {st['yc']:.1f}, v/u_g = {st['vy'] / case['u_g']:.4f}, "
+              f"{time.perf_counter() - t0:.1f} s", file=log, flush=True)
+        if status:
+            break
+    wall = time.perf_counter() - t0
+    n = sim.steps_done
+    h = sim.history(0, 1, n)
+    v = -h[:, 7] / case["u_g"]
+    out = {"case": case["name"], "density_ratio": density_ratio, "scheme": scheme,
+           "kernel": kernel, "collision": collision, "precision": precision, "steps": int(n),
+           "stopped_by": stop_reason(status),
+           "v_star_max": float(v.max()), "v_star_max_step": int(v.argmax()) + 1,
+           "y_final": float(h[-1, 5]), "mlups": case["nx"] * case["ny"] * n / wall / 1e6,
+           "seconds": wall}
+    sim.close()
+    return out
+
+
 def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="verlet",
                          internal_mass="feng", precision="fp64", log=sys.stderr) -> dict:
     """Two particles settling along +x (Sec. 2.9.4) until a support reaches
@@ -224,7 +280,7 @@ def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="
     passed = np.nonzero(hh[:, 4] > hl[:, 4])[0]
     out = {"case": case["name"], "scheme": scheme, "kernel": kernel, "collision": collision,
            "integrator": integrator, "internal_mass": internal_mass, "precision": precision,
-           "steps": int(n), "stopped_by": "wall" if status else "step budget",
+           "steps": int(n), "stopped_by": stop_reason(status),
            "re_f_max_heavy": float(re_h.max()), "re_f_max_light": float(re_l.max()),
            "min_gap_over_d": float(gap.min()), "min_gap_step": int(gap.argmin()) + 1,
            "overtake_step": int(passed[0]) + 1 if len(passed) else None,
@@ -249,6 +305,12 @@ def main(argv=None):
     oc.add_argument("--kernel", nargs="+", default=["hat", "P4"])
     oc.add_argument("--collision", default="BGK")
     oc.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    se = sub.add_parser("settling", help="Sec. 2.9.3 single-particle sedimentation")
+    se.add_argument("--density-ratio", type=float, nargs="+", default=[1.5, 1.1, 1.01])
+    se.add_argument("--scheme", nargs="+", default=["DF", "MDF", "DFC"])
+    se.add_argument("--kernel", nargs="+", default=["P4", "hat"])
+    se.add_argument("--collision", default="BGK")
+    se.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     wi = sub.add_parser("wake-interaction", help="Sec. 2.9.4 two-particle wake interaction")
     wi.add_argument("--scheme", default="DF")
     wi.add_argument("--kernel", default="P4")
@@ -261,6 +323,13 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("studies: no HIP device", file=sys.stderr)
         return 1
+    if args.study == "settling":
+        for rr in args.density_ratio:
+            for kernel in args.kernel:
+                for scheme in args.scheme:
+                    r = run_settling(rr, scheme, kernel, args.collision, args.precision)
+                    print(json.dumps(r), flush=True)
+        return 0
     if args.study == "wake-interaction":
         for integ in args.integrator:
             for im in args.internal_mass:

@@ -310,6 +310,28 @@ def test_zou_he_body_force_channel_closed_form(ny):
     assert np.abs(uy).max() < 1e-15
 
 
+@pytest.mark.parametrize("tau,grows", [(0.56, True), (0.5641, False)])
+def test_zou_he_bgk_wall_mode_stability_margin(tau, grows):
+    """Under BGK the rest-wall closure carries a wall-bound mode (about three
+    nodes long, in the first two rows off the wall) that grows below tau of
+    about 0.561 and is damped above it: a 1e-6 perturbation of a quiescent
+    periodic channel grows more than tenfold between steps 500 and 3000 at
+    tau = 0.56 and decays at 0.5641, the relaxation time of the density-
+    ratio-1.5 sedimentation under the Mach rule of Appendix A.1."""
+    nx, ny = 64, 32
+    s = oracle.OracleSim(_box(BGK, nx, ny, (PERIODIC, PERIODIC, ZOU_HE, ZOU_HE), tau=tau))
+    s.set_populations(random_populations(nx, ny, 3, amp=1e-6))
+    amp = []
+    for n in (500, 2500):
+        s.step(n)
+        _, ux, uy = s.fields()
+        amp.append(max(np.abs(ux).max(), np.abs(uy).max()))
+    if grows:
+        assert amp[1] > 10 * amp[0]
+    else:
+        assert amp[1] < amp[0]
+
+
 def test_zero_gradient_copy_and_bounce_back_rules():
     """After a step: entering populations at the outlet column equal those of
     the adjacent column; at a wall node the population entering from the

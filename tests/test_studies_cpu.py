@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import ib_cases
-from paper_2609_02298_amd.studies import flow_statistics
+from paper_2609_02298_amd.studies import flow_statistics, stop_reason
 
 
 def test_statistics_of_a_pure_shedding_signal():
@@ -89,3 +89,23 @@ def test_paper_wake_interaction_parameters():
     assert (h["density_ratio"], l["density_ratio"]) == (1.5, 1.25)
     assert c["gravity"] == (2.156e-4, 0.0) and c["bc"] == (ib_cases.ZOU_HE,) * 4
     assert abs(c["nu"] - 0.03) < 1e-15
+
+
+@pytest.mark.parametrize("ratio,tau_printed", [(1.5, 0.56), (1.1, 0.64), (1.01, 0.95), (1.25, 1.41)])
+def test_paper_settling_parameters(ratio, tau_printed):
+    """Sec. 2.9.3 on 1281 x 3841 (D = 160): the Mach rule of Appendix A.1 at
+    Ma = 0.064 gives each printed relaxation time to its two digits; the
+    gravity velocity scale u_g is Ma c_s for every density ratio."""
+    c = ib_cases.paper_settling(ratio)
+    assert (c["nx"], c["ny"]) == (1281, 3841)
+    assert round(c["tau"], 2) == tau_printed
+    assert math.isclose(c["u_g"] * math.sqrt(3.0), 0.064, rel_tol=1e-12)
+    b = c["bodies"][0]
+    assert (b["xc"], b["yc"], b["diameter"], b["n_markers"]) == (640.0, 2560.0, 160.0, 754)
+    assert c["bc"] == (ib_cases.ZOU_HE,) * 4 and c["gravity"][0] == 0.0 and c["gravity"][1] < 0
+
+
+def test_stop_reasons():
+    assert stop_reason(0) == "step budget"
+    assert stop_reason(-5) == "wall or contact"
+    assert stop_reason(-4) == "diverged"
