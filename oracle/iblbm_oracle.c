@@ -490,12 +490,17 @@ static void body_pre(or_sim *s, or_body *b, int64_t n) {
     b->dimx = st[10]; b->dimy = st[11];
   }
   place_markers(b);
-  /* Rigid-body marker velocity U_d = v + Omega x (X_k - X_c), with the
-   * half-step velocities (reading). */
+  /* Rigid-body marker velocity U_d = v + Omega x (X_k - X_c) (Sec. 2.7).
+   * Reading: under Velocity-Verlet v and Omega are the last full-step
+   * values v^n, Omega^n, still in b->vx, b->vy, b->om here; the half-step
+   * values only advance the position.  Otherwise the velocity just set. */
+  const int verlet = b->d.motion == OR_FREE && b->d.integrator != OR_EULER_A1;
+  const double ux = verlet ? b->vx : b->vhx, uy = verlet ? b->vy : b->vhy;
+  const double uo = verlet ? b->om : b->omh;
   for (int k = 0; k < b->nb; k++) {
     double rx = b->X[k] - b->xc, ry = b->Y[k] - b->yc;
-    b->Udx[k] = b->vhx - b->omh * ry;
-    b->Udy[k] = b->vhy + b->omh * rx;
+    b->Udx[k] = ux - uo * ry;
+    b->Udy[k] = uy + uo * rx;
   }
 }
 

@@ -391,7 +391,7 @@ __device__ __forceinline__ void interp2(const WsLayout &L, int k, int h, const d
 // Steps 2-3: markers, weights and the compact support.  Returns the node
 // count, or -1 with error flags in ish[0].
 __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B, const WsLayout &L, double xc,
-                            double yc, double vhx, double vhy, double omh, int ylo, int *ish,
+                            double yc, double udx, double udy, double udo, int ylo, int *ish,
                             int *wsum) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nb = B.nb, ns = B.ns, s = ns / 2, nx = c.nx, ny = c.ny;
@@ -404,8 +404,8 @@ __device__ __forceinline__ int build_tables(const CaseDesc &c, const BodyDesc &B
     const double Y = yc + B.radius * B.sin_t[k];
     L.X[k] = X;
     L.Y[k] = Y;
-    L.Udx[k] = vhx - omh * (Y - yc);
-    L.Udy[k] = vhy + omh * (X - xc);
+    L.Udx[k] = udx - udo * (Y - yc);
+    L.Udy[k] = udy + udo * (X - xc);
     const int ix0 = (int)floor(X) - (s - 1), iy0 = (int)floor(Y) - (s - 1);
     L.ix0[k] = ix0;
     L.iy0[k] = iy0;
@@ -605,6 +605,15 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       yc += vhy;
       omh = bs->om + bs->torque / (2.0 * B.Is);
     }
+    // Rigid-body velocity the markers are driven to: the one just set, but
+    // under Velocity-Verlet the last full-step v^n, Omega^n (the half-step
+    // values only advance the position).  With the half-step values the
+    // torque-only rotation feeds back on itself by a factor -I_f,eff/I_s per
+    // step, which exceeds one near neutral buoyancy.
+    const bool verlet = B.motion == kFree && B.integrator != kEulerA1;
+    bsh[13] = verlet ? bs->vx : vhx;
+    bsh[14] = verlet ? bs->vy : vhy;
+    bsh[15] = verlet ? bs->om : omh;
     bs->xc = xc; bs->yc = yc;
     bs->vhx = vhx; bs->vhy = vhy; bs->omh = omh;
     bsh[0] = xc; bsh[1] = yc; bsh[2] = vhx; bsh[3] = vhy; bsh[4] = omh;
@@ -653,7 +662,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     __syncthreads();
     S = L.S[0];
   } else {
-    S = build_tables(c, B, L, xc, yc, vhx, vhy, omh, ylo, ish, ish + 16);
+    S = build_tables(c, B, L, xc, yc, bsh[13], bsh[14], bsh[15], ylo, ish, ish + 16);
     if (S < 0) {
       if (tid == 0) {
         const int f = ish[3] | ish[0];

@@ -264,7 +264,7 @@ def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="
         sim.sync()
         done = sim.steps_done
         st = [sim.forces(b, check=False) for b in range(2)]
-        status = max(abs(x["status"]) for x in st)
+        status = next((x["status"] for x in st if x["status"]), 0)
         print(f"  {case['name']} {scheme}/{kernel}/{collision}/{integrator}/{internal_mass} "
               f"{precision}: {done} steps, x = {st[0]['xc']:.1f} / {st[1]['xc']:.1f}, "
               f"{time.perf_counter() - t0:.1f} s", file=log, flush=True)
