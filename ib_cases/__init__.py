@@ -202,9 +202,12 @@ def paper_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator
     nb = int(round(math.pi * D / (2.0 / 3.0)))
 
     def body(x, y, ratio):
-        return dict(xc=x / h, yc=(y + 1.0) / h, diameter=D, n_markers=nb, scheme=sch, kernel=ker,
-                    mdf_iters=5, motion=FREE, density_ratio=ratio, internal_mass=internal_mass,
-                    integrator=integrator)
+        b = dict(xc=x / h, yc=(y + 1.0) / h, diameter=D, n_markers=nb, scheme=sch, kernel=ker,
+                 mdf_iters=5, motion=FREE, density_ratio=ratio, internal_mass=internal_mass,
+                 integrator=integrator)
+        if sch == MDF:
+            b.update(ADAPTIVE_MDF)
+        return b
     tau = 0.59
     return dict(
         name=f"paper-wake-interaction-{nx}x{ny}", nx=nx, ny=ny, collision=col, tau=tau,
