@@ -270,6 +270,41 @@ def test_free_bodies(prec, pair, im, integ):
     assert fr["vy"] < 0
 
 
+@pytest.mark.parametrize("scheme,kernel,prec", [
+    ("DF", "P4", ib.FP64), ("MDF", "P4", ib.FP64), ("DFC", "P4", ib.FP64),
+    ("DF", "hat", ib.FP64), ("MDF", "hat", ib.FP64), ("DFC", "hat", ib.FP64),
+    ("MDF", "P4", ib.FP32_SHIFTED), ("DFC", "P4", ib.FP32_SHIFTED)])
+def test_settling_in_zou_he_box(scheme, kernel, prec):
+    """The single-particle sedimentation of Sec. 2.9.3 on a reduced lattice:
+    Zou-He walls on all four sides, BGK, Velocity-Verlet with the Feng
+    correction, marker spacing 2/3, the adaptive MDF of Sec. 2.5.2; a
+    density-ratio-1.5 disk of D = 20 released at rest, 60 steps.  The
+    fluid field is compared too, since the walls act on it."""
+    say(f"settling zou-he box {scheme}/{kernel} prec={prec}")
+    D = 20.0
+    body = dict(xc=48.0, yc=110.0, diameter=D, n_markers=int(round(math.pi * D / (2.0 / 3.0))),
+                scheme=ib_cases.SCHEMES[scheme], kernel=ib_cases.KERNELS[kernel], mdf_iters=5,
+                motion=ib.FREE, density_ratio=1.5, internal_mass=ib.IM_FENG, integrator=ib.VERLET)
+    if scheme == "MDF":
+        body.update(ib_cases.ADAPTIVE_MDF)
+    case = dict(nx=97, ny=161, collision=ib.BGK, tau=0.6, bc=(ib.ZOU_HE,) * 4, u_bc=0.0,
+                gravity=(0.0, -1e-4), bodies=[body])
+    sim, ref = make_pair(case, prec)
+    tol = F64_DRAG if prec == ib.FP64 else F32_DRAG
+    for t in (15, 60):
+        n = t - sim.steps_done
+        sim.step(n)
+        ref.step(n)
+        fs, fr = sim.forces(0), ref.body_state(0)
+        assert abs(fs["vy"] - fr["vy"]) < tol * abs(fr["vy"]), (t, fs["vy"], fr["vy"])
+        assert abs(fs["fy"] - fr["fy"]) < tol * abs(fr["fy"]), (t, fs["fy"], fr["fy"])
+        assert abs(fs["yc"] - fr["yc"]) < tol * abs(fr["yc"] - 110.0) + 1e-13, t
+        if scheme == "MDF":
+            assert fs["mdf_iters"] == fr["mdf_iters"], t
+    assert compare_fields(sim, ref, None) < (F64_FIELD if prec == ib.FP64 else F32_FIELD)
+    assert fr["vy"] < 0
+
+
 # ---------------------------------------------------------- full workloads
 @pytest.fixture(scope="module")
 def cylinder_channel_ref():
