@@ -148,12 +148,15 @@ def paper_inline_oscillation(scheme="MDF", kernel="P4", collision="BGK",
 
 
 def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
-                   steps=150000, mach=0.064) -> dict:
+                   steps=None, mach=0.064, height_d=24.0) -> dict:
     """The single-particle sedimentation of Sec. 2.9.3: a W x L = 2 x 6 cm
     channel on 1281 x 3841 nodes (spacing W / 1280), d = 0.25 cm (D = 160),
     released at rest at (1, 4) cm, g = 980 cm/s^2 along -y, nu = 0.01 cm^2/s
     (0.1 for the density-ratio-1.25 control), no-slip Zou-He walls on all
     four sides, Velocity-Verlet with the explicit-history correction.
+    height_d = 60 gives the extended channel of App. C.2 (1281 x 9601, the
+    particle again released 8 D below the top wall); the step budget
+    defaults to 6250 per D of height.
 
     The lattice viscosity follows the Mach rule of Appendix A.1: with
     Ar = (rho_r - 1) g d^3 / nu^2, nu_lat = Ma D / (3 Ar)^(1/2), tau =
@@ -163,8 +166,11 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
     gives tau = 0.5641.  The time step is dt = nu_lat dx^2 / nu and g_lat =
     g dt^2 / dx.  Marker spacing 2/3 (reading; 754 markers).  u_g =
     (|rho_r - 1| g_lat D)^(1/2) is the velocity scale of Table IV."""
-    nx, ny, D = 1281, 3841, 160.0
+    D = 160.0
+    nx, ny = 1281, int(round(height_d * D)) + 1
     dx, d, g_phys = 2.0 / 1280.0, 0.25, 980.0
+    if steps is None:
+        steps = int(round(6250 * height_d))
     nu = 0.1 if density_ratio == 1.25 else 0.01
     ar = abs(density_ratio - 1.0) * g_phys * d ** 3 / nu ** 2
     nu_lat = mach * D / math.sqrt(3.0 * ar)
@@ -174,7 +180,8 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
     sch = SCHEMES[scheme] if isinstance(scheme, str) else scheme
     ker = KERNELS[kernel] if isinstance(kernel, str) else kernel
     col = COLLISIONS[collision] if isinstance(collision, str) else collision
-    body = dict(xc=1.0 / dx, yc=4.0 / dx, diameter=D, n_markers=int(round(math.pi * D / (2.0 / 3.0))),
+    body = dict(xc=1.0 / dx, yc=(height_d - 8.0) * D, diameter=D,
+                n_markers=int(round(math.pi * D / (2.0 / 3.0))),
                 scheme=sch, kernel=ker, mdf_iters=5, motion=FREE, density_ratio=density_ratio,
                 internal_mass=IM_FENG, integrator=VERLET)
     if sch == MDF:
@@ -183,7 +190,7 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
         name=f"paper-settling-{nx}x{ny}-r{density_ratio}", nx=nx, ny=ny, collision=col, tau=tau,
         trt_magic=0.25, cm_s_q=1.2, cm_s_eps=1.4, rho0=1.0, bc=(ZOU_HE,) * 4, u_bc=0.0,
         gravity=(0.0, -g), diameter=D, u_g=math.sqrt(abs(density_ratio - 1.0) * g * D),
-        bodies=[body], steps=steps)
+        nu=nu_lat, bodies=[body], steps=steps)
 
 
 def paper_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator=VERLET,

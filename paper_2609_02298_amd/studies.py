@@ -201,17 +201,21 @@ def stop_reason(status: int) -> str:
 
 
 def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str = "BGK",
-                 precision: str = "fp64", log=sys.stderr) -> dict:
-    """One particle settling in the closed channel (Sec. 2.9.3) until its
-    support reaches the bottom wall or the step budget is spent: the largest
-    settling speed over u_g (the quantity of Table IV) and the step it
-    occurs at."""
+                 precision: str = "fp64", height_d: float = 24.0, log=sys.stderr) -> dict:
+    """One particle settling in the closed channel (Sec. 2.9.3; height_d = 60
+    for the extended channel of App. C.2) until its support reaches the
+    bottom wall or the step budget is spent.  Reports the largest settling
+    speed over u_g (the quantity of Table IV) and its step, and the peak
+    Re_f = |v_y| D / nu (Table C.1) over the whole fall and over the first
+    15.5 D of it (the standard channel's contact-safe horizon)."""
     import ib_cases
     from . import ib_lbm as ib
 
-    case = ib_cases.paper_settling(density_ratio, scheme=scheme, kernel=kernel, collision=collision)
+    case = ib_cases.paper_settling(density_ratio, scheme=scheme, kernel=kernel, collision=collision,
+                                   height_d=height_d)
     prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
     nsteps = case["steps"]
+    y0 = case["bodies"][0]["yc"]
     sim = ib.Sim(case, precision=prec, history_capacity=nsteps)
     t0 = time.perf_counter()
     done, status = 0, 0
@@ -230,10 +234,16 @@ def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str 
     n = sim.steps_done
     h = sim.history(0, 1, n)
     v = -h[:, 7] / case["u_g"]
+    fall = (y0 - h[:, 5]) / case["diameter"]
+    win = fall <= 15.5
+    to_re = case["u_g"] * case["diameter"] / case["nu"]
     out = {"case": case["name"], "density_ratio": density_ratio, "scheme": scheme,
            "kernel": kernel, "collision": collision, "precision": precision, "steps": int(n),
            "stopped_by": stop_reason(status),
            "v_star_max": float(v.max()), "v_star_max_step": int(v.argmax()) + 1,
+           "v_star_max_fall_15_5": float(v[win].max()),
+           "re_f_max": float(v.max() * to_re), "re_f_max_fall_15_5": float(v[win].max() * to_re),
+           "fall_final_d": float(fall[-1]),
            "y_final": float(h[-1, 5]), "mlups": case["nx"] * case["ny"] * n / wall / 1e6,
            "seconds": wall}
     sim.close()
@@ -311,6 +321,8 @@ def main(argv=None):
     se.add_argument("--kernel", nargs="+", default=["P4", "hat"])
     se.add_argument("--collision", default="BGK")
     se.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    se.add_argument("--height-d", type=float, default=24.0,
+                    help="channel height in diameters: 24 (Sec. 2.9.3) or 60 (App. C.2)")
     wi = sub.add_parser("wake-interaction", help="Sec. 2.9.4 two-particle wake interaction")
     wi.add_argument("--scheme", default="DF")
     wi.add_argument("--kernel", default="P4")
@@ -327,7 +339,7 @@ def main(argv=None):
         for rr in args.density_ratio:
             for kernel in args.kernel:
                 for scheme in args.scheme:
-                    r = run_settling(rr, scheme, kernel, args.collision, args.precision)
+                    r = run_settling(rr, scheme, kernel, args.collision, args.precision, args.height_d)
                     print(json.dumps(r), flush=True)
         return 0
     if args.study == "wake-interaction":

@@ -109,3 +109,15 @@ def test_stop_reasons():
     assert stop_reason(0) == "step budget"
     assert stop_reason(-5) == "wall or contact"
     assert stop_reason(-4) == "diverged"
+
+
+def test_paper_settling_extended_channel():
+    """App. C.2: the 60 D channel keeps the width, spacing and relaxation
+    time and releases the particle 8 D below the top wall, so that its
+    contact-safe fall is 51.5 D."""
+    std, tall = ib_cases.paper_settling(1.5), ib_cases.paper_settling(1.5, height_d=60.0)
+    assert (tall["nx"], tall["ny"]) == (1281, 9601)
+    assert tall["tau"] == std["tau"] and tall["u_g"] == std["u_g"] and tall["nu"] == std["nu"]
+    assert tall["bodies"][0]["yc"] == 8320.0 and std["bodies"][0]["yc"] == 2560.0
+    assert (tall["ny"] - 1 - tall["bodies"][0]["yc"]) / 160.0 == 8.0
+    assert tall["steps"] == 375000 and std["steps"] == 150000
