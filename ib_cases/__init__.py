@@ -148,7 +148,7 @@ def paper_inline_oscillation(scheme="MDF", kernel="P4", collision="BGK",
 
 
 def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
-                   steps=None, mach=0.064, height_d=24.0) -> dict:
+                   steps=None, mach=0.064, height_d=24.0, internal_mass=IM_FENG) -> dict:
     """The single-particle sedimentation of Sec. 2.9.3: a W x L = 2 x 6 cm
     channel on 1281 x 3841 nodes (spacing W / 1280), d = 0.25 cm (D = 160),
     released at rest at (1, 4) cm, g = 980 cm/s^2 along -y, nu = 0.01 cm^2/s
@@ -156,7 +156,8 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
     four sides, Velocity-Verlet with the explicit-history correction.
     height_d = 60 gives the extended channel of App. C.2 (1281 x 9601, the
     particle again released 8 D below the top wall); the step budget
-    defaults to 6250 per D of height.
+    defaults to 6250 per D of height.  internal_mass = IM_NONE is the
+    scheme-(A) arm of the ablation of Table B.5.
 
     The lattice viscosity follows the Mach rule of Appendix A.1: with
     Ar = (rho_r - 1) g d^3 / nu^2, nu_lat = Ma D / (3 Ar)^(1/2), tau =
@@ -183,7 +184,7 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
     body = dict(xc=1.0 / dx, yc=(height_d - 8.0) * D, diameter=D,
                 n_markers=int(round(math.pi * D / (2.0 / 3.0))),
                 scheme=sch, kernel=ker, mdf_iters=5, motion=FREE, density_ratio=density_ratio,
-                internal_mass=IM_FENG, integrator=VERLET)
+                internal_mass=internal_mass, integrator=VERLET)
     if sch == MDF:
         body.update(ADAPTIVE_MDF)
     return dict(

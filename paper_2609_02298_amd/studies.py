@@ -201,7 +201,8 @@ def stop_reason(status: int) -> str:
 
 
 def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str = "BGK",
-                 precision: str = "fp64", height_d: float = 24.0, log=sys.stderr) -> dict:
+                 precision: str = "fp64", height_d: float = 24.0, internal_mass: str = "feng",
+                 log=sys.stderr) -> dict:
     """One particle settling in the closed channel (Sec. 2.9.3; height_d = 60
     for the extended channel of App. C.2) until its support reaches the
     bottom wall or the step budget is spent.  Reports the largest settling
@@ -212,7 +213,8 @@ def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str 
     from . import ib_lbm as ib
 
     case = ib_cases.paper_settling(density_ratio, scheme=scheme, kernel=kernel, collision=collision,
-                                   height_d=height_d)
+                                   height_d=height_d,
+                                   internal_mass=ib.IM_FENG if internal_mass == "feng" else ib.IM_NONE)
     prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
     nsteps = case["steps"]
     y0 = case["bodies"][0]["yc"]
@@ -238,8 +240,8 @@ def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str 
     win = fall <= 15.5
     to_re = case["u_g"] * case["diameter"] / case["nu"]
     out = {"case": case["name"], "density_ratio": density_ratio, "scheme": scheme,
-           "kernel": kernel, "collision": collision, "precision": precision, "steps": int(n),
-           "stopped_by": stop_reason(status),
+           "kernel": kernel, "collision": collision, "precision": precision,
+           "internal_mass": internal_mass, "steps": int(n), "stopped_by": stop_reason(status),
            "v_star_max": float(v.max()), "v_star_max_step": int(v.argmax()) + 1,
            "v_star_max_fall_15_5": float(v[win].max()),
            "re_f_max": float(v.max() * to_re), "re_f_max_fall_15_5": float(v[win].max() * to_re),
@@ -323,6 +325,7 @@ def main(argv=None):
     se.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     se.add_argument("--height-d", type=float, default=24.0,
                     help="channel height in diameters: 24 (Sec. 2.9.3) or 60 (App. C.2)")
+    se.add_argument("--internal-mass", nargs="+", default=["feng"], choices=["feng", "none"])
     wi = sub.add_parser("wake-interaction", help="Sec. 2.9.4 two-particle wake interaction")
     wi.add_argument("--scheme", default="DF")
     wi.add_argument("--kernel", default="P4")
@@ -339,8 +342,10 @@ def main(argv=None):
         for rr in args.density_ratio:
             for kernel in args.kernel:
                 for scheme in args.scheme:
-                    r = run_settling(rr, scheme, kernel, args.collision, args.precision, args.height_d)
-                    print(json.dumps(r), flush=True)
+                    for im in args.internal_mass:
+                        r = run_settling(rr, scheme, kernel, args.collision, args.precision,
+                                         args.height_d, im)
+                        print(json.dumps(r), flush=True)
         return 0
     if args.study == "wake-interaction":
         for integ in args.integrator:

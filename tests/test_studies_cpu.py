@@ -121,3 +121,14 @@ def test_paper_settling_extended_channel():
     assert tall["bodies"][0]["yc"] == 8320.0 and std["bodies"][0]["yc"] == 2560.0
     assert (tall["ny"] - 1 - tall["bodies"][0]["yc"]) / 160.0 == 8.0
     assert tall["steps"] == 375000 and std["steps"] == 150000
+
+
+def test_paper_settling_internal_mass_arm():
+    """Table B.5: the scheme-(A) arm differs from the baseline only in the
+    internal-mass treatment of the body."""
+    a = ib_cases.paper_settling(1.5, internal_mass=ib_cases.IM_NONE)
+    b = ib_cases.paper_settling(1.5)
+    assert a["bodies"][0]["internal_mass"] == ib_cases.IM_NONE
+    assert b["bodies"][0]["internal_mass"] == ib_cases.IM_FENG
+    a["bodies"][0]["internal_mass"] = ib_cases.IM_FENG
+    assert a == b
