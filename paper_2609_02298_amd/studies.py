@@ -38,6 +38,7 @@ library returns; the flow is computed by the HIP kernels.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import sys
 import time
@@ -252,6 +253,31 @@ def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str 
     return out
 
 
+def acceleration_proxy(vx, vy, u_g: float, D: float, cadence: int) -> np.ndarray:
+    """Particle-bound acceleration proxy of Sec. 2.8, |a*| = |dv*/dt*| with
+    v* = v / u_g and t* = t u_g / D, from velocity records stored every
+    `cadence` steps.  Central differences inside the record, one-sided ones
+    at its ends (reading: the paper defines the quantity, not the
+    difference formula)."""
+    v = np.stack([np.asarray(vx, float), np.asarray(vy, float)]) / u_g
+    d = np.gradient(v, cadence * u_g / D, axis=1)
+    return np.hypot(d[0], d[1])
+
+
+def phase_peaks(a_heavy, a_light, t_star, t_closest: float, t_exchange: float) -> dict:
+    """Largest |a*| of each particle before the closest approach and after
+    the role exchange (the phases of Sec. 5.2.3 / Table C.4), and the
+    light-over-heavy ratios of those peaks with their post/pre contrast."""
+    t_star = np.asarray(t_star, float)
+    pre, post = t_star < t_closest, t_star > t_exchange
+    out = {"pre_heavy": float(np.max(a_heavy[pre])), "pre_light": float(np.max(a_light[pre])),
+           "post_heavy": float(np.max(a_heavy[post])), "post_light": float(np.max(a_light[post]))}
+    out["ratio_pre"] = out["pre_light"] / out["pre_heavy"]
+    out["ratio_post"] = out["post_light"] / out["post_heavy"]
+    out["contrast"] = out["ratio_post"] / out["ratio_pre"]
+    return out
+
+
 def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="verlet",
                          internal_mass="feng", precision="fp64", log=sys.stderr) -> dict:
     """Two particles settling along +x (Sec. 2.9.4) until a support reaches
@@ -297,6 +323,21 @@ def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="
            "min_gap_over_d": float(gap.min()), "min_gap_step": int(gap.argmin()) + 1,
            "overtake_step": int(passed[0]) + 1 if len(passed) else None,
            "mlups": case["nx"] * case["ny"] * n / wall / 1e6, "seconds": wall}
+    if len(passed):
+        # acceleration proxy on records stored every 500 and 100 steps (the
+        # first at the cadence itself), each particle on its own u_g; t* on
+        # the heavy particle's, as are the phase boundaries
+        g = float(np.hypot(*case["gravity"]))
+        ug_h = math.sqrt((case["bodies"][0]["density_ratio"] - 1.0) * g * D)
+        ug_l = math.sqrt((case["bodies"][1]["density_ratio"] - 1.0) * g * D)
+        t_close = (int(gap.argmin()) + 1) * ug_h / D
+        t_exch = (int(passed[0]) + 1) * ug_h / D
+        out["t_star_closest"], out["t_star_exchange"] = t_close, t_exch
+        for cad in (500, 100):
+            idx = np.arange(cad - 1, n, cad)
+            ah = acceleration_proxy(hh[idx, 6], hh[idx, 7], ug_h, D, cad)
+            al = acceleration_proxy(hl[idx, 6], hl[idx, 7], ug_l, D, cad)
+            out[f"a_star_{cad}"] = phase_peaks(ah, al, (idx + 1) * ug_h / D, t_close, t_exch)
     sim.close()
     return out
 

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import ib_cases
-from paper_2609_02298_amd.studies import flow_statistics, stop_reason
+from paper_2609_02298_amd.studies import (acceleration_proxy, flow_statistics, phase_peaks,
+                                          stop_reason)
 
 
 def test_statistics_of_a_pure_shedding_signal():
@@ -132,3 +133,31 @@ def test_paper_settling_internal_mass_arm():
     assert b["bodies"][0]["internal_mass"] == ib_cases.IM_FENG
     a["bodies"][0]["internal_mass"] = ib_cases.IM_FENG
     assert a == b
+
+
+def test_acceleration_proxy_of_a_uniform_acceleration():
+    """v = a t along a fixed direction: |dv*/dt*| = |a| D / u_g^2 at every
+    record, ends included (Sec. 2.8)."""
+    a, u_g, D, cad = (3e-7, -4e-7), 0.09, 80.0, 500
+    t = cad * np.arange(1, 60)
+    out = acceleration_proxy(a[0] * t, a[1] * t, u_g, D, cad)
+    np.testing.assert_allclose(out, math.hypot(*a) * D / u_g ** 2, rtol=1e-12)
+
+
+def test_acceleration_proxy_of_a_circular_motion():
+    """v = V (cos w t, sin w t): |dv/dt| = V w, up to the central difference's
+    sin(w h)/(w h) inside the record."""
+    V, w, u_g, D, cad = 0.05, 2e-4, 0.1, 40.0, 100
+    t = cad * np.arange(1, 200)
+    out = acceleration_proxy(V * np.cos(w * t), V * np.sin(w * t), u_g, D, cad)
+    h = w * cad
+    np.testing.assert_allclose(out[1:-1], V * w * D / u_g ** 2 * math.sin(h) / h, rtol=1e-10)
+
+
+def test_phase_peaks():
+    t = np.arange(10.0)
+    ah = np.array([1, 2, 1, 1, 9, 9, 1, 4, 1, 1.0])
+    al = np.array([3, 1, 1, 1, 9, 9, 1, 1, 8, 1.0])
+    p = phase_peaks(ah, al, t, t_closest=3.5, t_exchange=5.5)
+    assert (p["pre_heavy"], p["pre_light"], p["post_heavy"], p["post_light"]) == (2, 3, 4, 8)
+    assert p["ratio_pre"] == 1.5 and p["ratio_post"] == 2.0 and math.isclose(p["contrast"], 4 / 3)
