@@ -195,15 +195,18 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
 
 
 def paper_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator=VERLET,
-                           internal_mass=IM_FENG, steps=60000) -> dict:
+                           internal_mass=IM_FENG, steps=60000, length_d=50.0) -> dict:
     """The two-particle wake-interaction channel of Sec. 2.9.4: Omega =
     [0, 10] x [-1, 1] on 4001 x 801 nodes (spacing 0.0025), d = 0.2 (D = 80),
     heavy particle (density ratio 1.5) at (0.8, -0.13) and light one (1.25)
     at (1.2, 0.13), gravity g = 2.156e-4 along +x, tau = 0.59, no-slip
     Zou-He walls on all four sides (Sec. 2.9.3); marker spacing 2/3
     (reading; 377 markers).  The reference baseline of Table V is DF,
-    Peskin 4-point, Velocity-Verlet with the explicit-history correction."""
-    nx, ny, h, D = 4001, 801, 0.0025, 80.0
+    Peskin 4-point, Velocity-Verlet with the explicit-history correction.
+    length_d = 60 gives the extended channel of App. C.2 / Table C.3
+    (4801 x 801, same spacing and starting positions)."""
+    ny, h, D = 801, 0.0025, 80.0
+    nx = int(round(length_d * D)) + 1
     sch = SCHEMES[scheme] if isinstance(scheme, str) else scheme
     ker = KERNELS[kernel] if isinstance(kernel, str) else kernel
     col = COLLISIONS[collision] if isinstance(collision, str) else collision

@@ -279,7 +279,8 @@ def phase_peaks(a_heavy, a_light, t_star, t_closest: float, t_exchange: float) -
 
 
 def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="verlet",
-                         internal_mass="feng", precision="fp64", log=sys.stderr) -> dict:
+                         internal_mass="feng", precision="fp64", length_d: float = 50.0,
+                         log=sys.stderr) -> dict:
     """Two particles settling along +x (Sec. 2.9.4) until a support reaches
     the end wall or the step budget is spent: the peak Reynolds number of
     each on the fluid-density basis Re_f = |v| D / nu (the quantity of
@@ -291,7 +292,7 @@ def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="
     case = ib_cases.paper_wake_interaction(
         scheme=scheme, kernel=kernel, collision=collision,
         integrator=ib.EULER_A1 if integrator == "euler" else ib.VERLET,
-        internal_mass=ib.IM_FENG if internal_mass == "feng" else ib.IM_NONE)
+        internal_mass=ib.IM_FENG if internal_mass == "feng" else ib.IM_NONE, length_d=length_d)
     prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
     nsteps = case["steps"]
     sim = ib.Sim(case, precision=prec, history_capacity=nsteps)
@@ -368,12 +369,14 @@ def main(argv=None):
                     help="channel height in diameters: 24 (Sec. 2.9.3) or 60 (App. C.2)")
     se.add_argument("--internal-mass", nargs="+", default=["feng"], choices=["feng", "none"])
     wi = sub.add_parser("wake-interaction", help="Sec. 2.9.4 two-particle wake interaction")
-    wi.add_argument("--scheme", default="DF")
+    wi.add_argument("--scheme", nargs="+", default=["DF"])
     wi.add_argument("--kernel", default="P4")
     wi.add_argument("--collision", default="BGK")
     wi.add_argument("--integrator", nargs="+", default=["verlet"], choices=["verlet", "euler"])
     wi.add_argument("--internal-mass", nargs="+", default=["feng", "none"], choices=["feng", "none"])
     wi.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    wi.add_argument("--length-d", type=float, default=50.0,
+                    help="channel length in diameters: 50 (Sec. 2.9.4) or 60 (Table C.3)")
     args = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
@@ -389,11 +392,12 @@ def main(argv=None):
                         print(json.dumps(r), flush=True)
         return 0
     if args.study == "wake-interaction":
-        for integ in args.integrator:
-            for im in args.internal_mass:
-                r = run_wake_interaction(args.scheme, args.kernel, args.collision, integ, im,
-                                         args.precision)
-                print(json.dumps(r), flush=True)
+        for scheme in args.scheme:
+            for integ in args.integrator:
+                for im in args.internal_mass:
+                    r = run_wake_interaction(scheme, args.kernel, args.collision, integ, im,
+                                             args.precision, args.length_d)
+                    print(json.dumps(r), flush=True)
         return 0
     if args.study == "inline-oscillation":
         for kernel in args.kernel:

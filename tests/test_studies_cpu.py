@@ -161,3 +161,12 @@ def test_phase_peaks():
     p = phase_peaks(ah, al, t, t_closest=3.5, t_exchange=5.5)
     assert (p["pre_heavy"], p["pre_light"], p["post_heavy"], p["post_light"]) == (2, 3, 4, 8)
     assert p["ratio_pre"] == 1.5 and p["ratio_post"] == 2.0 and math.isclose(p["contrast"], 4 / 3)
+
+
+def test_paper_wake_interaction_extended_channel():
+    """Table C.3: the 60 D channel lengthens the domain at the same spacing,
+    with the particles at the same starting nodes."""
+    std, ext = ib_cases.paper_wake_interaction(), ib_cases.paper_wake_interaction(length_d=60.0)
+    assert (std["nx"], std["ny"]) == (4001, 801) and (ext["nx"], ext["ny"]) == (4801, 801)
+    assert [(b["xc"], b["yc"]) for b in ext["bodies"]] == [(b["xc"], b["yc"]) for b in std["bodies"]]
+    assert ext["tau"] == std["tau"] and ext["gravity"] == std["gravity"]
