@@ -148,7 +148,8 @@ def paper_inline_oscillation(scheme="MDF", kernel="P4", collision="BGK",
 
 
 def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
-                   steps=None, mach=0.064, height_d=24.0, internal_mass=IM_FENG) -> dict:
+                   steps=None, mach=0.064, height_d=24.0, internal_mass=IM_FENG,
+                   diameter=160.0) -> dict:
     """The single-particle sedimentation of Sec. 2.9.3: a W x L = 2 x 6 cm
     channel on 1281 x 3841 nodes (spacing W / 1280), d = 0.25 cm (D = 160),
     released at rest at (1, 4) cm, g = 980 cm/s^2 along -y, nu = 0.01 cm^2/s
@@ -157,7 +158,9 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
     height_d = 60 gives the extended channel of App. C.2 (1281 x 9601, the
     particle again released 8 D below the top wall); the step budget
     defaults to 6250 per D of height.  internal_mass = IM_NONE is the
-    scheme-(A) arm of the ablation of Table B.5.
+    scheme-(A) arm of the ablation of Table B.5.  diameter = 240 is the
+    refined grid of App. C.5 (1921 x 5761 nodes; the Mach rule then gives
+    tau = 0.596).
 
     The lattice viscosity follows the Mach rule of Appendix A.1: with
     Ar = (rho_r - 1) g d^3 / nu^2, nu_lat = Ma D / (3 Ar)^(1/2), tau =
@@ -167,9 +170,10 @@ def paper_settling(density_ratio=1.5, scheme="DF", kernel="P4", collision="BGK",
     gives tau = 0.5641.  The time step is dt = nu_lat dx^2 / nu and g_lat =
     g dt^2 / dx.  Marker spacing 2/3 (reading; 754 markers).  u_g =
     (|rho_r - 1| g_lat D)^(1/2) is the velocity scale of Table IV."""
-    D = 160.0
-    nx, ny = 1281, int(round(height_d * D)) + 1
-    dx, d, g_phys = 2.0 / 1280.0, 0.25, 980.0
+    D = float(diameter)
+    nx, ny = int(round(8.0 * D)) + 1, int(round(height_d * D)) + 1
+    d, g_phys = 0.25, 980.0
+    dx = d / D
     if steps is None:
         steps = int(round(6250 * height_d))
     nu = 0.1 if density_ratio == 1.25 else 0.01

@@ -749,12 +749,15 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
       return IB_LBM_E_RANGE;
     }
   }
-  // workspace sizing over sub-lattice positions of the centre
+  // workspace sizing over sub-lattice positions of the centre, placed so
+  // that every stencil lies at positive coordinates (support_count marks an
+  // empty row with a negative column)
+  const double c0 = std::ceil(B.radius) + 2 * B.ns + 8;
   int maxn = 0, maxr = 0;
   for (int a = 0; a < 4; a++)
     for (int q = 0; q < 4; q++) {
       int rows = 0;
-      const int n = support_count(100.0 + 0.25 * a + 0.0625, 100.0 + 0.25 * q + 0.125, B.radius, nb,
+      const int n = support_count(c0 + 0.25 * a + 0.0625, c0 + 0.25 * q + 0.125, B.radius, nb,
                                   B.ns, ct, stb, &rows);
       maxn = std::max(maxn, n);
       maxr = std::max(maxr, rows);
@@ -907,7 +910,11 @@ ib_lbm_status ib_lbm_forces(ib_lbm_sim *s, int32_t body_id, ib_lbm_body_state *o
     return IB_LBM_E_DIVERGED;
   }
   if (b.flags & (IB_LBM_FLAG_RANGE | IB_LBM_FLAG_OVERLAP | kFlagCapacity)) {
-    set_err(&s->err, "body %d left the lattice or met another body (flags %d)", body_id, b.flags);
+    if (b.flags & kFlagCapacity)
+      set_err(&s->err, "body %d outgrew its support tables (flags %d): fewer markers or a smaller body",
+              body_id, b.flags);
+    else
+      set_err(&s->err, "body %d left the lattice or met another body (flags %d)", body_id, b.flags);
     return IB_LBM_E_RANGE;
   }
   return IB_LBM_OK;

@@ -203,7 +203,7 @@ def stop_reason(status: int) -> str:
 
 def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str = "BGK",
                  precision: str = "fp64", height_d: float = 24.0, internal_mass: str = "feng",
-                 log=sys.stderr) -> dict:
+                 diameter: float = 160.0, log=sys.stderr) -> dict:
     """One particle settling in the closed channel (Sec. 2.9.3; height_d = 60
     for the extended channel of App. C.2) until its support reaches the
     bottom wall or the step budget is spent.  Reports the largest settling
@@ -214,7 +214,7 @@ def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str 
     from . import ib_lbm as ib
 
     case = ib_cases.paper_settling(density_ratio, scheme=scheme, kernel=kernel, collision=collision,
-                                   height_d=height_d,
+                                   height_d=height_d, diameter=diameter,
                                    internal_mass=ib.IM_FENG if internal_mass == "feng" else ib.IM_NONE)
     prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
     nsteps = case["steps"]
@@ -235,6 +235,13 @@ def run_settling(density_ratio: float, scheme: str, kernel: str, collision: str 
             break
     wall = time.perf_counter() - t0
     n = sim.steps_done
+    if n == 0:
+        out = {"case": case["name"], "density_ratio": density_ratio, "scheme": scheme,
+               "kernel": kernel, "collision": collision, "precision": precision,
+               "internal_mass": internal_mass, "steps": 0, "stopped_by": stop_reason(status),
+               "flags": int(st["flags"])}
+        sim.close()
+        return out
     h = sim.history(0, 1, n)
     v = -h[:, 7] / case["u_g"]
     fall = (y0 - h[:, 5]) / case["diameter"]
@@ -368,6 +375,8 @@ def main(argv=None):
     se.add_argument("--height-d", type=float, default=24.0,
                     help="channel height in diameters: 24 (Sec. 2.9.3) or 60 (App. C.2)")
     se.add_argument("--internal-mass", nargs="+", default=["feng"], choices=["feng", "none"])
+    se.add_argument("--diameter", type=float, default=160.0,
+                    help="particle diameter in nodes: 160 (Sec. 2.9.3) or 240 (App. C.5)")
     wi = sub.add_parser("wake-interaction", help="Sec. 2.9.4 two-particle wake interaction")
     wi.add_argument("--scheme", nargs="+", default=["DF"])
     wi.add_argument("--kernel", default="P4")
@@ -388,7 +397,7 @@ def main(argv=None):
                 for scheme in args.scheme:
                     for im in args.internal_mass:
                         r = run_settling(rr, scheme, kernel, args.collision, args.precision,
-                                         args.height_d, im)
+                                         args.height_d, im, args.diameter)
                         print(json.dumps(r), flush=True)
         return 0
     if args.study == "wake-interaction":

@@ -170,3 +170,14 @@ def test_paper_wake_interaction_extended_channel():
     assert (std["nx"], std["ny"]) == (4001, 801) and (ext["nx"], ext["ny"]) == (4801, 801)
     assert [(b["xc"], b["yc"]) for b in ext["bodies"]] == [(b["xc"], b["yc"]) for b in std["bodies"]]
     assert ext["tau"] == std["tau"] and ext["gravity"] == std["gravity"]
+
+
+def test_paper_settling_refined_grid():
+    """App. C.5: D = 240 on 1921 x 5761 nodes, the release point and the
+    gravity velocity scale unchanged in physical and Mach terms."""
+    c = ib_cases.paper_settling(1.5, diameter=240.0)
+    assert (c["nx"], c["ny"]) == (1921, 5761)
+    b = c["bodies"][0]
+    assert (b["xc"], b["yc"], b["n_markers"]) == (960.0, 3840.0, 1131)
+    assert round(c["tau"], 3) == 0.596
+    assert math.isclose(c["u_g"] * math.sqrt(3.0), 0.064, rel_tol=1e-12)
