@@ -45,6 +45,13 @@ COLLISIONS = {"BGK": BGK, "TRT": TRT, "CMMRT": CMMRT}
 ST0_RE100 = 0.165
 
 
+# Largest relaxation time given to CM-MRT sweep cases.  With the paper's
+# higher-order rates s_q = 1.2, s_eps = 1.4 (Eq. 5) the operator linearised
+# about rest amplifies a short-wave mode (k_x = pi) once tau exceeds about
+# 1.79; 1.75 keeps every mode on or inside the unit circle.
+CMMRT_TAU_MAX = 1.75
+
+
 # The adaptive MDF of the paper's runs (Sec. 2.5.2, App. A.2): N in [5, 20],
 # L-infinity slip-residual tolerance 1e-4.
 ADAPTIVE_MDF = dict(mdf_nmin=5, mdf_iters=20, mdf_tol=1e-4)
@@ -277,13 +284,19 @@ def sedimentation(pair: bool = False, steps=200000, nx=400, ny=2000, diameter=20
 
 
 def sweep_cases(n_cases: int = 256, seed: int = 0, rate: float | None = None,
-                u_max: float = 0.1, tau_min: float = 0.515) -> list[dict]:
+                u_max: float = 0.1, tau_min: float = 0.515,
+                tau_max_cmmrt: float = CMMRT_TAU_MAX) -> list[dict]:
     """Parameter-sweep cases: width w = round(exp U(ln 128, ln 2048)) = ny,
     aspect U(2,4), nx = round(a w), D = w/10, Re ~ U(20, 200), scheme x kernel
     x collision uniform over the 18 combinations, steps ~ U{2000..20000};
     fixed-cylinder channel faces with u_max = 0.1; Re capped so that
-    tau >= tau_min.  Arrival times are cumulative Exponential(1/rate) draws
-    (all zero when rate is None: burst arrival)."""
+    tau >= tau_min, and for CM-MRT cases raised so that tau <= tau_max_cmmrt
+    (the central-moment operator with s_q = 1.2, s_eps = 1.4 amplifies a
+    short-wave mode above tau ~ 1.79).  Every capped case records
+    re_capped = True and the reason in cap.  Arrival times are cumulative
+    Exponential(1/rate) draws (all zero when rate is None: burst arrival).
+    The caps change no draw, so the other cases are those of the uncapped
+    sweep."""
     rng = np.random.default_rng(seed)
     combos = [(s, k, c) for s in (DF, MDF, DFC) for k in (HAT, PESKIN4) for c in (BGK, TRT, CMMRT)]
     cases = []
@@ -297,18 +310,22 @@ def sweep_cases(n_cases: int = 256, seed: int = 0, rate: float | None = None,
         s, k, c = combos[int(rng.integers(0, len(combos)))]
         steps = int(rng.integers(2000, 20001))
         tau = tau_from(u_max, D, re)
-        capped = False
+        capped, cap = False, None
         if tau < tau_min:
             re = 3.0 * u_max * D / (tau_min - 0.5)
             tau = tau_from(u_max, D, re)
-            capped = True
+            capped, cap = True, "tau_min"
+        elif c == CMMRT and tau > tau_max_cmmrt:
+            re = 3.0 * u_max * D / (tau_max_cmmrt - 0.5)
+            tau = tau_from(u_max, D, re)
+            capped, cap = True, "cmmrt_tau_max"
         if rate is not None:
             t += rng.exponential(1.0 / rate)
         cases.append(dict(
             name=f"sweep-{seed}-{i}", nx=nx, ny=w, collision=c, tau=tau, trt_magic=0.25,
             cm_s_q=1.2, cm_s_eps=1.4, rho0=1.0,
             bc=(VEL_PARABOLIC, ZERO_GRADIENT, BOUNCE_BACK, BOUNCE_BACK), u_bc=u_max, u_ref=u_max,
-            diameter=D, re=re, re_capped=capped,
+            diameter=D, re=re, re_capped=capped, cap=cap,
             bodies=[dict(xc=nx / 4.0, yc=w / 2.0, diameter=D, n_markers=0, scheme=s, kernel=k,
                          mdf_iters=5)],
             steps=steps, arrival=t))

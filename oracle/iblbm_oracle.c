@@ -437,18 +437,21 @@ void or_body_full_kick(double ms, double mf, double Is, const double *g, double 
 /* Euler-explicit update of Eq. (A1), the integrator of the paper's
  * wake-interaction cross-check: v^(n+1) = (1 + r) v^n - r v^(n-1) +
  * (F_hydro^n + F_g)/m_s with r = m_f/m_s (= rho_f/rho_s) for the Feng form
- * and r = 0 without it; the rotation carries the internal angular-momentum
- * increment the same way, Omega^(n+1) = (1 + r) Omega^n - r Omega^(n-1) +
- * T^n/I_s (reading: the increment is that of the rigid interior,
- * I_f (Omega^n - Omega^(n-1)) with I_f/I_s = r); X^(n+1) = X^n + v^(n+1)
- * (reading).  st: 0 x 1 y 2 vx 3 vy 4 vpx 5 vpy 6 om 7 Fhx 8 Fhy 9 T
- * 10 Omega^(n-1); on return 2,3,6 hold the new velocities, 4,5,10 the old. */
+ * and r = 0 without it.  The rotation carries the internal angular-momentum
+ * increment in both arms (Sec. 2.7: the ablation of Sec. 5.2 holds the
+ * rotational update fixed and toggles only the translational correction):
+ * Omega^(n+1) = (1 + q) Omega^n - q Omega^(n-1) + T^n/I_s with q = I_f/I_s
+ * = m_f/m_s (reading: the increment is that of the rigid interior,
+ * I_f (Omega^n - Omega^(n-1))); X^(n+1) = X^n + v^(n+1) (reading).
+ * st: 0 x 1 y 2 vx 3 vy 4 vpx 5 vpy 6 om 7 Fhx 8 Fhy 9 T 10 Omega^(n-1);
+ * on return 2,3,6 hold the new velocities, 4,5,10 the old. */
 void or_body_euler(double ms, double mf, double Is, int internal_mass, const double *g, double *st) {
   const double r = internal_mass == OR_IM_FENG ? mf / ms : 0.0;
   const double Fgx = (ms - mf) * g[0], Fgy = (ms - mf) * g[1];
   const double vx = (1.0 + r) * st[2] - r * st[4] + (st[7] + Fgx) / ms;
   const double vy = (1.0 + r) * st[3] - r * st[5] + (st[8] + Fgy) / ms;
-  const double om = (1.0 + r) * st[6] - r * st[10] + st[9] / Is;
+  const double q = mf / ms;
+  const double om = (1.0 + q) * st[6] - q * st[10] + st[9] / Is;
   st[4] = st[2];
   st[5] = st[3];
   st[10] = st[6];

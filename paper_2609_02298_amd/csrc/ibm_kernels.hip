@@ -574,13 +574,16 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       // Euler-explicit update of Eq. (A1) from the force of the last step:
       // v^(n+1) = (1 + r) v^n - r v^(n-1) + (F^n + F_g)/m_s with r = m_f/m_s
       // (0 without internal mass); the rotation with the rigid interior's
-      // angular-momentum increment; the position by the new velocity.
+      // angular-momentum increment, I_f/I_s = m_f/m_s, in both arms (the
+      // internal-mass switch acts on the translation only); the position by
+      // the new velocity.
       const double r = B.internal_mass == kImFeng ? B.mf / B.ms : 0.0;
+      const double q = B.mf / B.ms;
       const double fgx = (B.ms - B.mf) * c.grav_x;
       const double fgy = (B.ms - B.mf) * c.grav_y;
       vhx = (1.0 + r) * bs->vx - r * bs->vpx + (bs->fhx + fgx) / B.ms;
       vhy = (1.0 + r) * bs->vy - r * bs->vpy + (bs->fhy + fgy) / B.ms;
-      omh = (1.0 + r) * bs->om - r * bs->omp + bs->torque / B.Is;
+      omh = (1.0 + q) * bs->om - q * bs->omp + bs->torque / B.Is;
       bs->vpx = bs->vx;
       bs->vpy = bs->vy;
       bs->omp = bs->om;

@@ -960,3 +960,170 @@ def test_verlet_rotation_stays_bounded_near_neutral_buoyancy():
         s.step(1)
         om.append(abs(s.body_state(0)["omega"]))
     assert max(om[-50:]) <= 10 * max(om[:50]) and max(om) < 1e-8
+
+
+# ------------------------------------------- Eq. (16)-(20): closed forms
+def _dfc_single_marker(kernel, X, Y, u0, ds, motion=FIXED, ud=0.0):
+    """One DFC marker of arc length ds at (X, Y) (a body of diameter ds/pi,
+    its marker at angle 0) in a uniform equilibrium stream u0 along x, rho = 1
+    on a periodic box.  With motion=PRESCRIBED_SIN the body moves along x with
+    amplitude ud/(2 pi f) and phase -2 pi f, so that at t = 1 (the first step)
+    it sits at X and moves at ud."""
+    s = _uniform_box(26, 24, u0)
+    D = ds / math.pi
+    body = dict(xc=X - D / 2, yc=Y, diameter=D, n_markers=1, scheme=DFC, kernel=kernel)
+    if motion == PRESCRIBED_SIN:
+        fr = 0.01
+        body.update(motion=PRESCRIBED_SIN, amp=(ud / (2 * math.pi * fr), 0.0), freq=fr,
+                    phase=-2 * math.pi * fr)
+    s.add_body(body)
+    s.step(1)
+    return s
+
+
+def _hat_wsum(X, Y):
+    """sum_x D_h(x - X)^2 for the hat kernel: per axis (1 - a)^2 + a^2 with a
+    the fractional offset (the two nodes of Eq. 9 that the marker touches)."""
+    a, b = X - math.floor(X), Y - math.floor(Y)
+    return ((1 - a) ** 2 + a ** 2) * ((1 - b) ** 2 + b ** 2)
+
+
+def test_dfc_fixed_peskin4_marker_in_uniform_stream_closed_form():
+    """Eq. (16)-(20) for one fixed P4 marker in a uniform stream u0 (rho =
+    rho_f = 1): f_bar_i - f*_i = f*_opp(i) - f*_i = -6 w_i e_i.u0, so
+    F_s = 2 ds lambda u0, and lambda = 1/(2 ds W_sum) with W_sum = sum_x D_h^2
+    = (3/8)^2 at any position (the P4 identity sum phi^2 = 3/8).  Hence
+    F_s = u0/(3/8)^2 along the stream, independent of ds and position."""
+    u0 = 0.05
+    for X, Y, ds in ((10.0, 10.0, 0.7), (10.3, 9.71, 0.35), (11.77, 10.5, 1.1)):
+        st = _dfc_single_marker(PESKIN4, X, Y, u0, ds).body_state(0)
+        assert abs(st["fx"] - u0 / (3 / 8) ** 2) < 1e-14
+        assert abs(st["fy"]) < 1e-15
+
+
+@pytest.mark.parametrize("kernel", [PESKIN4, HAT])
+def test_dfc_moving_marker_closed_form(kernel):
+    """Eq. (16) with a moving marker: f_bar_i = f*_opp(i) + 6 w_i rho_f e_i.U_d,
+    so in the uniform stream F_s = (rho u0 - rho_f U_d)/(rho_f W_sum).  A
+    marker moving with the fluid (U_d = u0) feels no force; one moving
+    against it (U_d = -u0) feels twice the fixed marker's.  This fixes the
+    coefficient and sign of the U_d term."""
+    u0 = 0.04
+    for X, Y, ds in ((10.25, 9.5, 0.8), (11.6, 10.13, 0.5)):
+        W = (3 / 8) ** 2 if kernel == PESKIN4 else _hat_wsum(X, Y)
+        for ud in (u0, -u0, 0.5 * u0):
+            s = _dfc_single_marker(kernel, X, Y, u0, ds, motion=PRESCRIBED_SIN, ud=ud)
+            m = s.markers(0)
+            assert abs(m[0, 0] - X) < 1e-12 and abs(m[0, 1] - Y) < 1e-12
+            assert abs(m[0, 2] - ud) < 1e-15 and m[0, 3] == 0.0
+            st = s.body_state(0)
+            assert abs(st["fx"] - (u0 - m[0, 2]) / W) < 1e-14, (kernel, X, ud)
+            assert abs(st["fy"]) < 1e-15
+
+
+# ------------------------------------------------ Eq. (A1): rotation arms
+def test_euler_a1_rotation_is_the_same_in_both_internal_mass_arms():
+    """Sec. 2.7: the Euler-explicit rotation carries the interior's angular-
+    momentum increment (I_f/I_s = m_f/m_s) whether or not the translational
+    internal-mass correction is on; only the translation differs."""
+    ms, mf, Is, g = 3.0, 2.0, 5.0, np.array([4e-4, -1e-3])
+    q = mf / ms
+    rng = np.random.default_rng(7)
+    a = np.zeros(12); b = np.zeros(12)
+    om = 0.0; omp = 0.0
+    for n in range(50):
+        T = rng.uniform(-0.3, 0.3)
+        a[9] = b[9] = T
+        oracle.body_euler(ms, mf, Is, IM_FENG, g, a)
+        oracle.body_euler(ms, mf, Is, IM_NONE, g, b)
+        om, omp = (1 + q) * om - q * omp + T / Is, om
+        assert a[6] == b[6] and a[10] == b[10]
+        assert abs(a[6] - om) < 1e-13
+    # the translation does differ between the arms
+    assert np.abs(a[2:4] - b[2:4]).max() > 1e-3
+
+
+# ------------------------------------------- Eq. (5): CM-MRT stability
+def _raw_moment_linear_model(tau, sq, se):
+    """Linearisation of Eq. (5) about rest (u = 0, rho = 1), derived here
+    independently: at u = 0 the central moments are the raw moments
+    m_pq = sum f e_x^p e_y^q, and to first order in u the equilibria of the
+    Maxwellian central moments become m20 = m02 = rho/3, m11 = 0, m21 =
+    j_y/3, m12 = j_x/3, m22 = rho/9 (rho and j conserved).  Returns the 9x9
+    map f_in -> f_out."""
+    P = [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)]
+    M = np.array([[EX[i] ** p * EY[i] ** q for i in range(9)] for p, q in P], float)
+    om = 1.0 / tau
+    L = np.diag([0, 0, 0, om, om, om, sq, sq, se])
+    E = np.zeros((9, 9))
+    E[0, 0] = E[1, 1] = E[2, 2] = 1.0
+    E[3, 0] = E[4, 0] = 1 / 3
+    E[6, 2] = E[7, 1] = 1 / 3
+    E[8, 0] = 1 / 9
+    return np.linalg.solve(M, ((np.eye(9) - L) + L @ E) @ M)
+
+
+def _oracle_jacobian_at_rest(tau, sq=1.2, se=1.4):
+    cfg = dict(nx=3, ny=3, collision=CMMRT, tau=tau, cm_s_q=sq, cm_s_eps=se)
+    f0 = oracle.equilibrium(1.0, 0.0, 0.0)
+    h = 1e-6
+    J = np.zeros((9, 9))
+    for j in range(9):
+        fp = f0.copy(); fp[j] += h
+        fm = f0.copy(); fm[j] -= h
+        J[:, j] = (oracle.collide_node(cfg, fp) - oracle.collide_node(cfg, fm)) / (2 * h)
+    return J
+
+
+def _spectral_radius(J, n):
+    """Largest |eigenvalue| of one collide+stream step of the linearised
+    scheme over the wave vectors of an n x n periodic box (streaming
+    multiplies population i by exp(-i k.e_i))."""
+    ks = 2 * math.pi * np.arange(n) / n
+    r = 0.0
+    for kx in ks:
+        for ky in ks:
+            A = np.exp(-1j * (kx * EX + ky * EY))[:, None] * J
+            r = max(r, np.abs(np.linalg.eigvals(A)).max())
+    return r
+
+
+@pytest.mark.parametrize("tau", [1.75, 1.8])
+def test_cmmrt_jacobian_at_rest_is_the_raw_moment_model(tau):
+    """The oracle's central-moment collision, linearised about rest, is the
+    raw-moment relaxation of the independent model above."""
+    np.testing.assert_allclose(_oracle_jacobian_at_rest(tau), _raw_moment_linear_model(tau, 1.2, 1.4),
+                               rtol=0, atol=1e-8)
+
+
+def test_cmmrt_linear_stability_limit():
+    """With the paper's s_q = 1.2, s_eps = 1.4 (Eq. 5) the scheme linearised
+    about rest has an amplified mode (k_x = pi, k_y near 0.93) once tau
+    exceeds about 1.79: every mode of a 40 x 40 box stays on or inside the
+    unit circle at tau = 1.75 and one grows by more than 0.2 % per step at
+    1.8.  With s_q = s_eps = 1 no mode grows even at tau = 2.19; mean flow
+    shrinks the growth (at u = 0.1 the tau = 1.8 modes are stable)."""
+    assert _spectral_radius(_raw_moment_linear_model(1.75, 1.2, 1.4), 40) < 1 + 1e-12
+    assert _spectral_radius(_raw_moment_linear_model(1.8, 1.2, 1.4), 40) > 1.002
+    assert _spectral_radius(_raw_moment_linear_model(2.19, 1.0, 1.0), 40) < 1 + 1e-12
+
+
+@pytest.mark.parametrize("tau,grows", [(1.75, False), (1.8, True)])
+def test_cmmrt_periodic_box_stability_margin(tau, grows):
+    """Time-marching the oracle on a 20 x 20 periodic box (which holds the
+    amplified wave vector (pi, 2 pi 3/20)) from a seeded near-rest state: the
+    density deviation decays at tau = 1.75 and grows at tau = 1.8."""
+    n = 20
+    s = oracle.OracleSim(_box(CMMRT, n, n, (PERIODIC,) * 4, tau=tau))
+    f = random_populations(n, n, 5, amp=1e-3)
+    s.set_populations(f)
+    d0 = np.abs(f.sum(0) - f.sum(0).mean()).max()
+    dev = []
+    for _ in range(4):
+        s.step(500)
+        r = s.populations().sum(0)
+        dev.append(np.abs(r - r.mean()).max() / d0)
+    if grows:
+        assert dev[1] < dev[2] < dev[3] and dev[3] > 5.0
+    else:
+        assert dev[3] < 1e-3

@@ -38,3 +38,23 @@ def test_summary_counts_and_spans():
     assert s["sequential"]["makespan_s"] == 2.0
     assert s["sequential"]["p99_latency_s"] == round(np.percentile([1.0, 1.5], 99), 4)
     assert s["peak_resident_gb"] == 1.0
+
+
+def test_sweep_keeps_cmmrt_cases_below_the_stability_limit():
+    """No CM-MRT sweep case gets a relaxation time above the limit of the
+    central-moment operator with s_q = 1.2, s_eps = 1.4; the capped cases
+    say so, and the cap changes no other case."""
+    import ib_cases
+    capped = ib_cases.sweep_cases(256, seed=0)
+    free = ib_cases.sweep_cases(256, seed=0, tau_max_cmmrt=1e9)
+    for c, f in zip(capped, free):
+        assert (c["nx"], c["ny"], c["collision"], c["steps"]) == (f["nx"], f["ny"], f["collision"],
+                                                                f["steps"])
+        if c["collision"] == ib_cases.CMMRT:
+            assert c["tau"] <= ib_cases.CMMRT_TAU_MAX + 1e-12
+        if c["cap"] == "cmmrt_tau_max":
+            assert c["re_capped"] and f["tau"] > ib_cases.CMMRT_TAU_MAX
+            assert abs(c["tau"] - ib_cases.CMMRT_TAU_MAX) < 1e-12
+        else:
+            assert c["tau"] == f["tau"]
+    assert sum(c["cap"] == "cmmrt_tau_max" for c in capped) == 2
