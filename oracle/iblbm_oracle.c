@@ -107,6 +107,14 @@ static void moments(const double *f, double Fx, double Fy, double *rho, double *
   *uy = (jy + 0.5 * Fy) / r;
 }
 
+/* b^e for e = 0, 1, 2 by repeated multiplication (each product rounded
+ * once, as a correctly rounded pow would). */
+static double ipow(double b, int e) {
+  double r = 1.0;
+  for (int k = 0; k < e; k++) r *= b;
+  return r;
+}
+
 /* Solve A x = b (n x n, row-major) by Gaussian elimination with partial
  * pivoting.  A and b are overwritten. */
 static void gauss_solve(int n, double *A, double *b, double *x) {
@@ -180,7 +188,7 @@ void or_collide_node(const or_config *cfg, const double *fin, double Fx, double 
     for (int m = 0; m < 9; m++) {
       k[m] = 0.0;
       for (int i = 0; i < 9; i++) {
-        T[m * 9 + i] = pow(EX[i] - ux, P[m]) * pow(EY[i] - uy, Q[m]);
+        T[m * 9 + i] = ipow(EX[i] - ux, P[m]) * ipow(EY[i] - uy, Q[m]);
         k[m] += T[m * 9 + i] * fin[i];
       }
     }
@@ -363,6 +371,14 @@ void or_destroy(or_sim *s) {
 int or_add_body(or_sim *s, const or_body_desc *d) {
   if (s->nbody >= OR_MAX_BODIES || d->diameter <= 0) return -1;
   if (s->nbody > 0 && s->body[0].d.scheme != d->scheme) return -1;
+  /* the coupled MDF path is a property of the sim: every body agrees, with
+   * the same bounds and tolerance */
+  if (s->nbody > 0 && d->scheme == OR_MDF &&
+      (s->body[0].d.mdf_coupled != d->mdf_coupled ||
+       (d->mdf_coupled && (s->body[0].d.mdf_iters != d->mdf_iters ||
+                           s->body[0].d.mdf_nmin != d->mdf_nmin ||
+                           s->body[0].d.mdf_tol != d->mdf_tol))))
+    return -1;
   if (d->scheme == OR_MDF && (d->mdf_iters < 1 || d->mdf_iters > 1000 || (d->mdf_tol > 0.0 && (d->mdf_nmin < 1 || d->mdf_nmin > d->mdf_iters))))
     return -1;
   or_body *b = &s->body[s->nbody];
@@ -375,7 +391,9 @@ int or_add_body(or_sim *s, const or_body_desc *d) {
   b->X = calloc(nb, 8); b->Y = calloc(nb, 8); b->Udx = calloc(nb, 8); b->Udy = calloc(nb, 8);
   b->Fx = calloc(nb, 8); b->Fy = calloc(nb, 8); b->lambda = calloc(nb, 8);
   b->mdfU = calloc(2 * nb, 8);
-  b->mdf_r = calloc(d->mdf_iters > 0 ? (size_t)d->mdf_iters : 1, 8);
+  /* residuals of one step: at most one per pass, plus the first and one per
+   * rejected trial of the coupled path (at most three) */
+  b->mdf_r = calloc((d->mdf_iters > 0 ? (size_t)d->mdf_iters : 1) + 4, 8);
   b->xc0 = b->xc = d->xc;
   b->yc0 = b->yc = d->yc;
   double rs = d->density_ratio * s->c.rho0, area = M_PI * b->radius * b->radius;
@@ -828,6 +846,150 @@ static void ibm_mdf(or_sim *s) {
   free(sy);
 }
 
+/* Largest |U_d - U(X_k)| over every marker of every body, with U
+ * interpolated from the node velocities (ux, uy); the per-marker errors go
+ * to each body's mdfU (x then y). */
+static double joint_residual(or_sim *s, const double *ux, const double *uy) {
+  double res = 0.0;
+  for (int b = 0; b < s->nbody; b++) {
+    or_body *B = &s->body[b];
+    double *ex = B->mdfU, *ey = B->mdfU + B->nb;
+    for (int k = 0; k < B->nb; k++) {
+      ex[k] = B->Udx[k] - interp(s, B->d.kernel, ux, B->X[k], B->Y[k]);
+      ey[k] = B->Udy[k] - interp(s, B->d.kernel, uy, B->X[k], B->Y[k]);
+      double r = sqrt(ex[k] * ex[k] + ey[k] * ey[k]);
+      res = r > res ? r : res;
+    }
+  }
+  return res;
+}
+
+static void record_residual(or_sim *s, double r) {
+  for (int b = 0; b < s->nbody; b++) {
+    or_body *B = &s->body[b];
+    if (B->mdf_nr < B->d.mdf_iters + 4) B->mdf_r[B->mdf_nr++] = r;
+  }
+}
+
+/* Coupled multi-body MDF (Sec. 2.5.2, the two-particle path): the bodies'
+ * forces share the fluid update of every pass, and the iteration is
+ * controlled on the residual of all markers together.  Reading of the
+ * paper's controls, in its order:
+ *   - each body's initial relaxation is omega_0 = min(omega_MDF, 0.8), and
+ *     a common factor c (1 at the start of every step) scales them;
+ *   - a pass is a trial: F^(n) = 2 rho(X_k)(U_d - U) from the current
+ *     interpolation, u += c omega_0/(2 rho) spread(F^(n)) for every body,
+ *     then the joint residual R' of the new velocities;
+ *   - if R' > 1.2 R (R: the residual before the trial) the trial is
+ *     rejected: the velocities return to their state before it and c is
+ *     halved; the iteration ends once c reaches 0.125, else the same F^(n)
+ *     is tried again with the halved factor;
+ *   - an accepted trial adds c omega_0 F^(n) to F_total and counts as a
+ *     pass; the iteration ends once at least mdf_nmin passes are accepted
+ *     and R < mdf_tol (when mdf_tol > 0), or after mdf_iters accepted passes.
+ * The single-body guard r_n > 1.5 r_(n-1) is not used on this path.  Every
+ * body reports the joint residual and the number of accepted passes. */
+static void ibm_mdf_coupled(or_sim *s) {
+  int n = s->n;
+  double *rho = s->tmpa, *ux = s->tmpb, *uy = s->tmpc;
+  post_stream_moments(s, rho, ux, uy);
+  double *sx = calloc(n, sizeof(double)), *sy = calloc(n, sizeof(double));
+  double *pux = malloc(sizeof(double) * n), *puy = malloc(sizeof(double) * n);
+  double *rX[OR_MAX_BODIES], *Fn[OR_MAX_BODIES], om0[OR_MAX_BODIES];
+  for (int b = 0; b < s->nbody; b++) {
+    or_body *B = &s->body[b];
+    rX[b] = calloc(B->nb, sizeof(double));
+    Fn[b] = calloc(2 * (size_t)B->nb, sizeof(double));
+    for (int k = 0; k < B->nb; k++) {
+      B->Fx[k] = B->Fy[k] = 0.0;
+      rX[b][k] = interp(s, B->d.kernel, rho, B->X[k], B->Y[k]);
+    }
+    om0[b] = B->omega_mdf < 0.8 ? B->omega_mdf : 0.8;
+    B->mdf_nr = 0;
+  }
+  const or_body_desc *d0 = &s->body[0].d;
+  const int nmax = d0->mdf_iters, nmin = d0->mdf_tol > 0.0 ? d0->mdf_nmin : d0->mdf_iters;
+  double c = 1.0;
+  double R = joint_residual(s, ux, uy);
+  record_residual(s, R);
+  int accepted = 0;
+  for (;;) {
+    if (accepted >= nmax || (d0->mdf_tol > 0.0 && accepted >= nmin && R < d0->mdf_tol)) break;
+    for (int b = 0; b < s->nbody; b++) {
+      or_body *B = &s->body[b];
+      const double *ex = B->mdfU, *ey = B->mdfU + B->nb;
+      for (int k = 0; k < B->nb; k++) {
+        Fn[b][k] = 2.0 * rX[b][k] * ex[k];
+        Fn[b][B->nb + k] = 2.0 * rX[b][k] * ey[k];
+      }
+    }
+    memcpy(pux, ux, sizeof(double) * n);
+    memcpy(puy, uy, sizeof(double) * n);
+    int stop = 0;
+    for (;;) {
+      for (int p = 0; p < n; p++) sx[p] = sy[p] = 0.0;
+      for (int b = 0; b < s->nbody; b++) {
+        or_body *B = &s->body[b];
+        const double w = c * om0[b];
+        for (int k = 0; k < B->nb; k++) {
+          spread_add(s, B->d.kernel, sx, w * Fn[b][k], B->X[k], B->Y[k], B->ds);
+          spread_add(s, B->d.kernel, sy, w * Fn[b][B->nb + k], B->X[k], B->Y[k], B->ds);
+        }
+      }
+      for (int p = 0; p < n; p++) {
+        ux[p] = pux[p] + sx[p] / (2.0 * rho[p]);
+        uy[p] = puy[p] + sy[p] / (2.0 * rho[p]);
+      }
+      const double Rt = joint_residual(s, ux, uy);
+      record_residual(s, Rt);
+      if (!(Rt > 1.2 * R)) {
+        for (int b = 0; b < s->nbody; b++) {
+          or_body *B = &s->body[b];
+          const double w = c * om0[b];
+          for (int k = 0; k < B->nb; k++) {
+            B->Fx[k] += w * Fn[b][k];
+            B->Fy[k] += w * Fn[b][B->nb + k];
+          }
+        }
+        accepted++;
+        R = Rt;
+        break;
+      }
+      /* reject: back to the velocities before the trial */
+      memcpy(ux, pux, sizeof(double) * n);
+      memcpy(uy, puy, sizeof(double) * n);
+      c *= 0.5;
+      if (c <= 0.125) {
+        stop = 1;
+        break;
+      }
+    }
+    if (stop) {
+      (void)joint_residual(s, ux, uy); /* per-marker errors of the kept state */
+      break;
+    }
+  }
+  for (int b = 0; b < s->nbody; b++) {
+    or_body *B = &s->body[b];
+    B->mdf_res = R;
+    B->mdf_iters_done = accepted;
+    free(rX[b]);
+    free(Fn[b]);
+  }
+  for (int p = 0; p < n; p++) s->Fx[p] = s->Fy[p] = 0.0;
+  for (int b = 0; b < s->nbody; b++) {
+    or_body *B = &s->body[b];
+    for (int k = 0; k < B->nb; k++) {
+      spread_add(s, B->d.kernel, s->Fx, B->Fx[k], B->X[k], B->Y[k], B->ds);
+      spread_add(s, B->d.kernel, s->Fy, B->Fy[k], B->X[k], B->Y[k], B->ds);
+    }
+  }
+  free(sx);
+  free(sy);
+  free(pux);
+  free(puy);
+}
+
 /* Distribution-function correction, Eq. (15)-(20).  All markers of all
  * bodies interpolate the uncorrected post-stream field first (one Jacobi
  * pass); W_total sums D_h over every marker of every body; rho_f = rho0. */
@@ -947,6 +1109,7 @@ int or_step(or_sim *s, int64_t nsteps) {
     if (s->nbody > 0) {
       int scheme = s->body[0].d.scheme;
       if (scheme == OR_DF) ibm_df(s);
+      else if (scheme == OR_MDF && s->body[0].d.mdf_coupled) ibm_mdf_coupled(s);
       else if (scheme == OR_MDF) ibm_mdf(s);
       else ibm_dfc(s);
       body_forces(s);

@@ -58,7 +58,8 @@ typedef struct {
   int32_t pad1;
   double mdf_tol;          /* > 0: adaptive MDF (Sec. 2.5.2, App. A.2); <= 0: mdf_iters passes */
   int32_t integrator;      /* free bodies: OR_VERLET (Eq. 23) or OR_EULER_A1 (Eq. A1) */
-  int32_t pad2;
+  int32_t mdf_coupled;     /* MDF: the bodies of the sim iterate jointly with the
+                              coupled-path controls of Sec. 2.5.2 (same value on every body) */
 } or_body_desc;
 
 typedef struct or_sim or_sim;

@@ -49,7 +49,7 @@ class _Body(C.Structure):
                 ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
                 ("phase", C.c_double), ("density_ratio", C.c_double),
                 ("mdf_nmin", C.c_int32), ("pad1", C.c_int32), ("mdf_tol", C.c_double),
-                ("integrator", C.c_int32), ("pad2", C.c_int32)]
+                ("integrator", C.c_int32), ("mdf_coupled", C.c_int32)]
 
 
 _lib = None
@@ -139,6 +139,7 @@ def make_body(b: dict) -> _Body:
     d.mdf_nmin = int(b.get("mdf_nmin", 1))
     d.mdf_tol = float(b.get("mdf_tol", 0.0))
     d.integrator = int(b.get("integrator", VERLET))
+    d.mdf_coupled = int(b.get("mdf_coupled", 0))
     return d
 
 

@@ -1127,3 +1127,86 @@ def test_cmmrt_periodic_box_stability_margin(tau, grows):
         assert dev[1] < dev[2] < dev[3] and dev[3] > 5.0
     else:
         assert dev[3] < 1e-3
+
+
+# ------------------------------ Sec. 2.5.2: coupled multi-body MDF controls
+def _coupled_single_markers(ds_list, u0=0.05, nmin=5, nmax=20, tol=1e-4, omega=0.0):
+    """Single-marker P4 bodies (arc spacings ds_list) far apart in a uniform
+    stream u0 with U_d = 0, one coupled MDF step.  For one marker the pass
+    is U <- U + w ds (3/8)^2 (U_d - U) (sum D_h^2 = (3/8)^2 for P4, rho = 1),
+    so the slip factor of a pass at relaxation w is q = 1 - w a,
+    a = ds (3/8)^2, and omega_MDF = 1/||A||_inf = 1/a unless omega > 0
+    sets it."""
+    nx, ny = 40 * len(ds_list) + 40, 40
+    s = _uniform_box(nx, ny, u0)
+    for i, ds in enumerate(ds_list):
+        D = ds / math.pi
+        s.add_body(dict(xc=30.0 + 40 * i + 0.3 - D / 2, yc=20.4, diameter=D, n_markers=1,
+                        scheme=MDF, kernel=PESKIN4, mdf_iters=nmax, mdf_nmin=nmin, mdf_tol=tol,
+                        mdf_omega=omega, mdf_coupled=1))
+    s.step(1)
+    return s
+
+
+def test_coupled_mdf_relaxation_cap_and_joint_residual():
+    """omega_0 = min(1/||A||_inf, 0.8): both markers relax at 0.8 (their own
+    omega_MDF is 20 and 8).  The joint residual max_b u0 q_b^n is that of the
+    slower body, so both bodies stop together at the N_max = 20 cap, each
+    with F_total = -2 w u0 sum_n q_b^n."""
+    u0, w = 0.05, 0.8
+    ds_list = (0.35, 0.9)
+    s = _coupled_single_markers(ds_list, u0)
+    q = [1 - w * ds * (3 / 8) ** 2 for ds in ds_list]
+    R = u0 * max(qq ** 20 for qq in q)
+    for b, qq in enumerate(q):
+        st = s.body_state(b)
+        assert st["mdf_iters"] == 20
+        assert abs(st["mdf_residual"] - R) < 1e-15
+        Ft = -2 * w * u0 * (1 - qq ** 20) / (1 - qq)
+        assert abs(s.markers(b)[0, 4] - Ft) < 1e-14
+    assert abs(s.mdf_omega(0) - 1 / (0.35 * (3 / 8) ** 2)) < 1e-9
+
+
+def test_coupled_mdf_rejects_growth_and_halves():
+    """omega_MDF = 1 (set), capped at 0.8; ds = 20: at w = 0.8 the factor is
+    1 - 0.8 a = -1.25, a growth of 25 %
+    (> 20 %), so the trial is rejected and the relaxation halved; at 0.4 it
+    is -0.125 and every pass is accepted.  The tolerance then stops the
+    iteration at N_min = 5 passes: R = u0 0.125^5, F_total = -2 (0.4) u0
+    sum_{n<5} (-0.125)^n."""
+    u0 = 0.05
+    s = _coupled_single_markers((20.0, 20.0), u0, omega=1.0)
+    for b in (0, 1):
+        st = s.body_state(b)
+        assert st["mdf_iters"] == 5
+        assert abs(st["mdf_residual"] - u0 * 0.125 ** 5) < 1e-17
+        Ft = -2 * 0.4 * u0 * (1 - (-0.125) ** 5) / (1 + 0.125)
+        assert abs(s.markers(b)[0, 4] - Ft) < 1e-15
+    r = s.mdf_residuals(0)
+    expect = [u0, 1.25 * u0] + [u0 * 0.125 ** k for k in range(1, 6)]
+    np.testing.assert_allclose(r, expect, rtol=1e-12)
+
+
+def test_coupled_mdf_terminates_at_one_eighth_relaxation():
+    """omega_MDF = 1 (set), capped at 0.8; ds = 80 (a = 11.25): the factors
+    at w = 0.8, 0.4, 0.2 are -8, -3.5,
+    -1.25, all rejected; the halved factor then reaches 0.125 of its initial
+    value and the iteration ends with no pass kept: no force, residual u0."""
+    u0 = 0.05
+    s = _coupled_single_markers((80.0,), u0, omega=1.0)
+    st = s.body_state(0)
+    assert st["mdf_iters"] == 0
+    assert abs(st["mdf_residual"] - u0) < 1e-16
+    assert s.markers(0)[0, 4] == 0.0 and s.markers(0)[0, 5] == 0.0
+    np.testing.assert_allclose(s.mdf_residuals(0), [u0, 8 * u0, 3.5 * u0, 1.25 * u0], rtol=1e-12)
+    fx, fy = s.force()
+    assert np.abs(fx).max() == 0.0 and np.abs(fy).max() == 0.0
+
+
+def test_coupled_mdf_bodies_must_agree():
+    s = oracle.OracleSim(_box(BGK, 120, 40, (PERIODIC,) * 4))
+    s.add_body(dict(xc=30.0, yc=20.0, diameter=8.0, scheme=MDF, kernel=PESKIN4, mdf_iters=20,
+                    mdf_nmin=5, mdf_tol=1e-4, mdf_coupled=1))
+    with pytest.raises(ValueError):
+        s.add_body(dict(xc=80.0, yc=20.0, diameter=8.0, scheme=MDF, kernel=PESKIN4, mdf_iters=20,
+                        mdf_nmin=5, mdf_tol=1e-4, mdf_coupled=0))
