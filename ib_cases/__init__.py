@@ -238,20 +238,23 @@ def paper_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator
         bodies=[body(0.8, -0.13, 1.5), body(1.2, 0.13, 1.25)], steps=steps)
 
 
-def oscillating_cylinder(steps=60000, nx=1200, ny=600, diameter=40.0) -> dict:
+def oscillating_cylinder(steps=60000, nx=1200, ny=600, diameter=40.0, st0: float = ST0_RE100,
+                         fixed: bool = False) -> dict:
     """Transversely oscillating cylinder: 1200x600, D = 40, Re = 100,
     y(t) = A sin(2 pi f t), A = 0.2 D, f = 0.8 St0 u_inf / D; MDF (k=5), P4,
-    TRT."""
+    TRT.  st0: the Strouhal number of the stationary cylinder's shedding on
+    this same setup (fixed=True gives that stationary case)."""
     u, re = 0.1, 100.0
-    f = 0.8 * ST0_RE100 * u / diameter
+    f = 0.8 * st0 * u / diameter
     return dict(
         name=f"oscillating-cylinder-{nx}x{ny}", nx=nx, ny=ny, collision=TRT,
         tau=tau_from(u, diameter, re), trt_magic=0.25, rho0=1.0,
         bc=(VEL_UNIFORM, ZERO_GRADIENT, VEL_UNIFORM, VEL_UNIFORM), u_bc=u, u_ref=u,
         diameter=diameter,
         bodies=[dict(xc=nx / 4.0, yc=ny / 2.0, diameter=diameter, n_markers=0, scheme=MDF,
-                     kernel=PESKIN4, mdf_iters=5, motion=PRESCRIBED_SIN,
-                     amp=(0.0, 0.2 * diameter), freq=f, phase=0.0)],
+                     kernel=PESKIN4, mdf_iters=5, motion=FIXED if fixed else PRESCRIBED_SIN,
+                     amp=(0.0, 0.0 if fixed else 0.2 * diameter), freq=0.0 if fixed else f,
+                     phase=0.0)],
         steps=steps)
 
 

@@ -15,8 +15,9 @@
  *   - hydrodynamic force and torque (Sec. 2.7), rigid-body Velocity-Verlet
  *     update (Eq. 21-23) with the explicit internal-mass force (Eq. A3).
  *
- * Units: lattice units, dx = dt = 1.  Populations are nine planes
- * f[i][y][x] with x fastest and directions
+ * Units: lattice units, dx = dt = 1.  Populations exchanged with the host
+ * are nine planes f[i][y][x] with x fastest (the device store is the
+ * library's own) and directions
  *   e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0) e4=(0,-1)
  *   e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1).
  *
@@ -42,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IB_LBM_ABI_VERSION 3u
+#define IB_LBM_ABI_VERSION 4u
 
 typedef enum {
   IB_LBM_OK = 0,
@@ -74,7 +75,8 @@ enum { IB_LBM_VERLET = 0, IB_LBM_EULER_A1 = 1 };
 enum { IB_LBM_SPREAD_GATHER = 0, IB_LBM_SPREAD_ATOMIC = 1 };
 
 /* Body flags reported in ib_lbm_body_state.flags */
-enum { IB_LBM_FLAG_NONFINITE = 1, IB_LBM_FLAG_RANGE = 2, IB_LBM_FLAG_OVERLAP = 4 };
+enum { IB_LBM_FLAG_NONFINITE = 1, IB_LBM_FLAG_RANGE = 2, IB_LBM_FLAG_OVERLAP = 4,
+       IB_LBM_FLAG_CAPACITY = 8, IB_LBM_FLAG_EXCHANGE = 16 };
 
 /* Optional device allocator (for example a caching allocator).  alloc returns
  * device memory of at least `bytes` usable on `stream`, or NULL. */
@@ -93,7 +95,8 @@ typedef struct {
  * most recent steps kept per body in the device history ring (0 -> 4096). */
 typedef struct {
   uint32_t abi_version; /* must equal IB_LBM_ABI_VERSION */
-  int32_t nx, ny;       /* nodes, x streamwise; 3 <= nx, ny; nx*ny < 2^31 */
+  int32_t nx, ny;       /* nodes, x streamwise; 3 <= nx < 65535, 3 <= ny < 32767,
+                           nx*ny < 2^31 (population offsets are 64-bit) */
   int32_t precision;    /* IB_LBM_FP64 | IB_LBM_FP32_SHIFTED */
   int32_t collision;    /* IB_LBM_BGK | IB_LBM_TRT | IB_LBM_CMMRT */
   int32_t history_capacity;
@@ -126,8 +129,25 @@ typedef struct {
  * Velocity-Verlet update of Eq. 23 (half-kick and drift before the step,
  * full kick after it), or the Euler-explicit update of Eq. A1 before the
  * step, v^(n+1) = (1 + r) v^n - r v^(n-1) + (F_hydro^n + F_g)/m_s with r =
- * rho0/rho_s (0 without internal mass), the rotation likewise with the
- * rigid interior's angular-momentum increment, X^(n+1) = X^n + v^(n+1).
+ * rho0/rho_s (0 without internal mass); the rotation carries the rigid
+ * interior's angular-momentum increment in both internal-mass arms (Sec.
+ * 2.7), Omega^(n+1) = (1 + q) Omega^n - q Omega^(n-1) + T^n/I_s with
+ * q = rho0/rho_s; X^(n+1) = X^n + v^(n+1).
+ * mdf_coupled (MDF, every body of the sim alike, with equal mdf_iters,
+ * mdf_nmin and mdf_tol): the coupled multi-body path of Sec. 2.5.2.  The
+ * bodies' passes share each fluid update and are controlled on the residual
+ * R of all markers together: each body relaxes at c min(omega_MDF, 0.8)
+ * with a common factor c (1 at the start of a step); after each trial pass
+ * the new R' is measured, and R' > 1.2 R rejects the trial (the velocities
+ * return to their state before it) and halves c, ending the iteration once
+ * c reaches 1/8; an accepted trial counts as a pass.  The iteration ends
+ * after mdf_iters accepted passes, or, with mdf_tol > 0, once at least
+ * mdf_nmin are accepted and R < mdf_tol.  Every body reports the joint
+ * residual and the accepted passes.  Such a sim runs the passes on the
+ * support nodes, cannot join a batch, and its bodies' IB workgroups meet
+ * once per trial through device memory (a wait bounded to about 2 s; on
+ * expiry the body reports IB_LBM_FLAG_EXCHANGE and the step stops with
+ * IB_LBM_E_STATE from ib_lbm_forces).
  * All bodies of one sim use the same scheme. */
 typedef struct {
   double xc, yc, diameter;
@@ -143,6 +163,7 @@ typedef struct {
   int32_t mdf_nmin; /* adaptive MDF: fewest passes before the tolerance stop */
   double mdf_tol;   /* > 0 selects the adaptive MDF; <= 0 the fixed form */
   int32_t integrator; /* FREE bodies: IB_LBM_VERLET | IB_LBM_EULER_A1 */
+  int32_t mdf_coupled; /* MDF: 1 selects the coupled multi-body path */
 } ib_lbm_body_desc;
 
 /* State of a body after the last completed step.  Forces are on the body
@@ -260,8 +281,10 @@ ib_lbm_status ib_lbm_get_launch(const ib_lbm_sim *s, ib_lbm_launch *l);
 /* Spreading variant: marker-sorted gather (default, deterministic) or
  * per-marker atomic scatter (order-dependent rounding). */
 ib_lbm_status ib_lbm_set_spread(ib_lbm_sim *s, int32_t mode);
-/* hipGraph use: steps_per_graph > 0 captures that many steps once and
- * replays them; 0 launches kernels directly. */
+/* hipGraph use: steps_per_graph > 0 captures that many steps once (one
+ * graph for each of the two lattices a run of steps can start from) and
+ * replays them; 0 launches kernels directly.  A capture happens at the first
+ * ib_lbm_step call that needs it, so that call may allocate. */
 ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph);
 
 /* Pipelined steps (default on).  For a sim with one body that is fixed or
@@ -270,16 +293,16 @@ ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph);
  * library-owned streams that overlap: the collide-stream of step n+1 starts
  * while the IB pass of step n is still running, and only its tiles next to
  * the body (the ones that read what the IB pass writes, or are read by it)
- * wait for that pass, through device-side counters with a bounded wait
- * (about 2 s; on expiry the sim halts with IB_LBM_E_STATE from
- * ib_lbm_forces).  Each ib_lbm_step call first synchronises the sim's
- * stream, and the sim's stream waits for both streams before the call
- * returns.  The collide-stream stream leaves one compute unit to the IB
- * pass.  Results are bitwise the same as unpipelined steps.  Steps replayed
- * from a graph (ib_lbm_set_graph) are not pipelined.  set_overlap(0/1)
- * forbids or allows it; get_overlap reports whether the current
- * configuration uses it (after the first step) and, if near_nodes is not
- * NULL, the number of nodes in the tiles that wait for the IB pass. */
+ * wait for that pass.  The two streams are ordered by HIP events only;
+ * nothing waits on the host.  The first call after ib_lbm_create or a
+ * state-reading call starts after the work already on the sim's stream, and
+ * the sim's stream waits for both streams before any later work.  The
+ * collide-stream stream leaves one compute unit to the IB pass.  Results
+ * are bitwise the same as unpipelined steps.  Steps replayed from a graph
+ * (ib_lbm_set_graph) are not pipelined.
+ * set_overlap(0/1) forbids or allows it; get_overlap reports whether the
+ * current configuration uses it (after the first step) and, if near_nodes
+ * is not NULL, the number of nodes in the tiles that wait for the IB pass. */
 ib_lbm_status ib_lbm_set_overlap(ib_lbm_sim *s, int32_t on);
 ib_lbm_status ib_lbm_get_overlap(const ib_lbm_sim *s, int32_t *in_use, int64_t *near_nodes);
 

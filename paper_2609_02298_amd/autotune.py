@@ -93,8 +93,13 @@ def _main(argv=None):
     ap.add_argument("--write", required=True, help="JSON table to write")
     ap.add_argument("lattices", nargs="*", default=["2000x800", "4096x4096"],
                     help="NXxNY entries, tuned for every collision model and precision")
+    ap.add_argument("--fresh", action="store_true",
+                    help="time every entry again instead of starting from the shipped table")
     args = ap.parse_args(argv)
     ib.load_library()
+    if args.fresh:
+        _cache.clear()
+        _cache["_fresh"] = True  # keeps the shipped table from being loaded on lookup
     for spec in args.lattices:
         nx, ny = (int(v) for v in spec.lower().split("x"))
         for prec in (ib.FP32_SHIFTED, ib.FP64):
@@ -102,6 +107,7 @@ def _main(argv=None):
                 sh = tune(nx, ny, col, prec)
                 print(f"{nx}x{ny} precision {prec} collision {col}: {sh} "
                       f"{_cache[_key(nx, ny, col, prec)]['us']:.1f} us", flush=True)
+    _cache.pop("_fresh", None)
     save_cache(args.write)
 
 

@@ -14,6 +14,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
+# The collide-stream kernels write every fused multiply-add out explicitly,
+# so that all their instances round alike: no automatic contraction there.
+PER_SOURCE = {"lbm_kernels.hip": ["-ffp-contract=off"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -21,7 +24,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = ["hipcc", *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *FLAGS, *PER_SOURCE.get(src, []), *lang, "-c", os.path.join(CSRC, src),
+               "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
         if r.returncode != 0:

@@ -58,7 +58,6 @@ struct ib_lbm_sim {
   std::string err;
   CaseDesc cd;  // host copy
   DevBuf f0, f1, force, state, ticket;
-  uint32_t ibm_seq = 0;  // launches of the replicated IB pass (ticket sequence)
   std::vector<HostBody> bodies;
   DevBuf d_bodies, d_case, d_prefix, d_slots, d_tmp;
   int nslots = 0;
@@ -66,10 +65,17 @@ struct ib_lbm_sim {
   int spread_mode = 0;
   int nslots_fast = 0;    // the first IB slots, run by the 1024-thread kernel
   int graph_steps = 0;
-  hipGraphExec_t graph_exec = nullptr;
+  // captured steps, one graph per parity of the input lattice at its start
+  // (the lattice of each step is a kernel argument)
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   int graph_len = 0;
   Timing timing;
   int64_t host_steps = 0;
+  // lattice holding the input of the next enqueued step: flipped by every
+  // enqueued step, reloaded from the device state by every call that reads
+  // it (they differ only once a halted case stops flipping it on the device,
+  // and a halted case's kernels do nothing)
+  int host_cur = 0;
   ib_lbm_batch *batch = nullptr;
   int lds_bytes = 0;
   // Pipelined steps (see plan_split): the tiles of the hold rectangle and
@@ -252,6 +258,47 @@ ib_lbm_status check_launch(const ib_lbm_launch *l, std::string *err) {
   return IB_LBM_OK;
 }
 
+void drop_graphs(ib_lbm_sim *s) {
+  for (auto &g : s->graph_exec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Arguments of the inner-node collide-stream of a sim stepped on its own,
+// with input lattice cur; mode as in LeanArgs.
+LeanArgs lean_args(const ib_lbm_sim *s, int cur, int force_on) {
+  const CaseDesc &c = s->cd;
+  LeanArgs a;
+  memset(&a, 0, sizeof a);
+  a.src = c.f[cur];
+  a.dst = c.f[cur ^ 1];
+  a.force = c.force;
+  a.state = c.state;
+  a.nx = c.nx;
+  a.ny = c.ny;
+  a.nseg = c.nseg;
+  a.tiles_x = c.tiles_x;
+  a.ntiles = c.tiles_x * c.tiles_y;
+  a.rpt = s->launch.rows_per_thread;
+  a.remap = s->launch.xcd_remap;
+  a.force_on = force_on;
+  a.htx0 = s->hold[0];
+  a.hty0 = s->hold[1];
+  a.hntx = s->split ? s->hold[2] : 0;
+  a.hnty = s->split ? s->hold[3] : 0;
+  a.omega = c.omega;
+  a.s_e = c.s_e;
+  a.s_o = c.s_o;
+  a.s_q = c.s_q;
+  a.s_eps = c.s_eps;
+  a.rho0 = c.rho0;
+  a.fluid_fx = c.fluid_fx;
+  a.fluid_fy = c.fluid_fy;
+  return a;
+}
+
 // Device tables of a sim stepped on its own: one case, its IB slots.
 // Decide whether a sim's steps can be pipelined.  The collide-stream of
 // the tiles away from the body (far tiles) does not read what the IB pass
@@ -300,9 +347,9 @@ bool body_fast(const HostBody &hb, int spread_mode) {
 // of a case's workgroups to finish, in either launch, completes the case).
 hipError_t launch_ibm_slots(int precision, const CaseDesc *cases, const IbmSlot *slots, int nfast, int n,
                             int lds_bytes, int spread_mode, hipStream_t stream) {
-  hipError_t e = launch_ibm(precision, cases, slots, nfast, lds_bytes, spread_mode, 1, 1, 0, nullptr, stream);
+  hipError_t e = launch_ibm(precision, cases, slots, nfast, lds_bytes, spread_mode, 1, 1, nullptr, stream);
   if (e != hipSuccess) return e;
-  return launch_ibm(precision, cases, slots + nfast, n - nfast, lds_bytes, spread_mode, 0, 1, 0, nullptr,
+  return launch_ibm(precision, cases, slots + nfast, n - nfast, lds_bytes, spread_mode, 0, 1, nullptr,
                     stream);
 }
 
@@ -340,9 +387,15 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   HIPCHK(s, hipMemcpy(s->d_prefix.p, pre, sizeof pre, hipMemcpyHostToDevice));
   std::vector<IbmSlot> slots, rest;
   const int n = std::max(1, (int)bd.size());
+  // the bodies of a coupled MDF case meet during their passes, so they run
+  // in one launch: the fast instance only if every one of them fits it
+  bool all_fast = !bd.empty();
+  for (int b = 0; b < (int)bd.size(); b++) all_fast &= body_fast(s->bodies[b], s->spread_mode);
+  const bool coupled = !bd.empty() && bd[0].mdf_coupled;
   for (int b = 0; b < n; b++) {
     const IbmSlot sl{0, bd.empty() ? -1 : b, n, 0};
-    if (!bd.empty() && body_fast(s->bodies[b], s->spread_mode)) slots.push_back(sl);
+    const bool fast = !bd.empty() && (coupled ? all_fast : body_fast(s->bodies[b], s->spread_mode));
+    if (fast) slots.push_back(sl);
     else rest.push_back(sl);
   }
   s->nslots_fast = (int)slots.size();
@@ -352,10 +405,7 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   s->lds_bytes = lds_budget(maxws);
   if ((st0 = plan_split(s))) return st0;
   s->tables_dirty = false;
-  if (s->graph_exec) {
-    (void)hipGraphExecDestroy(s->graph_exec);
-    s->graph_exec = nullptr;
-  }
+  drop_graphs(s);
   return IB_LBM_OK;
 }
 
@@ -383,27 +433,27 @@ static bool has_zou_he(const CaseDesc &c) {
   return c.bc[0] == kZouHe || c.bc[1] == kZouHe || c.bc[2] == kZouHe || c.bc[3] == kZouHe;
 }
 
-// Enqueue one step of a sim on `stream`: collide-stream, then the IB pass.
-ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream) {
+// Enqueue one step of a sim on `stream` whose input lattice is cur:
+// collide-stream, face nodes, Zou-He walls, then the IB pass.
+ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream, int cur) {
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
-  const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
   EventPair p0{}, p1{};
   if (timed) {
     p0 = take_pair(s->timing);
     HIPCHK(s, hipEventRecord(p0.a, stream));
   }
-  HIPCHK(s, launch_collide_stream(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
-                                  (const int32_t *)s->d_prefix.p, 1, ntiles, sh, stream));
+  HIPCHK(s, launch_collide_stream_lean(s->cd.precision, s->cd.collision, lean_args(s, cur, 1), 0, sh,
+                                       stream));
   if (timed) {
     HIPCHK(s, hipEventRecord(p0.b, stream));
     s->timing.ev[0].push_back(p0);
   }
   HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
                                         (const int32_t *)s->d_prefix.p + 2, 1,
-                                        face_blocks(s->cd.nx, s->cd.ny), -1, 1,
+                                        face_blocks(s->cd.nx, s->cd.ny), cur, 1,
                                         general_zero_gradient(s->cd), stream));
   if (has_zou_he(s->cd))
-    HIPCHK(s, launch_zou_he(s->cd.precision, (const CaseDesc *)s->d_case.p, s->cd.nx, s->cd.ny, -1,
+    HIPCHK(s, launch_zou_he(s->cd.precision, (const CaseDesc *)s->d_case.p, s->cd.nx, s->cd.ny, cur,
                             stream));
   if (timed) {
     p1 = take_pair(s->timing);
@@ -441,11 +491,10 @@ ib_lbm_status ensure_pipe_streams(ib_lbm_sim *s) {
   }
   if (!s->iq) HIPCHK(s, hipStreamCreateWithFlags(&s->iq, hipStreamNonBlocking));
   if (!s->ticket.p) {
-    // the replicated IB workgroup's ticket, advanced once per launch
+    // the replicated IB workgroup's counter, advanced by every copy
     ib_lbm_status st = dev_alloc(s, &s->ticket, 256);
     if (st) return st;
-    HIPCHK(s, hipMemset(s->ticket.p, 0, 256));
-    s->ibm_seq = 0;
+    HIPCHK(s, hipMemsetAsync(s->ticket.p, 0, 256, s->stream));
   }
   // the events only order work between streams of this device: a
   // device-scope release suffices (the default system-scope release writes
@@ -459,32 +508,26 @@ ib_lbm_status ensure_pipe_streams(ib_lbm_sim *s) {
   return IB_LBM_OK;
 }
 
-// Enqueue nsteps pipelined steps.  Step n: the hold tiles and then the IB
-// pass on iq, the far tiles on lq.  The far tiles of step n follow the hold
-// tiles of step n-1 (which push into far nodes and whose inputs the far
-// tiles of step n overwrite); the hold tiles of step n follow the far tiles
-// of step n-1 for the same two reasons, and the IB pass of step n-1 by
-// stream order.  Both streams start after the work already on the sim's
-// stream, which then waits for both.
-ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
-  CaseState cs;
-  ib_lbm_status st = read_state(s, &cs);
-  if (st) return st;
-  if (cs.flags & kCaseHalted) return IB_LBM_OK;  // nothing would run
-  if ((st = ensure_pipe_streams(s))) return st;
+// Enqueue nsteps pipelined steps after the work already on `main`, the
+// first with input lattice cur0.  Step n: the hold tiles and then the IB
+// pass on iq, the far tiles, face nodes and Zou-He walls on lq.  The far
+// tiles of step n follow the hold tiles of step n-1 (which push into far
+// nodes and whose inputs the far tiles of step n overwrite); the hold tiles
+// of step n follow the far tiles and face nodes of step n-1 for the same
+// two reasons, and the IB pass of step n-1 by stream order.  The Zou-He
+// wall pass of step n rebuilds wall nodes from the pushes of every node
+// next to them, so it also follows the hold tiles of step n (rounded to
+// whole tiles, the hold rectangle can reach row 1 or column 1).  `main`
+// then waits for both streams.  Nothing here reads device state.
+ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed, hipStream_t main, int cur0) {
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
-  const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
-  HIPCHK(s, hipEventRecord(s->ev_start, s->stream));
+  HIPCHK(s, hipEventRecord(s->ev_start, main));
   HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_start, 0));
   HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_start, 0));
-  PipeArgs pa{};
-  pa.htx0 = s->hold[0];
-  pa.hty0 = s->hold[1];
-  pa.hntx = s->hold[2];
-  pa.hnty = s->hold[3];
   const CaseDesc *dc = (const CaseDesc *)s->d_case.p;
   for (int64_t i = 0; i < nsteps; i++) {
-    pa.cur = cs.cur ^ (int)(i & 1);
+    const int cur = cur0 ^ (int)(i & 1);
+    const LeanArgs la = lean_args(s, cur, 0);
     EventPair p0{}, p1{};
     // far tiles of step i after the hold tiles of step i-1
     if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_near, 0));
@@ -492,7 +535,7 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
       p0 = take_pair(s->timing);
       HIPCHK(s, hipEventRecord(p0.a, s->lq));
     }
-    HIPCHK(s, launch_collide_stream_pipe(s->cd.precision, s->cd.collision, dc, ntiles, sh, pa, 0, s->lq));
+    HIPCHK(s, launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 2, sh, s->lq));
     if (timed) {
       HIPCHK(s, hipEventRecord(p0.b, s->lq));
       s->timing.ev[0].push_back(p0);
@@ -500,16 +543,19 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
     // face nodes lie outside the hold rectangle's reach (plan_split)
     HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
                                           (const int32_t *)s->d_prefix.p + 2, 1,
-                                          face_blocks(s->cd.nx, s->cd.ny), pa.cur, 0,
+                                          face_blocks(s->cd.nx, s->cd.ny), cur, 0,
                                           general_zero_gradient(s->cd), s->lq));
-    if (has_zou_he(s->cd))
-      HIPCHK(s, launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, pa.cur, s->lq));
     // hold tiles of step i after the far tiles of step i-1 (the wait is
     // enqueued before ev_far is recorded again for step i)
     if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_far, 0));
     HIPCHK(s, hipEventRecord(s->ev_far, s->lq));
-    HIPCHK(s, launch_collide_stream_pipe(s->cd.precision, s->cd.collision, dc, ntiles, sh, pa, 1, s->iq));
+    HIPCHK(s, launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 1, sh, s->iq));
     HIPCHK(s, hipEventRecord(s->ev_near, s->iq));
+    if (has_zou_he(s->cd)) {
+      // every push into a wall node, hold tiles included, has landed
+      HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_near, 0));
+      HIPCHK(s, launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, cur, s->lq));
+    }
     if (timed) {
       p1 = take_pair(s->timing);
       HIPCHK(s, hipEventRecord(p1.a, s->iq));
@@ -517,7 +563,7 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
     // one copy of the single body's IB workgroup per XCD; the first to start
     // runs the pass (the far tiles on the other stream fill the chip)
     HIPCHK(s, launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, 1, s->lds_bytes,
-                         s->spread_mode, s->nslots_fast, 8, ++s->ibm_seq, (uint32_t *)s->ticket.p, s->iq));
+                         s->spread_mode, s->nslots_fast, 8, (uint32_t *)s->ticket.p, s->iq));
     if (timed) {
       HIPCHK(s, hipEventRecord(p1.b, s->iq));
       s->timing.ev[1].push_back(p1);
@@ -525,8 +571,20 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed) {
   }
   HIPCHK(s, hipEventRecord(s->ev_lq, s->lq));
   HIPCHK(s, hipEventRecord(s->ev_iq, s->iq));
-  HIPCHK(s, hipStreamWaitEvent(s->stream, s->ev_lq, 0));
-  HIPCHK(s, hipStreamWaitEvent(s->stream, s->ev_iq, 0));
+  HIPCHK(s, hipStreamWaitEvent(main, s->ev_lq, 0));
+  HIPCHK(s, hipStreamWaitEvent(main, s->ev_iq, 0));
+  return IB_LBM_OK;
+}
+
+// Enqueue nsteps steps of a sim on `stream` from input lattice cur0,
+// pipelined when the sim allows it and `pipelined` is set.
+ib_lbm_status enqueue_steps(ib_lbm_sim *s, int64_t nsteps, bool timed, hipStream_t stream, int cur0,
+                            bool pipelined) {
+  if (s->split && pipelined) return enqueue_pipelined(s, nsteps, timed, stream, cur0);
+  for (int64_t i = 0; i < nsteps; i++) {
+    ib_lbm_status st = enqueue_sim_step(s, timed, stream, cur0 ^ (int)(i & 1));
+    if (st) return st;
+  }
   return IB_LBM_OK;
 }
 
@@ -539,6 +597,7 @@ ib_lbm_status usable(ib_lbm_sim *s) {
 ib_lbm_status read_state(ib_lbm_sim *s, CaseState *cs) {
   HIPCHK(s, hipStreamSynchronize(s->stream));
   HIPCHK(s, hipMemcpy(cs, s->state.p, sizeof(CaseState), hipMemcpyDeviceToHost));
+  s->host_cur = cs->cur;
   return IB_LBM_OK;
 }
 
@@ -552,7 +611,8 @@ size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_
   if (!cfg) return 0;
   const size_t elem = cfg->precision == IB_LBM_FP64 ? 8 : 4;
   const size_t n = (size_t)cfg->nx * cfg->ny;
-  size_t bytes = 2 * 9 * n * elem + 2 * n * elem + sizeof(CaseState) + sizeof(CaseDesc) + 256;
+  const size_t lat = cfg->nx > 0 && cfg->ny > 0 ? (size_t)pop_values(cfg->nx, cfg->ny) : 0;
+  size_t bytes = 2 * lat * elem + 2 * n * elem + sizeof(CaseState) + sizeof(CaseDesc) + 256;
   const int hist = cfg->history_capacity > 0 ? cfg->history_capacity : 4096;
   for (int b = 0; b < n_bodies; b++) {
     const int nb = n_markers ? n_markers[b] : 256;
@@ -561,7 +621,8 @@ size_t ib_lbm_footprint(const ib_lbm_config *cfg, int32_t n_bodies, const int32_
     const int mr = (int)std::ceil(D) + 12, mn = (int)(8 * M_PI * D + 8 * mr + 64);
     // (the MDF workspace may carry the marker-space velocities, 2 n_b)
     bytes += (size_t)(std::max(ws_doubles_for(kDFC, nb, 4, mr, mn, (int)elem),
-                               ws_doubles_for(kMDF, nb, 4, mr, mn, (int)elem) + 2 * nb) +
+                               ws_doubles_for(kMDF, nb, 4, mr, mn, (int)elem) +
+                                   std::max(2 * nb, ws_coupled_doubles(nb, mn))) +
                       ws_tab_total(kMDF, nb, 4, mr, mn) + 2 * mn) * 8 +
              (size_t)nb * (8 + 1 + 2) * 8 +
              (size_t)hist * kHistCols * 8 + sizeof(BodyState) + sizeof(BodyDesc);
@@ -618,6 +679,7 @@ ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out) {
   c.precision = cfg->precision;
   for (int f = 0; f < 4; f++) c.bc[f] = cfg->bc[f];
   c.plane = (int64_t)cfg->nx * cfg->ny;
+  c.nseg = pop_segments(cfg->nx);
   c.omega = 1.0 / cfg->tau;
   // TRT (Sec. 2.2): the even rate sets the viscosity; Lambda_o = Lambda_eo / Lambda_e.
   c.s_e = 1.0 / cfg->tau;
@@ -637,8 +699,9 @@ ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out) {
   c.grav_y = cfg->gravity[1];
   const size_t elem = cfg->precision == IB_LBM_FP64 ? 8 : 4;
   ib_lbm_status st;
-  if ((st = dev_alloc(s, &s->f0, 9 * (size_t)c.plane * elem))) return fail(st, s->err.c_str());
-  if ((st = dev_alloc(s, &s->f1, 9 * (size_t)c.plane * elem))) return fail(st, s->err.c_str());
+  const size_t lat = (size_t)pop_values(c.nx, c.ny) * elem;
+  if ((st = dev_alloc(s, &s->f0, lat))) return fail(st, s->err.c_str());
+  if ((st = dev_alloc(s, &s->f1, lat))) return fail(st, s->err.c_str());
   if ((st = dev_alloc(s, &s->force, 2 * (size_t)c.plane * elem))) return fail(st, s->err.c_str());
   if ((st = dev_alloc(s, &s->state, sizeof(CaseState)))) return fail(st, s->err.c_str());
   c.f[0] = s->f0.p;
@@ -677,13 +740,24 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
       (b->scheme == IB_LBM_MDF && b->mdf_tol > 0 &&
        (b->mdf_nmin < 1 || b->mdf_nmin > b->mdf_iters)) ||
       (b->motion == IB_LBM_FREE && !(b->density_ratio > 0)) ||
-      (b->integrator != IB_LBM_VERLET && b->integrator != IB_LBM_EULER_A1)) {
+      (b->integrator != IB_LBM_VERLET && b->integrator != IB_LBM_EULER_A1) ||
+      (b->mdf_coupled != 0 && b->mdf_coupled != 1)) {
     set_err(&s->err, "invalid body description");
     return IB_LBM_E_INVALID;
   }
   if (!s->bodies.empty() && s->bodies[0].d.scheme != b->scheme) {
     set_err(&s->err, "all bodies of a sim must use the same scheme");
     return IB_LBM_E_INVALID;
+  }
+  const bool coupled = b->scheme == IB_LBM_MDF && b->mdf_coupled;
+  if (b->scheme == IB_LBM_MDF && !s->bodies.empty()) {
+    const ib_lbm_body_desc &o = s->bodies[0].d;
+    if ((o.mdf_coupled != 0) != coupled ||
+        (coupled && (o.mdf_iters != b->mdf_iters || (o.mdf_tol > 0) != (b->mdf_tol > 0) ||
+                     (b->mdf_tol > 0 && (o.mdf_tol != b->mdf_tol || o.mdf_nmin != b->mdf_nmin))))) {
+      set_err(&s->err, "coupled MDF: every body alike, with equal bounds and tolerance");
+      return IB_LBM_E_INVALID;
+    }
   }
   HostBody hb;
   hb.d = *b;
@@ -700,6 +774,7 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.mdf_iters = b->scheme == IB_LBM_MDF ? b->mdf_iters : 1;
   B.mdf_tol = b->scheme == IB_LBM_MDF && b->mdf_tol > 0 ? b->mdf_tol : 0.0;
   B.mdf_nmin = B.mdf_tol > 0 ? b->mdf_nmin : B.mdf_iters;
+  B.mdf_coupled = coupled ? 1 : 0;
   B.motion = b->motion;
   B.internal_mass = b->internal_mass;
   B.integrator = b->integrator;
@@ -774,7 +849,8 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   // bounds |l - k| by (n_b / pi) asin(ns sqrt 2 / (2 R)).  Used when the
   // band is narrow and the workspace with it still fits in LDS.
   B.mdf_band = 0;
-  if (b->scheme == IB_LBM_MDF && B.ns * std::sqrt(2.0) < 2.0 * B.radius) {
+  if (coupled) B.ws_doubles += ws_coupled_doubles(nb, B.max_nodes);
+  if (b->scheme == IB_LBM_MDF && !coupled && B.ns * std::sqrt(2.0) < 2.0 * B.radius) {
     const int w = (int)std::floor(nb / M_PI * std::asin(B.ns * std::sqrt(2.0) / (2.0 * B.radius))) + 1;
     // U at the markers is new space; the band (its half, B being
     // symmetric) overlays the two node-velocity arrays
@@ -842,40 +918,43 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
     return IB_LBM_E_STATE;
   }
   if ((st = build_sim_tables(s))) return st;
+  if (s->split && (st = ensure_pipe_streams(s))) return st;
   s->started = true;
   int64_t left = nsteps;
   if (s->graph_steps > 0 && !s->timing.on && left >= s->graph_steps) {
-    if (!s->graph_exec || s->graph_len != s->graph_steps) {
-      if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
-      s->graph_exec = nullptr;
-      // capture on a private stream (the caller's may be the null stream),
-      // replay on the caller's stream
-      if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-      hipGraph_t g;
-      HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-      for (int i = 0; i < s->graph_steps; i++) {
-        st = enqueue_sim_step(s, false, s->cap_stream);
+    if (s->graph_len != s->graph_steps) {
+      drop_graphs(s);
+      s->graph_len = s->graph_steps;
+    }
+    // capture on a private stream (the caller's may be the null stream),
+    // replay on the caller's stream; one graph per starting lattice
+    if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    while (left >= s->graph_len) {
+      hipGraphExec_t &ge = s->graph_exec[s->host_cur];
+      if (!ge) {
+        hipGraph_t g;
+        HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        // captured steps are plain steps on the capturing stream: capturing
+        // the two-stream pipelined step crashed the host process in the HIP
+        // runtime (cause not identified), so that path is switched off
+        st = enqueue_steps(s, s->graph_len, false, s->cap_stream, s->host_cur, false);
         if (st) {
           hipGraph_t dummy;
           (void)hipStreamEndCapture(s->cap_stream, &dummy);
           return st;
         }
+        HIPCHK(s, hipStreamEndCapture(s->cap_stream, &g));
+        HIPCHK(s, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
       }
-      HIPCHK(s, hipStreamEndCapture(s->cap_stream, &g));
-      HIPCHK(s, hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0));
-      (void)hipGraphDestroy(g);
-      s->graph_len = s->graph_steps;
-    }
-    while (left >= s->graph_len) {
-      HIPCHK(s, hipGraphLaunch(s->graph_exec, s->stream));
+      HIPCHK(s, hipGraphLaunch(ge, s->stream));
       left -= s->graph_len;
+      s->host_cur ^= s->graph_len & 1;
     }
   }
-  if (s->split && left > 0) {
-    if ((st = enqueue_pipelined(s, left, s->timing.on))) return st;
-  } else {
-    for (int64_t i = 0; i < left; i++)
-      if ((st = enqueue_sim_step(s, s->timing.on, s->stream))) return st;
+  if (left > 0) {
+    if ((st = enqueue_steps(s, left, s->timing.on, s->stream, s->host_cur, true))) return st;
+    s->host_cur ^= (int)(left & 1);
   }
   s->host_steps += nsteps;
   return IB_LBM_OK;
@@ -908,6 +987,11 @@ ib_lbm_status ib_lbm_forces(ib_lbm_sim *s, int32_t body_id, ib_lbm_body_state *o
   if (b.flags & IB_LBM_FLAG_NONFINITE) {
     set_err(&s->err, "non-finite force or velocity at body %d", body_id);
     return IB_LBM_E_DIVERGED;
+  }
+  if (b.flags & kFlagExchange) {
+    set_err(&s->err, "body %d: the coupled MDF workgroups of the case did not meet (flags %d)",
+            body_id, b.flags);
+    return IB_LBM_E_STATE;
   }
   if (b.flags & (IB_LBM_FLAG_RANGE | IB_LBM_FLAG_OVERLAP | kFlagCapacity)) {
     if (b.flags & kFlagCapacity)
@@ -1024,13 +1108,16 @@ ib_lbm_status ib_lbm_markers(ib_lbm_sim *s, int32_t body_id, double *out, int32_
   return IB_LBM_OK;
 }
 
-ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, double u_ref,
-                                 double *summary, double *per_marker) {
-  ib_lbm_status st = usable(s);
-  if (st) return st;
-  if (!summary || body_id < 0 || body_id >= (int)s->bodies.size() || kappa < 0 || !(u_ref > 0))
-    return IB_LBM_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+// Diagnostics of body_id staged in device memory at d (8 + 6 n_b doubles),
+// then copied to the host.  Allocates nothing.
+ib_lbm_status diagnostics_into(ib_lbm_sim *s, int32_t body_id, int32_t kappa, double u_ref,
+                               double *summary, double *per_marker, double *d) {
   CaseState cs;
+  ib_lbm_status st;
   if ((st = read_state(s, &cs))) return st;
   if (cs.step < 1) {
     set_err(&s->err, "diagnostics need a completed step");
@@ -1047,14 +1134,27 @@ ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, 
     return IB_LBM_E_DIVERGED;
   }
   const int nb = hb.dev.nb;
-  if ((st = ensure_tmp(s, (size_t)(8 + 6 * nb) * 8))) return st;
-  double *d = (double *)s->d_tmp.p;
   HIPCHK(s, launch_diagnostics(s->cd, cs.cur, (const double *)hb.markers.p, nb, b.xc, b.yc, vx, vy,
                                om, hb.dev.radius, hb.dev.ds, kappa, u_ref, d, d + 8, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   HIPCHK(s, hipMemcpy(summary, d, 8 * 8, hipMemcpyDeviceToHost));
   if (per_marker) HIPCHK(s, hipMemcpy(per_marker, d + 8, (size_t)nb * 6 * 8, hipMemcpyDeviceToHost));
   return IB_LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, double u_ref,
+                                 double *summary, double *per_marker) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!summary || body_id < 0 || body_id >= (int)s->bodies.size() || kappa < 0 || !(u_ref > 0))
+    return IB_LBM_E_INVALID;
+  const int nb = s->bodies[body_id].dev.nb;
+  if ((st = ensure_tmp(s, (size_t)(8 + 6 * nb) * 8))) return st;
+  return diagnostics_into(s, body_id, kappa, u_ref, summary, per_marker, (double *)s->d_tmp.p);
 }
 
 ib_lbm_status ib_lbm_steps_done(ib_lbm_sim *s, int64_t *steps) {
@@ -1078,7 +1178,7 @@ ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s) {
   if (!s) return IB_LBM_E_INVALID;
   if (s->batch) ib_lbm_batch_detach(s->batch, s);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  drop_graphs(s);
   if (s->lq) (void)hipStreamSynchronize(s->lq);
   if (s->iq) (void)hipStreamSynchronize(s->iq);
   for (int k = 0; k < kTimingKinds; k++)
@@ -1192,14 +1292,13 @@ ib_lbm_status ib_lbm_time_collide_stream(ib_lbm_sim *s, int32_t launches, double
   if ((st = build_sim_tables(s))) return st;
   s->started = true;
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
-  const int ntiles = s->cd.tiles_x * s->cd.tiles_y;
+  const LeanArgs la = lean_args(s, s->host_cur, 1);
   hipEvent_t a, b;
   HIPCHK(s, hipEventCreate(&a));
   HIPCHK(s, hipEventCreate(&b));
   hipError_t e = hipEventRecord(a, s->stream);
   for (int i = 0; i < launches && e == hipSuccess; i++)
-    e = launch_collide_stream(s->cd.precision, s->cd.collision, (const CaseDesc *)s->d_case.p,
-                              (const int32_t *)s->d_prefix.p, 1, ntiles, sh, s->stream);
+    e = launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 0, sh, s->stream);
   if (e == hipSuccess) e = hipEventRecord(b, s->stream);
   if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0;
@@ -1263,6 +1362,10 @@ ib_lbm_status ib_lbm_batch_attach(ib_lbm_batch *b, ib_lbm_sim *s) {
     set_err(&b->err, "sims with Zou-He walls are stepped on their own, not in a batch");
     return IB_LBM_E_INVALID;
   }
+  if (!s->bodies.empty() && s->bodies[0].dev.mdf_coupled) {
+    set_err(&b->err, "sims with coupled MDF bodies are stepped on their own, not in a batch");
+    return IB_LBM_E_INVALID;
+  }
   ib_lbm_status st = build_sim_tables(s);
   if (st) return st;
   s->batch = b;
@@ -1280,6 +1383,13 @@ ib_lbm_status ib_lbm_batch_detach(ib_lbm_batch *b, ib_lbm_sim *s) {
   b->sims.erase(it);
   s->batch = nullptr;
   b->dirty = true;
+  // stepped on its own again: no target, and the lattice index the batch
+  // launches left in the device state
+  CaseState cs;
+  BHIPCHK(b, hipMemcpy(&cs, s->state.p, sizeof cs, hipMemcpyDeviceToHost));
+  cs.target = std::numeric_limits<int64_t>::max();
+  BHIPCHK(b, hipMemcpy(s->state.p, &cs, sizeof cs, hipMemcpyHostToDevice));
+  s->host_cur = cs.cur;
   return IB_LBM_OK;
 }
 

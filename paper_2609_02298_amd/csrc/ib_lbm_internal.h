@@ -24,7 +24,7 @@ enum { kFixed = 0, kPrescribedSin = 1, kFree = 2 };
 enum { kImNone = 0, kImFeng = 1 };
 
 // body flags (same values as the public IB_LBM_FLAG_*)
-enum { kFlagNonfinite = 1, kFlagRange = 2, kFlagOverlap = 4, kFlagCapacity = 8 };
+enum { kFlagNonfinite = 1, kFlagRange = 2, kFlagOverlap = 4, kFlagCapacity = 8, kFlagExchange = 16 };
 // case flags
 enum { kCaseHalted = 1 };
 
@@ -32,6 +32,27 @@ constexpr int kMaxBodiesPerCase = 8;
 constexpr int kIbmThreads = 512;
 constexpr int kIbmThreadsFast = 1024;
 constexpr int kHistCols = 16;
+
+// Population storage of a lattice.  Each row is cut along x into segments
+// of kSeg nodes (the last one padded), and the nine populations of one
+// segment are stored one after the other, kSeg values each:
+//   value (i, x, y) at ((y * nseg + x / kSeg) * 9 + i) * kSeg + x % kSeg.
+// A wave of 64 nodes of one row then reads and writes nine runs of 64
+// values that lie together in one block of 9 kSeg values, rather than in
+// nine planes far apart; on lattices larger than the Infinity Cache that
+// keeps more of the HBM traffic in open DRAM pages.  Offsets are 64-bit.
+constexpr int kSegLog = 6;
+constexpr int kSeg = 1 << kSegLog;
+constexpr int kSegBlock = 9 * kSeg;  // values of one segment
+__host__ __device__ inline int pop_segments(int nx) { return (nx + kSeg - 1) >> kSegLog; }
+// offset of population 0 of node (x, y); population i is kSeg * i further
+__host__ __device__ inline int64_t pop_node(int x, int y, int nseg) {
+  return ((int64_t)y * nseg + (x >> kSegLog)) * kSegBlock + (x & (kSeg - 1));
+}
+// values of one lattice
+__host__ __device__ inline int64_t pop_values(int nx, int ny) {
+  return (int64_t)ny * pop_segments(nx) * kSegBlock;
+}
 
 // Mutable per-case state, device resident.
 struct CaseState {
@@ -42,6 +63,11 @@ struct CaseState {
   int32_t done;    // IB workgroups of this step that have finished
   int32_t fbox_valid;  // the union of the bodies' force boxes below is set
   int32_t fbox[4];     // x0 y0 x1 y1 of the nodes that carry IB force
+  // Coupled MDF: the IB workgroups of the case exchange their residuals
+  // through xr (two rounds' worth, alternating), counting arrivals in xcnt;
+  // the last workgroup of a step resets xcnt.
+  int32_t xcnt, xpad;
+  double xr[2][kMaxBodiesPerCase];
 };
 
 // Mutable per-body state, device resident.
@@ -70,6 +96,7 @@ struct BodyDesc {
   int32_t motion, internal_mass;
   int32_t integrator;   // free bodies: kVerlet (Eq. 23) or kEulerA1 (Eq. A1)
   int32_t mdf_band;     // > 0: MDF passes in marker space with this band half-width
+  int32_t mdf_coupled;  // MDF bodies of the case iterate jointly (coupled path)
   int32_t ns;           // support width: 2 (hat) or 4 (P4)
   int32_t window;       // half width of the angular marker window of the gather
   int32_t max_rows, max_nodes;
@@ -99,13 +126,14 @@ struct CaseDesc {
   int32_t collision, precision;
   int32_t bc[4];
   int32_t tiles_x, tiles_y;
-  int32_t nbodies, pad;
-  int64_t plane;        // nx*ny
+  int32_t nbodies;
+  int32_t nseg;         // population segments per row, pop_segments(nx)
+  int64_t plane;        // nx*ny (nodes; the force field has two planes of this size)
   double omega, s_e, s_o, s_q, s_eps;  // relaxation rates
   double rho0, u_bc, inv_ny2;
   double fluid_fx, fluid_fy;
   double grav_x, grav_y;  // gravity acting on bodies (Eq. 22)
-  void *f[2];           // two population lattices (9 planes each)
+  void *f[2];           // two population lattices (segment-blocked, see pop_node)
   void *force;          // IB force density, 2 planes
   CaseState *state;
   BodyDesc *bodies;     // device array of nbodies
@@ -123,7 +151,9 @@ struct CaseDesc {
 //            [padded to even: the end of the hot part]
 //            ix0 iy0 (nb each), ra1 rl1 ra2 (mr each), off (mr+1),
 //            noff (mn+1), nent (nb*ns*ns) [padded to even]
-//   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each)
+//   per step, DF/MDF: rhoX Fx Fy Ftx Fty (nb each), nrho nux nuy (mn each),
+//                     then Ux Uy (nb each, marker-space or coupled MDF) and,
+//                     coupled MDF, Fnx Fny (nb each), pux puy (mn each)
 //   per step, DFC:    Ftx Fty lam (nb each), dlt (9 nb), then the staged
 //                     populations (9 mn of T), overlaid by the W_total node
 //                     array while the correction scale is built and, at the
@@ -150,6 +180,9 @@ __host__ __device__ inline int ws_dyn_doubles(int scheme, int nb, int ns, int mn
   if (scheme == 2) return nb * 12 + (9 * mn * pop_bytes + 7) / 8;
   return nb * 5 + mn * 3;
 }
+// the coupled MDF path adds the marker errors and unrelaxed forces (4 nb)
+// and the node velocities before a trial pass (2 mn)
+__host__ __device__ inline int ws_coupled_doubles(int nb, int mn) { return 4 * nb + 2 * mn; }
 
 // One IB workgroup: the body `body` of case `cas` (body = -1: a case without
 // bodies, which only advances the step counter).
@@ -175,34 +208,46 @@ struct LaunchShape {
   int32_t block_x, block_y, rows_per_thread, xcd_remap;
 };
 
-// Arguments of one pipelined step of a single case: cur, the lattice
-// holding the step's input; the hold rectangle of tiles (htx0, hty0, hntx,
-// hnty).
-struct PipeArgs {
-  int32_t cur;
+// Everything the inner-node collide-stream of one case reads, passed by
+// value.  A sim stepped on its own knows on the host which lattice holds
+// the step's input, so a workgroup's first memory accesses are its
+// populations, with the case's halt flag (and force box) loaded beside
+// them, rather than a chain of loads through the case descriptor and
+// state.  mode: 0 every tile, 1 only the tiles of the hold rectangle
+// (htx0, hty0, hntx x hnty tiles; they read the IB force at every node),
+// 2 every tile outside it (no IB force).  force_on (mode 0): read the IB
+// force inside the case's force box.
+struct LeanArgs {
+  const void *src;
+  void *dst;
+  void *force;
+  const CaseState *state;
+  int32_t nx, ny, nseg, tiles_x, ntiles, rpt, remap, force_on;
   int32_t htx0, hty0, hntx, hnty;
+  double omega, s_e, s_o, s_q, s_eps, rho0, fluid_fx, fluid_fy;
 };
 
 // ---- kernel launchers (defined in the .hip files) ----
+// Inner nodes of every case of a batch, each case's input lattice from its
+// device state (batches flatten (case, tile) through tile_prefix).
 hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
                                  const int32_t *tile_prefix, int ncases, int ntiles,
                                  LaunchShape shape, hipStream_t stream);
+// Inner nodes of one case with its arguments by value (see LeanArgs).
+hipError_t launch_collide_stream_lean(int precision, int collision, const LeanArgs &a, int mode,
+                                      LaunchShape shape, hipStream_t stream);
 // The face nodes (rows 0 and ny-1, columns 0, nx-2, nx-1) with the face
 // closures; face_prefix[i] is the first workgroup of case i (face_blocks per
 // case), nblocks the total; cur < 0 takes each case's lattice from its state.
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
                                        const int32_t *face_prefix, int ncases, int nblocks, int cur,
                                        int force, int general_zg, hipStream_t stream);
-// One part of a pipelined step: near = 1 the hold rectangle, 0 the other tiles.
-hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
-                                      LaunchShape shape, const PipeArgs &pa, int near,
-                                      hipStream_t stream);
-// IB launch over nslots slots; replicas > 1 (with a per-slot ticket and
-// the launch's sequence number, see ibm_kernel) lets the first-started copy
-// of each slot run it.
+// IB launch over nslots slots; replicas > 1 (with a per-slot counter that
+// every copy advances, see ibm_kernel) lets the first-started copy of each
+// slot run it.
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
-                      int lds_bytes, int spread_mode, int fast, int replicas, uint32_t seq,
-                      uint32_t *ticket, hipStream_t stream);
+                      int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
+                      hipStream_t stream);
 hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,

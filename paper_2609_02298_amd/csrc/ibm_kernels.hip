@@ -152,6 +152,7 @@ struct WsLayout {
   double *nrho, *nux, *nuy, *nW;                                 // per-step, nodes
   double *Ux, *Uy, *Bm;  // marker-space MDF: velocities at the markers, band matrix
   int bw;                // its half-width (0: the passes run on the support nodes)
+  double *Fnx, *Fny, *pux, *puy;  // coupled MDF: unrelaxed forces, node velocities before a trial
   int *lmin, *lmax, *rmin, *rmax, *cnt, *ncnt, *nfill;  // construction scratch (per-step area)
 };
 
@@ -177,6 +178,7 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
   // space and the LDS instantiation uses LDS instructions)
   L.rhoX = L.Fx = L.Fy = L.lam = L.dlt = L.nrho = L.nW = L.nux = L.nuy = d;
   L.Ux = L.Uy = L.Bm = d;
+  L.Fnx = L.Fny = L.pux = L.puy = d;
   L.bw = 0;
   L.stage = (void *)d;
   if (B.scheme != kDFC) {
@@ -184,7 +186,12 @@ __device__ __forceinline__ WsLayout carve(double *base, const BodyDesc &B) {
     L.nrho = d; d += mn;
     L.nux = d; d += mn; L.nuy = d; d += mn;
     L.bw = B.mdf_band;
-    L.Ux = d; d += B.mdf_band > 0 ? nb : 0; L.Uy = d; d += B.mdf_band > 0 ? nb : 0;
+    const bool mk = B.mdf_band > 0 || B.mdf_coupled;
+    L.Ux = d; d += mk ? nb : 0; L.Uy = d; d += mk ? nb : 0;
+    if (B.mdf_coupled) {
+      L.Fnx = d; d += nb; L.Fny = d; d += nb;
+      L.pux = d; d += mn; L.puy = d; d += mn;
+    }
     // the band overlays the node velocities, which the marker-space passes
     // no longer need once U^(1) is interpolated
     L.Bm = L.nux;
@@ -528,6 +535,60 @@ __device__ __forceinline__ void copy_doubles(double *dst, const double *src, int
   if ((n & 1) && (int)threadIdx.x == first) dst[n - 1] = src[n - 1];
 }
 
+// Largest value of r over the workgroup (every thread returns it).
+__device__ __forceinline__ double block_max(double r, double *red) {
+  r = wave_max(r);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+  __syncthreads();
+  double m = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = fmax(m, red[w]);
+  return m;
+}
+
+// Coupled MDF: the workgroups of a case's bodies publish their residuals of
+// one round and take the largest over the case.  Thread 0 stores its value
+// in the round's slot (rounds alternate between two slots: a workgroup can
+// only start round e + 2 after every workgroup has counted itself into
+// round e + 1, by which time round e's slot has been read), counts itself in
+// with a release, and waits with acquire loads, bounded to about 2 s, until
+// every body of the case has counted itself into this round.  On expiry the
+// body is flagged and the exchange returns a NaN, which ends its iteration;
+// a body that failed before its passes counts itself into every round at
+// once and leaves a NaN, which the exchange passes on.
+constexpr int kExchangeSpins = 1 << 22;
+__device__ __forceinline__ double case_exchange_max(CaseState *cs, int body, int nbc, int round,
+                                                    double r, double *bsh_x, int *flag) {
+  if (threadIdx.x == 0) {
+    const int slot = round & 1;
+    __hip_atomic_store(&cs->xr[slot][body], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&cs->xcnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int target = (round + 1) * nbc;
+    int spins = 0;
+    while (__hip_atomic_load(&cs->xcnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target &&
+           spins < kExchangeSpins) {
+      __builtin_amdgcn_s_sleep(8);
+      spins++;
+    }
+    double m = r;
+    if (spins >= kExchangeSpins) {
+      m = __builtin_nan("");
+      *flag = 1;
+    } else {
+      for (int b = 0; b < nbc; b++) {
+        const double v = __hip_atomic_load(&cs->xr[slot][b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        m = v != v ? v : fmax(m, v);
+        if (m != m) break;
+      }
+    }
+    *bsh_x = m;
+  }
+  __syncthreads();
+  const double m = *bsh_x;
+  __syncthreads();
+  return m;
+}
+
 // FAST: the 1024-thread instance for DF/MDF bodies with an LDS workspace
 // and gather spreading (no DFC or atomic-scatter code, so that it fits 128
 // VGPRs); marker loops then run one lane per stencil row.
@@ -630,6 +691,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     ish[3] = bs->flags;
     ish[4] = bs->tables_full;
     ish[5] = 0;  // set by build_tables when a node's list outgrows its fixed-width copy
+    ish[6] = 0;  // set when the coupled-MDF workgroups of the case fail to meet
   }
   if (tid == 64) {
     // what the end of the pass needs from the descriptors, staged on chip
@@ -673,6 +735,15 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         bs->box_valid = 0;
         ish[50] = f;
         ish[51] = 0;
+        if (B.scheme == kMDF && B.mdf_coupled) {
+          // the other bodies of a coupled case would wait for this one:
+          // leave a NaN residual and count this body into every round
+          const int body = (int)(&B - c.bodies);
+          const double nan = __builtin_nan("");
+          __hip_atomic_store(&c.state->xr[0][body], nan, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&c.state->xr[1][body], nan, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(&c.state->xcnt, 1 << 24, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       return;
     }
@@ -700,9 +771,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         const int j = j0 + u * nth;
         if (j < S) {
           const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-          const uint32_t p = (uint32_t)y * nx + x;
+          const T *fp = fpop + pop_node(x, y, c.nseg);
 #pragma unroll
-          for (int i = 0; i < 9; i++) v[u][i] = fpop[i * plane + p];
+          for (int i = 0; i < 9; i++) v[u][i] = fp[i * kSeg];
         }
       }
 #pragma unroll
@@ -738,6 +809,113 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
           L.Fty[k] = 2.0 * rX * (L.Udy[k] - Uy);
         }
       }
+    } else if (B.mdf_coupled) {
+      // Coupled multi-body MDF (Sec. 2.5.2, the two-particle path), on the
+      // support nodes.  Every trial pass spreads c omega_0 F^(n), omega_0 =
+      // min(omega_MDF, 0.8), into the node velocities, re-interpolates them
+      // and takes the residual R' of all the case's markers (the bodies'
+      // workgroups exchange theirs); R' > 1.2 R rejects the trial (the node
+      // velocities return to their saved state) and halves c, ending the
+      // iteration once c reaches 1/8, else the trial is a pass: F_total takes
+      // it and the next F^(n) comes from the new interpolation.  The
+      // iteration ends after mdf_iters passes, or, with a tolerance, once at
+      // least mdf_nmin passes are kept and R < tol.  Every workgroup of the
+      // case takes the same decisions from the same exchanged values.
+      const int N = B.mdf_iters;
+      const double tol = B.mdf_tol;
+      const int nmin = tol > 0.0 ? B.mdf_nmin : N;
+      const double om0 = fmin(B.omega_mdf, 0.8);
+      const int body = (int)(&B - c.bodies), nbc = c.nbodies;
+      CaseState *cs = c.state;
+      int round = 0;
+      // pass 1's interpolation of u* and rho(X): errors, unrelaxed forces
+      double rloc = 0.0;
+      for (int kk = tid; kk < LPM * nb; kk += nth) {
+        const int k = kk / LPM, h = kk % LPM;
+        const double rX = interp1<NS, LPM>(L, k, h, L.nrho);
+        double Ux, Uy;
+        interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
+        if (h == 0) {
+          const double ex = L.Udx[k] - Ux, ey = L.Udy[k] - Uy;
+          L.rhoX[k] = rX;
+          L.Fnx[k] = 2.0 * rX * ex;
+          L.Fny[k] = 2.0 * rX * ey;
+          L.Ftx[k] = 0.0;
+          L.Fty[k] = 0.0;
+          rloc = fmax(rloc, sqrt(ex * ex + ey * ey));
+        }
+      }
+      double R = case_exchange_max(cs, body, nbc, round++, block_max(rloc, red), &bsh[16], &ish[6]);
+      for (int j = tid; j < S; j += nth) L.nrho[j] = ds / (2.0 * L.nrho[j]);
+      __syncthreads();
+      double cf = 1.0;
+      int kept = 0;
+      bool stop = R != R;
+      while (!stop && kept < N && !(tol > 0.0 && kept >= nmin && R < tol)) {
+        for (int j = tid; j < S; j += nth) {
+          L.pux[j] = L.nux[j];
+          L.puy[j] = L.nuy[j];
+        }
+        for (;;) {
+          const double w = cf * om0;
+          for (int k = tid; k < nb; k += nth) {
+            L.Fx[k] = w * L.Fnx[k];
+            L.Fy[k] = w * L.Fny[k];
+          }
+          __syncthreads();
+          for (int j = tid; j < S; j += nth) {
+            double sx, sy;
+            gather2<NS>(L, j, L.Fx, L.Fy, sx, sy);
+            L.nux[j] = L.pux[j] + sx * L.nrho[j];
+            L.nuy[j] = L.puy[j] + sy * L.nrho[j];
+          }
+          __syncthreads();
+          rloc = 0.0;
+          for (int kk = tid; kk < LPM * nb; kk += nth) {
+            const int k = kk / LPM, h = kk % LPM;
+            double Ux, Uy;
+            interp2<NS, LPM>(L, k, h, L.nux, L.nuy, Ux, Uy);
+            if (h == 0) {
+              const double ex = L.Udx[k] - Ux, ey = L.Udy[k] - Uy;
+              L.Ux[k] = ex;
+              L.Uy[k] = ey;
+              rloc = fmax(rloc, sqrt(ex * ex + ey * ey));
+            }
+          }
+          const double Rt =
+              case_exchange_max(cs, body, nbc, round++, block_max(rloc, red), &bsh[16], &ish[6]);
+          if (Rt != Rt) {
+            stop = true;
+            break;
+          }
+          if (!(Rt > 1.2 * R)) {
+            for (int k = tid; k < nb; k += nth) {
+              L.Ftx[k] += L.Fx[k];
+              L.Fty[k] += L.Fy[k];
+              L.Fnx[k] = 2.0 * L.rhoX[k] * L.Ux[k];
+              L.Fny[k] = 2.0 * L.rhoX[k] * L.Uy[k];
+            }
+            kept++;
+            R = Rt;
+            __syncthreads();
+            break;
+          }
+          // rejected: back to the velocities before the trial
+          for (int j = tid; j < S; j += nth) {
+            L.nux[j] = L.pux[j];
+            L.nuy[j] = L.puy[j];
+          }
+          __syncthreads();
+          cf *= 0.5;
+          if (cf <= 0.125) {
+            stop = true;
+            break;
+          }
+        }
+      }
+      resmax = R;
+      if (tid == 0) ish[11] = kept;
+      __syncthreads();
     } else if (FAST && L.bw > 0) {
       // MDF, Eq. (12)-(14), in marker space.  Interpolating the updated node
       // velocities of Eq. (14) gives U^(n+1) = U^(n) + omega B F^(n) with
@@ -1022,9 +1200,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         const int j = j0 + u * nth;
         if (j < S) {
           const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-          const uint32_t p = (uint32_t)y * nx + x;
+          const T *fp = fpop + pop_node(x, y, c.nseg);
 #pragma unroll
-          for (int i = 0; i < 9; i++) v[u][i] = fpop[i * plane + p];
+          for (int i = 0; i < 9; i++) v[u][i] = fp[i * kSeg];
         }
       }
 #pragma unroll
@@ -1091,11 +1269,11 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
 #pragma unroll
           for (int i = 0; i < 9; i++) corr[i] += DLT(L, k, i) * w;
         });
-        const uint32_t p = (uint32_t)y * nx + x;
+        T *fw = fpop_w + pop_node(x, y, c.nseg);
 #pragma unroll
         for (int i = 0; i < 9; i++) {
           const T nv = (T)((double)stg[i * mn + j] + corr[i] * ds);
-          fpop_w[i * plane + p] = nv;
+          fw[i * kSeg] = nv;
           stg[i * mn + j] = nv;
         }
       }
@@ -1113,13 +1291,13 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         __syncthreads();
         for (int j = tid; j < S; j += nth) {
           const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-          const uint32_t p = (uint32_t)y * nx + x;
+          T *fw = fpop_w + pop_node(x, y, c.nseg);
           const T na = (T)((double)stg[i0 * mn + j] + accx[j] * ds);
-          fpop_w[i0 * plane + p] = na;
+          fw[i0 * kSeg] = na;
           stg[i0 * mn + j] = na;
           if (i0 + 1 < 9) {
             const T nb2 = (T)((double)stg[(i0 + 1) * mn + j] + accy[j] * ds);
-            fpop_w[(i0 + 1) * plane + p] = nb2;
+            fw[(i0 + 1) * kSeg] = nb2;
             stg[(i0 + 1) * mn + j] = nb2;
           }
         }
@@ -1220,6 +1398,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       vx = 0.0; vy = 0.0; om = 0.0;
     }
     flags |= ish[3];
+    if (ish[6]) flags |= kFlagExchange;
     bs->fhx = a;
     bs->fhy = b;
     bs->torque = cq;
@@ -1249,23 +1428,27 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
 // the FAST instance (every body of the launch DF/MDF, in LDS, gather
 // spreading; see body_step).  With replicas > 1 each slot is launched that
 // many times (one workgroup per XCD for replicas = 8) and the first of them
-// to start takes the slot: it moves ticket[slot] from seq - 1 to seq, the
-// others leave at once.  A pass that shares the chip with a large launch on
-// another stream then starts on whichever XCD frees a compute unit first.
+// to start takes the slot: every copy adds one to the slot's counter
+// ticket[slot], which stream order leaves at a multiple of `replicas` when
+// a launch begins, and the copy that draws that multiple runs the pass; the
+// others leave at once.  No per-launch argument is involved, so the launch
+// can be replayed from a captured graph.  A pass that shares the chip with
+// a large launch on another stream then starts on whichever XCD frees a
+// compute unit first.
 template <typename T, bool FAST>
 __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kernel(
     const CaseDesc *__restrict__ cases, const IbmSlot *__restrict__ slots, int lds_doubles,
-    int spread_mode, int replicas, uint32_t seq, uint32_t *ticket) {
+    int spread_mode, int replicas, uint32_t *ticket) {
   extern __shared__ double dyn[];
   __shared__ double red[6 * ((FAST ? kIbmThreadsFast : kIbmThreads) / 64)];
   // ish: [0..15] flags and switches, [16..48] scan scratch, [50..55] the
   // body's final flags, force-box flag and force box
   __shared__ int ish[56];
-  __shared__ double bsh[16];
+  __shared__ double bsh[17];
   const int slot = replicas > 1 ? (int)blockIdx.x / replicas : (int)blockIdx.x;
   // the ticket is taken by a thread of wave 1 while all threads read the
   // slot and the case state; nothing is written before the outcome is known
-  if (replicas > 1 && threadIdx.x == 64) ish[49] = atomicCAS(&ticket[slot], seq - 1u, seq) == seq - 1u;
+  if (replicas > 1 && threadIdx.x == 64) ish[49] = atomicAdd(&ticket[slot], 1u) % (uint32_t)replicas == 0u;
   const IbmSlot sl = slots[slot];
   const CaseDesc &c = cases[sl.cas];
   CaseState *cs = c.state;
@@ -1310,6 +1493,7 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
       cs->cur = cur ^ 1;
       cs->step = step + 1;
     }
+    cs->xcnt = 0;
     return;
   }
   __threadfence();
@@ -1349,6 +1533,7 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
       }
     }
   cs->done = 0;
+  cs->xcnt = 0;
   if (bflags) {
     cs->flags |= kCaseHalted;
   } else {
@@ -1362,16 +1547,18 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
 }
 
 // ---- boundary-fidelity diagnostics (Sec. 2.8, marker profiles of Sec. 4.2)
-// Density and velocity at node p with the pending IB force (Eq. 4).
+// Density and velocity at node (x, y) with the pending IB force (Eq. 4).
 template <typename T>
-__device__ __forceinline__ void node_moments(const CaseDesc &c, const T *f, const T *frc, uint32_t p,
+__device__ __forceinline__ void node_moments(const CaseDesc &c, const T *f, const T *frc, int x, int y,
                                              double &rho, double &ux, double &uy) {
   const bool shift = sizeof(T) == 4;
   const uint32_t plane = (uint32_t)c.plane;
+  const uint32_t p = (uint32_t)y * c.nx + x;
+  const T *fp = f + pop_node(x, y, c.nseg);
   double s = 0, jx = 0, jy = 0;
 #pragma unroll
   for (int i = 0; i < 9; i++) {
-    const double v = (double)f[i * plane + p] + (shift ? c_w[i] * c.rho0 : 0.0);
+    const double v = (double)fp[i * kSeg] + (shift ? c_w[i] * c.rho0 : 0.0);
     s += v;
     jx += v * c_exi[i];
     jy += v * c_eyi[i];
@@ -1419,7 +1606,7 @@ diag_kernel(CaseDesc c, int buf, const double *mk, int nb, double xc, double yc,
       for (int jx = 0; jx < 2; jx++) {
         const double w = delta1(kHat, (double)(x0 + jx) - X) * delta1(kHat, (double)(y0 + jy) - Y);
         double r, u, v;
-        node_moments<T>(c, f, frc, (uint32_t)(y0 + jy) * nx + (x0 + jx), r, u, v);
+        node_moments<T>(c, f, frc, x0 + jx, y0 + jy, r, u, v);
         rk += r * w;
         uxk += u * w;
         uyk += v * w;
@@ -1456,7 +1643,7 @@ diag_kernel(CaseDesc c, int buf, const double *mk, int nb, double xc, double yc,
       const double rx = x - xc, ry = y - yc;
       if (rx * rx + ry * ry >= ri * ri) continue;
       double r, u, v;
-      node_moments<T>(c, f, frc, (uint32_t)y * nx + x, r, u, v);
+      node_moments<T>(c, f, frc, x, y, r, u, v);
       const double dx = u - (vx - om * ry), dy = v - (vy + om * rx);
       const double mg = sqrt(dx * dx + dy * dy) / u_ref;
       s_in += mg;
@@ -1507,8 +1694,8 @@ hipError_t launch_diagnostics(const CaseDesc &c, int buf, const double *markers,
 int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
-                      int lds_bytes, int spread_mode, int fast, int replicas, uint32_t seq,
-                      uint32_t *ticket, hipStream_t stream) {
+                      int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
+                      hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
   static bool configured = false;
   if (!configured) {
@@ -1529,17 +1716,17 @@ hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots
   if (precision == kPrecFP64) {
     if (fast)
       hipLaunchKernelGGL((ibm_kernel<double, true>), dim3(grid), dim3(kIbmThreadsFast), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
     else
       hipLaunchKernelGGL((ibm_kernel<double, false>), dim3(grid), dim3(kIbmThreads), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
   } else {
     if (fast)
       hipLaunchKernelGGL((ibm_kernel<float, true>), dim3(grid), dim3(kIbmThreadsFast), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
     else
       hipLaunchKernelGGL((ibm_kernel<float, false>), dim3(grid), dim3(kIbmThreads), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, seq, ticket);
+                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
   }
   return hipGetLastError();
 }

@@ -1,7 +1,8 @@
 // Fused D2Q9 collide + stream for gfx950.
 //
 // One thread owns one node per row it visits: it reads the node's nine
-// post-stream populations (coalesced: nine planes, x fastest), collides them
+// post-stream populations (coalesced: nine runs of 64 values of the node's
+// row segment, see pop_node), collides them
 // with BGK + Guo forcing (Eq. 1-4), TRT (Sec. 2.2) or the central-moment
 // operator (Eq. 5), and pushes the nine results to the neighbours of the
 // other lattice ("two-lattice push"), applying the face closures on the fly.
@@ -29,56 +30,71 @@ __device__ __forceinline__ R wgt(int i) {
 }
 
 // ---------------------------------------------------------------- collision
+// This file is compiled without automatic contraction of multiply-adds
+// (-ffp-contract=off): every fused multiply-add is written out with fmad, so
+// each kernel that inlines the collision (plain, pipelined, batched steps,
+// face nodes) performs exactly the same rounding, and a node's result does
+// not depend on which launch updated it.
+template <typename R>
+__device__ __forceinline__ R fmad(R a, R b, R c) {
+  if constexpr (sizeof(R) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
 // f holds the stored values (f, or g = f - w rho0 when SHIFT).  sum_f is
-// sum_i f_i, so the equilibrium in either form is w_i (sum_f + rho P_i(u)).
+// sum_i f_i, so the equilibrium in either form is w_i (sum_f + rho P_i(u)),
+// P_i = 3 e.u + 4.5 (e.u)^2 - 1.5 u.u; m15uu = -1.5 u.u.
 // Everything is computed in place to keep the register footprint small.
 template <typename R>
-__device__ __forceinline__ R eq_term(int i, R sum, R rho, R ux, R uy, R uu) {
+__device__ __forceinline__ R eq_term(int i, R sum, R rho, R ux, R uy, R m15uu) {
   const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
-  return wgt<R>(i) * (sum + rho * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
+  return wgt<R>(i) * fmad(rho, fmad(R(4.5) * eu, eu, fmad(R(3), eu, m15uu)), sum);
 }
+// Guo source w_i [3 (e - u) + 9 (e.u) e].F
 template <typename R>
 __device__ __forceinline__ R guo_term(int i, R ux, R uy, R Fx, R Fy, R uF) {
   const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
   const R eF = R(EXI(i)) * Fx + R(EYI(i)) * Fy;
-  return wgt<R>(i) * (R(3) * (eF - uF) + R(9) * eu * eF);
+  return wgt<R>(i) * fmad(R(9) * eu, eF, R(3) * (eF - uF));
 }
 
-template <typename R, bool SHIFT, int COL>
-__device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c) {
+// C carries the rates (omega, s_e, s_o, s_q, s_eps) and rho0: a CaseDesc or
+// the by-value LeanArgs.
+template <typename R, bool SHIFT, int COL, typename C>
+__device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const C &c) {
   const R sum = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const R rho = SHIFT ? R(c.rho0) + sum : sum;
   const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   const R inv_rho = R(1) / rho;
-  const R ux = (jx + R(0.5) * Fx) * inv_rho;
-  const R uy = (jy + R(0.5) * Fy) * inv_rho;
+  const R ux = fmad(R(0.5), Fx, jx) * inv_rho;
+  const R uy = fmad(R(0.5), Fy, jy) * inv_rho;
 
   if constexpr (COL == kBGK) {
-    const R uu = ux * ux + uy * uy;
-    const R uF = ux * Fx + uy * Fy;
+    const R m15uu = R(-1.5) * fmad(ux, ux, uy * uy);
+    const R uF = fmad(ux, Fx, uy * Fy);
     const R om = R(c.omega);
-    const R pf = R(1) - R(0.5) * om;
+    const R pf = fmad(R(-0.5), om, R(1));
 #pragma unroll
     for (int i = 0; i < 9; i++)
-      f[i] = f[i] - om * (f[i] - eq_term<R>(i, sum, rho, ux, uy, uu)) +
-             pf * guo_term<R>(i, ux, uy, Fx, Fy, uF);
+      f[i] = fmad(pf, guo_term<R>(i, ux, uy, Fx, Fy, uF),
+                  fmad(-om, f[i] - eq_term<R>(i, sum, rho, ux, uy, m15uu), f[i]));
   } else if constexpr (COL == kTRT) {
-    const R uu = ux * ux + uy * uy;
-    const R uF = ux * Fx + uy * Fy;
+    const R m15uu = R(-1.5) * fmad(ux, ux, uy * uy);
+    const R uF = fmad(ux, Fx, uy * Fy);
     const R se = R(c.s_e), so = R(c.s_o);
-    const R pe = R(1) - R(0.5) * se, po = R(1) - R(0.5) * so;
-    f[0] = f[0] - se * (f[0] - eq_term<R>(0, sum, rho, ux, uy, uu)) +
-           pe * guo_term<R>(0, ux, uy, Fx, Fy, uF);
+    const R pe = fmad(R(-0.5), se, R(1)), po = fmad(R(-0.5), so, R(1));
+    f[0] = fmad(pe, guo_term<R>(0, ux, uy, Fx, Fy, uF),
+                fmad(-se, f[0] - eq_term<R>(0, sum, rho, ux, uy, m15uu), f[0]));
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
       const int j = OPPI(i);
       if (j < i) continue;
-      const R ei = eq_term<R>(i, sum, rho, ux, uy, uu), ej = eq_term<R>(j, sum, rho, ux, uy, uu);
+      const R ei = eq_term<R>(i, sum, rho, ux, uy, m15uu), ej = eq_term<R>(j, sum, rho, ux, uy, m15uu);
       const R si = guo_term<R>(i, ux, uy, Fx, Fy, uF), sj = guo_term<R>(j, ux, uy, Fx, Fy, uF);
       const R fp = R(0.5) * (f[i] + f[j]), fm = R(0.5) * (f[i] - f[j]);
-      const R even = -se * (fp - R(0.5) * (ei + ej)) + pe * R(0.5) * (si + sj);
-      const R odd = -so * (fm - R(0.5) * (ei - ej)) + po * R(0.5) * (si - sj);
+      const R even = fmad(pe, R(0.5) * (si + sj), -se * fmad(R(-0.5), ei + ej, fp));
+      const R odd = fmad(po, R(0.5) * (si - sj), -so * fmad(R(-0.5), ei - ej, fm));
       f[i] = f[i] + even + odd;
       f[j] = f[j] + even - odd;
     }
@@ -92,13 +108,14 @@ __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c
     R a10 = f[3], a11 = f[0], a12 = f[1];
     R a20 = f[6], a21 = f[2], a22 = f[5];
     const R ux2 = ux * ux, uy2 = uy * uy;
-    // forward along x: (v-1, v0, v1) -> (k0, k1, k2)
+    // forward along x: (v-1, v0, v1) -> (k0, k1, k2):
+    // k0 = s0, k1 = s1 - u s0, k2 = s2 - 2 u s1 + u^2 s0
 #define IBL_FWD(u, u2, m, z, p)                                  \
     {                                                            \
       const R s0 = (m) + (z) + (p), s1 = (p) - (m), s2 = (p) + (m); \
       (m) = s0;                                                  \
-      (z) = s1 - (u) * s0;                                       \
-      (p) = s2 - R(2) * (u) * s1 + (u2) * s0;                    \
+      (z) = fmad(-(u), s0, s1);                                  \
+      (p) = fmad((u2), s0, fmad(R(-2) * (u), s1, s2));           \
     }
     IBL_FWD(ux, ux2, a00, a01, a02);
     IBL_FWD(ux, ux2, a10, a11, a12);
@@ -117,27 +134,28 @@ __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const CaseDesc &c
     const R om = R(c.omega), sq = R(c.s_q), seps = R(c.s_eps);
     const R r0 = SHIFT ? R(c.rho0) : R(0);
     const R third = R(1) / R(3);
-    const R E20 = sum * third - r0 * ux2;
-    const R E02 = sum * third - r0 * uy2;
+    const R E20 = fmad(-r0, ux2, sum * third);
+    const R E02 = fmad(-r0, uy2, sum * third);
     const R E11 = -r0 * ux * uy;
     const R E21 = r0 * uy * (third + ux2);
     const R E12 = r0 * ux * (third + uy2);
-    const R E22 = sum * (R(1) / R(9)) - r0 * (third * (ux2 + uy2) + ux2 * uy2);
-    const R pq = (R(1) - R(0.5) * sq) * third;
+    const R E22 = fmad(-r0, fmad(third, ux2 + uy2, ux2 * uy2), sum * (R(1) / R(9)));
+    const R pq = fmad(R(-0.5), sq, R(1)) * third;
     a01 += Fx;                                       // k10
     a10 += Fy;                                       // k01
-    a02 = a02 - om * (a02 - E20);                    // k20
-    a20 = a20 - om * (a20 - E02);                    // k02
-    a11 = a11 - om * (a11 - E11);                    // k11
-    a12 = a12 - sq * (a12 - E21) + pq * Fy;          // k21
-    a21 = a21 - sq * (a21 - E12) + pq * Fx;          // k12
-    a22 = a22 - seps * (a22 - E22);                  // k22
-    // back: central -> raw moments, then the 3-point values at -1, 0, 1
+    a02 = fmad(-om, a02 - E20, a02);                 // k20
+    a20 = fmad(-om, a20 - E02, a20);                 // k02
+    a11 = fmad(-om, a11 - E11, a11);                 // k11
+    a12 = fmad(pq, Fy, fmad(-sq, a12 - E21, a12));   // k21
+    a21 = fmad(pq, Fx, fmad(-sq, a21 - E12, a21));   // k12
+    a22 = fmad(-seps, a22 - E22, a22);               // k22
+    // back: central -> raw moments, then the 3-point values at -1, 0, 1:
+    // M1 = k1 + u k0, M2 = k2 + 2 u k1 + u^2 k0
 #define IBL_BWD(u, u2, m, z, p)                                  \
     {                                                            \
       const R M0 = (m);                                          \
-      const R M1 = (z) + (u) * M0;                               \
-      const R M2 = (p) + R(2) * (u) * (z) + (u2) * M0;           \
+      const R M1 = fmad((u), M0, (z));                           \
+      const R M2 = fmad((u2), M0, fmad(R(2) * (u), (z), (p)));   \
       (z) = M0 - M2;                                             \
       (p) = R(0.5) * (M2 + M1);                                  \
       (m) = R(0.5) * (M2 - M1);                                  \
@@ -178,8 +196,7 @@ __device__ __forceinline__ bool is_vel(int b) { return b == kVelParabolic || b =
 //   code short.
 template <typename T, bool GZG>
 __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
-  const int nx = c.nx, ny = c.ny;
-  const uint32_t plane = (uint32_t)c.plane;
+  const int nx = c.nx, ny = c.ny, nseg = c.nseg;
   int xd = x + c_ex[i], yd = y + c_ey[i];
   bool cw = xd < 0, ce = xd >= nx, cs = yd < 0, cn = yd >= ny;
   if (cw && c.bc[kFaceW] == kPeriodic) { xd += nx; cw = false; }
@@ -217,14 +234,14 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
       v = v - T(6) * wgt<T>(i) * T(c.rho0) * (T(c_ex[i]) * uw);
     }
   }
+  T *d = dst + j * kSeg;
   if (!GZG) {
-    dst[(uint32_t)j * plane + (uint32_t)ys * nx + xs] = v;
+    d[pop_node(xs, ys, nseg)] = v;
     if (c.bc[kFaceE] == kZeroGradient && xs == nx - 2 && (j == 3 || j == 6 || j == 7))
-      dst[(uint32_t)j * plane + (uint32_t)ys * nx + (nx - 1)] = v;
+      d[pop_node(nx - 1, ys, nseg)] = v;
     return;
   }
-  T *d = dst + (uint32_t)j * plane;
-  d[(uint32_t)ys * nx + xs] = v;
+  d[pop_node(xs, ys, nseg)] = v;
   // the column (W / E) and row (S / N) this value is copied to, and their
   // corner when both apply
   int xc = -1, yc = -1;
@@ -232,10 +249,10 @@ __device__ void push_one(const CaseDesc &c, T *dst, int x, int y, int i, T v) {
   if (c.bc[kFaceE] == kZeroGradient && xs == nx - 2 && c_ex[j] < 0) xc = nx - 1;
   if (c.bc[kFaceS] == kZeroGradient && ys == 1 && c_ey[j] > 0) yc = 0;
   if (c.bc[kFaceN] == kZeroGradient && ys == ny - 2 && c_ey[j] < 0) yc = ny - 1;
-  if (xc >= 0) d[(uint32_t)ys * nx + xc] = v;
+  if (xc >= 0) d[pop_node(xc, ys, nseg)] = v;
   if (yc >= 0) {
-    d[(uint32_t)yc * nx + xs] = v;
-    if (xc >= 0) d[(uint32_t)yc * nx + xc] = v;
+    d[pop_node(xs, yc, nseg)] = v;
+    if (xc >= 0) d[pop_node(xc, yc, nseg)] = v;
   }
 }
 
@@ -271,6 +288,27 @@ __device__ __forceinline__ void node_force(T *frc, uint32_t plane, uint32_t p, i
   }
 }
 
+// Offsets, from a node's population-0 offset, of the nodes its pushes reach
+// in x: e_x = +1 from the last lane of a segment lands in the next segment,
+// e_x = -1 from its first lane in the previous one.
+__device__ __forceinline__ int seg_dx_plus(int x) {
+  return (x & (kSeg - 1)) == kSeg - 1 ? kSegBlock - (kSeg - 1) : 1;
+}
+__device__ __forceinline__ int seg_dx_minus(int x) {
+  return (x & (kSeg - 1)) == 0 ? (kSeg - 1) - kSegBlock : -1;
+}
+
+// The nine pushes of an inner node (every link stays inside the lattice).
+// d: the destination lattice at the node's population-0 offset; rs: values
+// per row (nseg kSegBlock).
+template <typename T>
+__device__ __forceinline__ void push_inner(T *__restrict__ d, int dxp, int dxm, int rs,
+                                           const T (&f)[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; i++)
+    d[i * kSeg + (EXI(i) > 0 ? dxp : (EXI(i) < 0 ? dxm : 0)) + EYI(i) * rs] = f[i];
+}
+
 // Collide and stream the inner nodes (1 <= x <= nx-3, 1 <= y <= ny-2) of
 // tile (tx, ty) of case c from f[cur] into f[cur^1]: every link stays inside
 // the lattice, so every push is a plain store.  The other nodes (the face
@@ -286,7 +324,7 @@ __device__ __forceinline__ void collide_stream_tile(const CaseDesc *cp, int tx, 
   T *__restrict__ dst = (T *)c.f[cur ^ 1];
   T *__restrict__ frc = (T *)c.force;
   const int TX = blockDim.x, TY = blockDim.y * rpt;
-  const int nx = c.nx, ny = c.ny;
+  const int nx = c.nx, ny = c.ny, nseg = c.nseg;
   const uint32_t plane = (uint32_t)c.plane;
   const int x = tx * TX + threadIdx.x;
   const int ybase = ty * TY;
@@ -300,69 +338,18 @@ __device__ __forceinline__ void collide_stream_tile(const CaseDesc *cp, int tx, 
   }
   const T ffx = T(c.fluid_fx), ffy = T(c.fluid_fy);
   if (x < 1 || x > nx - 3) return;
+  const int dxp = seg_dx_plus(x), dxm = seg_dx_minus(x), rs = nseg * kSegBlock;
   for (int r = 0; r < rpt; r++) {
     const int y = ybase + threadIdx.y + r * blockDim.y;
     if (y < 1 || y > ny - 2) continue;
-    const uint32_t p = (uint32_t)y * nx + x;
+    const int64_t b0 = pop_node(x, y, nseg);
     T f[9];
 #pragma unroll
-    for (int i = 0; i < 9; i++) f[i] = src[(uint32_t)i * plane + p];
+    for (int i = 0; i < 9; i++) f[i] = src[b0 + i * kSeg];
     T Fx = ffx, Fy = ffy;
-    node_force<T>(frc, plane, p, x, y, tile_force, fb0, fy0, fb1, fy1, Fx, Fy);
+    node_force<T>(frc, plane, (uint32_t)y * nx + x, x, y, tile_force, fb0, fy0, fb1, fy1, Fx, Fy);
     collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
-#pragma unroll
-    for (int i = 0; i < 9; i++) dst[(uint32_t)i * plane + p + EXI(i) + EYI(i) * nx] = f[i];
-  }
-}
-
-// The hold-rectangle tiles of a pipelined step (a few dozen workgroups on
-// the step's critical path, so latency rather than bandwidth): every row's
-// populations and IB force are loaded before any is used, and before the
-// case's halt flag is known.  The force is read at every node: outside the
-// force box it is zero (each step's collide-stream consumes the box of the
-// previous IB pass), so the result is that of collide_stream_tile.
-template <typename T, int COL, int RPT>
-__device__ __forceinline__ void collide_stream_tile_near(const CaseDesc *cp, int tx, int ty, int cur) {
-  const CaseDesc &c = *cp;
-  const CaseState *cs = c.state;
-  const T *__restrict__ src = (const T *)c.f[cur];
-  T *__restrict__ dst = (T *)c.f[cur ^ 1];
-  T *__restrict__ frc = (T *)c.force;
-  const int TX = blockDim.x, TY = blockDim.y * RPT;
-  const int nx = c.nx, ny = c.ny;
-  const uint32_t plane = (uint32_t)c.plane;
-  const int x = tx * TX + threadIdx.x;
-  const int ybase = ty * TY;
-  if (x < 1 || x > nx - 3) return;
-  T f[RPT][9], fa[RPT], fb[RPT];
-  bool ok[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; r++) {
-    const int y = ybase + threadIdx.y + r * blockDim.y;
-    ok[r] = y >= 1 && y <= ny - 2;
-    const uint32_t p = (uint32_t)(ok[r] ? y : 1) * nx + x;
-#pragma unroll
-    for (int i = 0; i < 9; i++) f[r][i] = src[(uint32_t)i * plane + p];
-    fa[r] = frc[p];
-    fb[r] = frc[plane + p];
-  }
-  if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
-  const T ffx = T(c.fluid_fx), ffy = T(c.fluid_fy);
-#pragma unroll
-  for (int r = 0; r < RPT; r++) {
-    if (!ok[r]) continue;
-    const int y = ybase + threadIdx.y + r * blockDim.y;
-    const uint32_t p = (uint32_t)y * nx + x;
-    T Fx = ffx, Fy = ffy;
-    if (fa[r] != T(0) || fb[r] != T(0)) {
-      Fx += fa[r];
-      Fy += fb[r];
-      frc[p] = T(0);
-      frc[plane + p] = T(0);
-    }
-    collide<T, sizeof(T) == 4, COL>(f[r], Fx, Fy, c);
-#pragma unroll
-    for (int i = 0; i < 9; i++) dst[(uint32_t)i * plane + p + EXI(i) + EYI(i) * nx] = f[r][i];
+    push_inner<T>(dst + b0, dxp, dxm, rs, f);
   }
 }
 
@@ -393,11 +380,93 @@ __global__ __launch_bounds__(1024) void collide_stream_kernel(const CaseDesc *__
   collide_stream_tile<T, COL>(cp, local % cp->tiles_x, local / cp->tiles_x, cs->cur, rpt, true);
 }
 
+__device__ __forceinline__ int ld_agent(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inner nodes of one case from by-value arguments (LeanArgs).  The halt
+// flag is loaded after each row's populations and tested once they have
+// arrived (an atomic load, which the compiler keeps in place), so that no
+// chain of dependent loads precedes the data.  The flag can only be set by
+// the IB pass of an earlier step; a pipelined far tile that misses a halt of
+// the concurrent IB pass writes only the lattice that the halted case no
+// longer reads.
+template <typename T, int COL, int MODE>
+__global__ __launch_bounds__(1024) void collide_stream_lean_kernel(const LeanArgs a) {
+  const int nb = gridDim.x;
+  int t = blockIdx.x;
+  if (a.remap) t = (t & 7) * (nb >> 3) + (t >> 3);
+  int tx, ty;
+  if (MODE == 1) {
+    if (t >= a.hntx * a.hnty) return;
+    tx = a.htx0 + t % a.hntx;
+    ty = a.hty0 + t / a.hntx;
+  } else {
+    if (t >= a.ntiles) return;
+    tx = t % a.tiles_x;
+    ty = t / a.tiles_x;
+    if (MODE == 2 && tx >= a.htx0 && tx < a.htx0 + a.hntx && ty >= a.hty0 && ty < a.hty0 + a.hnty)
+      return;
+  }
+  const T *__restrict__ src = (const T *)a.src;
+  T *__restrict__ dst = (T *)a.dst;
+  T *__restrict__ frc = (T *)a.force;
+  const CaseState *cs = a.state;
+  const int rpt = a.rpt;
+  const int TX = blockDim.x, TY = blockDim.y * rpt;
+  const int nx = a.nx, ny = a.ny, nseg = a.nseg;
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const int x = tx * TX + threadIdx.x;
+  if (x < 1 || x > nx - 3) return;
+  const int ybase = ty * TY;
+  const int dxp = seg_dx_plus(x), dxm = seg_dx_minus(x), rs = nseg * kSegBlock;
+  const T ffx = T(a.fluid_fx), ffy = T(a.fluid_fy);
+  for (int r = 0; r < rpt; r++) {
+    const int y = ybase + threadIdx.y + r * blockDim.y;
+    if (y < 1 || y > ny - 2) continue;
+    const int64_t b0 = pop_node(x, y, nseg);
+    T f[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) f[i] = src[b0 + i * kSeg];
+    const uint32_t p = (uint32_t)y * nx + x;
+    T Fx = ffx, Fy = ffy;
+    T fa = T(0), fb = T(0);
+    if (MODE == 1) {
+      fa = frc[p];
+      fb = frc[plane + p];
+    }
+    // the flag and the force box, as loads issued after the populations
+    // (kept in place as atomics) that arrive with them
+    const int halted = ld_agent(&cs->flags) & kCaseHalted;
+    int fv = 0, f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+    if (MODE == 0) {
+      fv = ld_agent(&cs->fbox_valid);
+      f0 = ld_agent(&cs->fbox[0]);
+      f1 = ld_agent(&cs->fbox[1]);
+      f2 = ld_agent(&cs->fbox[2]);
+      f3 = ld_agent(&cs->fbox[3]);
+    }
+    if (halted) return;
+    if (MODE == 1) {
+      if (fa != T(0) || fb != T(0)) {
+        Fx += fa;
+        Fy += fb;
+        frc[p] = T(0);
+        frc[plane + p] = T(0);
+      }
+    } else if (MODE == 0) {
+      node_force<T>(frc, plane, p, x, y, a.force_on && fv != 0, f0, f1, f2, f3, Fx, Fy);
+    }
+    collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, a);
+    push_inner<T>(dst + b0, dxp, dxm, rs, f);
+  }
+}
+
 // The face nodes of every case, kFaceBlock per workgroup (face_prefix[i] is
 // the first workgroup of case i, so the case is uniform in a workgroup), with
 // the face closures.  cur < 0: each case's current lattice from its state;
-// otherwise the lattice given (a pipelined step, whose case state the IB pass
-// may be updating).
+// otherwise the lattice given (a sim stepped on its own, whose case state
+// the IB pass of a pipelined step may be updating).
 template <typename T, int COL, bool GZG>
 __global__ __launch_bounds__(kFaceBlock) void collide_stream_face_kernel(const CaseDesc *__restrict__ cases,
                                                                   const int32_t *__restrict__ face_prefix,
@@ -432,24 +501,25 @@ __global__ __launch_bounds__(kFaceBlock) void collide_stream_face_kernel(const C
   }
   const uint32_t plane = (uint32_t)c.plane;
   const uint32_t p = (uint32_t)y * nx + x;
+  const int64_t pn = pop_node(x, y, c.nseg);
   // The populations are loaded before the case state is known (a latency
   // chain on a small launch): from the given lattice, or from both lattices
   // when the state names it.
   T f[9];
   int cur = cur_arg;
   if (cur >= 0) {
-    const T *__restrict__ src = (const T *)c.f[cur];
+    const T *__restrict__ src = (const T *)c.f[cur] + pn;
 #pragma unroll
-    for (int i = 0; i < 9; i++) f[i] = src[(uint32_t)i * plane + p];
+    for (int i = 0; i < 9; i++) f[i] = src[i * kSeg];
     if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
   } else {
-    const T *__restrict__ s0 = (const T *)c.f[0];
-    const T *__restrict__ s1 = (const T *)c.f[1];
+    const T *__restrict__ s0 = (const T *)c.f[0] + pn;
+    const T *__restrict__ s1 = (const T *)c.f[1] + pn;
     T g[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
-      f[i] = s0[(uint32_t)i * plane + p];
-      g[i] = s1[(uint32_t)i * plane + p];
+      f[i] = s0[i * kSeg];
+      g[i] = s1[i * kSeg];
     }
     if (cs->step >= cs->target || (cs->flags & kCaseHalted)) return;
     cur = cs->cur;
@@ -507,12 +577,10 @@ __global__ __launch_bounds__(256) void zou_he_kernel(const CaseDesc *__restrict_
   } else if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) {
     return;
   }
-  T *__restrict__ f = (T *)c.f[cur ^ 1];
-  const uint32_t plane = (uint32_t)c.plane;
-  const uint32_t p = (uint32_t)y * nx + x;
+  T *__restrict__ f = (T *)c.f[cur ^ 1] + pop_node(x, y, c.nseg);
   T v[9];
 #pragma unroll
-  for (int i = 0; i < 9; i++) v[i] = f[i * plane + p];
+  for (int i = 0; i < 9; i++) v[i] = f[i * kSeg];
   if ((w || e) && (so || no)) {
     const int sx = w ? 1 : -1, sy = so ? 1 : -1;
     const int ix = sx > 0 ? 1 : 3, iy = sy > 0 ? 2 : 4;
@@ -523,31 +591,31 @@ __global__ __launch_bounds__(256) void zou_he_kernel(const CaseDesc *__restrict_
     v[ix] = v[OPPI(ix)];
     v[iy] = v[OPPI(iy)];
     v[id] = v[OPPI(id)];
-    const uint32_t pc = (uint32_t)(y + sy) * nx + (x + sx);
+    const T *fc = (const T *)c.f[cur ^ 1] + pop_node(x + sx, y + sy, c.nseg);
     double rc = 0.0, known = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; i++) {
-      rc += (double)f[i * plane + pc];
+      rc += (double)fc[i * kSeg];
       if (i != ia && i != ib) known += (double)v[i];
     }
     const T b = T(0.5 * (rc - known));
-    f[ix * plane + p] = v[ix];
-    f[iy * plane + p] = v[iy];
-    f[id * plane + p] = v[id];
-    f[ia * plane + p] = b;
-    f[ib * plane + p] = b;
+    f[ix * kSeg] = v[ix];
+    f[iy * kSeg] = v[iy];
+    f[id * kSeg] = v[id];
+    f[ia * kSeg] = b;
+    f[ib * kSeg] = b;
   } else if (so || no) {
     const int in = so ? 2 : 4, d1 = so ? 5 : 8, d2 = so ? 6 : 7;
     const T t = T(0.5) * (v[1] - v[3]);
-    f[in * plane + p] = v[OPPI(in)];
-    f[d1 * plane + p] = v[OPPI(d1)] - t;
-    f[d2 * plane + p] = v[OPPI(d2)] + t;
+    f[in * kSeg] = v[OPPI(in)];
+    f[d1 * kSeg] = v[OPPI(d1)] - t;
+    f[d2 * kSeg] = v[OPPI(d2)] + t;
   } else {
     const int in = w ? 1 : 3, d1 = w ? 5 : 6, d2 = w ? 8 : 7;
     const T t = T(0.5) * (v[2] - v[4]);
-    f[in * plane + p] = v[OPPI(in)];
-    f[d1 * plane + p] = v[OPPI(d1)] - t;
-    f[d2 * plane + p] = v[OPPI(d2)] + t;
+    f[in * kSeg] = v[OPPI(in)];
+    f[d1 * kSeg] = v[OPPI(d1)] - t;
+    f[d2 * kSeg] = v[OPPI(d2)] + t;
   }
 }
 
@@ -559,42 +627,6 @@ hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int c
   else
     hipLaunchKernelGGL(zou_he_kernel<float>, dim3(blocks), dim3(256), 0, stream, c, cur);
   return hipGetLastError();
-}
-
-// One part of a pipelined step of a single case (see PipeArgs): the tiles
-// of the hold rectangle (NEAR), which read the IB force and are read by the
-// IB pass, or all other tiles, which do neither (force = 0, passed at run
-// time, which keeps this instance's register allocation that of the plain
-// kernel).  The input lattice `cur` comes from the host: the IB pass of the
-// previous step may still be updating the case state while the far tiles
-// run.
-template <typename T, int COL, bool NEAR>
-__global__ __launch_bounds__(1024) void collide_stream_pipe_kernel(const CaseDesc *__restrict__ cases,
-                                                                   int ntiles, int rpt, int xcd_remap,
-                                                                   PipeArgs pa, int force) {
-  const CaseDesc *cp = cases;
-  const CaseState *cs = cp->state;
-  const int nb = gridDim.x;
-  int t = blockIdx.x;
-  if (xcd_remap) t = (t & 7) * (nb >> 3) + (t >> 3);
-  if (NEAR) {
-    if (t >= pa.hntx * pa.hnty) return;
-    const int tx = pa.htx0 + t % pa.hntx, ty = pa.hty0 + t / pa.hntx;
-    if (rpt == 1) {
-      collide_stream_tile_near<T, COL, 1>(cp, tx, ty, pa.cur);
-    } else if (rpt == 2) {
-      collide_stream_tile_near<T, COL, 2>(cp, tx, ty, pa.cur);
-    } else {
-      if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
-      collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, true);
-    }
-    return;
-  }
-  if (__hip_atomic_load(&cs->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kCaseHalted) return;
-  if (t >= ntiles) return;
-  const int tx = t % cp->tiles_x, ty = t / cp->tiles_x;
-  if (tx >= pa.htx0 && tx < pa.htx0 + pa.hntx && ty >= pa.hty0 && ty < pa.hty0 + pa.hnty) return;
-  collide_stream_tile<T, COL>(cp, tx, ty, pa.cur, rpt, force != 0);
 }
 
 #define IBL_DISPATCH(precision, collision, LAUNCH)                                             \
@@ -641,22 +673,19 @@ hipError_t launch_collide_stream_faces(int precision, int collision, const CaseD
   return hipGetLastError();
 }
 
-hipError_t launch_collide_stream_pipe(int precision, int collision, const CaseDesc *cases, int ntiles,
-                                      LaunchShape shape, const PipeArgs &pa, int near,
-                                      hipStream_t stream) {
-  if (ntiles <= 0) return hipSuccess;
-  int grid = near ? pa.hntx * pa.hnty : ntiles;
-  if (shape.xcd_remap) grid = (grid + 7) / 8 * 8;
+hipError_t launch_collide_stream_lean(int precision, int collision, const LeanArgs &a, int mode,
+                                      LaunchShape shape, hipStream_t stream) {
+  int grid = mode == 1 ? a.hntx * a.hnty : a.ntiles;
+  if (grid <= 0) return hipSuccess;
+  if (a.remap) grid = (grid + 7) / 8 * 8;
   dim3 block(shape.block_x, shape.block_y);
-  const int rpt = shape.rows_per_thread;
-  const int remap = shape.xcd_remap;
-#define IBL_LAUNCH(T, C)                                                                        \
-  if (near)                                                                                     \
-    hipLaunchKernelGGL((collide_stream_pipe_kernel<T, C, true>), dim3(grid), block, 0, stream,  \
-                       cases, ntiles, rpt, remap, pa, 1);                                       \
-  else                                                                                          \
-    hipLaunchKernelGGL((collide_stream_pipe_kernel<T, C, false>), dim3(grid), block, 0, stream, \
-                       cases, ntiles, rpt, remap, pa, 0)
+#define IBL_LAUNCH(T, C)                                                                           \
+  if (mode == 1)                                                                                   \
+    hipLaunchKernelGGL((collide_stream_lean_kernel<T, C, 1>), dim3(grid), block, 0, stream, a);   \
+  else if (mode == 2)                                                                              \
+    hipLaunchKernelGGL((collide_stream_lean_kernel<T, C, 2>), dim3(grid), block, 0, stream, a);   \
+  else                                                                                             \
+    hipLaunchKernelGGL((collide_stream_lean_kernel<T, C, 0>), dim3(grid), block, 0, stream, a)
   IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
   return hipGetLastError();
@@ -677,13 +706,13 @@ __global__ void init_eq_kernel(CaseDesc c, int buf) {
   else if (c.bc[0] == kVelUniform || c.bc[1] == kVelUniform || c.bc[2] == kVelUniform ||
            c.bc[3] == kVelUniform)
     ux = c.u_bc;
-  T *f = (T *)c.f[buf];
+  T *f = (T *)c.f[buf] + pop_node((int)(p - (int64_t)y * c.nx), y, c.nseg);
   const bool shift = sizeof(T) == 4;
   for (int i = 0; i < 9; i++) {
     const double eu = c_ex[i] * ux;
     const double w = wgt<double>(i);
     const double feq = w * c.rho0 * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * ux * ux);
-    f[i * c.plane + p] = (T)(shift ? feq - w * c.rho0 : feq);
+    f[i * kSeg] = (T)(shift ? feq - w * c.rho0 : feq);
   }
   T *frc = (T *)c.force;
   frc[p] = T(0);
@@ -705,12 +734,13 @@ template <typename T>
 __global__ void fields_kernel(CaseDesc c, int buf, double *rho, double *ux, double *uy) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= c.plane) return;
-  const T *f = (const T *)c.f[buf];
+  const int y = (int)(p / c.nx), x = (int)(p - (int64_t)y * c.nx);
+  const T *f = (const T *)c.f[buf] + pop_node(x, y, c.nseg);
   const T *frc = (const T *)c.force;
   const bool shift = sizeof(T) == 4;
   double s = 0, jx = 0, jy = 0;
   for (int i = 0; i < 9; i++) {
-    const double v = (double)f[i * c.plane + p] + (shift ? wgt<double>(i) * c.rho0 : 0.0);
+    const double v = (double)f[i * kSeg] + (shift ? wgt<double>(i) * c.rho0 : 0.0);
     s += v;
     jx += v * c_ex[i];
     jy += v * c_ey[i];
@@ -738,20 +768,22 @@ template <typename T>
 __global__ void export_kernel(CaseDesc c, int buf, double *out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= c.plane) return;
-  const T *f = (const T *)c.f[buf];
+  const int y = (int)(p / c.nx), x = (int)(p - (int64_t)y * c.nx);
+  const T *f = (const T *)c.f[buf] + pop_node(x, y, c.nseg);
   const bool shift = sizeof(T) == 4;
   for (int i = 0; i < 9; i++)
-    out[i * c.plane + p] = (double)f[i * c.plane + p] + (shift ? wgt<double>(i) * c.rho0 : 0.0);
+    out[i * c.plane + p] = (double)f[i * kSeg] + (shift ? wgt<double>(i) * c.rho0 : 0.0);
 }
 
 template <typename T>
 __global__ void import_kernel(CaseDesc c, int buf, const double *in) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= c.plane) return;
-  T *f = (T *)c.f[buf];
+  const int y = (int)(p / c.nx), x = (int)(p - (int64_t)y * c.nx);
+  T *f = (T *)c.f[buf] + pop_node(x, y, c.nseg);
   const bool shift = sizeof(T) == 4;
   for (int i = 0; i < 9; i++)
-    f[i * c.plane + p] = (T)(in[i * c.plane + p] - (shift ? wgt<double>(i) * c.rho0 : 0.0));
+    f[i * kSeg] = (T)(in[i * c.plane + p] - (shift ? wgt<double>(i) * c.rho0 : 0.0));
 }
 
 template <typename T>

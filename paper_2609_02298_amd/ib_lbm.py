@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libib_lbm.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 FP64, FP32_SHIFTED = 0, 1
 BGK, TRT, CMMRT = 0, 1, 2
@@ -82,7 +82,8 @@ class BodyDesc(C.Structure):
                 ("mdf_iters", C.c_int32), ("mdf_omega", C.c_double), ("motion", C.c_int32),
                 ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
                 ("phase", C.c_double), ("density_ratio", C.c_double),
-                ("mdf_nmin", C.c_int32), ("mdf_tol", C.c_double), ("integrator", C.c_int32)]
+                ("mdf_nmin", C.c_int32), ("mdf_tol", C.c_double), ("integrator", C.c_int32),
+                ("mdf_coupled", C.c_int32)]
 
 
 class BodyState(C.Structure):
@@ -288,6 +289,7 @@ def make_body(b: dict) -> BodyDesc:
     d.mdf_nmin = int(b.get("mdf_nmin", 1))
     d.mdf_tol = float(b.get("mdf_tol", 0.0))
     d.integrator = int(b.get("integrator", VERLET))
+    d.mdf_coupled = int(b.get("mdf_coupled", 0))
     return d
 
 

@@ -350,6 +350,134 @@ def run_wake_interaction(scheme="DF", kernel="P4", collision="BGK", integrator="
     return out
 
 
+# ---- the benchmark configurations at their stated lengths, FP32 vs FP64
+def _launch_for(case, prec):
+    from . import autotune
+    return autotune.lookup(case["nx"], case["ny"], case["collision"], prec)
+
+
+def _run_steps(sim, nsteps, label, log, chunk=20000):
+    t0 = time.perf_counter()
+    done = 0
+    while done < nsteps:
+        n = min(chunk, nsteps - done)
+        sim.step(n)
+        sim.sync()
+        done += n
+        print(f"  {label}: {done}/{nsteps} steps, {time.perf_counter() - t0:.1f} s", file=log,
+              flush=True)
+        if sim.forces(0, check=False)["status"] != 0:
+            break
+    return time.perf_counter() - t0
+
+
+def run_unsteady_cylinder(re: float, scheme: str, kernel: str, collision: str, precision: str,
+                          steps: int = 100000, log=sys.stderr) -> dict:
+    """Configuration 2: the 2000 x 800 fixed cylinder (D = 80, 251 markers,
+    u_inf = 0.1) for `steps` steps; mean C_d, rms C_l and St over the last
+    30 % of the steps (wake started as in perturb_wake)."""
+    import ib_cases
+    from . import ib_lbm as ib
+
+    case = ib_cases.unsteady_cylinder(scheme=scheme, kernel=kernel, collision=collision, re=re,
+                                      steps=steps)
+    prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
+    sim = ib.Sim(case, precision=prec, history_capacity=steps)
+    launch = _launch_for(case, prec)
+    if launch:
+        sim.set_launch(**launch)
+    perturb_wake(sim, case)
+    wall = _run_steps(sim, steps, f"{case['name']} {scheme}/{kernel}/{collision} {precision}", log)
+    st = sim.forces(0, check=False)
+    done = sim.steps_done
+    avg0 = int(0.7 * done) + 1
+    h = sim.history(0, avg0, done - avg0 + 1)
+    stats = flow_statistics(h[:, 1], h[:, 2], case["u_ref"], case["diameter"], case["rho0"])
+    sim.close()
+    return {"config": 2, "re": re, "scheme": scheme, "kernel": kernel, "collision": collision,
+            "precision": precision, "steps": done, "status": st["status"],
+            "average_window": [avg0, done], **stats,
+            "slip_mean_over_uinf": float(h[:, 9].mean() / case["u_ref"]),
+            "mlups": case["nx"] * case["ny"] * done / wall / 1e6}
+
+
+def run_oscillating_cylinder(precision: str, st0: float | None, steps: int = 60000,
+                             log=sys.stderr) -> dict:
+    """Configuration 3: the 1200 x 600 cylinder (D = 40, Re = 100, MDF / P4 /
+    TRT).  st0 None: the stationary cylinder of the same setup, whose
+    shedding Strouhal number (zero crossings of the lift over the last 30 %)
+    sets the frequency; else the transverse oscillation y = 0.2 D sin(2 pi f
+    t) with f = 0.8 st0 u_inf / D, reporting the marker slip and the drag and
+    lift over the last 30 % and their histories' extremes."""
+    import ib_cases
+    from . import ib_lbm as ib
+
+    fixed = st0 is None
+    case = ib_cases.oscillating_cylinder(steps=steps, st0=st0 or ib_cases.ST0_RE100, fixed=fixed)
+    prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
+    sim = ib.Sim(case, precision=prec, history_capacity=steps)
+    launch = _launch_for(case, prec)
+    if launch:
+        sim.set_launch(**launch)
+    perturb_wake(sim, case)
+    label = f"oscillating cylinder {'stationary' if fixed else 'moving'} {precision}"
+    wall = _run_steps(sim, steps, label, log)
+    st = sim.forces(0, check=False)
+    done = sim.steps_done
+    avg0 = int(0.7 * done) + 1
+    h = sim.history(0, avg0, done - avg0 + 1)
+    stats = flow_statistics(h[:, 1], h[:, 2], case["u_ref"], case["diameter"], case["rho0"])
+    q = 0.5 * case["rho0"] * case["u_ref"] ** 2 * case["diameter"]
+    out = {"config": 3, "motion": "fixed" if fixed else "transverse", "precision": precision,
+           "steps": done, "status": st["status"], "average_window": [avg0, done], **stats,
+           "cd_max": float(h[:, 1].max() / q), "cl_max": float(np.abs(h[:, 2]).max() / q),
+           "slip_mean_over_uinf": float(h[:, 9].mean() / case["u_ref"]),
+           "slip_max_over_uinf": float(h[:, 10].max() / case["u_ref"]),
+           "mlups": case["nx"] * case["ny"] * done / wall / 1e6}
+    if not fixed:
+        out["st0"] = st0
+        out["frequency"] = case["bodies"][0]["freq"]
+    sim.close()
+    return out
+
+
+def run_sedimentation(pair: bool, precision: str, steps: int = 200000, log=sys.stderr) -> dict:
+    """Configuration 4: sedimentation in the 400 x 2000 Zou-He box (D = 20,
+    Ar ~ 1000, DFC / P4 / CM-MRT, Feng correction, FP64 body update) for up
+    to `steps` steps, stopping when a support reaches a wall (no contact
+    model).  Reports each body's largest settling speed |v_y| (and over u_g
+    = (0.5 g D)^(1/2)) and its speed at the last step."""
+    import ib_cases
+    from . import ib_lbm as ib
+
+    case = ib_cases.sedimentation(pair=pair, steps=steps)
+    prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
+    sim = ib.Sim(case, precision=prec, history_capacity=steps)
+    wall = _run_steps(sim, steps, f"sedimentation {'pair' if pair else 'single'} {precision}", log)
+    done = sim.steps_done
+    bodies = []
+    for b in range(len(case["bodies"])):
+        st = sim.forces(b, check=False)
+        h = sim.history(b, 1, done)
+        vy = h[:, 7]
+        k = int(np.argmax(np.abs(vy)))
+        bodies.append({"density_ratio": case["bodies"][b]["density_ratio"],
+                       "v_settle_max": float(abs(vy[k])), "step_of_max": int(h[k, 0]),
+                       "v_settle_max_over_ug": float(abs(vy[k]) / case["u_ref"]),
+                       "v_final": float(vy[-1]), "y_final": float(h[-1, 5]),
+                       "status": st["status"]})
+    sim.close()
+    return {"config": 4, "pair": pair, "precision": precision, "steps": done,
+            "stop": "support reached a wall" if done < steps else "step budget", "bodies": bodies,
+            "mlups": case["nx"] * case["ny"] * done / wall / 1e6}
+
+
+def rel_diff(a, b):
+    if a is None or b is None:
+        return None
+    return abs(a - b) / abs(b) if b != 0 else abs(a - b)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="study", required=True)
@@ -386,11 +514,48 @@ def main(argv=None):
     wi.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     wi.add_argument("--length-d", type=float, default=50.0,
                     help="channel length in diameters: 50 (Sec. 2.9.4) or 60 (Table C.3)")
+    cf = sub.add_parser("configs", help="benchmark configurations 2-4 at their stated lengths, "
+                                           "FP32 shifted against FP64")
+    cf.add_argument("which", choices=["unsteady-cylinder", "oscillating-cylinder", "sedimentation"])
+    cf.add_argument("--re", type=float, nargs="+", default=[100.0, 200.0])
+    cf.add_argument("--scheme", nargs="+", default=["DF", "MDF", "DFC"])
+    cf.add_argument("--kernel", nargs="+", default=["hat", "P4"])
+    cf.add_argument("--collision", nargs="+", default=["BGK", "TRT", "CMMRT"])
+    cf.add_argument("--steps", type=int, default=None)
     args = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         print("studies: no HIP device", file=sys.stderr)
         return 1
+    if args.study == "configs":
+        if args.which == "unsteady-cylinder":
+            for re in args.re:
+                for col in args.collision:
+                    for kernel in args.kernel:
+                        for scheme in args.scheme:
+                            r = {p: run_unsteady_cylinder(re, scheme, kernel, col, p,
+                                                          args.steps or 100000)
+                                 for p in ("fp64", "fp32")}
+                            r["fp32_vs_fp64"] = {k: rel_diff(r["fp32"][k], r["fp64"][k])
+                                                 for k in ("cd_mean", "cl_rms", "st_fft", "st_zero")}
+                            print(json.dumps(r), flush=True)
+        elif args.which == "oscillating-cylinder":
+            n = args.steps or 60000
+            st = run_oscillating_cylinder("fp64", None, n)
+            print(json.dumps(st), flush=True)
+            st0 = st["st_zero"]
+            r = {p: run_oscillating_cylinder(p, st0, n) for p in ("fp64", "fp32")}
+            r["fp32_vs_fp64"] = {k: rel_diff(r["fp32"][k], r["fp64"][k])
+                                 for k in ("cd_mean", "cl_rms", "slip_mean_over_uinf", "cd_max",
+                                           "cl_max")}
+            print(json.dumps(r), flush=True)
+        else:
+            for pair in (False, True):
+                r = {p: run_sedimentation(pair, p, args.steps or 200000) for p in ("fp64", "fp32")}
+                r["fp32_vs_fp64"] = [rel_diff(a["v_settle_max"], b["v_settle_max"])
+                                     for a, b in zip(r["fp32"]["bodies"], r["fp64"]["bodies"])]
+                print(json.dumps(r), flush=True)
+        return 0
     if args.study == "settling":
         for rr in args.density_ratio:
             for kernel in args.kernel:
