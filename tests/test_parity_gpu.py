@@ -642,7 +642,14 @@ def test_coupled_mdf_pair_step_by_step(prec, free):
             assert abs(fs["mdf_residual"] - fr["mdf_residual"]) <= (1e-9 if f64 else 1e-3) * fr["mdf_residual"] + 1e-16
         counts.append(int(fr["mdf_iters"]))
     say(f"  kept passes per step: {counts}")
-    assert compare_fields(sim, ref, None) < (F64_FIELD if f64 else F32_FIELD)
+    ftol = F64_FIELD if f64 else F32_FIELD
+    if free and f64:
+        # The settling pair moves at 8e-4 after 40 steps, a thousandth of the
+        # populations' scale: the oracle itself, its populations perturbed
+        # once by 1e-16 (relative), ends 2e-12 away in this measure, and
+        # 3e-12 when perturbed every step.
+        ftol = 1e-11
+    assert compare_fields(sim, ref, None) < ftol
 
 
 def test_coupled_mdf_is_rejected_where_it_cannot_run():
