@@ -265,6 +265,21 @@ ib_lbm_status ib_lbm_markers(ib_lbm_sim *s, int32_t body_id, double *out, int32_
 ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, double u_ref,
                                  double *summary, double *per_marker);
 
+/* ib_lbm_diagnostics for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same computation and
+ * outputs, staged in a library-owned static device array instead of a
+ * buffer the sim allocates on demand.  Allocates nothing; like
+ * ib_lbm_diagnostics it synchronises the sim's stream and copies to host, so
+ * it is not for use inside a stream capture.  The array holds the summary
+ * and up to 8192 markers' rows; a body with more markers gives
+ * IB_LBM_E_INVALID.  Every value returned is written by the call itself, so
+ * nothing carries over from an earlier call.  Each GPU holds its own copy
+ * until the process ends, shared by every call on that GPU: calls that
+ * overlap on one GPU (from several host threads) race and must be
+ * serialised by the caller.  Runs on the sim's device. */
+ib_lbm_status ib_lbm_diagnostics_noalloc(ib_lbm_sim *s, int32_t body_id, int32_t kappa,
+                                         double u_ref, double *summary, double *per_marker);
+
 /* Completed steps (synchronises). */
 ib_lbm_status ib_lbm_steps_done(ib_lbm_sim *s, int64_t *steps);
 ib_lbm_status ib_lbm_sync(ib_lbm_sim *s);

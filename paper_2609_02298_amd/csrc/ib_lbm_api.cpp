@@ -76,6 +76,7 @@ struct ib_lbm_sim {
   // it (they differ only once a halted case stops flipping it on the device,
   // and a halted case's kernels do nothing)
   int host_cur = 0;
+  int dev = 0;  // the device current at creation
   ib_lbm_batch *batch = nullptr;
   int lds_bytes = 0;
   // Pipelined steps (see plan_split): the tiles of the hold rectangle and
@@ -671,6 +672,7 @@ ib_lbm_status ib_lbm_create(const ib_lbm_config *cfg, ib_lbm_sim **out) {
     return fail(IB_LBM_E_INVALID, "TRT needs a positive magic parameter");
   if (!(cfg->rho0 > 0.0)) return fail(IB_LBM_E_INVALID, "rho0 must be positive");
   s->stream = (hipStream_t)cfg->stream;
+  if (hipGetDevice(&s->dev) != hipSuccess) return fail(IB_LBM_E_DEVICE, "no HIP device");
   CaseDesc &c = s->cd;
   memset(&c, 0, sizeof c);
   c.nx = cfg->nx;
@@ -1155,6 +1157,30 @@ ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, 
   const int nb = s->bodies[body_id].dev.nb;
   if ((st = ensure_tmp(s, (size_t)(8 + 6 * nb) * 8))) return st;
   return diagnostics_into(s, body_id, kappa, u_ref, summary, per_marker, (double *)s->d_tmp.p);
+}
+
+ib_lbm_status ib_lbm_diagnostics_noalloc(ib_lbm_sim *s, int32_t body_id, int32_t kappa, double u_ref,
+                                         double *summary, double *per_marker) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!summary || body_id < 0 || body_id >= (int)s->bodies.size() || kappa < 0 || !(u_ref > 0))
+    return IB_LBM_E_INVALID;
+  const int nb = s->bodies[body_id].dev.nb;
+  if (nb > diag_scratch_markers()) {
+    set_err(&s->err, "ib_lbm_diagnostics_noalloc: %d markers exceed the static staging of %d", nb,
+            diag_scratch_markers());
+    return IB_LBM_E_INVALID;
+  }
+  // the staging of the sim's device, its address taken once per device
+  int dev = 0;
+  HIPCHK(s, hipGetDevice(&dev));
+  if (dev != s->dev) HIPCHK(s, hipSetDevice(s->dev));
+  double *d = nullptr;
+  hipError_t e = diag_scratch(&d);
+  if (e == hipSuccess) st = diagnostics_into(s, body_id, kappa, u_ref, summary, per_marker, d);
+  if (dev != s->dev) (void)hipSetDevice(dev);
+  HIPCHK(s, e);
+  return st;
 }
 
 ib_lbm_status ib_lbm_steps_done(ib_lbm_sim *s, int64_t *steps) {

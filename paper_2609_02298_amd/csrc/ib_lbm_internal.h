@@ -260,5 +260,9 @@ hipError_t launch_diagnostics(const CaseDesc &c, int buf, const double *markers,
                               double ds, int kappa, double u_ref, double *out, double *pm,
                               hipStream_t stream);
 int ibm_max_lds_bytes();
+// Staging of the allocation-free diagnostics: its device address on the
+// current device (taken once per device), and its capacity in markers.
+hipError_t diag_scratch(double **ptr);
+int diag_scratch_markers();
 
 }  // namespace iblbm

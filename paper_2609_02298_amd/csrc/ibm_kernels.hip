@@ -24,6 +24,8 @@
 // the marker order of the plain definition.  An atomic-scatter variant is
 // kept for comparison.  The workspace lives in LDS when it fits (LDS
 // instantiation), else in a global buffer of the body.
+#include <mutex>
+
 #include "ib_lbm_internal.h"
 
 namespace iblbm {
@@ -1689,6 +1691,34 @@ hipError_t launch_diagnostics(const CaseDesc &c, int buf, const double *markers,
     hipLaunchKernelGGL(diag_kernel<float>, dim3(1), dim3(kDiagThreads), 0, stream, c, buf, markers,
                        nb, xc, yc, vx, vy, om, radius, 2.0 * radius, ds, kappa, u_ref, out, pm);
   return hipGetLastError();
+}
+
+// Device staging of the allocation-free diagnostics entry point: the
+// summary (8 doubles) and up to kDiagScratchMarkers per-marker rows of 6.
+// Each GPU holds its own copy for the life of the process; host code reaches
+// it only through the address hipGetSymbolAddress returns on that device.
+constexpr int kDiagScratchMarkers = 8192;
+static __device__ __align__(256) double scratch[8 + 6 * kDiagScratchMarkers];
+
+int diag_scratch_markers() { return kDiagScratchMarkers; }
+
+hipError_t diag_scratch(double **ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double *addr[kMaxDevices];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (double *)p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 int ibm_max_lds_bytes() { return kIbmDynLds; }

@@ -39,7 +39,8 @@ STATUS = {1: "PENDING", 0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE",
 EXPORTS = [
     "ib_lbm_abi_version", "ib_lbm_create", "ib_lbm_add_body", "ib_lbm_step", "ib_lbm_forces",
     "ib_lbm_history", "ib_lbm_fields", "ib_lbm_get_populations", "ib_lbm_set_populations",
-    "ib_lbm_force_field", "ib_lbm_markers", "ib_lbm_diagnostics", "ib_lbm_steps_done",
+    "ib_lbm_force_field", "ib_lbm_markers", "ib_lbm_diagnostics", "ib_lbm_diagnostics_noalloc",
+    "ib_lbm_steps_done",
     "ib_lbm_sync",
     "ib_lbm_destroy", "ib_lbm_last_error", "ib_lbm_footprint", "ib_lbm_set_launch",
     "ib_lbm_get_launch", "ib_lbm_set_spread", "ib_lbm_set_graph", "ib_lbm_timing_enable",
@@ -166,6 +167,7 @@ def load_library(path: str = LIB_PATH):
     L.ib_lbm_force_field.argtypes = [vp, dp, dp]
     L.ib_lbm_markers.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int32)]
     L.ib_lbm_diagnostics.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, dp, dp]
+    L.ib_lbm_diagnostics_noalloc.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, dp, dp]
     L.ib_lbm_steps_done.argtypes = [vp, C.POINTER(C.c_int64)]
     L.ib_lbm_sync.argtypes = [vp]
     L.ib_lbm_destroy.argtypes = [vp]
@@ -403,6 +405,15 @@ class Sim:
         pm = np.zeros((self.nmarkers[body], 6))
         self._check(self.L.ib_lbm_diagnostics(self.h, int(body), int(kappa), float(u_ref), _dp(sm),
                                                _dp(pm)), self.h)
+        return dict(zip(self.DIAG_KEYS, sm.tolist())), pm
+
+    def diagnostics_noalloc(self, body: int = 0, kappa: int = 2, u_ref: float = 1.0):
+        """The same through ib_lbm_diagnostics_noalloc (static device staging,
+        no device allocation)."""
+        sm = np.zeros(8)
+        pm = np.zeros((self.nmarkers[body], 6))
+        self._check(self.L.ib_lbm_diagnostics_noalloc(self.h, int(body), int(kappa), float(u_ref),
+                                                       _dp(sm), _dp(pm)), self.h)
         return dict(zip(self.DIAG_KEYS, sm.tolist())), pm
 
     @property
