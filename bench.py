@@ -326,7 +326,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "collide_stream_kernel",
+                     "traffic": traffic, "kernel": "collide_stream_lean_kernel (all tiles)",
                      "bytes_per_node": bpn, "nodes_per_launch": lbm_nodes,
                      "avg_launch_us": round(lbm_avg_s * 1e6, 3),
                      "launch": r["launch"]},
