@@ -34,6 +34,7 @@ HAT, PESKIN4 = 0, 1
 FIXED, PRESCRIBED_SIN, FREE = 0, 1, 2
 IM_NONE, IM_FENG = 0, 1
 VERLET, EULER_A1 = 0, 1
+UD_RIGID, UD_TAYLOR_GREEN = 0, 1
 
 SCHEMES = {"DF": DF, "MDF": MDF, "DFC": DFC}
 KERNELS = {"hat": HAT, "P4": PESKIN4}
@@ -362,6 +363,42 @@ def random_populations(nx: int, ny: int, seed: int, rho0: float = 1.0, amp: floa
     rng = np.random.default_rng(seed)
     base = (w * rho0 * (1.0 + 3.0 * (ex * u[0] + ey * u[1])))[:, None, None]
     return np.ascontiguousarray(base * (1.0 + amp * rng.uniform(-1.0, 1.0, (9, ny, nx))))
+
+
+def taylor_green_ib(D: int, scheme=None, kernel=PESKIN4, collision=BGK, u0: float = 0.04,
+                    re: float = 10.0, mdf_adaptive: bool = True) -> dict:
+    """The Taylor-Green check of App. D.1 (Eq. D1, k = pi/L, u0 = 0.04,
+    Re = 10, measured at t = L/u0) with L = D lattice units.  Reading: the
+    box is one period of the field, 2D x 2D nodes, periodic on every face;
+    nu = u0 D / Re.  scheme None: pure LBM.  Otherwise the IB-LBM mode: a
+    ring of round(pi D) markers of diameter D centred at (D, D), held in
+    place, whose desired velocity is Eq. D1 at each marker and step."""
+    n = 2 * int(D)
+    nu = u0 * D / re
+    case = dict(name=f"taylor-green-D{int(D)}", nx=n, ny=n, collision=collision, tau=0.5 + 3.0 * nu,
+                trt_magic=0.25, cm_s_q=1.2, cm_s_eps=1.4, rho0=1.0, bc=(PERIODIC,) * 4,
+                u_bc=0.0, u_ref=u0, diameter=float(D), tg_u0=u0, tg_nu=nu,
+                steps=int(round(D / u0)), bodies=[])
+    if scheme is not None:
+        sch = SCHEMES[scheme] if isinstance(scheme, str) else scheme
+        ker = KERNELS[kernel] if isinstance(kernel, str) else kernel
+        b = dict(xc=float(D), yc=float(D), diameter=float(D), n_markers=0, scheme=sch, kernel=ker,
+                 mdf_iters=5, motion=FIXED, udes=UD_TAYLOR_GREEN, tg_u0=u0, tg_k=math.pi / D,
+                 tg_nu=nu)
+        if sch == MDF and mdf_adaptive:
+            b.update(ADAPTIVE_MDF)
+        case["bodies"] = [b]
+    return case
+
+
+def taylor_green_pressure_density(nx: int, ny: int, u0: float, rho0: float = 1.0) -> np.ndarray:
+    """Density of the Taylor-Green pressure field at t = 0 on a periodic
+    nx x ny box (k = 2 pi / n per axis): rho = rho0 (1 - 3 u0^2/4 (cos 2kx +
+    cos 2ky)) for a square box (the pressure -rho0 u0^2/4 (...) over c_s^2)."""
+    x = np.arange(nx)[None, :] + 0.0
+    y = np.arange(ny)[:, None] + 0.0
+    kx, ky = 2 * math.pi / nx, 2 * math.pi / ny
+    return rho0 * (1.0 - 0.75 * u0 * u0 * (np.cos(2 * kx * x) + np.cos(2 * ky * y)))
 
 
 def taylor_green_velocity(nx: int, ny: int, u0: float, t: float = 0.0, nu: float = 0.0):

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IB_LBM_ABI_VERSION 4u
+#define IB_LBM_ABI_VERSION 5u
 
 typedef enum {
   IB_LBM_OK = 0,
@@ -72,6 +72,8 @@ enum { IB_LBM_HAT = 0, IB_LBM_PESKIN4 = 1 };
 enum { IB_LBM_FIXED = 0, IB_LBM_PRESCRIBED_SIN = 1, IB_LBM_FREE = 2 };
 enum { IB_LBM_IM_NONE = 0, IB_LBM_IM_FENG = 1 };
 enum { IB_LBM_VERLET = 0, IB_LBM_EULER_A1 = 1 };
+/* desired marker velocity of a body (ib_lbm_body_desc.udes) */
+enum { IB_LBM_UD_RIGID = 0, IB_LBM_UD_TAYLOR_GREEN = 1 };
 enum { IB_LBM_SPREAD_GATHER = 0, IB_LBM_SPREAD_ATOMIC = 1 };
 
 /* Body flags reported in ib_lbm_body_state.flags */
@@ -148,6 +150,14 @@ typedef struct {
  * once per trial through device memory (a wait bounded to about 2 s; on
  * expiry the body reports IB_LBM_FLAG_EXCHANGE and the step stops with
  * IB_LBM_E_STATE from ib_lbm_forces).
+ * udes: the desired velocity of the markers.  IB_LBM_UD_RIGID: the body's
+ * rigid motion, U_d = V + Omega x (X_k - X_c) (Sec. 2.7).
+ * IB_LBM_UD_TAYLOR_GREEN (the IB-LBM mode of the Taylor-Green check, App.
+ * D.1; FIXED bodies only): the decaying vortex of Eq. D1 at each marker,
+ * U_d = tg_u0 exp(-2 tg_nu tg_k^2 t) (-cos(k X) sin(k Y), sin(k X) cos(k Y))
+ * with k = tg_k > 0, the origin at node (0, 0) and t the time level the
+ * step advances to (n + 1 in the step from n); tg_nu >= 0.  Such a body has
+ * no boundary-fidelity diagnostics (IB_LBM_E_INVALID).
  * All bodies of one sim use the same scheme. */
 typedef struct {
   double xc, yc, diameter;
@@ -164,6 +174,9 @@ typedef struct {
   double mdf_tol;   /* > 0 selects the adaptive MDF; <= 0 the fixed form */
   int32_t integrator; /* FREE bodies: IB_LBM_VERLET | IB_LBM_EULER_A1 */
   int32_t mdf_coupled; /* MDF: 1 selects the coupled multi-body path */
+  int32_t udes;     /* IB_LBM_UD_RIGID | IB_LBM_UD_TAYLOR_GREEN */
+  int32_t reserved;
+  double tg_u0, tg_k, tg_nu; /* Eq. D1 parameters of IB_LBM_UD_TAYLOR_GREEN */
 } ib_lbm_body_desc;
 
 /* State of a body after the last completed step.  Forces are on the body
@@ -231,6 +244,15 @@ ib_lbm_status ib_lbm_fields(ib_lbm_sim *s, double *rho, double *ux, double *uy);
  * FP32 shifted store the values are converted from / to g = f - w_i rho0. */
 ib_lbm_status ib_lbm_get_populations(ib_lbm_sim *s, double *f);
 ib_lbm_status ib_lbm_set_populations(ib_lbm_sim *s, const double *f);
+
+/* Overwrite the current populations with the equilibrium of Eq. 2,
+ * f_i = w_i rho (1 + 3 e_i.u + 4.5 (e_i.u)^2 - 1.5 u.u), of host fields
+ * (nx*ny doubles each, x fastest; rho NULL -> rho0 everywhere), evaluated in
+ * FP64 on the device and stored as g = f - w_i rho0 in the FP32 store.  The
+ * IB force field and the step count are left as they are.
+ * IB_LBM_E_INVALID for a null ux or uy. */
+ib_lbm_status ib_lbm_set_equilibrium(ib_lbm_sim *s, const double *rho, const double *ux,
+                                     const double *uy);
 
 /* Eulerian IB force density of the last IB pass (host, ny*nx each). */
 ib_lbm_status ib_lbm_force_field(ib_lbm_sim *s, double *fx, double *fy);

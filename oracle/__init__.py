@@ -21,5 +21,5 @@ from .oracle import (  # noqa: F401
     BGK, TRT, CMMRT,
     PERIODIC, BOUNCE_BACK, VEL_PARABOLIC, VEL_UNIFORM, ZERO_GRADIENT, ZOU_HE,
     DF, MDF, DFC, HAT, PESKIN4, FIXED, PRESCRIBED_SIN, FREE, IM_NONE, IM_FENG,
-    VERLET, EULER_A1,
+    VERLET, EULER_A1, UD_RIGID, UD_TAYLOR_GREEN,
 )

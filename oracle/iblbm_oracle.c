@@ -381,6 +381,10 @@ int or_add_body(or_sim *s, const or_body_desc *d) {
     return -1;
   if (d->scheme == OR_MDF && (d->mdf_iters < 1 || d->mdf_iters > 1000 || (d->mdf_tol > 0.0 && (d->mdf_nmin < 1 || d->mdf_nmin > d->mdf_iters))))
     return -1;
+  /* Taylor-Green markers stay where they are placed */
+  if (d->udes == OR_UD_TAYLOR_GREEN && (d->motion != OR_FIXED || !(d->tg_k > 0.0) || !(d->tg_nu >= 0.0)))
+    return -1;
+  if (d->udes != OR_UD_RIGID && d->udes != OR_UD_TAYLOR_GREEN) return -1;
   or_body *b = &s->body[s->nbody];
   memset(b, 0, sizeof(*b));
   b->d = *d;
@@ -522,6 +526,19 @@ static void body_pre(or_sim *s, or_body *b, int64_t n) {
     double rx = b->X[k] - b->xc, ry = b->Y[k] - b->yc;
     b->Udx[k] = ux - uo * ry;
     b->Udy[k] = uy + uo * rx;
+  }
+  if (b->d.udes == OR_UD_TAYLOR_GREEN) {
+    /* IB-LBM mode of the Taylor-Green check (App. D.1): the desired velocity
+     * of each (fixed) marker is the decaying vortex of Eq. D1 at the marker,
+     * with the origin at node (0, 0).  Reading: it is evaluated at t_(n+1),
+     * the time level the step advances to, as the prescribed kinematics
+     * above are. */
+    const double k = b->d.tg_k, t = t1;
+    const double amp = b->d.tg_u0 * exp(-2.0 * b->d.tg_nu * k * k * t);
+    for (int m = 0; m < b->nb; m++) {
+      b->Udx[m] = -amp * cos(k * b->X[m]) * sin(k * b->Y[m]);
+      b->Udy[m] = amp * sin(k * b->X[m]) * cos(k * b->Y[m]);
+    }
   }
 }
 

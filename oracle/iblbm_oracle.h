@@ -28,6 +28,7 @@ enum { OR_HAT = 0, OR_PESKIN4 = 1 };
 enum { OR_FIXED = 0, OR_PRESCRIBED_SIN = 1, OR_FREE = 2 };
 enum { OR_IM_NONE = 0, OR_IM_FENG = 1 };
 enum { OR_VERLET = 0, OR_EULER_A1 = 1 };
+enum { OR_UD_RIGID = 0, OR_UD_TAYLOR_GREEN = 1 };
 
 typedef struct {
   int32_t nx, ny;
@@ -60,6 +61,11 @@ typedef struct {
   int32_t integrator;      /* free bodies: OR_VERLET (Eq. 23) or OR_EULER_A1 (Eq. A1) */
   int32_t mdf_coupled;     /* MDF: the bodies of the sim iterate jointly with the
                               coupled-path controls of Sec. 2.5.2 (same value on every body) */
+  int32_t udes;            /* desired marker velocity: OR_UD_RIGID (the body's rigid
+                              motion, Sec. 2.7) or OR_UD_TAYLOR_GREEN (Eq. D1, fixed
+                              markers of the IB-LBM Taylor-Green mode, App. D.1) */
+  int32_t pad2;
+  double tg_u0, tg_k, tg_nu;  /* Eq. D1: amplitude u0, wavenumber k, viscosity nu */
 } or_body_desc;
 
 typedef struct or_sim or_sim;

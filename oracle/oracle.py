@@ -23,6 +23,7 @@ HAT, PESKIN4 = 0, 1
 FIXED, PRESCRIBED_SIN, FREE = 0, 1, 2
 IM_NONE, IM_FENG = 0, 1
 VERLET, EULER_A1 = 0, 1
+UD_RIGID, UD_TAYLOR_GREEN = 0, 1
 
 
 def build_oracle(force: bool = True) -> str:
@@ -49,7 +50,9 @@ class _Body(C.Structure):
                 ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
                 ("phase", C.c_double), ("density_ratio", C.c_double),
                 ("mdf_nmin", C.c_int32), ("pad1", C.c_int32), ("mdf_tol", C.c_double),
-                ("integrator", C.c_int32), ("mdf_coupled", C.c_int32)]
+                ("integrator", C.c_int32), ("mdf_coupled", C.c_int32),
+                ("udes", C.c_int32), ("pad2", C.c_int32), ("tg_u0", C.c_double),
+                ("tg_k", C.c_double), ("tg_nu", C.c_double)]
 
 
 _lib = None
@@ -140,6 +143,10 @@ def make_body(b: dict) -> _Body:
     d.mdf_tol = float(b.get("mdf_tol", 0.0))
     d.integrator = int(b.get("integrator", VERLET))
     d.mdf_coupled = int(b.get("mdf_coupled", 0))
+    d.udes = int(b.get("udes", UD_RIGID))
+    d.tg_u0 = float(b.get("tg_u0", 0.0))
+    d.tg_k = float(b.get("tg_k", 0.0))
+    d.tg_nu = float(b.get("tg_nu", 0.0))
     return d
 
 

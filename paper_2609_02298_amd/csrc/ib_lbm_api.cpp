@@ -743,7 +743,10 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
        (b->mdf_nmin < 1 || b->mdf_nmin > b->mdf_iters)) ||
       (b->motion == IB_LBM_FREE && !(b->density_ratio > 0)) ||
       (b->integrator != IB_LBM_VERLET && b->integrator != IB_LBM_EULER_A1) ||
-      (b->mdf_coupled != 0 && b->mdf_coupled != 1)) {
+      (b->mdf_coupled != 0 && b->mdf_coupled != 1) ||
+      (b->udes != IB_LBM_UD_RIGID && b->udes != IB_LBM_UD_TAYLOR_GREEN) ||
+      (b->udes == IB_LBM_UD_TAYLOR_GREEN &&
+       (b->motion != IB_LBM_FIXED || !(b->tg_k > 0) || !(b->tg_nu >= 0) || !std::isfinite(b->tg_u0)))) {
     set_err(&s->err, "invalid body description");
     return IB_LBM_E_INVALID;
   }
@@ -780,6 +783,10 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.motion = b->motion;
   B.internal_mass = b->internal_mass;
   B.integrator = b->integrator;
+  B.udes = b->udes;
+  B.tg_u0 = b->tg_u0;
+  B.tg_k = b->tg_k;
+  B.tg_nu = b->tg_nu;
   B.ns = b->kernel == IB_LBM_HAT ? 2 : 4;
   B.radius = 0.5 * b->diameter;
   B.ds = M_PI * b->diameter / nb;
@@ -1082,6 +1089,24 @@ ib_lbm_status ib_lbm_set_populations(ib_lbm_sim *s, const double *f) {
   return IB_LBM_OK;
 }
 
+ib_lbm_status ib_lbm_set_equilibrium(ib_lbm_sim *s, const double *rho, const double *ux,
+                                    const double *uy) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (!ux || !uy) return IB_LBM_E_INVALID;
+  CaseState cs;
+  if ((st = read_state(s, &cs))) return st;
+  const size_t n = (size_t)s->cd.plane;
+  if ((st = ensure_tmp(s, 3 * n * 8))) return st;
+  double *d = (double *)s->d_tmp.p;
+  HIPCHK(s, hipMemcpy(d, ux, n * 8, hipMemcpyHostToDevice));
+  HIPCHK(s, hipMemcpy(d + n, uy, n * 8, hipMemcpyHostToDevice));
+  if (rho) HIPCHK(s, hipMemcpy(d + 2 * n, rho, n * 8, hipMemcpyHostToDevice));
+  HIPCHK(s, launch_set_equilibrium(s->cd, cs.cur, rho ? d + 2 * n : nullptr, d, d + n, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return IB_LBM_OK;
+}
+
 ib_lbm_status ib_lbm_force_field(ib_lbm_sim *s, double *fx, double *fy) {
   ib_lbm_status st = usable(s);
   if (st) return st;
@@ -1154,6 +1179,10 @@ ib_lbm_status ib_lbm_diagnostics(ib_lbm_sim *s, int32_t body_id, int32_t kappa, 
   if (st) return st;
   if (!summary || body_id < 0 || body_id >= (int)s->bodies.size() || kappa < 0 || !(u_ref > 0))
     return IB_LBM_E_INVALID;
+  if (s->bodies[body_id].d.udes != IB_LBM_UD_RIGID) {
+    set_err(&s->err, "boundary diagnostics are defined for rigid bodies");
+    return IB_LBM_E_INVALID;
+  }
   const int nb = s->bodies[body_id].dev.nb;
   if ((st = ensure_tmp(s, (size_t)(8 + 6 * nb) * 8))) return st;
   return diagnostics_into(s, body_id, kappa, u_ref, summary, per_marker, (double *)s->d_tmp.p);
@@ -1165,6 +1194,10 @@ ib_lbm_status ib_lbm_diagnostics_noalloc(ib_lbm_sim *s, int32_t body_id, int32_t
   if (st) return st;
   if (!summary || body_id < 0 || body_id >= (int)s->bodies.size() || kappa < 0 || !(u_ref > 0))
     return IB_LBM_E_INVALID;
+  if (s->bodies[body_id].d.udes != IB_LBM_UD_RIGID) {
+    set_err(&s->err, "boundary diagnostics are defined for rigid bodies");
+    return IB_LBM_E_INVALID;
+  }
   const int nb = s->bodies[body_id].dev.nb;
   if (nb > diag_scratch_markers()) {
     set_err(&s->err, "ib_lbm_diagnostics_noalloc: %d markers exceed the static staging of %d", nb,

@@ -15,6 +15,7 @@ namespace iblbm {
 enum { kPrecFP64 = 0, kPrecFP32 = 1 };
 enum { kBGK = 0, kTRT = 1, kCMMRT = 2 };
 enum { kVerlet = 0, kEulerA1 = 1 };
+enum { kUdRigid = 0, kUdTaylorGreen = 1 };
 enum { kPeriodic = 0, kBounceBack = 1, kVelParabolic = 2, kVelUniform = 3, kZeroGradient = 4,
        kZouHe = 5 };
 enum { kFaceW = 0, kFaceE = 1, kFaceS = 2, kFaceN = 3 };
@@ -97,6 +98,7 @@ struct BodyDesc {
   int32_t integrator;   // free bodies: kVerlet (Eq. 23) or kEulerA1 (Eq. A1)
   int32_t mdf_band;     // > 0: MDF passes in marker space with this band half-width
   int32_t mdf_coupled;  // MDF bodies of the case iterate jointly (coupled path)
+  int32_t udes;         // desired velocity: kUdRigid or kUdTaylorGreen (Eq. D1)
   int32_t ns;           // support width: 2 (hat) or 4 (P4)
   int32_t window;       // half width of the angular marker window of the gather
   int32_t max_rows, max_nodes;
@@ -105,6 +107,7 @@ struct BodyDesc {
   double radius, ds, dtheta, omega_mdf;
   double xc0, yc0, amp[2], freq, phase;
   double ms, mf, Is;
+  double tg_u0, tg_k, tg_nu;  // Eq. D1 (kUdTaylorGreen)
   const double *cos_t, *sin_t;  // marker directions (n_b each)
   double *ws;           // global workspace (used when it does not fit in LDS)
   double *tab_cache;    // cached geometry tables of a fixed body (ws_tab doubles)
@@ -254,6 +257,8 @@ hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, do
                          hipStream_t stream);
 hipError_t launch_export(const CaseDesc &c, int buf, double *out, hipStream_t stream);
 hipError_t launch_import(const CaseDesc &c, int buf, const double *in, hipStream_t stream);
+hipError_t launch_set_equilibrium(const CaseDesc &c, int buf, const double *rho, const double *ux,
+                                  const double *uy, hipStream_t stream);
 hipError_t launch_force_export(const CaseDesc &c, double *fx, double *fy, hipStream_t stream);
 hipError_t launch_diagnostics(const CaseDesc &c, int buf, const double *markers, int nb, double xc,
                               double yc, double vx, double vy, double om, double radius,

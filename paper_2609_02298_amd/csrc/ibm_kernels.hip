@@ -757,6 +757,18 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       }
     }
   }
+  if (B.udes == kUdTaylorGreen) {
+    // IB-LBM mode of the Taylor-Green check (App. D.1): the fixed markers are
+    // driven to the decaying vortex of Eq. D1 at t_{n+1}, origin at node (0, 0)
+    const double k = B.tg_k;
+    const double amp = B.tg_u0 * exp(-2.0 * B.tg_nu * k * k * (double)(step + 1));
+    for (int m = tid; m < nb; m += nth) {
+      const double X = L.X[m], Y = L.Y[m];
+      L.Udx[m] = -amp * cos(k * X) * sin(k * Y);
+      L.Udy[m] = amp * sin(k * X) * cos(k * Y);
+    }
+    __syncthreads();
+  }
   const double ds = B.ds;
   double fsum_x = 0, fsum_y = 0, tq = 0, resmax = 0;
 

@@ -45,17 +45,60 @@ __device__ __forceinline__ R fmad(R a, R b, R c) {
 // sum_i f_i, so the equilibrium in either form is w_i (sum_f + rho P_i(u)),
 // P_i = 3 e.u + 4.5 (e.u)^2 - 1.5 u.u; m15uu = -1.5 u.u.
 // Everything is computed in place to keep the register footprint small.
+//
+// BGK and TRT work on the four pairs (i, opposite of i) and the rest
+// population.  With a = e_i.u, A = e_i.j (j = rho u, the momentum with half
+// the force) and b = e_i.F for the first of a pair, the equilibrium splits
+// into its even part w (sum_f + rho (4.5 a^2 - 1.5 u.u)) and its odd part
+// +-3 w A, and the Guo source w [3 (e - u) + 9 (e.u) e].F into the even part
+// w (9 a b - 3 u.F) and the odd part +-3 w b.  The even part of the
+// non-equilibrium relaxes at s_e, the odd part at s_o (BGK: both omega), each
+// source part is weighted by 1 - s/2 (Eq. 3-4 and the TRT of Sec. 2.2).
+// Writing the pairs this way takes about half the arithmetic of evaluating
+// nine equilibria; a node without force skips the source terms (they are
+// exactly zero there).
+//
+// The odd part carries the equilibrium's momentum, which the collision must
+// return unchanged.  3w = 1/3 or 1/12 is not a binary number: rounded to
+// FP32 it is 3e-8 too large, and the collision would then add that fraction
+// of s_o j to the momentum at every node and step, a systematic force that
+// shifts a long FP32 run's drag by 1e-4.  In FP32 the product therefore
+// carries the constant's rounding residue as a second term, so the
+// momentum is returned to within rounding that does not accumulate.
 template <typename R>
-__device__ __forceinline__ R eq_term(int i, R sum, R rho, R ux, R uy, R m15uu) {
-  const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
-  return wgt<R>(i) * fmad(rho, fmad(R(4.5) * eu, eu, fmad(R(3), eu, m15uu)), sum);
+struct PairOut {
+  R e, o;  // even and odd increments: f_i += e + o, f_opp += e - o
+};
+
+// x * c for the exact constant c = 1/n (n = 3, 12): FP64 as is, FP32 with
+// the residue c - fl32(c) as a second term.
+template <typename R, int N>
+__device__ __forceinline__ R times_inv(R x) {
+  constexpr double c = 1.0 / N;
+  if constexpr (sizeof(R) == 4) {
+    constexpr float hi = (float)c;
+    constexpr float lo = (float)(c - (double)hi);
+    return fmad(x, R(hi), x * R(lo));
+  } else {
+    return x * R(c);
+  }
 }
-// Guo source w_i [3 (e - u) + 9 (e.u) e].F
-template <typename R>
-__device__ __forceinline__ R guo_term(int i, R ux, R uy, R Fx, R Fy, R uF) {
-  const R eu = R(EXI(i)) * ux + R(EYI(i)) * uy;
-  const R eF = R(EXI(i)) * Fx + R(EYI(i)) * Fy;
-  return wgt<R>(i) * fmad(R(9) * eu, eF, R(3) * (eF - uF));
+
+template <typename R, int N3W>
+__device__ __forceinline__ PairOut<R> pair_relax(R fi, R fj, R a, R A, R w, R sum, R rho,
+                                                 R m15uu, R se, R so) {
+  const R ev = w * fmad(rho, fmad(R(4.5) * a, a, m15uu), sum);
+  const R od = times_inv<R, N3W>(A);
+  PairOut<R> r;
+  r.e = se * fmad(R(-0.5), fi + fj, ev);
+  r.o = so * fmad(R(-0.5), fi - fj, od);
+  return r;
+}
+
+template <typename R, int N3W>
+__device__ __forceinline__ void pair_source(PairOut<R> &r, R a, R b, R w, R m3uF, R pe, R po) {
+  r.e = fmad(pe, w * fmad(R(9) * a, b, m3uF), r.e);
+  r.o = fmad(po, times_inv<R, N3W>(b), r.o);
 }
 
 // C carries the rates (omega, s_e, s_o, s_q, s_eps) and rho0: a CaseDesc or
@@ -67,37 +110,40 @@ __device__ __forceinline__ void collide(R (&f)[9], R Fx, R Fy, const C &c) {
   const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   const R inv_rho = R(1) / rho;
-  const R ux = fmad(R(0.5), Fx, jx) * inv_rho;
-  const R uy = fmad(R(0.5), Fy, jy) * inv_rho;
+  const R jfx = fmad(R(0.5), Fx, jx), jfy = fmad(R(0.5), Fy, jy);
+  const R ux = jfx * inv_rho;
+  const R uy = jfy * inv_rho;
 
-  if constexpr (COL == kBGK) {
+  if constexpr (COL == kBGK || COL == kTRT) {
     const R m15uu = R(-1.5) * fmad(ux, ux, uy * uy);
-    const R uF = fmad(ux, Fx, uy * Fy);
-    const R om = R(c.omega);
-    const R pf = fmad(R(-0.5), om, R(1));
-#pragma unroll
-    for (int i = 0; i < 9; i++)
-      f[i] = fmad(pf, guo_term<R>(i, ux, uy, Fx, Fy, uF),
-                  fmad(-om, f[i] - eq_term<R>(i, sum, rho, ux, uy, m15uu), f[i]));
-  } else if constexpr (COL == kTRT) {
-    const R m15uu = R(-1.5) * fmad(ux, ux, uy * uy);
-    const R uF = fmad(ux, Fx, uy * Fy);
-    const R se = R(c.s_e), so = R(c.s_o);
-    const R pe = fmad(R(-0.5), se, R(1)), po = fmad(R(-0.5), so, R(1));
-    f[0] = fmad(pe, guo_term<R>(0, ux, uy, Fx, Fy, uF),
-                fmad(-se, f[0] - eq_term<R>(0, sum, rho, ux, uy, m15uu), f[0]));
-#pragma unroll
-    for (int i = 1; i <= 8; i++) {
-      const int j = OPPI(i);
-      if (j < i) continue;
-      const R ei = eq_term<R>(i, sum, rho, ux, uy, m15uu), ej = eq_term<R>(j, sum, rho, ux, uy, m15uu);
-      const R si = guo_term<R>(i, ux, uy, Fx, Fy, uF), sj = guo_term<R>(j, ux, uy, Fx, Fy, uF);
-      const R fp = R(0.5) * (f[i] + f[j]), fm = R(0.5) * (f[i] - f[j]);
-      const R even = fmad(pe, R(0.5) * (si + sj), -se * fmad(R(-0.5), ei + ej, fp));
-      const R odd = fmad(po, R(0.5) * (si - sj), -so * fmad(R(-0.5), ei - ej, fm));
-      f[i] = f[i] + even + odd;
-      f[j] = f[j] + even - odd;
+    const R se = COL == kBGK ? R(c.omega) : R(c.s_e);
+    const R so = COL == kBGK ? R(c.omega) : R(c.s_o);
+    const R w1 = R(1) / R(9), w2 = R(1) / R(36), w0 = R(4) / R(9);
+    // pairs (1,3), (2,4), (5,7), (6,8): e.u = ux, uy, ux + uy, uy - ux
+    const R a5 = ux + uy, a6 = uy - ux;
+    PairOut<R> p1 = pair_relax<R, 3>(f[1], f[3], ux, jfx, w1, sum, rho, m15uu, se, so);
+    PairOut<R> p2 = pair_relax<R, 3>(f[2], f[4], uy, jfy, w1, sum, rho, m15uu, se, so);
+    PairOut<R> p5 = pair_relax<R, 12>(f[5], f[7], a5, jfx + jfy, w2, sum, rho, m15uu, se, so);
+    PairOut<R> p6 = pair_relax<R, 12>(f[6], f[8], a6, jfy - jfx, w2, sum, rho, m15uu, se, so);
+    R d0 = se * (w0 * fmad(rho, m15uu, sum) - f[0]);
+    if (Fx != R(0) || Fy != R(0)) {
+      const R m3uF = R(-3) * fmad(ux, Fx, uy * Fy);
+      const R pe = fmad(R(-0.5), se, R(1)), po = fmad(R(-0.5), so, R(1));
+      pair_source<R, 3>(p1, ux, Fx, w1, m3uF, pe, po);
+      pair_source<R, 3>(p2, uy, Fy, w1, m3uF, pe, po);
+      pair_source<R, 12>(p5, a5, Fx + Fy, w2, m3uF, pe, po);
+      pair_source<R, 12>(p6, a6, Fy - Fx, w2, m3uF, pe, po);
+      d0 = fmad(pe, w0 * m3uF, d0);
     }
+    f[0] = f[0] + d0;
+    f[1] = (f[1] + p1.e) + p1.o;
+    f[3] = (f[3] + p1.e) - p1.o;
+    f[2] = (f[2] + p2.e) + p2.o;
+    f[4] = (f[4] + p2.e) - p2.o;
+    f[5] = (f[5] + p5.e) + p5.o;
+    f[7] = (f[7] + p5.e) - p5.o;
+    f[6] = (f[6] + p6.e) + p6.o;
+    f[8] = (f[8] + p6.e) - p6.o;
   } else {
     // Central moments k_pq = sum_i f_i (e_x - u_x)^p (e_y - u_y)^q.  D2Q9 is
     // the tensor product of {-1,0,1} x {-1,0,1}, so the transform factorises
@@ -784,6 +830,37 @@ __global__ void import_kernel(CaseDesc c, int buf, const double *in) {
   const bool shift = sizeof(T) == 4;
   for (int i = 0; i < 9; i++)
     f[i * kSeg] = (T)(in[i * c.plane + p] - (shift ? wgt<double>(i) * c.rho0 : 0.0));
+}
+
+// f = f^eq(rho, u) of Eq. 2 at every node from FP64 fields (rho null:
+// rho0), shifted by w_i rho0 in the FP32 store.
+template <typename T>
+__global__ void set_eq_kernel(CaseDesc c, int buf, const double *rho, const double *ux,
+                              const double *uy) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= c.plane) return;
+  const int y = (int)(p / c.nx), x = (int)(p - (int64_t)y * c.nx);
+  T *f = (T *)c.f[buf] + pop_node(x, y, c.nseg);
+  const bool shift = sizeof(T) == 4;
+  const double r = rho ? rho[p] : c.rho0, u = ux[p], v = uy[p];
+  const double uu = u * u + v * v;
+  for (int i = 0; i < 9; i++) {
+    const double eu = c_ex[i] * u + c_ey[i] * v;
+    const double w = wgt<double>(i);
+    const double feq = w * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    f[i * kSeg] = (T)(shift ? feq - w * c.rho0 : feq);
+  }
+}
+
+hipError_t launch_set_equilibrium(const CaseDesc &c, int buf, const double *rho, const double *ux,
+                                  const double *uy, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)((c.plane + threads - 1) / threads);
+  if (c.precision == kPrecFP64)
+    hipLaunchKernelGGL(set_eq_kernel<double>, dim3(blocks), dim3(threads), 0, stream, c, buf, rho, ux, uy);
+  else
+    hipLaunchKernelGGL(set_eq_kernel<float>, dim3(blocks), dim3(threads), 0, stream, c, buf, rho, ux, uy);
+  return hipGetLastError();
 }
 
 template <typename T>

@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libib_lbm.so")
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 FP64, FP32_SHIFTED = 0, 1
 BGK, TRT, CMMRT = 0, 1, 2
@@ -26,6 +26,7 @@ HAT, PESKIN4 = 0, 1
 FIXED, PRESCRIBED_SIN, FREE = 0, 1, 2
 IM_NONE, IM_FENG = 0, 1
 VERLET, EULER_A1 = 0, 1
+UD_RIGID, UD_TAYLOR_GREEN = 0, 1
 SPREAD_GATHER, SPREAD_ATOMIC = 0, 1
 FLAG_NONFINITE, FLAG_RANGE, FLAG_OVERLAP = 1, 2, 4
 
@@ -39,7 +40,7 @@ STATUS = {1: "PENDING", 0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE",
 EXPORTS = [
     "ib_lbm_abi_version", "ib_lbm_create", "ib_lbm_add_body", "ib_lbm_step", "ib_lbm_forces",
     "ib_lbm_history", "ib_lbm_fields", "ib_lbm_get_populations", "ib_lbm_set_populations",
-    "ib_lbm_force_field", "ib_lbm_markers", "ib_lbm_diagnostics", "ib_lbm_diagnostics_noalloc",
+    "ib_lbm_set_equilibrium", "ib_lbm_force_field", "ib_lbm_markers", "ib_lbm_diagnostics", "ib_lbm_diagnostics_noalloc",
     "ib_lbm_steps_done",
     "ib_lbm_sync",
     "ib_lbm_destroy", "ib_lbm_last_error", "ib_lbm_footprint", "ib_lbm_set_launch",
@@ -84,7 +85,8 @@ class BodyDesc(C.Structure):
                 ("internal_mass", C.c_int32), ("amp", C.c_double * 2), ("freq", C.c_double),
                 ("phase", C.c_double), ("density_ratio", C.c_double),
                 ("mdf_nmin", C.c_int32), ("mdf_tol", C.c_double), ("integrator", C.c_int32),
-                ("mdf_coupled", C.c_int32)]
+                ("mdf_coupled", C.c_int32), ("udes", C.c_int32), ("reserved", C.c_int32),
+                ("tg_u0", C.c_double), ("tg_k", C.c_double), ("tg_nu", C.c_double)]
 
 
 class BodyState(C.Structure):
@@ -164,6 +166,7 @@ def load_library(path: str = LIB_PATH):
     L.ib_lbm_fields.argtypes = [vp, dp, dp, dp]
     L.ib_lbm_get_populations.argtypes = [vp, dp]
     L.ib_lbm_set_populations.argtypes = [vp, dp]
+    L.ib_lbm_set_equilibrium.argtypes = [vp, dp, dp, dp]
     L.ib_lbm_force_field.argtypes = [vp, dp, dp]
     L.ib_lbm_markers.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int32)]
     L.ib_lbm_diagnostics.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, dp, dp]
@@ -292,6 +295,10 @@ def make_body(b: dict) -> BodyDesc:
     d.mdf_tol = float(b.get("mdf_tol", 0.0))
     d.integrator = int(b.get("integrator", VERLET))
     d.mdf_coupled = int(b.get("mdf_coupled", 0))
+    d.udes = int(b.get("udes", UD_RIGID))
+    d.tg_u0 = float(b.get("tg_u0", 0.0))
+    d.tg_k = float(b.get("tg_k", 0.0))
+    d.tg_nu = float(b.get("tg_nu", 0.0))
     return d
 
 
@@ -383,6 +390,16 @@ class Sim:
         f = np.ascontiguousarray(f, np.float64)
         assert f.shape == (9, self.ny, self.nx)
         self._check(self.L.ib_lbm_set_populations(self.h, _dp(f)), self.h)
+
+    def set_equilibrium(self, ux: np.ndarray, uy: np.ndarray, rho: np.ndarray | None = None):
+        """Populations = the equilibrium of (rho, u) at every node (rho None:
+        rho0), computed on the device."""
+        shape = (self.ny, self.nx)
+        ux = np.ascontiguousarray(np.broadcast_to(ux, shape), np.float64)
+        uy = np.ascontiguousarray(np.broadcast_to(uy, shape), np.float64)
+        r = None if rho is None else np.ascontiguousarray(np.broadcast_to(rho, shape), np.float64)
+        self._check(self.L.ib_lbm_set_equilibrium(self.h, None if r is None else _dp(r), _dp(ux),
+                                                  _dp(uy)), self.h)
 
     def force(self):
         fx = np.empty((self.ny, self.nx)); fy = np.empty_like(fx)

@@ -27,6 +27,13 @@ period between zero crossings of the lift, the kernel-interpolated slip of
 the last step normalised by u_inf (Table III), the boundary diagnostics of
 Sec. 2.8 on the final field, the mean MDF pass count and the run's MLUPS.
 
+``python -m paper_2609_02298_amd.studies taylor-green [--D 10 20 40 80]
+[--mode pure DF MDF DFC] [--kernel P4 hat]`` runs the Taylor-Green check of
+App. D.1 (Eq. D1, u0 = 0.04, Re = 10, t = L/u0) in pure LBM and in the
+IB-LBM mode whose marker ring carries the analytic velocity, and prints the
+L2 relative velocity errors with the pairwise and fitted convergence orders
+(Tables D.1 / D.2).
+
 Coefficients: C_d = 2 F_x / (rho0 u_inf^2 D), C_l = 2 F_y / (rho0 u_inf^2 D),
 St = f D / u_inf (the normalisation is not printed in the paper; this is the
 usual one).  Above Re = 50 the symmetric start state gets a small
@@ -472,6 +479,34 @@ def run_sedimentation(pair: bool, precision: str, steps: int = 200000, log=sys.s
             "mlups": case["nx"] * case["ny"] * done / wall / 1e6}
 
 
+def run_taylor_green(D: int, scheme: str | None, kernel: str, precision: str = "fp64",
+                     collision: str = "BGK") -> dict:
+    """App. D.1: the Taylor-Green check at resolution D (pure LBM when
+    scheme is None, else the IB-LBM mode of ``ib_cases.taylor_green_ib``),
+    started from the equilibrium of Eq. D1 with the vortex's pressure, and
+    its L2 relative velocity error at t = L/u0."""
+    import ib_cases
+    from . import ib_lbm as ib
+
+    case = ib_cases.taylor_green_ib(D, scheme, kernel, collision=ib_cases.COLLISIONS[collision])
+    prec = ib.FP64 if precision == "fp64" else ib.FP32_SHIFTED
+    sim = ib.Sim(case, precision=prec)
+    n, u0, nu, steps = case["nx"], case["tg_u0"], case["tg_nu"], case["steps"]
+    ux, uy = ib_cases.taylor_green_velocity(n, n, u0)
+    sim.set_equilibrium(ux, uy, ib_cases.taylor_green_pressure_density(n, n, u0))
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    wall = time.perf_counter() - t0
+    _, vx, vy = sim.fields()
+    sim.close()
+    ax, ay = ib_cases.taylor_green_velocity(n, n, u0, steps, nu)
+    l2 = float(np.sqrt(((vx - ax) ** 2 + (vy - ay) ** 2).sum() / (ax ** 2 + ay ** 2).sum()))
+    return {"study": "taylor-green", "D": D, "mode": scheme or "pure", "kernel": kernel,
+            "collision": collision, "precision": precision, "steps": steps, "l2": l2,
+            "seconds": wall}
+
+
 def rel_diff(a, b):
     if a is None or b is None:
         return None
@@ -514,6 +549,12 @@ def main(argv=None):
     wi.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     wi.add_argument("--length-d", type=float, default=50.0,
                     help="channel length in diameters: 50 (Sec. 2.9.4) or 60 (Table C.3)")
+    tg = sub.add_parser("taylor-green", help="App. D.1 Taylor-Green convergence, pure LBM and "
+                                              "the IB-LBM mode (Tables D.1 / D.2)")
+    tg.add_argument("--D", type=int, nargs="+", default=[10, 20, 40, 80])
+    tg.add_argument("--mode", nargs="+", default=["pure", "DF", "MDF", "DFC"])
+    tg.add_argument("--kernel", nargs="+", default=["P4", "hat"])
+    tg.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     cf = sub.add_parser("configs", help="benchmark configurations 2-4 at their stated lengths, "
                                            "FP32 shifted against FP64")
     cf.add_argument("which", choices=["unsteady-cylinder", "oscillating-cylinder", "sedimentation"])
@@ -527,6 +568,21 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("studies: no HIP device", file=sys.stderr)
         return 1
+    if args.study == "taylor-green":
+        for kernel in args.kernel:
+            for mode in args.mode:
+                if mode == "pure" and kernel != args.kernel[0]:
+                    continue
+                rows = [run_taylor_green(D, None if mode == "pure" else mode, kernel, args.precision)
+                        for D in args.D]
+                for r in rows:
+                    print(json.dumps(r), flush=True)
+                e = [r["l2"] for r in rows]
+                orders = [float(np.log2(a / b)) for a, b in zip(e, e[1:])]
+                fit = float(-np.polyfit(np.log(args.D), np.log(e), 1)[0]) if len(e) > 1 else None
+                print(json.dumps({"summary": mode, "kernel": kernel, "D": args.D, "l2": e,
+                                  "pairwise_orders": orders, "fitted_order": fit}), flush=True)
+        return 0
     if args.study == "configs":
         if args.which == "unsteady-cylinder":
             for re in args.re:

@@ -1210,3 +1210,82 @@ def test_coupled_mdf_bodies_must_agree():
     with pytest.raises(ValueError):
         s.add_body(dict(xc=80.0, yc=20.0, diameter=8.0, scheme=MDF, kernel=PESKIN4, mdf_iters=20,
                         mdf_nmin=5, mdf_tol=1e-4, mdf_coupled=0))
+
+
+# ------------------------------------------------ IB-LBM Taylor-Green mode
+def _tg_state(case):
+    """Equilibrium populations of Eq. D1 at t = 0 with the vortex's pressure."""
+    import ib_cases
+    n, u0 = case["nx"], case["tg_u0"]
+    ux, uy = ib_cases.taylor_green_velocity(n, n, u0)
+    rho = ib_cases.taylor_green_pressure_density(n, n, u0)
+    f = np.zeros((9, n, n))
+    for j in range(n):
+        for i in range(n):
+            f[:, j, i] = oracle.equilibrium(rho[j, i], ux[j, i], uy[j, i])
+    return f
+
+
+def _tg_l2(D, scheme, kernel, **bkw):
+    """L2 relative velocity error of the Taylor-Green check at t = L/u0."""
+    import ib_cases
+    case = ib_cases.taylor_green_ib(D, scheme, kernel)
+    for b in case["bodies"]:
+        b.update(bkw)
+    s = oracle.OracleSim(case)
+    for b in case["bodies"]:
+        s.add_body(b)
+    s.set_populations(_tg_state(case))
+    s.step(case["steps"])
+    _, vx, vy = s.fields()
+    n = case["nx"]
+    ax, ay = ib_cases.taylor_green_velocity(n, n, case["tg_u0"], case["steps"], case["tg_nu"])
+    return math.sqrt(((vx - ax) ** 2 + (vy - ay) ** 2).sum() / (ax ** 2 + ay ** 2).sum())
+
+
+@pytest.mark.parametrize("scheme,col", [(DF, 2), (MDF, 3), (DFC, 4)])
+def test_taylor_green_ib_mode_matches_table_d1(scheme, col):
+    """The IB-LBM mode of the Taylor-Green check (App. D.1) with the Peskin
+    4-point kernel: the L2 errors at D = 10, 20, 40 lie within 15% of the
+    values Table D.1 prints for DF, MDF (adaptive) and DFC.  The marker ring
+    and the time level of the desired velocity are readings; a wrong sign,
+    wavenumber or decay of Eq. D1, or the desired velocity taken one step
+    earlier, moves the errors by far more."""
+    table = np.loadtxt(os.path.join(GOLDEN, "taylor_green_table_d1.txt"))
+    for D, printed in zip((10, 20, 40), table[:3, col]):
+        e = _tg_l2(D, scheme, PESKIN4)
+        assert abs(e / printed - 1.0) < 0.15, (D, e, printed)
+
+
+@pytest.mark.parametrize("scheme", [DF, DFC])
+def test_taylor_green_ib_mode_second_order_with_hat(scheme):
+    """Second-order convergence of the IB-LBM Taylor-Green mode with the hat
+    kernel (the companion sweep of Table D.2): the error falls by 2^1.8 to
+    2^2.6 per halving of the spacing from D = 10 to 20 to 40."""
+    e = [_tg_l2(D, scheme, HAT) for D in (10, 20, 40)]
+    for a, b in zip(e, e[1:]):
+        assert 1.8 < math.log2(a / b) < 2.6, e
+
+
+def test_taylor_green_markers_carry_the_analytic_velocity():
+    """The desired velocity drives the result: the same ring with the rigid
+    desired velocity of a body at rest stops the vortex where it sits (error
+    of order one), while the analytic desired velocity of Eq. D1 leaves the
+    error at the discretisation level.  On a fluid reset to rest, one DF
+    step from rest gives each marker F = 2 U_d (rho = 1, U = 0), with U_d
+    the vortex at the time level the step advances to (t = 1)."""
+    assert _tg_l2(20, DF, PESKIN4) < 0.02
+    assert _tg_l2(20, DF, PESKIN4, udes=oracle.UD_RIGID) > 0.5
+    import ib_cases
+    case = ib_cases.taylor_green_ib(20, DF, PESKIN4)
+    s = oracle.OracleSim(case)
+    s.add_body(case["bodies"][0])
+    rest = np.zeros((9, case["nx"], case["ny"]))
+    rest[:] = oracle.equilibrium(1.0, 0.0, 0.0)[:, None, None]
+    s.set_populations(rest)
+    s.step(1)
+    m = s.markers(0)
+    k, u0, nu = math.pi / 20, case["tg_u0"], case["tg_nu"]
+    amp = u0 * math.exp(-2 * nu * k * k * 1)
+    np.testing.assert_allclose(m[:, 4], -2 * amp * np.cos(k * m[:, 0]) * np.sin(k * m[:, 1]), atol=1e-15)
+    np.testing.assert_allclose(m[:, 5], 2 * amp * np.sin(k * m[:, 0]) * np.cos(k * m[:, 1]), atol=1e-15)
