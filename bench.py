@@ -227,6 +227,7 @@ def largest_leg(steps32: int = 60, steps64: int = 30):
         a = bpn * lbm_nodes / avg / 1e9
         out[pname] = {"value": round(nodes * steps / r["seconds"] / 1e6, 1), "unit": "MLUPS",
                       "roofline_achieved_GBs": round(a, 1), "roofline_frac": round(a / HBM_PEAK_GBS, 4),
+                      "traffic": measured_traffic(f"{c['name']}-{pname}-{out['collision']}"),
                       "avg_launch_us": round(avg * 1e6, 2),
                       "ib_pass_avg_us": round(r["ibm_ms"] / max(r["n_ibm"], 1) * 1e3, 2),
                       "population_bytes": 2 * 9 * nodes * bpn // 18, "launch": r["launch"]}

@@ -430,13 +430,18 @@ __device__ __forceinline__ int ld_agent(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Inner nodes of one case from by-value arguments (LeanArgs).  The halt
-// flag is loaded after each row's populations and tested once they have
-// arrived (an atomic load, which the compiler keeps in place), so that no
-// chain of dependent loads precedes the data.  The flag can only be set by
-// the IB pass of an earlier step; a pipelined far tile that misses a halt of
-// the concurrent IB pass writes only the lattice that the halted case no
-// longer reads.
+// A word that is the same for the whole launch and that no kernel running
+// beside this one writes, loaded through the scalar data cache: after the
+// first wave of a compute unit the others find it there, instead of every
+// wave of the chip asking the one L2 channel that holds it.
+__device__ __forceinline__ int ld_uniform(const int32_t *p) {
+  return *(const __attribute__((address_space(4))) int32_t *)p;
+}
+
+// Inner nodes of one case from by-value arguments (LeanArgs).  The case's
+// halt flag and force box are words of its state that every wave needs; they
+// are read through the scalar data cache (one miss per compute unit), not
+// as vector loads that would all meet in one L2 channel.
 template <typename T, int COL, int MODE>
 __global__ __launch_bounds__(1024) void collide_stream_lean_kernel(const LeanArgs a) {
   const int nb = gridDim.x;
@@ -467,6 +472,21 @@ __global__ __launch_bounds__(1024) void collide_stream_lean_kernel(const LeanArg
   const int ybase = ty * TY;
   const int dxp = seg_dx_plus(x), dxm = seg_dx_minus(x), rs = nseg * kSegBlock;
   const T ffx = T(a.fluid_fx), ffy = T(a.fluid_fy);
+  // A halted case keeps its lattices as they are.  The flag is set by the IB
+  // pass of an earlier launch; a pipelined far tile (MODE 2) runs beside the
+  // IB pass of the previous step and may miss a halt that pass sets, and then
+  // writes only the lattice that the halted case no longer reads.
+  if (ld_uniform(&cs->flags) & kCaseHalted) return;
+  // the force box (MODE 0): written by the IB pass of an earlier launch,
+  // never by one running beside this kernel
+  int fv = 0, f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+  if (MODE == 0) {
+    fv = ld_uniform(&cs->fbox_valid);
+    f0 = ld_uniform(&cs->fbox[0]);
+    f1 = ld_uniform(&cs->fbox[1]);
+    f2 = ld_uniform(&cs->fbox[2]);
+    f3 = ld_uniform(&cs->fbox[3]);
+  }
   for (int r = 0; r < rpt; r++) {
     const int y = ybase + threadIdx.y + r * blockDim.y;
     if (y < 1 || y > ny - 2) continue;
@@ -481,18 +501,6 @@ __global__ __launch_bounds__(1024) void collide_stream_lean_kernel(const LeanArg
       fa = frc[p];
       fb = frc[plane + p];
     }
-    // the flag and the force box, as loads issued after the populations
-    // (kept in place as atomics) that arrive with them
-    const int halted = ld_agent(&cs->flags) & kCaseHalted;
-    int fv = 0, f0 = 0, f1 = 0, f2 = 0, f3 = 0;
-    if (MODE == 0) {
-      fv = ld_agent(&cs->fbox_valid);
-      f0 = ld_agent(&cs->fbox[0]);
-      f1 = ld_agent(&cs->fbox[1]);
-      f2 = ld_agent(&cs->fbox[2]);
-      f3 = ld_agent(&cs->fbox[3]);
-    }
-    if (halted) return;
     if (MODE == 1) {
       if (fa != T(0) || fb != T(0)) {
         Fx += fa;
