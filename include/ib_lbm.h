@@ -196,10 +196,14 @@ typedef struct {
 
 /* Launch shape of the collide-stream kernel: block_x threads along x (a
  * multiple of 64), block_y thread rows, rows_per_thread nodes per thread
- * along y.  The tile is block_x x (block_y * rows_per_thread) nodes. */
+ * along y.  The tile is block_x x (block_y * rows_per_thread) nodes.
+ * ib_threads: workgroup size of the IB pass (one workgroup per body): 0 for
+ * the library's choice (1024 for DF/MDF bodies whose workspace fits in LDS,
+ * 512 otherwise), or 256, 512 or 1024 (the second kind takes at most 512). */
 typedef struct {
   int32_t block_x, block_y, rows_per_thread;
   int32_t xcd_remap; /* 1: keep neighbouring tiles on one XCD */
+  int32_t ib_threads;
 } ib_lbm_launch;
 
 typedef struct ib_lbm_sim ib_lbm_sim;

@@ -1,4 +1,4 @@
-"""Launch-shape autotuner for the collide-stream kernel.
+"""Launch-shape autotuner for the collide-stream kernel and the IB pass.
 
 Times candidate tile shapes through the C ABI (HIP events around each
 collide-stream launch on the library's stream) on a body-free lattice of the
@@ -8,6 +8,10 @@ fastest.  Results are cached in memory and in a JSON table keyed by
 (launch_table.json, written on an MI355X by ``python -m
 paper_2609_02298_amd.autotune --write PATH``) is loaded first, so tuned
 workloads start without re-tuning.
+
+The IB pass runs one workgroup per body; its size (256, 512 or 1024
+threads) is tuned per body description and precision by timing the pass on
+the workload itself (``tune_ib``; ``--ib`` tunes the benchmark's bodies).
 """
 from __future__ import annotations
 
@@ -87,6 +91,69 @@ def tune(nx, ny, collision, precision, candidates=None, steps=40, stream=None) -
     return dict(best[1])
 
 
+IB_CANDIDATES = (256, 512, 1024)
+
+
+def _ib_key(case, precision):
+    """IB-pass entries are keyed by what the pass's work depends on: the
+    body (scheme, kernel, markers, MDF bounds) and the precision."""
+    parts = []
+    for b in case.get("bodies", []):
+        nb = int(b.get("n_markers", 0)) or int(round(3.141592653589793 * b["diameter"]))
+        parts.append(f"s{b.get('scheme', 0)}k{b.get('kernel', 0)}n{nb}"
+                     f"m{b.get('mdf_iters', 5)}t{b.get('mdf_tol', 0.0):g}")
+    return f"ib-p{precision}-" + "-".join(parts)
+
+
+def time_ib(case, precision, threads, steps=40, shape=None) -> float:
+    """Average IB-pass duration in microseconds (HIP events around each pass
+    of plain, unpipelined steps) with the given workgroup size."""
+    s = ib.Sim(case, precision=precision)
+    try:
+        s.set_launch(**dict(shape or {}, ib_threads=threads))
+        s.set_overlap(False)
+        s.step(4)
+        s.sync()
+        s.timing(True)
+        s.step(steps)
+        ms, n = s.timing_read(1)
+    finally:
+        s.close()
+    return ms / max(n, 1) * 1e3
+
+
+def tune_ib(case, precision, candidates=IB_CANDIDATES, steps=40) -> int:
+    """Best IB workgroup size for the case's bodies (from the table, else
+    timed on this case)."""
+    if not case.get("bodies"):
+        return 0
+    k = _ib_key(case, precision)
+    if not _cache:
+        load_cache(TABLE)
+    if k in _cache:
+        return int(_cache[k]["ib_threads"])
+    shape = tune(case["nx"], case["ny"], case["collision"], precision)
+    best = None
+    for t in candidates:
+        us = time_ib(case, precision, t, steps, shape)
+        if best is None or us < best[0]:
+            best = (us, t)
+    _cache[k] = {"ib_threads": best[1], "us": best[0]}
+    return best[1]
+
+
+def _bench_cases():
+    """The bodies the benchmark steps: the headline cylinder with fixed and
+    adaptive MDF, and the largest sweep case."""
+    import ib_cases
+    head = ib_cases.unsteady_cylinder(scheme="MDF", kernel="P4", collision="TRT", re=100.0)
+    adapt = ib_cases.unsteady_cylinder(scheme="MDF", kernel="P4", collision="TRT", re=100.0)
+    adapt["bodies"][0].update(ib_cases.ADAPTIVE_MDF)
+    sweep = ib_cases.sweep_cases(256, seed=0)
+    big = max(sweep, key=lambda c: c["nx"] * c["ny"])
+    return [head, adapt, big]
+
+
 def _main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="tune the collide-stream launch shape of workloads")
@@ -95,6 +162,8 @@ def _main(argv=None):
                     help="NXxNY entries, tuned for every collision model and precision")
     ap.add_argument("--fresh", action="store_true",
                     help="time every entry again instead of starting from the shipped table")
+    ap.add_argument("--ib", action="store_true",
+                    help="also tune the IB-pass workgroup size of the benchmark's bodies")
     args = ap.parse_args(argv)
     ib.load_library()
     if args.fresh:
@@ -107,6 +176,12 @@ def _main(argv=None):
                 sh = tune(nx, ny, col, prec)
                 print(f"{nx}x{ny} precision {prec} collision {col}: {sh} "
                       f"{_cache[_key(nx, ny, col, prec)]['us']:.1f} us", flush=True)
+    if args.ib:
+        for case in _bench_cases():
+            for prec in (ib.FP32_SHIFTED, ib.FP64):
+                t = tune_ib(case, prec)
+                k = _ib_key(case, prec)
+                print(f"{case['name']} IB {k}: {t} threads {_cache[k]['us']:.1f} us", flush=True)
     _cache.pop("_fresh", None)
     save_cache(args.write)
 

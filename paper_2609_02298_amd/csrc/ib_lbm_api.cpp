@@ -252,7 +252,8 @@ void fill_case_tiles(CaseDesc *c, const ib_lbm_launch &l) {
 
 ib_lbm_status check_launch(const ib_lbm_launch *l, std::string *err) {
   if (!l || l->block_x <= 0 || l->block_x % 64 || l->block_y <= 0 || l->rows_per_thread <= 0 ||
-      l->block_x * l->block_y > 1024 || l->rows_per_thread > 64) {
+      l->block_x * l->block_y > 1024 || l->rows_per_thread > 64 ||
+      (l->ib_threads != 0 && l->ib_threads != 256 && l->ib_threads != 512 && l->ib_threads != 1024)) {
     set_err(err, "invalid launch shape");
     return IB_LBM_E_INVALID;
   }
@@ -347,11 +348,12 @@ bool body_fast(const HostBody &hb, int spread_mode) {
 // the rest on the general one (bodies of one case may sit in both; the last
 // of a case's workgroups to finish, in either launch, completes the case).
 hipError_t launch_ibm_slots(int precision, const CaseDesc *cases, const IbmSlot *slots, int nfast, int n,
-                            int lds_bytes, int spread_mode, hipStream_t stream) {
-  hipError_t e = launch_ibm(precision, cases, slots, nfast, lds_bytes, spread_mode, 1, 1, nullptr, stream);
+                            int lds_bytes, int spread_mode, int threads, hipStream_t stream) {
+  hipError_t e = launch_ibm(precision, cases, slots, nfast, lds_bytes, spread_mode, 1, 1, nullptr,
+                            threads, stream);
   if (e != hipSuccess) return e;
   return launch_ibm(precision, cases, slots + nfast, n - nfast, lds_bytes, spread_mode, 0, 1, nullptr,
-                    stream);
+                    threads, stream);
 }
 
 ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
@@ -461,7 +463,8 @@ ib_lbm_status enqueue_sim_step(ib_lbm_sim *s, bool timed, hipStream_t stream, in
     HIPCHK(s, hipEventRecord(p1.a, stream));
   }
   HIPCHK(s, launch_ibm_slots(s->cd.precision, (const CaseDesc *)s->d_case.p, (const IbmSlot *)s->d_slots.p,
-                             s->nslots_fast, s->nslots, s->lds_bytes, s->spread_mode, stream));
+                             s->nslots_fast, s->nslots, s->lds_bytes, s->spread_mode,
+                             s->launch.ib_threads, stream));
   if (timed) {
     HIPCHK(s, hipEventRecord(p1.b, stream));
     s->timing.ev[1].push_back(p1);
@@ -564,7 +567,8 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed, hipSt
     // one copy of the single body's IB workgroup per XCD; the first to start
     // runs the pass (the far tiles on the other stream fill the chip)
     HIPCHK(s, launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, 1, s->lds_bytes,
-                         s->spread_mode, s->nslots_fast, 8, (uint32_t *)s->ticket.p, s->iq));
+                         s->spread_mode, s->nslots_fast, 8, (uint32_t *)s->ticket.p,
+                         s->launch.ib_threads, s->iq));
     if (timed) {
       HIPCHK(s, hipEventRecord(p1.b, s->iq));
       s->timing.ev[1].push_back(p1);
@@ -1549,7 +1553,8 @@ static ib_lbm_status batch_enqueue_step(ib_lbm_batch *b, hipStream_t stream) {
                                            g.nface_blocks, -1, 1, g.general_zg, stream));
   }
   BHIPCHK(b, launch_ibm_slots(b->precision, (const CaseDesc *)b->d_cases.p, (const IbmSlot *)b->d_slots.p,
-                              b->nslots_fast, b->nslots, b->lds_bytes, b->spread_mode, stream));
+                              b->nslots_fast, b->nslots, b->lds_bytes, b->spread_mode,
+                              b->launch.ib_threads, stream));
   return IB_LBM_OK;
 }
 

@@ -247,10 +247,11 @@ hipError_t launch_collide_stream_faces(int precision, int collision, const CaseD
                                        int force, int general_zg, hipStream_t stream);
 // IB launch over nslots slots; replicas > 1 (with a per-slot counter that
 // every copy advances, see ibm_kernel) lets the first-started copy of each
-// slot run it.
+// slot run it.  threads: workgroup size (0: the instance's default), capped
+// at the instance's launch bound.
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
-                      hipStream_t stream);
+                      int threads, hipStream_t stream);
 hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,

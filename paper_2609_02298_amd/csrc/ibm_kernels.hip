@@ -1737,7 +1737,7 @@ int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
-                      hipStream_t stream) {
+                      int threads, hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
   static bool configured = false;
   if (!configured) {
@@ -1755,19 +1755,23 @@ hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots
   const int lds_doubles = lds_bytes / 8;
   if (replicas < 1) replicas = 1;
   const int grid = nslots * replicas;
+  // the kernel's loops stride by the workgroup size and its staging needs
+  // more than one wave: any of 256, 512, 1024 up to the launch bound
+  const int bound = fast ? kIbmThreadsFast : kIbmThreads;
+  const int nt = threads >= 256 ? (threads < bound ? threads : bound) : bound;
   if (precision == kPrecFP64) {
     if (fast)
-      hipLaunchKernelGGL((ibm_kernel<double, true>), dim3(grid), dim3(kIbmThreadsFast), lds_bytes,
+      hipLaunchKernelGGL((ibm_kernel<double, true>), dim3(grid), dim3(nt), lds_bytes,
                          stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
     else
-      hipLaunchKernelGGL((ibm_kernel<double, false>), dim3(grid), dim3(kIbmThreads), lds_bytes,
+      hipLaunchKernelGGL((ibm_kernel<double, false>), dim3(grid), dim3(nt), lds_bytes,
                          stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
   } else {
     if (fast)
-      hipLaunchKernelGGL((ibm_kernel<float, true>), dim3(grid), dim3(kIbmThreadsFast), lds_bytes,
+      hipLaunchKernelGGL((ibm_kernel<float, true>), dim3(grid), dim3(nt), lds_bytes,
                          stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
     else
-      hipLaunchKernelGGL((ibm_kernel<float, false>), dim3(grid), dim3(kIbmThreads), lds_bytes,
+      hipLaunchKernelGGL((ibm_kernel<float, false>), dim3(grid), dim3(nt), lds_bytes,
                          stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
   }
   return hipGetLastError();

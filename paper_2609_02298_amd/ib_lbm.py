@@ -103,7 +103,7 @@ class BodyState(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("block_x", C.c_int32), ("block_y", C.c_int32), ("rows_per_thread", C.c_int32),
-                ("xcd_remap", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("ib_threads", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -439,8 +439,8 @@ class Sim:
         self._check(self.L.ib_lbm_steps_done(self.h, C.byref(v)), self.h)
         return v.value
 
-    def set_launch(self, block_x=64, block_y=4, rows_per_thread=2, xcd_remap=1):
-        l = Launch(block_x, block_y, rows_per_thread, xcd_remap)
+    def set_launch(self, block_x=64, block_y=4, rows_per_thread=2, xcd_remap=1, ib_threads=0):
+        l = Launch(block_x, block_y, rows_per_thread, xcd_remap, ib_threads)
         self._check(self.L.ib_lbm_set_launch(self.h, C.byref(l)), self.h)
 
     def get_launch(self) -> dict:
@@ -519,8 +519,8 @@ class Batch:
     def set_graph(self, steps_per_graph: int):
         self._check(self.L.ib_lbm_batch_set_graph(self.h, int(steps_per_graph)))
 
-    def set_launch(self, block_x=128, block_y=2, rows_per_thread=1, xcd_remap=1):
-        l = Launch(block_x, block_y, rows_per_thread, xcd_remap)
+    def set_launch(self, block_x=128, block_y=2, rows_per_thread=1, xcd_remap=1, ib_threads=0):
+        l = Launch(block_x, block_y, rows_per_thread, xcd_remap, ib_threads)
         self._check(self.L.ib_lbm_batch_set_launch(self.h, C.byref(l)))
 
     def set_spread(self, mode: int):
@@ -566,7 +566,7 @@ class Server:
         c.spread = int(spread)
         if launch:
             c.launch = Launch(launch["block_x"], launch["block_y"], launch["rows_per_thread"],
-                              launch.get("xcd_remap", 1))
+                              launch.get("xcd_remap", 1), launch.get("ib_threads", 0))
         c.stream = stream
         self.precision = int(precision)
         h = C.c_void_p()

@@ -860,6 +860,30 @@ def test_run_to_run_bitwise_and_gather_vs_atomic():
     assert rel(e.populations(), d.populations()) < 1e-13
 
 
+@pytest.mark.parametrize("scheme,kernel", [(ib.MDF, ib.PESKIN4), (ib.DF, ib.HAT), (ib.DFC, ib.PESKIN4)])
+def test_ib_workgroup_size_changes_rounding_only(scheme, kernel):
+    """The IB pass at 256, 512 and 1024 threads per body: the same result up
+    to the order of the force sums, and the oracle's within tolerance."""
+    say(f"IB workgroup sizes scheme={scheme} kernel={kernel}")
+    case = body_case(scheme, kernel, ib.TRT)
+    ref = oracle.OracleSim(case)
+    ref.add_body(case["bodies"][0])
+    ref.step(20)
+    _, rx, ry = ref.fields()
+    out = []
+    for t in (256, 512, 1024):
+        s = ib.Sim(case)
+        s.set_launch(64, 2, 1, 1, ib_threads=t)
+        assert s.get_launch()["ib_threads"] == t
+        s.step(20)
+        out.append((s.populations(), s.forces(0)["fx"]))
+        assert compare_fields(s, ref, None) < F64_FIELD
+        s.close()
+    for f, fx in out[1:]:
+        assert rel(f, out[0][0]) < 1e-13
+        assert abs(fx - out[0][1]) < 1e-12 * abs(out[0][1])
+
+
 def test_graph_replay_matches_direct_launches():
     case = body_case(ib.DFC, ib.PESKIN4, ib.TRT)
     a = ib.Sim(case); g = ib.Sim(case)
