@@ -70,6 +70,7 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True, wan
         # has this lattice, else tune now
         from paper_2609_02298_amd import autotune
         launch = autotune.tune(case["nx"], case["ny"], case["collision"], precision)
+        launch = dict(launch, ib_threads=autotune.tune_ib(case, precision))
     sim = ib.Sim(case, precision=precision)
     if launch:
         sim.set_launch(**launch)
@@ -181,17 +182,25 @@ def serving_leg(precision, launch, n_cases: int, step_scale: int, budget_gb: flo
 
     cases = ib_cases.sweep_cases(n_cases, seed=seed)
     steps = [max(1, c["steps"] // step_scale) for c in cases]
-    seq = serving.sequential(cases, precision, steps=steps, launch=launch)
+    log = sys.stderr
+    seq = serving.sequential(cases, precision, steps=steps, launch=launch, progress=log)
     rate = 1.25 * len(cases) / seq["wall"]
     # arrival gaps from their own stream so that the cases are the same in
     # every mode
     gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, len(cases))
     arrivals = np.cumsum(gaps) - gaps[0]
     budget = int(budget_gb * 2**30)
+    timeout = 600.0 + 20.0 * seq["wall"]
     burst = serving.serve(cases, precision, steps=steps, hbm_budget=budget, quantum=quantum,
-                          launch=launch)
+                          launch=launch, timeout=timeout, progress=log)
+    # the same burst with each round's batch steps replayed from captured
+    # HIP graphs of graph_steps steps
+    graph_steps = 32
+    burst_graph = serving.serve(cases, precision, steps=steps, hbm_budget=budget, quantum=quantum,
+                                graph_steps=graph_steps, launch=launch, timeout=timeout,
+                                progress=log)
     pois = serving.serve(cases, precision, steps=steps, arrivals=arrivals, hbm_budget=budget,
-                         quantum=quantum, launch=launch)
+                         quantum=quantum, launch=launch, timeout=timeout, progress=log)
     nodes = [c["nx"] * c["ny"] for c in cases]
     return {
         "workload": f"sweep seed {seed}: {len(cases)} cases, {min(nodes)}-{max(nodes)} nodes, "
@@ -200,6 +209,7 @@ def serving_leg(precision, launch, n_cases: int, step_scale: int, budget_gb: flo
         "hbm_budget_gb": budget_gb, "quantum": quantum,
         "node_updates": int(sum(n * k for n, k in zip(nodes, steps))),
         "burst": serving.summary(cases, burst, seq),
+        "burst_graph": dict(serving.summary(cases, burst_graph, seq), graph_steps=graph_steps),
         "poisson": dict(serving.summary(cases, pois, seq, arrivals=list(arrivals)),
                         rate_per_s=round(rate, 3)),
     }

@@ -36,7 +36,7 @@ def fifo_latencies(arrivals, service) -> list[float]:
 
 
 def sequential(cases, precision: int, steps=None, launch: dict | None = None,
-               fields: bool = False) -> dict:
+               fields: bool = False, progress=None) -> dict:
     """Plain solves, one sim at a time on the current stream: create, add
     bodies, step, read forces (and fields), destroy.  Service time of each
     case includes its creation and teardown."""
@@ -59,6 +59,9 @@ def sequential(cases, precision: int, steps=None, launch: dict | None = None,
         torch.cuda.synchronize()
         r["service"] = time.perf_counter() - t0
         out.append(r)
+        if progress is not None and (i + 1) % 32 == 0:
+            print(f"  sequential: {i + 1}/{len(cases)} cases, {time.perf_counter() - t_all:.1f} s",
+                  file=progress, flush=True)
     wall = time.perf_counter() - t_all
     nu = sum(case_nodes(c) * r["steps_done"] for c, r in zip(cases, out))
     return dict(results=out, wall=wall, node_updates=nu)
@@ -66,7 +69,8 @@ def sequential(cases, precision: int, steps=None, launch: dict | None = None,
 
 def serve(cases, precision: int, steps=None, arrivals=None, hbm_budget: int = 16 << 30,
           max_resident: int = 64, quantum: int = 256, graph_steps: int = 0,
-          launch: dict | None = None, fields: bool = False, timeout: float = 600.0) -> dict:
+          launch: dict | None = None, fields: bool = False, timeout: float = 600.0,
+          progress=None) -> dict:
     """Submit every case at its arrival time (seconds after the start; None:
     all at once) to a fresh server and wait for all results."""
     srv = B.Server(precision=precision, hbm_budget=hbm_budget, max_resident=max_resident,
@@ -90,6 +94,9 @@ def serve(cases, precision: int, steps=None, arrivals=None, hbm_budget: int = 16
             if r is None:
                 raise TimeoutError(f"request {ids[i]} of case {i} did not finish in {timeout} s")
             results[i] = r
+            if progress is not None and (i + 1) % 32 == 0:
+                print(f"  served: {i + 1}/{len(cases)} results, {time.perf_counter() - t0:.1f} s",
+                      file=progress, flush=True)
         wall = time.perf_counter() - t0
         stats = srv.stats()
     finally:

@@ -58,3 +58,23 @@ def test_sweep_keeps_cmmrt_cases_below_the_stability_limit():
         else:
             assert c["tau"] == f["tau"]
     assert sum(c["cap"] == "cmmrt_tau_max" for c in capped) == 2
+
+
+def test_sweep_keeps_trt_cases_above_the_floor():
+    """No TRT sweep case gets a relaxation time below TRT_TAU_MIN; the
+    lifted cases say so, and the floor changes no other case."""
+    import ib_cases
+    lifted = ib_cases.sweep_cases(256, seed=0)
+    free = ib_cases.sweep_cases(256, seed=0, tau_min_trt=0.0)
+    n = 0
+    for c, f in zip(lifted, free):
+        assert (c["nx"], c["ny"], c["collision"], c["steps"]) == (f["nx"], f["ny"], f["collision"],
+                                                                f["steps"])
+        if c["collision"] == ib_cases.TRT:
+            assert c["tau"] >= ib_cases.TRT_TAU_MIN - 1e-12
+        if c["cap"] == "trt_tau_min":
+            n += 1
+            assert f["tau"] < ib_cases.TRT_TAU_MIN and abs(c["tau"] - ib_cases.TRT_TAU_MIN) < 1e-12
+        else:
+            assert c["tau"] == f["tau"]
+    assert n >= 3
