@@ -22,8 +22,8 @@ import os
 from . import ib_lbm as ib
 
 DEFAULT_CANDIDATES = [
-    dict(block_x=bx, block_y=by, rows_per_thread=rpt, xcd_remap=1)
-    for bx, by, rpt in itertools.product((64, 128, 256), (1, 2, 4), (1, 2, 4))
+    dict(block_x=bx, block_y=by, rows_per_thread=rpt, xcd_remap=remap)
+    for remap, bx, by, rpt in itertools.product((1, 0), (64, 128, 256, 512, 1024), (1, 2, 4), (1, 2, 4))
     if bx * by <= 1024
 ]
 
