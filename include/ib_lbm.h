@@ -322,10 +322,14 @@ ib_lbm_status ib_lbm_get_launch(const ib_lbm_sim *s, ib_lbm_launch *l);
 /* Spreading variant: marker-sorted gather (default, deterministic) or
  * per-marker atomic scatter (order-dependent rounding). */
 ib_lbm_status ib_lbm_set_spread(ib_lbm_sim *s, int32_t mode);
-/* hipGraph use: steps_per_graph > 0 captures that many steps once (one
+/* hipGraph use: steps_per_graph > 0 records that many steps once (one
  * graph for each of the two lattices a run of steps can start from) and
- * replays them; 0 launches kernels directly.  A capture happens at the first
- * ib_lbm_step call that needs it, so that call may allocate. */
+ * replays them; 0 launches kernels directly.  Plain steps are captured from a
+ * stream; pipelined steps (below) are built as an explicit graph of the same
+ * kernels with their ordering as node dependencies, both graphs at the first
+ * replay.  Recording happens at the first ib_lbm_step call that needs it, so
+ * that call may allocate; steps beyond a multiple of steps_per_graph are
+ * launched directly. */
 ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph);
 
 /* Pipelined steps (default on).  For a sim with one body that is fixed or
@@ -339,8 +343,9 @@ ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph);
  * state-reading call starts after the work already on the sim's stream, and
  * the sim's stream waits for both streams before any later work.  The
  * collide-stream stream leaves one compute unit to the IB pass.  Results
- * are bitwise the same as unpipelined steps.  Steps replayed from a graph
- * (ib_lbm_set_graph) are not pipelined.
+ * are bitwise the same as unpipelined steps.  In steps replayed from a graph
+ * (ib_lbm_set_graph) the collide-stream launches run without that stream's
+ * compute-unit mask.
  * set_overlap(0/1) forbids or allows it; get_overlap reports whether the
  * current configuration uses it (after the first step) and, if near_nodes
  * is not NULL, the number of nodes in the tiles that wait for the IB pass. */

@@ -27,6 +27,8 @@ DEFAULT_CANDIDATES = [
     if bx * by <= 1024
 ]
 
+REFINE = 6  # candidates timed again before the choice
+
 _cache: dict = {}
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_table.json")
 
@@ -82,11 +84,18 @@ def tune(nx, ny, collision, precision, candidates=None, steps=40, stream=None) -
         load_cache(TABLE)
     if k in _cache:
         return dict(_cache[k]["shape"])
+    # one timing of every candidate, then the fastest few again, longer and
+    # three times each: single timings of near-equal shapes differ by a few
+    # per cent from run to run
+    first = sorted(((time_shape(nx, ny, collision, precision, sh, steps, stream), i)
+                    for i, sh in enumerate(candidates or DEFAULT_CANDIDATES)))
+    cands = candidates or DEFAULT_CANDIDATES
     best = None
-    for sh in candidates or DEFAULT_CANDIDATES:
-        t = time_shape(nx, ny, collision, precision, sh, steps, stream)
-        if best is None or t < best[0]:
-            best = (t, sh)
+    for _, i in first[:REFINE]:
+        ts = sorted(time_shape(nx, ny, collision, precision, cands[i], 3 * steps, stream)
+                    for _ in range(3))
+        if best is None or ts[1] < best[0]:
+            best = (ts[1], cands[i])
     _cache[k] = {"shape": best[1], "us": best[0]}
     return dict(best[1])
 

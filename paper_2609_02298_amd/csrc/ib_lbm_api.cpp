@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <limits>
 #include <string>
 #include <vector>
@@ -581,6 +582,70 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed, hipSt
   return IB_LBM_OK;
 }
 
+// The pipelined steps as an explicitly built graph: the same kernels and
+// arguments as enqueue_pipelined, with its event ordering as node
+// dependencies.  Far tiles of step i after the face nodes (and Zou-He walls)
+// of step i-1 and the hold tiles of step i-1; face nodes after the far
+// tiles; hold tiles after the face nodes and the IB pass of step i-1;
+// Zou-He walls after the face nodes and the hold tiles of the step; the IB
+// pass after the hold tiles.  Launching the graph costs the host one call,
+// where the events cost it two cross-stream hops per step (about 17 us
+// each); the far tiles lose the compute-unit mask of their stream, which the
+// IB pass's per-XCD copies make up for.  Stream capture is not used.
+ib_lbm_status build_pipelined_graph(ib_lbm_sim *s, int64_t nsteps, int cur0, hipGraphExec_t *out) {
+  LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
+  const CaseDesc *dc = (const CaseDesc *)s->d_case.p;
+  const bool zh = has_zou_he(s->cd);
+  hipGraph_t g = nullptr;
+  HIPCHK(s, hipGraphCreate(&g, 0));
+  hipGraphNode_t prev_lq = nullptr, prev_hold = nullptr, prev_ib = nullptr;
+  hipError_t e = hipSuccess;
+  auto add = [&](std::initializer_list<hipGraphNode_t> deps, auto &&launch) -> hipGraphNode_t {
+    hipGraphNode_t d[4];
+    size_t n = 0;
+    for (hipGraphNode_t x : deps)
+      if (x) d[n++] = x;
+    NodeSink ns{g, d, n, nullptr};
+    if (e == hipSuccess) e = launch(&ns);
+    return ns.node;
+  };
+  for (int64_t i = 0; i < nsteps && e == hipSuccess; i++) {
+    const int cur = cur0 ^ (int)(i & 1);
+    const LeanArgs la = lean_args(s, cur, 0);
+    hipGraphNode_t far = add({prev_lq, prev_hold}, [&](NodeSink *ns) {
+      return launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 2, sh, nullptr, ns);
+    });
+    hipGraphNode_t face = add({far ? far : prev_lq, far ? nullptr : prev_hold}, [&](NodeSink *ns) {
+      return launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
+                                         (const int32_t *)s->d_prefix.p + 2, 1,
+                                         face_blocks(s->cd.nx, s->cd.ny), cur, 0,
+                                         general_zero_gradient(s->cd), nullptr, ns);
+    });
+    hipGraphNode_t lq_end = face ? face : far;
+    hipGraphNode_t hold = add({prev_lq, prev_ib}, [&](NodeSink *ns) {
+      return launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 1, sh, nullptr, ns);
+    });
+    if (zh) {
+      hipGraphNode_t z = add({lq_end, hold}, [&](NodeSink *ns) {
+        return launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, cur, nullptr, ns);
+      });
+      if (z) lq_end = z;
+    }
+    hipGraphNode_t ib = add({hold ? hold : prev_ib}, [&](NodeSink *ns) {
+      return launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, 1, s->lds_bytes,
+                        s->spread_mode, s->nslots_fast, 8, (uint32_t *)s->ticket.p,
+                        s->launch.ib_threads, nullptr, ns);
+    });
+    if (lq_end) prev_lq = lq_end;
+    if (hold) prev_hold = hold;
+    if (ib) prev_ib = ib;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(s, e);
+  return IB_LBM_OK;
+}
+
 // Enqueue nsteps steps of a sim on `stream` from input lattice cur0,
 // pipelined when the sim allows it and `pipelined` is set.
 ib_lbm_status enqueue_steps(ib_lbm_sim *s, int64_t nsteps, bool timed, hipStream_t stream, int cur0,
@@ -939,8 +1004,14 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
       drop_graphs(s);
       s->graph_len = s->graph_steps;
     }
-    // capture on a private stream (the caller's may be the null stream),
-    // replay on the caller's stream; one graph per starting lattice
+    // pipelined steps: an explicitly built graph per starting lattice, both
+    // made at the first replay; plain steps: captured on a private stream
+    // (the caller's may be the null stream); replayed on the caller's stream
+    if (s->split) {
+      for (int p = 0; p < 2; p++)
+        if (!s->graph_exec[p] && (st = build_pipelined_graph(s, s->graph_len, p, &s->graph_exec[p])))
+          return st;
+    }
     if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     while (left >= s->graph_len) {
       hipGraphExec_t &ge = s->graph_exec[s->host_cur];
@@ -949,7 +1020,8 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
         HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
         // captured steps are plain steps on the capturing stream: capturing
         // the two-stream pipelined step crashed the host process in the HIP
-        // runtime (cause not identified), so that path is switched off
+        // runtime (cause not identified), so pipelined graphs are built
+        // explicitly above instead
         st = enqueue_steps(s, s->graph_len, false, s->cap_stream, s->host_cur, false);
         if (st) {
           hipGraph_t dummy;

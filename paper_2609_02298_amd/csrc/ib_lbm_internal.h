@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <tuple>
+#include <utility>
+
 namespace iblbm {
 
 enum { kPrecFP64 = 0, kPrecFP32 = 1 };
@@ -231,6 +234,38 @@ struct LeanArgs {
 };
 
 // ---- kernel launchers (defined in the .hip files) ----
+// A launcher either launches on its stream or, given a NodeSink, adds the
+// same kernel with the same arguments as a node of an explicitly built
+// graph, after the sink's dependencies (node is null when nothing is added).
+struct NodeSink {
+  hipGraph_t graph;
+  const hipGraphNode_t *deps;
+  size_t ndeps;
+  hipGraphNode_t node;
+};
+
+template <typename Tup, size_t... I>
+inline void arg_pointers(Tup &t, void **p, std::index_sequence<I...>) {
+  ((p[I] = (void *)&std::get<I>(t)), ...);
+}
+
+template <typename... P, typename... A>
+inline hipError_t issue(void (*kernel)(P...), dim3 grid, dim3 block, unsigned shmem,
+                        hipStream_t stream, NodeSink *ns, A &&...args) {
+  std::tuple<std::decay_t<P>...> vals(std::forward<A>(args)...);
+  void *ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+  arg_pointers(vals, ptrs, std::index_sequence_for<P...>{});
+  if (!ns) return hipLaunchKernel((const void *)kernel, grid, block, ptrs, shmem, stream);
+  hipKernelNodeParams p{};
+  p.func = (void *)kernel;
+  p.gridDim = grid;
+  p.blockDim = block;
+  p.sharedMemBytes = shmem;
+  p.kernelParams = ptrs;
+  p.extra = nullptr;
+  return hipGraphAddKernelNode(&ns->node, ns->graph, ns->deps, ns->ndeps, &p);
+}
+
 // Inner nodes of every case of a batch, each case's input lattice from its
 // device state (batches flatten (case, tile) through tile_prefix).
 hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *cases,
@@ -238,21 +273,23 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
                                  LaunchShape shape, hipStream_t stream);
 // Inner nodes of one case with its arguments by value (see LeanArgs).
 hipError_t launch_collide_stream_lean(int precision, int collision, const LeanArgs &a, int mode,
-                                      LaunchShape shape, hipStream_t stream);
+                                      LaunchShape shape, hipStream_t stream, NodeSink *ns = nullptr);
 // The face nodes (rows 0 and ny-1, columns 0, nx-2, nx-1) with the face
 // closures; face_prefix[i] is the first workgroup of case i (face_blocks per
 // case), nblocks the total; cur < 0 takes each case's lattice from its state.
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
                                        const int32_t *face_prefix, int ncases, int nblocks, int cur,
-                                       int force, int general_zg, hipStream_t stream);
+                                       int force, int general_zg, hipStream_t stream,
+                                       NodeSink *ns = nullptr);
 // IB launch over nslots slots; replicas > 1 (with a per-slot counter that
 // every copy advances, see ibm_kernel) lets the first-started copy of each
 // slot run it.  threads: workgroup size (0: the instance's default), capped
 // at the instance's launch bound.
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
-                      int threads, hipStream_t stream);
-hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream);
+                      int threads, hipStream_t stream, NodeSink *ns = nullptr);
+hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream,
+                         NodeSink *ns = nullptr);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
                          hipStream_t stream);

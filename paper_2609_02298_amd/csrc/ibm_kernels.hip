@@ -1737,7 +1737,7 @@ int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
-                      int threads, hipStream_t stream) {
+                      int threads, hipStream_t stream, NodeSink *ns) {
   if (nslots <= 0) return hipSuccess;
   static bool configured = false;
   if (!configured) {
@@ -1759,22 +1759,15 @@ hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots
   // more than one wave: any of 256, 512, 1024 up to the launch bound
   const int bound = fast ? kIbmThreadsFast : kIbmThreads;
   const int nt = threads >= 256 ? (threads < bound ? threads : bound) : bound;
-  if (precision == kPrecFP64) {
-    if (fast)
-      hipLaunchKernelGGL((ibm_kernel<double, true>), dim3(grid), dim3(nt), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
-    else
-      hipLaunchKernelGGL((ibm_kernel<double, false>), dim3(grid), dim3(nt), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
-  } else {
-    if (fast)
-      hipLaunchKernelGGL((ibm_kernel<float, true>), dim3(grid), dim3(nt), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
-    else
-      hipLaunchKernelGGL((ibm_kernel<float, false>), dim3(grid), dim3(nt), lds_bytes,
-                         stream, cases, slots, lds_doubles, spread_mode, replicas, ticket);
-  }
-  return hipGetLastError();
+  if (precision == kPrecFP64)
+    return fast ? issue(ibm_kernel<double, true>, dim3(grid), dim3(nt), lds_bytes, stream, ns, cases,
+                        slots, lds_doubles, spread_mode, replicas, ticket)
+                : issue(ibm_kernel<double, false>, dim3(grid), dim3(nt), lds_bytes, stream, ns, cases,
+                        slots, lds_doubles, spread_mode, replicas, ticket);
+  return fast ? issue(ibm_kernel<float, true>, dim3(grid), dim3(nt), lds_bytes, stream, ns, cases,
+                      slots, lds_doubles, spread_mode, replicas, ticket)
+              : issue(ibm_kernel<float, false>, dim3(grid), dim3(nt), lds_bytes, stream, ns, cases,
+                      slots, lds_doubles, spread_mode, replicas, ticket);
 }
 
 }  // namespace iblbm

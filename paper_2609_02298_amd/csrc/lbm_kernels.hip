@@ -673,14 +673,12 @@ __global__ __launch_bounds__(256) void zou_he_kernel(const CaseDesc *__restrict_
   }
 }
 
-hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream) {
+hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream,
+                         NodeSink *ns) {
   const int n = 2 * nx + 2 * (ny - 2);
   const int blocks = (n + 255) / 256;
-  if (precision == kPrecFP64)
-    hipLaunchKernelGGL(zou_he_kernel<double>, dim3(blocks), dim3(256), 0, stream, c, cur);
-  else
-    hipLaunchKernelGGL(zou_he_kernel<float>, dim3(blocks), dim3(256), 0, stream, c, cur);
-  return hipGetLastError();
+  if (precision == kPrecFP64) return issue(zou_he_kernel<double>, dim3(blocks), dim3(256), 0, stream, ns, c, cur);
+  return issue(zou_he_kernel<float>, dim3(blocks), dim3(256), 0, stream, ns, c, cur);
 }
 
 #define IBL_DISPATCH(precision, collision, LAUNCH)                                             \
@@ -713,36 +711,29 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
 
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
                                        const int32_t *face_prefix, int ncases, int nblocks, int cur,
-                                       int force, int general_zg, hipStream_t stream) {
+                                       int force, int general_zg, hipStream_t stream, NodeSink *ns) {
   if (nblocks <= 0) return hipSuccess;
 #define IBL_LAUNCH(T, C)                                                                         \
-  if (general_zg)                                                                                \
-    hipLaunchKernelGGL((collide_stream_face_kernel<T, C, true>), dim3(nblocks), dim3(kFaceBlock), \
-                       0, stream, cases, face_prefix, ncases, nblocks, cur, force);              \
-  else                                                                                           \
-    hipLaunchKernelGGL((collide_stream_face_kernel<T, C, false>), dim3(nblocks), dim3(kFaceBlock), \
-                       0, stream, cases, face_prefix, ncases, nblocks, cur, force)
+  return general_zg ? issue(collide_stream_face_kernel<T, C, true>, dim3(nblocks), dim3(kFaceBlock), \
+                            0, stream, ns, cases, face_prefix, ncases, nblocks, cur, force)        \
+                    : issue(collide_stream_face_kernel<T, C, false>, dim3(nblocks), dim3(kFaceBlock), \
+                            0, stream, ns, cases, face_prefix, ncases, nblocks, cur, force)
   IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
-  return hipGetLastError();
 }
 
 hipError_t launch_collide_stream_lean(int precision, int collision, const LeanArgs &a, int mode,
-                                      LaunchShape shape, hipStream_t stream) {
+                                      LaunchShape shape, hipStream_t stream, NodeSink *ns) {
   int grid = mode == 1 ? a.hntx * a.hnty : a.ntiles;
   if (grid <= 0) return hipSuccess;
   if (a.remap) grid = (grid + 7) / 8 * 8;
   dim3 block(shape.block_x, shape.block_y);
-#define IBL_LAUNCH(T, C)                                                                           \
-  if (mode == 1)                                                                                   \
-    hipLaunchKernelGGL((collide_stream_lean_kernel<T, C, 1>), dim3(grid), block, 0, stream, a);   \
-  else if (mode == 2)                                                                              \
-    hipLaunchKernelGGL((collide_stream_lean_kernel<T, C, 2>), dim3(grid), block, 0, stream, a);   \
-  else                                                                                             \
-    hipLaunchKernelGGL((collide_stream_lean_kernel<T, C, 0>), dim3(grid), block, 0, stream, a)
+#define IBL_LAUNCH(T, C)                                                                              \
+  return mode == 1   ? issue(collide_stream_lean_kernel<T, C, 1>, dim3(grid), block, 0, stream, ns, a) \
+         : mode == 2 ? issue(collide_stream_lean_kernel<T, C, 2>, dim3(grid), block, 0, stream, ns, a) \
+                     : issue(collide_stream_lean_kernel<T, C, 0>, dim3(grid), block, 0, stream, ns, a)
   IBL_DISPATCH(precision, collision, IBL_LAUNCH)
 #undef IBL_LAUNCH
-  return hipGetLastError();
 }
 #undef IBL_DISPATCH
 

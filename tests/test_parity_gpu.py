@@ -1194,6 +1194,39 @@ def test_time_collide_stream_counts_inner_nodes():
     assert 0.0 < us < 1e5
 
 
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+@pytest.mark.parametrize("walls", [False, True])
+def test_pipelined_graph_replay_is_bitwise_the_direct_steps(prec, walls):
+    """Pipelined steps replayed from the explicitly built graph (4 steps per
+    graph, both starting lattices) are bitwise the directly launched
+    pipelined steps and the plain steps, over calls that mix replays and
+    direct remainders, with eager work between the calls; with and without
+    Zou-He walls (the wall pass is a node of its own)."""
+    say(f"pipelined graph replay prec={prec} walls={walls}")
+    case = _split_case(ib.MDF, ib.PESKIN4, ib.TRT)
+    if walls:
+        case.update(bc=(ib.PERIODIC, ib.PERIODIC, ib.ZOU_HE, ib.ZOU_HE), u_bc=0.0,
+                    fluid_force=(4e-6, 0.0))
+    sims = []
+    for overlap, graph in ((False, 0), (True, 0), (True, 4)):
+        sim = ib.Sim(case, precision=prec)
+        sim.set_launch(64, 1, 1, 1)
+        sim.set_overlap(overlap)
+        sim.set_graph(graph)
+        sims.append(sim)
+    for n in (5, 10, 3, 8):
+        for sim in sims:
+            sim.step(n)
+        fx = [sim.forces(0)["fx"] for sim in sims]
+        pops = [sim.populations() for sim in sims]
+        assert [sim.overlap()[0] for sim in sims] == [False, True, True]
+        assert fx[1] == fx[0] and fx[2] == fx[0]
+        assert np.array_equal(pops[1], pops[0]) and np.array_equal(pops[2], pops[0])
+    assert sims[2].steps_done == 26
+    for sim in sims:
+        sim.close()
+
+
 def test_split_step_over_many_calls_is_the_plain_step():
     """Pipelined steps issued over many small calls (each IB launch of a
     pipelined step is replicated once per XCD and the first copy to start
