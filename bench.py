@@ -69,8 +69,7 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True, wan
         # the shipped table (written by the autotuner on an MI355X) when it
         # has this lattice, else tune now
         from paper_2609_02298_amd import autotune
-        launch = autotune.tune(case["nx"], case["ny"], case["collision"], precision)
-        launch = dict(launch, ib_threads=autotune.tune_ib(case, precision))
+        launch = autotune.tune_step(case, precision)
     sim = ib.Sim(case, precision=precision)
     if launch:
         sim.set_launch(**launch)

@@ -11,7 +11,10 @@ workloads start without re-tuning.
 
 The IB pass runs one workgroup per body; its size (256, 512 or 1024
 threads) is tuned per body description and precision by timing the pass on
-the workload itself (``tune_ib``; ``--ib`` tunes the benchmark's bodies).
+the workload itself (``tune_ib``).  For a workload with bodies the tile
+shape is then chosen by the time of whole steps (``tune_step``): the tiles
+that wait for the IB pass in a pipelined step are whole tiles, so wide tiles
+can lengthen the step.  ``--ib`` tunes both for the benchmark's workloads.
 """
 from __future__ import annotations
 
@@ -151,6 +154,56 @@ def tune_ib(case, precision, candidates=IB_CANDIDATES, steps=40) -> int:
     return best[1]
 
 
+# Shapes tried for whole pipelined steps: the kernel's best shape plus
+# narrow tiles, which keep the rectangle of tiles that wait for the IB pass
+# (rounded to whole tiles) small.
+STEP_CANDIDATES = [
+    dict(block_x=bx, block_y=by, rows_per_thread=rpt, xcd_remap=1)
+    for bx, by, rpt in ((64, 1, 1), (64, 1, 2), (64, 2, 1), (64, 2, 2), (64, 4, 1), (128, 1, 1),
+                        (128, 1, 2), (128, 2, 1), (256, 1, 1), (256, 1, 2))
+]
+
+
+def time_step(case, precision, shape, steps=100, warmup=20) -> float:
+    """Wall-clock microseconds per step of the workload itself (its bodies,
+    faces and pipelining), with the given launch shape."""
+    import time
+    s = ib.Sim(case, precision=precision)
+    try:
+        s.set_launch(**shape)
+        s.step(warmup)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        return (time.perf_counter() - t0) / steps * 1e6
+    finally:
+        s.close()
+
+
+def tune_step(case, precision, steps=100) -> dict:
+    """Launch shape and IB workgroup size for a workload with bodies, chosen
+    by whole-step time: in a pipelined step the tiles that wait for the IB
+    pass are whole tiles, so the shape that is fastest for the collide-stream
+    alone can lengthen the step."""
+    base = dict(tune(case["nx"], case["ny"], case["collision"], precision))
+    if not case.get("bodies"):
+        return base
+    ibt = tune_ib(case, precision)
+    k = "step-" + _key(case["nx"], case["ny"], case["collision"], precision) + "-" + _ib_key(case, precision)
+    if k in _cache:
+        return dict(_cache[k]["shape"], ib_threads=ibt)
+    cands = [base] + [c for c in STEP_CANDIDATES if c != base]
+    best = None
+    for sh in cands:
+        sh = dict(sh, ib_threads=ibt)
+        t = sorted(time_step(case, precision, sh, steps) for _ in range(2))[0]
+        if best is None or t < best[0]:
+            best = (t, sh)
+    _cache[k] = {"shape": {n: v for n, v in best[1].items() if n != "ib_threads"}, "us_per_step": best[0]}
+    return dict(best[1])
+
+
 def _bench_cases():
     """The bodies the benchmark steps: the headline cylinder with fixed and
     adaptive MDF, and the largest sweep case."""
@@ -191,6 +244,10 @@ def _main(argv=None):
                 t = tune_ib(case, prec)
                 k = _ib_key(case, prec)
                 print(f"{case['name']} IB {k}: {t} threads {_cache[k]['us']:.1f} us", flush=True)
+                sh = tune_step(case, prec)
+                ks = "step-" + _key(case["nx"], case["ny"], case["collision"], prec) + "-" + k
+                print(f"{case['name']} step {ks}: {sh} {_cache[ks]['us_per_step']:.2f} us per step",
+                      flush=True)
     _cache.pop("_fresh", None)
     save_cache(args.write)
 

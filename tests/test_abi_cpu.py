@@ -89,3 +89,19 @@ def test_product_path_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
                 assert "iblbm_oracle" not in txt, fn
+
+
+@pytest.mark.parametrize("nx,ny", [(65535, 40), (40, 32767), (46341, 46341), (2, 50), (50, 2)])
+def test_create_rejects_lattices_outside_the_limits_before_any_device_call(nx, ny):
+    """ib_lbm_create validates the lattice before it touches the device: on a
+    host without a GPU an oversized or degenerate lattice gives
+    IB_LBM_E_INVALID, not IB_LBM_E_DEVICE (nx < 65535, ny < 32767,
+    nx ny < 2^31, both at least 3)."""
+    import ctypes
+    _ensure_built()
+    L = ib.load_library()
+    cfg = B.make_config(dict(nx=nx, ny=ny, tau=0.8))
+    h = ctypes.c_void_p()
+    st = L.ib_lbm_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert st == -1, st
+    assert not h.value
