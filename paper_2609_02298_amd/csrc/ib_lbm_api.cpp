@@ -525,17 +525,25 @@ ib_lbm_status ensure_pipe_streams(ib_lbm_sim *s) {
 // whole tiles, the hold rectangle can reach row 1 or column 1).  `main`
 // then waits for both streams.  Nothing here reads device state.
 ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed, hipStream_t main, int cur0) {
+  if (nsteps <= 0) return IB_LBM_OK;
   LaunchShape sh{s->launch.block_x, s->launch.block_y, s->launch.rows_per_thread, s->launch.xcd_remap};
+  const bool zh = has_zou_he(s->cd);
   HIPCHK(s, hipEventRecord(s->ev_start, main));
   HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_start, 0));
   HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_start, 0));
   const CaseDesc *dc = (const CaseDesc *)s->d_case.p;
   for (int64_t i = 0; i < nsteps; i++) {
     const int cur = cur0 ^ (int)(i & 1);
+    const bool last = i + 1 == nsteps;
     const LeanArgs la = lean_args(s, cur, 0);
     EventPair p0{}, p1{};
-    // far tiles of step i after the hold tiles of step i-1
-    if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_near, 0));
+    // Each wait is enqueued before its event is recorded again for step i:
+    // the hold tiles of step i after the face nodes (and so the far tiles)
+    // of step i-1, the far tiles of step i after the hold tiles of step i-1.
+    if (i > 0) {
+      HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_far, 0));
+      HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_near, 0));
+    }
     if (timed) {
       p0 = take_pair(s->timing);
       HIPCHK(s, hipEventRecord(p0.a, s->lq));
@@ -545,21 +553,22 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed, hipSt
       HIPCHK(s, hipEventRecord(p0.b, s->lq));
       s->timing.ev[0].push_back(p0);
     }
-    // face nodes lie outside the hold rectangle's reach (plan_split)
+    // face nodes lie outside the hold rectangle's reach (plan_split); the
+    // events ride on the launches themselves
+    LaunchTarget face_done, hold_done;
+    face_done.done = s->ev_far;
+    hold_done.done = s->ev_near;
     HIPCHK(s, launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
                                           (const int32_t *)s->d_prefix.p + 2, 1,
                                           face_blocks(s->cd.nx, s->cd.ny), cur, 0,
-                                          general_zero_gradient(s->cd), s->lq));
-    // hold tiles of step i after the far tiles of step i-1 (the wait is
-    // enqueued before ev_far is recorded again for step i)
-    if (i > 0) HIPCHK(s, hipStreamWaitEvent(s->iq, s->ev_far, 0));
-    HIPCHK(s, hipEventRecord(s->ev_far, s->lq));
-    HIPCHK(s, launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 1, sh, s->iq));
-    HIPCHK(s, hipEventRecord(s->ev_near, s->iq));
-    if (has_zou_he(s->cd)) {
+                                          general_zero_gradient(s->cd), s->lq, &face_done));
+    HIPCHK(s, launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 1, sh, s->iq, &hold_done));
+    if (zh) {
       // every push into a wall node, hold tiles included, has landed
+      LaunchTarget zou_done;
+      zou_done.done = last ? s->ev_lq : nullptr;
       HIPCHK(s, hipStreamWaitEvent(s->lq, s->ev_near, 0));
-      HIPCHK(s, launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, cur, s->lq));
+      HIPCHK(s, launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, cur, s->lq, &zou_done));
     }
     if (timed) {
       p1 = take_pair(s->timing);
@@ -567,17 +576,18 @@ ib_lbm_status enqueue_pipelined(ib_lbm_sim *s, int64_t nsteps, bool timed, hipSt
     }
     // one copy of the single body's IB workgroup per XCD; the first to start
     // runs the pass (the far tiles on the other stream fill the chip)
+    LaunchTarget ib_done;
+    ib_done.done = last ? s->ev_iq : nullptr;
     HIPCHK(s, launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, 1, s->lds_bytes,
                          s->spread_mode, s->nslots_fast, 8, (uint32_t *)s->ticket.p,
-                         s->launch.ib_threads, s->iq));
+                         s->launch.ib_threads, s->iq, &ib_done));
     if (timed) {
       HIPCHK(s, hipEventRecord(p1.b, s->iq));
       s->timing.ev[1].push_back(p1);
     }
   }
-  HIPCHK(s, hipEventRecord(s->ev_lq, s->lq));
-  HIPCHK(s, hipEventRecord(s->ev_iq, s->iq));
-  HIPCHK(s, hipStreamWaitEvent(main, s->ev_lq, 0));
+  // the last launch on each stream carries the event the sim's stream waits for
+  HIPCHK(s, hipStreamWaitEvent(main, zh ? s->ev_lq : s->ev_far, 0));
   HIPCHK(s, hipStreamWaitEvent(main, s->ev_iq, 0));
   return IB_LBM_OK;
 }
@@ -605,33 +615,33 @@ ib_lbm_status build_pipelined_graph(ib_lbm_sim *s, int64_t nsteps, int cur0, hip
     size_t n = 0;
     for (hipGraphNode_t x : deps)
       if (x) d[n++] = x;
-    NodeSink ns{g, d, n, nullptr};
+    LaunchTarget ns{g, d, n, nullptr};
     if (e == hipSuccess) e = launch(&ns);
     return ns.node;
   };
   for (int64_t i = 0; i < nsteps && e == hipSuccess; i++) {
     const int cur = cur0 ^ (int)(i & 1);
     const LeanArgs la = lean_args(s, cur, 0);
-    hipGraphNode_t far = add({prev_lq, prev_hold}, [&](NodeSink *ns) {
+    hipGraphNode_t far = add({prev_lq, prev_hold}, [&](LaunchTarget *ns) {
       return launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 2, sh, nullptr, ns);
     });
-    hipGraphNode_t face = add({far ? far : prev_lq, far ? nullptr : prev_hold}, [&](NodeSink *ns) {
+    hipGraphNode_t face = add({far ? far : prev_lq, far ? nullptr : prev_hold}, [&](LaunchTarget *ns) {
       return launch_collide_stream_faces(s->cd.precision, s->cd.collision, dc,
                                          (const int32_t *)s->d_prefix.p + 2, 1,
                                          face_blocks(s->cd.nx, s->cd.ny), cur, 0,
                                          general_zero_gradient(s->cd), nullptr, ns);
     });
     hipGraphNode_t lq_end = face ? face : far;
-    hipGraphNode_t hold = add({prev_lq, prev_ib}, [&](NodeSink *ns) {
+    hipGraphNode_t hold = add({prev_lq, prev_ib}, [&](LaunchTarget *ns) {
       return launch_collide_stream_lean(s->cd.precision, s->cd.collision, la, 1, sh, nullptr, ns);
     });
     if (zh) {
-      hipGraphNode_t z = add({lq_end, hold}, [&](NodeSink *ns) {
+      hipGraphNode_t z = add({lq_end, hold}, [&](LaunchTarget *ns) {
         return launch_zou_he(s->cd.precision, dc, s->cd.nx, s->cd.ny, cur, nullptr, ns);
       });
       if (z) lq_end = z;
     }
-    hipGraphNode_t ib = add({hold ? hold : prev_ib}, [&](NodeSink *ns) {
+    hipGraphNode_t ib = add({hold ? hold : prev_ib}, [&](LaunchTarget *ns) {
       return launch_ibm(s->cd.precision, dc, (const IbmSlot *)s->d_slots.p, 1, s->lds_bytes,
                         s->spread_mode, s->nslots_fast, 8, (uint32_t *)s->ticket.p,
                         s->launch.ib_threads, nullptr, ns);

@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <tuple>
@@ -234,14 +235,18 @@ struct LeanArgs {
 };
 
 // ---- kernel launchers (defined in the .hip files) ----
-// A launcher either launches on its stream or, given a NodeSink, adds the
-// same kernel with the same arguments as a node of an explicitly built
-// graph, after the sink's dependencies (node is null when nothing is added).
-struct NodeSink {
-  hipGraph_t graph;
-  const hipGraphNode_t *deps;
-  size_t ndeps;
-  hipGraphNode_t node;
+// A launcher launches on its stream unless given a LaunchTarget.  With a
+// graph, the target takes the same kernel with the same arguments as a node
+// of that explicitly built graph, after its dependencies (node is null when
+// nothing is added).  Without one, the kernel is launched on the stream with
+// `done` as the launch's completion event: the event is recorded by the
+// kernel's own completion, with no separate marker packet behind it.
+struct LaunchTarget {
+  hipGraph_t graph = nullptr;
+  const hipGraphNode_t *deps = nullptr;
+  size_t ndeps = 0;
+  hipGraphNode_t node = nullptr;
+  hipEvent_t done = nullptr;
 };
 
 template <typename Tup, size_t... I>
@@ -249,13 +254,23 @@ inline void arg_pointers(Tup &t, void **p, std::index_sequence<I...>) {
   ((p[I] = (void *)&std::get<I>(t)), ...);
 }
 
+// What a launcher returns when it has no work: a direct launch's completion
+// event is still recorded, so that waits on it keep their order.
+inline hipError_t nothing_to_launch(hipStream_t stream, LaunchTarget *ns) {
+  if (ns && !ns->graph && ns->done) return hipEventRecord(ns->done, stream);
+  return hipSuccess;
+}
+
 template <typename... P, typename... A>
 inline hipError_t issue(void (*kernel)(P...), dim3 grid, dim3 block, unsigned shmem,
-                        hipStream_t stream, NodeSink *ns, A &&...args) {
+                        hipStream_t stream, LaunchTarget *ns, A &&...args) {
   std::tuple<std::decay_t<P>...> vals(std::forward<A>(args)...);
   void *ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
   arg_pointers(vals, ptrs, std::index_sequence_for<P...>{});
   if (!ns) return hipLaunchKernel((const void *)kernel, grid, block, ptrs, shmem, stream);
+  if (!ns->graph)
+    return hipExtLaunchKernel((const void *)kernel, grid, block, ptrs, shmem, stream, nullptr,
+                              ns->done, 0);
   hipKernelNodeParams p{};
   p.func = (void *)kernel;
   p.gridDim = grid;
@@ -273,23 +288,23 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
                                  LaunchShape shape, hipStream_t stream);
 // Inner nodes of one case with its arguments by value (see LeanArgs).
 hipError_t launch_collide_stream_lean(int precision, int collision, const LeanArgs &a, int mode,
-                                      LaunchShape shape, hipStream_t stream, NodeSink *ns = nullptr);
+                                      LaunchShape shape, hipStream_t stream, LaunchTarget *ns = nullptr);
 // The face nodes (rows 0 and ny-1, columns 0, nx-2, nx-1) with the face
 // closures; face_prefix[i] is the first workgroup of case i (face_blocks per
 // case), nblocks the total; cur < 0 takes each case's lattice from its state.
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
                                        const int32_t *face_prefix, int ncases, int nblocks, int cur,
                                        int force, int general_zg, hipStream_t stream,
-                                       NodeSink *ns = nullptr);
+                                       LaunchTarget *ns = nullptr);
 // IB launch over nslots slots; replicas > 1 (with a per-slot counter that
 // every copy advances, see ibm_kernel) lets the first-started copy of each
 // slot run it.  threads: workgroup size (0: the instance's default), capped
 // at the instance's launch bound.
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
-                      int threads, hipStream_t stream, NodeSink *ns = nullptr);
+                      int threads, hipStream_t stream, LaunchTarget *ns = nullptr);
 hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream,
-                         NodeSink *ns = nullptr);
+                         LaunchTarget *ns = nullptr);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
                          hipStream_t stream);

@@ -1737,8 +1737,8 @@ int ibm_max_lds_bytes() { return kIbmDynLds; }
 
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
-                      int threads, hipStream_t stream, NodeSink *ns) {
-  if (nslots <= 0) return hipSuccess;
+                      int threads, hipStream_t stream, LaunchTarget *ns) {
+  if (nslots <= 0) return nothing_to_launch(stream, ns);
   static bool configured = false;
   if (!configured) {
     // allow the large dynamic LDS workspace (gfx950 has 160 KB per CU)

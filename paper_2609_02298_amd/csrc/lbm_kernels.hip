@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void zou_he_kernel(const CaseDesc *__restrict_
 }
 
 hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream,
-                         NodeSink *ns) {
+                         LaunchTarget *ns) {
   const int n = 2 * nx + 2 * (ny - 2);
   const int blocks = (n + 255) / 256;
   if (precision == kPrecFP64) return issue(zou_he_kernel<double>, dim3(blocks), dim3(256), 0, stream, ns, c, cur);
@@ -711,8 +711,8 @@ hipError_t launch_collide_stream(int precision, int collision, const CaseDesc *c
 
 hipError_t launch_collide_stream_faces(int precision, int collision, const CaseDesc *cases,
                                        const int32_t *face_prefix, int ncases, int nblocks, int cur,
-                                       int force, int general_zg, hipStream_t stream, NodeSink *ns) {
-  if (nblocks <= 0) return hipSuccess;
+                                       int force, int general_zg, hipStream_t stream, LaunchTarget *ns) {
+  if (nblocks <= 0) return nothing_to_launch(stream, ns);
 #define IBL_LAUNCH(T, C)                                                                         \
   return general_zg ? issue(collide_stream_face_kernel<T, C, true>, dim3(nblocks), dim3(kFaceBlock), \
                             0, stream, ns, cases, face_prefix, ncases, nblocks, cur, force)        \
@@ -723,9 +723,9 @@ hipError_t launch_collide_stream_faces(int precision, int collision, const CaseD
 }
 
 hipError_t launch_collide_stream_lean(int precision, int collision, const LeanArgs &a, int mode,
-                                      LaunchShape shape, hipStream_t stream, NodeSink *ns) {
+                                      LaunchShape shape, hipStream_t stream, LaunchTarget *ns) {
   int grid = mode == 1 ? a.hntx * a.hnty : a.ntiles;
-  if (grid <= 0) return hipSuccess;
+  if (grid <= 0) return nothing_to_launch(stream, ns);
   if (a.remap) grid = (grid + 7) / 8 * 8;
   dim3 block(shape.block_x, shape.block_y);
 #define IBL_LAUNCH(T, C)                                                                              \
