@@ -33,13 +33,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
 def kernel_source_hash() -> str:
-    """Hash of what the collide-stream kernels are built from: their source
-    and the shared definitions (structs, helpers) ahead of the launcher
-    declarations in the internal header."""
+    """Hash of what the collide-stream kernels are built from: their source,
+    the shared collide-stream device code, and the shared definitions
+    (structs, helpers) ahead of the launcher declarations in the internal
+    header."""
     csrc = os.path.join(ROOT, "paper_2609_02298_amd", "csrc")
     h = hashlib.sha256()
-    with open(os.path.join(csrc, "lbm_kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    for name in ("lbm_kernels.hip", "lbm_device.h"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
     with open(os.path.join(csrc, "ib_lbm_internal.h"), "rb") as fh:
         head = fh.read()
     h.update(head.split(b"// ---- kernel launchers")[0])
@@ -86,6 +88,7 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True, wan
     # MDF passes applied in each timed step (history column 12)
     passes = sim.history(0, warmup + 1, steps)[:, 12] if steps else np.zeros(0)
     split, near = sim.overlap()
+    fused = sim.fused()
     # IB pass duration from HIP events around each pass in a separate run of
     # unpipelined steps (the events add host and queue work to every step, so
     # the wall-clock run above has none)
@@ -117,7 +120,7 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True, wan
     lbm_ms, n_lbm = lbm_us * 1e-3, 1
     out = dict(seconds=t1 - t0, lbm_ms=lbm_ms, n_lbm=n_lbm, ibm_ms=ibm_ms, n_ibm=n_ibm,
                inner_nodes=inner,
-               split=split, near_nodes=near,
+               split=split, near_nodes=near, fused=fused,
                fx=st["fx"], status=st["status"], steps_done=sim.steps_done,
                diag=diag, diag_ms=float(np.median(dts)) * 1e3,
                passes_mean=float(passes.mean()) if len(passes) else 0.0,
@@ -340,7 +343,10 @@ def main():
                      "bytes_per_node": bpn, "nodes_per_launch": lbm_nodes,
                      "avg_launch_us": round(lbm_avg_s * 1e6, 3),
                      "launch": r["launch"]},
-        "pipelined_steps": {"in_use": r["split"], "nodes_waiting_for_ib": r["near_nodes"]},
+        # fused: one launch per step (the IB pass beside every tile); else
+        # pipelined: two streams, the tiles next to the body after the pass
+        "pipelined_steps": {"in_use": r["split"], "fused": r["fused"],
+                            "nodes_waiting_for_ib": 0 if r["fused"] else r["near_nodes"]},
         "ib_pass_avg_us": round(r["ibm_ms"] / max(r["n_ibm"], 1) * 1e3, 3),
         "hbm_fraction_of_step": round(bpn * nodes * args.steps / r["seconds"] / 1e9 / HBM_PEAK_GBS, 4),
         "lattice_bytes": 2 * 9 * nodes * (bpn // 18),

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IB_LBM_ABI_VERSION 5u
+#define IB_LBM_ABI_VERSION 6u
 
 typedef enum {
   IB_LBM_OK = 0,
@@ -351,6 +351,24 @@ ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph);
  * is not NULL, the number of nodes in the tiles that wait for the IB pass. */
 ib_lbm_status ib_lbm_set_overlap(ib_lbm_sim *s, int32_t on);
 ib_lbm_status ib_lbm_get_overlap(const ib_lbm_sim *s, int32_t *in_use, int64_t *near_nodes);
+
+/* Fused steps (default on).  A pipelined sim (see ib_lbm_set_overlap) whose
+ * single body is fixed, DF or MDF on the 1024-thread IB kernel, with BGK or
+ * TRT collision and no Zou-He wall, takes one launch per step on the sim's
+ * stream, with no second stream and no events.  Workgroup 0 runs the IB
+ * pass: it collides the nodes that push into the body's support itself,
+ * from the step's input lattice and the force of the previous pass, while
+ * the other workgroups collide and stream every node.  The tiles that read
+ * the IB force count themselves on the case state before the pass writes
+ * the new force.  Results are bitwise those of unpipelined steps, and the
+ * steps can be captured and replayed (ib_lbm_set_graph).  The first call
+ * builds the list of nodes the pass collides from the body's support (after
+ * one pipelined step if none has run; a synchronising copy, and it may
+ * allocate); kernel timing (ib_lbm_timing_enable) runs pipelined steps.
+ * set_fused(0/1) forbids or allows it; get_fused reports whether the
+ * current configuration uses it (after the first step). */
+ib_lbm_status ib_lbm_set_fused(ib_lbm_sim *s, int32_t on);
+ib_lbm_status ib_lbm_get_fused(const ib_lbm_sim *s, int32_t *in_use);
 
 /* Kernel timing with HIP events (direct launches only).  which: 0
  * collide-stream, 1 immersed boundary.  With pipelined steps a collide-stream

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <map>
 #include <limits>
 #include <string>
 #include <vector>
@@ -30,6 +31,11 @@ struct HostBody {
   ib_lbm_body_desc d;
   BodyDesc dev;  // host copy of the device description
   DevBuf cos_t, sin_t, ws, tab, acc, markers, lambda, history, state;
+  // fused steps: the force copy and staged pushes (fixed DF/MDF bodies), and
+  // the nodes the IB pass collides itself with their push map, built once
+  // the device has built the body's tables
+  DevBuf fprev, pstage, src;
+  bool src_ready = false;
 };
 
 struct EventPair {
@@ -88,6 +94,12 @@ struct ib_lbm_sim {
   hipStream_t lq = nullptr, iq = nullptr;
   hipEvent_t ev_start = nullptr, ev_lq = nullptr, ev_iq = nullptr, ev_near = nullptr,
              ev_far = nullptr;
+  // Fused steps (see plan_fused): one launch per step on the sim's stream.
+  bool fused_allowed = true;  // allowed by the caller
+  bool fused = false;         // in use for the current tables
+  int32_t fhold[4] = {0, 0, 0, 0};  // hold rectangle in tiles of the fused shape
+  int fbx = kFusedThreads, fby = 1, frpt = 4;  // the fused launch's tile shape
+  uint32_t fused_seq = 0;  // sequence number of the last fused launch (CaseState::gate)
 };
 
 struct ib_lbm_batch {
@@ -338,6 +350,37 @@ ib_lbm_status plan_split(ib_lbm_sim *s) {
   return IB_LBM_OK;
 }
 
+bool body_fast(const HostBody &hb, int spread_mode);
+static bool has_zou_he(const CaseDesc &c);
+
+// Fused steps (one launch per step, step_fused_kernel): a pipelined sim
+// (plan_split) whose single body is fixed, DF or MDF on the 1024-thread IB
+// kernel, with BGK or TRT and no Zou-He wall.  The hold rectangle is the
+// pipelined one, in tiles of the fused shape (fbx x fby, frpt rows per
+// thread): the tiles that read the IB force.
+ib_lbm_status plan_fused(ib_lbm_sim *s) {
+  s->fused = false;
+  if (!s->fused_allowed || !s->split || s->bodies.size() != 1) return IB_LBM_OK;
+  const HostBody &hb = s->bodies[0];
+  const ib_lbm_body_desc &d = hb.d;
+  if (d.motion != IB_LBM_FIXED || d.scheme == IB_LBM_DFC || hb.dev.mdf_coupled) return IB_LBM_OK;
+  if (!body_fast(hb, s->spread_mode) || hb.dev.max_nodes >= 32768 || !hb.fprev.p || !hb.pstage.p)
+    return IB_LBM_OK;
+  if (s->cd.collision != IB_LBM_BGK && s->cd.collision != IB_LBM_TRT) return IB_LBM_OK;
+  if (has_zou_he(s->cd) || pop_values(s->cd.nx, s->cd.ny) >= (int64_t)INT32_MAX) return IB_LBM_OK;
+  const double r = 0.5 * d.diameter;
+  const int lo = d.kernel == IB_LBM_PESKIN4 ? 1 : 0, hi = d.kernel == IB_LBM_PESKIN4 ? 2 : 1;
+  const int x0 = (int)std::floor(d.xc - r) - lo - 2, y0 = (int)std::floor(d.yc - r) - lo - 2;
+  const int x1 = (int)std::floor(d.xc + r) + hi + 2, y1 = (int)std::floor(d.yc + r) + hi + 2;
+  const int TX = s->fbx, TY = s->fby * s->frpt;
+  s->fhold[0] = x0 / TX;
+  s->fhold[1] = y0 / TY;
+  s->fhold[2] = x1 / TX - x0 / TX + 1;
+  s->fhold[3] = y1 / TY - y0 / TY + 1;
+  s->fused = true;
+  return IB_LBM_OK;
+}
+
 // A body runs on the 1024-thread IB kernel when it is DF/MDF, its workspace
 // fits in LDS and spreading is by gather; the choice depends on the body
 // alone, so a body's results do not depend on its batch-mates.
@@ -408,6 +451,7 @@ ib_lbm_status build_sim_tables(ib_lbm_sim *s) {
   s->nslots = n;
   s->lds_bytes = lds_budget(maxws);
   if ((st0 = plan_split(s))) return st0;
+  if ((st0 = plan_fused(s))) return st0;
   s->tables_dirty = false;
   drop_graphs(s);
   return IB_LBM_OK;
@@ -656,10 +700,99 @@ ib_lbm_status build_pipelined_graph(ib_lbm_sim *s, int64_t nsteps, int cur0, hip
   return IB_LBM_OK;
 }
 
+// The nodes whose pushes reach the support of the fused sim's body, and
+// their push map (BodyDesc::src), from the support the device
+// built at the body's first IB pass (the hot part of its cached tables:
+// the support node list nxy and its length S).  Sorted by row and column,
+// so that the pass reads the lattice in runs.
+ib_lbm_status build_fused_sources(ib_lbm_sim *s) {
+  HostBody &hb = s->bodies[0];
+  const BodyDesc &B = hb.dev;
+  std::vector<double> hot((size_t)B.ws_tab_hot);
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, hipMemcpy(hot.data(), hb.tab.p, hot.size() * 8, hipMemcpyDeviceToHost));
+  const int32_t *ints = (const int32_t *)(hot.data() + ws_table_doubles(B.nb, B.ns));
+  const int32_t *nxy = ints + B.nb * B.ns;
+  const int S = ints[B.nb * B.ns + B.max_nodes + ell_width(B.ns) * B.max_nodes];
+  if (S <= 0 || S > B.max_nodes) {
+    set_err(&s->err, "fused step: the body's support table is not built");
+    return IB_LBM_E_STATE;
+  }
+  std::map<int64_t, int> sup;  // (y, x) -> support index
+  auto key = [](int x, int y) { return ((int64_t)y << 32) | (uint32_t)x; };
+  for (int j = 0; j < S; j++) sup[key(nxy[j] & 0xffff, nxy[j] >> 16)] = j;
+  static const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  std::map<int64_t, int> src;  // (y, x) of every node that pushes into the support
+  for (int j = 0; j < S; j++) {
+    const int x = nxy[j] & 0xffff, y = nxy[j] >> 16;
+    for (int i = 0; i < 9; i++) src[key(x - ex[i], y - ey[i])] = 0;
+  }
+  const int n = (int)src.size();
+  std::vector<SrcNode> rec(n);
+  int u = 0;
+  for (auto &e : src) {
+    const int y = (int)(e.first >> 32), x = (int)(uint32_t)e.first;
+    if (x < 1 || x > s->cd.nx - 3 || y < 1 || y > s->cd.ny - 2) {
+      set_err(&s->err, "fused step: a support neighbour is not an inner node");
+      return IB_LBM_E_STATE;
+    }
+    SrcNode &r = rec[u];
+    memset(&r, 0, sizeof r);
+    r.off = (int32_t)pop_node(x, y, s->cd.nseg);
+    for (int i = 0; i < 9; i++) {
+      auto it = sup.find(key(x + ex[i], y + ey[i]));
+      r.map[i] = (int16_t)(it == sup.end() ? -1 : it->second);
+    }
+    u++;
+  }
+  dev_free(s, &hb.src);
+  ib_lbm_status st = dev_alloc(s, &hb.src, (size_t)n * sizeof(SrcNode));
+  if (st) return st;
+  HIPCHK(s, hipMemcpy(hb.src.p, rec.data(), (size_t)n * sizeof(SrcNode), hipMemcpyHostToDevice));
+  hb.dev.src = (const SrcNode *)hb.src.p;
+  hb.dev.n_src = n;
+  HIPCHK(s, hipMemcpy(s->d_bodies.p, &hb.dev, sizeof(BodyDesc), hipMemcpyHostToDevice));
+  hb.src_ready = true;
+  return IB_LBM_OK;
+}
+
+// Enqueue nsteps fused steps on `stream` from input lattice cur0: one
+// launch each, ordered by the stream alone (see step_fused_kernel).
+ib_lbm_status enqueue_fused(ib_lbm_sim *s, int64_t nsteps, hipStream_t stream, int cur0) {
+  for (int64_t i = 0; i < nsteps; i++) {
+    const int cur = cur0 ^ (int)(i & 1);
+    FusedArgs fa;
+    memset(&fa, 0, sizeof fa);
+    fa.lean = lean_args(s, cur, 0);
+    const int TX = s->fbx, TY = s->fby * s->frpt;
+    fa.lean.tiles_x = (s->cd.nx + TX - 1) / TX;
+    fa.lean.ntiles = fa.lean.tiles_x * ((s->cd.ny + TY - 1) / TY);
+    fa.lean.rpt = s->frpt;
+    fa.lean.remap = 1;
+    fa.lean.htx0 = s->fhold[0];
+    fa.lean.hty0 = s->fhold[1];
+    fa.lean.hntx = s->fhold[2];
+    fa.lean.hnty = s->fhold[3];
+    fa.c = (const CaseDesc *)s->d_case.p;
+    fa.face_prefix = (const int32_t *)s->d_prefix.p + 2;
+    fa.nface = face_blocks(s->cd.nx, s->cd.ny);
+    fa.gzg = general_zero_gradient(s->cd);
+    fa.bx = s->fbx;
+    fa.by = s->fby;
+    fa.cur = cur;
+    fa.seq = (int32_t)(++s->fused_seq);
+    fa.nsrc = (s->bodies[0].dev.n_src + kFusedThreads - 1) / kFusedThreads;
+    HIPCHK(s, launch_step_fused(s->cd.precision, s->cd.collision, fa, s->lds_bytes, stream));
+  }
+  return IB_LBM_OK;
+}
+
 // Enqueue nsteps steps of a sim on `stream` from input lattice cur0,
 // pipelined when the sim allows it and `pipelined` is set.
 ib_lbm_status enqueue_steps(ib_lbm_sim *s, int64_t nsteps, bool timed, hipStream_t stream, int cur0,
                             bool pipelined) {
+  if (s->fused && s->bodies[0].src_ready && !timed) return enqueue_fused(s, nsteps, stream, cur0);
   if (s->split && pipelined) return enqueue_pipelined(s, nsteps, timed, stream, cur0);
   for (int64_t i = 0; i < nsteps; i++) {
     ib_lbm_status st = enqueue_sim_step(s, timed, stream, cur0 ^ (int)(i & 1));
@@ -986,6 +1119,19 @@ ib_lbm_status ib_lbm_add_body(ib_lbm_sim *s, const ib_lbm_body_desc *b, int32_t 
   B.lambda_cache = (double *)hb.lambda.p;
   B.history = (double *)hb.history.p;
   B.state = (BodyState *)hb.state.p;
+  B.src = nullptr;
+  B.n_src = 0;
+  B.fprev = nullptr;
+  B.pstage = nullptr;
+  if (b->motion == IB_LBM_FIXED && b->scheme != IB_LBM_DFC) {
+    // fused steps: the copy of the last force (zero, as the force field
+    // starts) and the staged pushes of the support nodes
+    if ((st = dev_alloc(s, &hb.fprev, (size_t)B.max_nodes * 2 * B.pop_bytes))) return st;
+    if ((st = dev_alloc(s, &hb.pstage, (size_t)B.max_nodes * 9 * B.pop_bytes))) return st;
+    HIPCHK(s, hipMemset(hb.fprev.p, 0, (size_t)B.max_nodes * 2 * B.pop_bytes));
+    B.fprev = hb.fprev.p;
+    B.pstage = hb.pstage.p;
+  }
   BodyState bst;
   memset(&bst, 0, sizeof bst);
   bst.xc = b->xc;
@@ -1009,6 +1155,22 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
   if (s->split && (st = ensure_pipe_streams(s))) return st;
   s->started = true;
   int64_t left = nsteps;
+  if (s->fused && !s->bodies[0].src_ready && left > 0 && !s->timing.on) {
+    // fused steps start from the support the device builds at the body's
+    // first IB pass: one pipelined step first if none has run
+    if (s->host_steps == 0) {
+      if ((st = enqueue_steps(s, 1, false, s->stream, s->host_cur, true))) return st;
+      s->host_cur ^= 1;
+      left -= 1;
+    }
+    st = build_fused_sources(s);
+    if (st == IB_LBM_E_STATE) {
+      // no support table (a halted case): pipelined steps
+      s->fused = false;
+      st = IB_LBM_OK;
+    }
+    if (st) return st;
+  }
   if (s->graph_steps > 0 && !s->timing.on && left >= s->graph_steps) {
     if (s->graph_len != s->graph_steps) {
       drop_graphs(s);
@@ -1017,7 +1179,7 @@ ib_lbm_status ib_lbm_step(ib_lbm_sim *s, int64_t nsteps) {
     // pipelined steps: an explicitly built graph per starting lattice, both
     // made at the first replay; plain steps: captured on a private stream
     // (the caller's may be the null stream); replayed on the caller's stream
-    if (s->split) {
+    if (s->split && !s->fused) {
       for (int p = 0; p < 2; p++)
         if (!s->graph_exec[p] && (st = build_pipelined_graph(s, s->graph_len, p, &s->graph_exec[p])))
           return st;
@@ -1333,6 +1495,7 @@ ib_lbm_status ib_lbm_destroy(ib_lbm_sim *s) {
     dev_free(s, &hb.cos_t); dev_free(s, &hb.sin_t); dev_free(s, &hb.ws); dev_free(s, &hb.markers);
     dev_free(s, &hb.tab); dev_free(s, &hb.acc);
     dev_free(s, &hb.lambda); dev_free(s, &hb.history); dev_free(s, &hb.state);
+    dev_free(s, &hb.fprev); dev_free(s, &hb.pstage); dev_free(s, &hb.src);
   }
   dev_free(s, &s->f0); dev_free(s, &s->f1); dev_free(s, &s->force); dev_free(s, &s->state);
   dev_free(s, &s->ticket);
@@ -1403,6 +1566,24 @@ ib_lbm_status ib_lbm_get_overlap(const ib_lbm_sim *s, int32_t *in_use, int64_t *
   return IB_LBM_OK;
 }
 
+ib_lbm_status ib_lbm_set_fused(ib_lbm_sim *s, int32_t on) {
+  ib_lbm_status st = usable(s);
+  if (st) return st;
+  if (on != 0 && on != 1) return IB_LBM_E_INVALID;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  if (s->fused_allowed != (on != 0)) {
+    s->fused_allowed = on != 0;
+    s->tables_dirty = true;
+  }
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_get_fused(const ib_lbm_sim *s, int32_t *in_use) {
+  if (!s || !in_use) return IB_LBM_E_INVALID;
+  *in_use = s->fused && !s->tables_dirty ? 1 : 0;
+  return IB_LBM_OK;
+}
+
 ib_lbm_status ib_lbm_set_graph(ib_lbm_sim *s, int32_t steps_per_graph) {
   ib_lbm_status st = usable(s);
   if (st) return st;
@@ -1451,6 +1632,9 @@ ib_lbm_status ib_lbm_time_collide_stream(ib_lbm_sim *s, int32_t launches, double
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   HIPCHK(s, e);
+  // the launches consumed the IB force: so does the copy fused steps read
+  for (auto &hb : s->bodies)
+    if (hb.fprev.p) HIPCHK(s, hipMemset(hb.fprev.p, 0, hb.fprev.bytes));
   *avg_us = ms * 1e3 / launches;
   if (inner_nodes) *inner_nodes = (int64_t)(s->cd.nx - 3) * (s->cd.ny - 2);
   return IB_LBM_OK;

@@ -71,7 +71,19 @@ struct CaseState {
   // Coupled MDF: the IB workgroups of the case exchange their residuals
   // through xr (two rounds' worth, alternating), counting arrivals in xcnt;
   // the last workgroup of a step resets xcnt.
-  int32_t xcnt, xpad;
+  int32_t xcnt;
+  // Fused steps: the workgroups of the tiles that read the IB force count
+  // themselves here once they have read (and cleared) it; the IB pass of the
+  // same launch writes the new force only after all of them, then resets it.
+  int32_t hold_seen;
+  // Fused steps: the IB pass sets this to the launch's sequence number once
+  // its loads from device memory are done; the tiles start streaming then
+  // (a schedule only: they do not depend on the pass).
+  int32_t gate;
+  // Fused steps: the workgroups that collide the nodes pushing into the
+  // support count themselves here once their pushes are staged; the IB pass
+  // takes the support's moments after all of them, then resets it.
+  int32_t src_seen;
   double xr[2][kMaxBodiesPerCase];
 };
 
@@ -93,6 +105,16 @@ struct BodyState {
   int32_t lambda_valid; // DFC cache filled (fixed bodies)
   int32_t tables_valid; // geometry tables cached (fixed bodies)
   int32_t tables_full;  // a step needs the whole cached table, not only its hot part
+};
+
+// A node whose pushes reach the support of a fused step's body: the offset
+// of its population 0 in a lattice (pop_node) and, per population i, the
+// support node it is pushed to (-1: none; map[0] is the node itself, also
+// the index of its force in BodyDesc::fprev).  32 bytes: two 16-byte loads.
+struct alignas(16) SrcNode {
+  int32_t off;
+  int16_t map[9];
+  int16_t pad[5];
 };
 
 // Constant per-body description plus pointers to the body's device buffers.
@@ -124,6 +146,17 @@ struct BodyDesc {
   double *markers_out;  // n_b x 8: X Y Udx Udy Fx Fy lambda ds
   double *lambda_cache; // n_b
   double *history;      // hist_cap x kHistCols
+  // Fused steps (fixed DF/MDF bodies): the IB pass collides the support
+  // nodes and their neighbours itself.  src: one SrcNode per such node
+  // (n_src of them).  fprev: the force the last pass wrote to the support
+  // nodes (2 x max_nodes, the population type); pstage: the pushed
+  // populations of the support nodes (population-major: 9 planes of
+  // max_nodes).  Null when unused.
+  const struct SrcNode *src;
+  int32_t n_src;
+  int32_t pad_src;
+  void *fprev;
+  void *pstage;
   BodyState *state;
 };
 
@@ -303,6 +336,29 @@ hipError_t launch_collide_stream_faces(int precision, int collision, const CaseD
 hipError_t launch_ibm(int precision, const CaseDesc *cases, const IbmSlot *slots, int nslots,
                       int lds_bytes, int spread_mode, int fast, int replicas, uint32_t *ticket,
                       int threads, hipStream_t stream, LaunchTarget *ns = nullptr);
+// One launch per step for a case with a single fixed DF/MDF body
+// (step_fused_kernel): workgroup 0 runs the IB pass; the next nsrc
+// workgroups collide the nodes that push into the body's support, from the
+// step's input lattice, and stage those pushes for the pass (CaseState::
+// src_seen); then the tiles of the hold rectangle (lean.htx0..hnty: every node that
+// carries IB force), which read and clear the force and count themselves in
+// CaseState::hold_seen; then the face nodes, one face workgroup of
+// kFaceBlock nodes per workgroup; then every other tile.  All workgroups have kFusedThreads
+// threads; a tile is a logical bx x by workgroup (bx * by = kFusedThreads)
+// with lean.rpt rows per thread.
+constexpr int kFusedThreads = 1024;
+struct FusedArgs {
+  LeanArgs lean;
+  const CaseDesc *c;
+  const int32_t *face_prefix;
+  int32_t nface, gzg, bx, by;
+  int32_t cur;  // the step's input lattice (faces and tiles; the IB pass reads the case state)
+  int32_t seq;  // the launch's sequence number (CaseState::gate)
+  int32_t nsrc; // workgroups of the support's own collision (BodyDesc::n_src nodes)
+};
+int fused_grid(const FusedArgs &a);
+hipError_t launch_step_fused(int precision, int collision, const FusedArgs &a, int lds_bytes,
+                             hipStream_t stream, LaunchTarget *ns = nullptr);
 hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream,
                          LaunchTarget *ns = nullptr);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);

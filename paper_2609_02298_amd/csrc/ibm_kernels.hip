@@ -27,6 +27,7 @@
 #include <mutex>
 
 #include "ib_lbm_internal.h"
+#include "lbm_device.h"
 
 namespace iblbm {
 
@@ -591,13 +592,65 @@ __device__ __forceinline__ double case_exchange_max(CaseState *cs, int body, int
   return m;
 }
 
+// Bounded wait of thread 0 until the hold-rectangle workgroups of a fused
+// step have all counted themselves (they have read and cleared the IB
+// force); false if they did not within the spin limit.
+constexpr int kHoldSpins = 1 << 22;
+__device__ __forceinline__ bool hold_wait(CaseState *cs, int nhold) {
+  int spins = 0;
+  while (__hip_atomic_load(&cs->hold_seen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < nhold &&
+         spins < kHoldSpins) {
+    __builtin_amdgcn_s_sleep(4);
+    spins++;
+  }
+  return spins < kHoldSpins;
+}
+
+// The tiles of a fused step wait here until the IB pass of the launch has
+// done its loads from device memory (CaseState::gate == seq), so that those
+// loads do not queue behind the tiles' streaming.  A schedule, not a
+// dependency: after the spin limit the workgroup goes ahead anyway.
+constexpr int kGateSpins = 1 << 16;
+__device__ __forceinline__ void gate_wait(const CaseState *cs, int seq) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(&cs->gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != seq &&
+           spins < kGateSpins) {
+      __builtin_amdgcn_s_sleep(16);
+      spins++;
+    }
+  }
+  __syncthreads();
+}
+__device__ __forceinline__ void gate_open(CaseState *cs, int seq) {
+  __hip_atomic_store(&cs->gate, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of thread 0 until the source workgroups of a fused step have
+// all staged their pushes; false if they did not within the spin limit.
+__device__ __forceinline__ bool src_wait(CaseState *cs, int nsrc) {
+  int spins = 0;
+  while (__hip_atomic_load(&cs->src_seen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < nsrc &&
+         spins < kHoldSpins) {
+    __builtin_amdgcn_s_sleep(2);
+    spins++;
+  }
+  return spins < kHoldSpins;
+}
+
 // FAST: the 1024-thread instance for DF/MDF bodies with an LDS workspace
 // and gather spreading (no DFC or atomic-scatter code, so that it fits 128
 // VGPRs); marker loops then run one lane per stencil row.
-template <typename T, bool LDS, int NS, bool FAST>
+// SELF_COL >= 0 (fused steps, a fixed body): the post-stream populations of
+// the support nodes are not read from the lattice, which the rest of the
+// launch is still writing, but from B.pstage, where the launch's nsrc
+// source workgroups (fused_src) have staged them; the pass writes the new
+// force only after the nhold hold-rectangle workgroups have read the
+// previous one.
+template <typename T, bool LDS, int NS, bool FAST, int SELF_COL = -1>
 __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, int64_t step, int cur,
                                           double *dyn, int spread_mode, double *red, int *ish,
-                                          double *bsh) {
+                                          double *bsh, int nhold = 0, int seq = 0, int nsrc = 0) {
   constexpr int LPM = FAST ? NS : 2;
   const int tid = threadIdx.x, nth = blockDim.x;
   BodyState *bs = B.state;
@@ -778,16 +831,27 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     // loads of UM nodes per thread are issued before any is used (one round
     // trip to device memory covers up to UM * 512 nodes)
     constexpr int UM = FAST ? 1 : (sizeof(T) == 4 ? 3 : 2);
+    T *const stg = (T *)B.pstage;
+    if constexpr (SELF_COL >= 0) {
+      // the launch's source workgroups have staged the support's pushes
+      if (tid == 0 && !src_wait(c.state, nsrc)) ish[3] |= kFlagExchange;
+      __syncthreads();
+    }
     for (int j0 = tid; j0 < S; j0 += UM * nth) {
       T v[UM][9];
 #pragma unroll
       for (int u = 0; u < UM; u++) {
         const int j = j0 + u * nth;
         if (j < S) {
-          const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
-          const T *fp = fpop + pop_node(x, y, c.nseg);
+          if constexpr (SELF_COL >= 0) {
 #pragma unroll
-          for (int i = 0; i < 9; i++) v[u][i] = fp[i * kSeg];
+            for (int i = 0; i < 9; i++) v[u][i] = stg[i * B.max_nodes + j];
+          } else {
+            const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
+            const T *fp = fpop + pop_node(x, y, c.nseg);
+#pragma unroll
+            for (int i = 0; i < 9; i++) v[u][i] = fp[i * kSeg];
+          }
         }
       }
 #pragma unroll
@@ -808,6 +872,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       }
     }
     __syncthreads();
+    // fused step: the pass's loads from device memory are done
+    if constexpr (SELF_COL >= 0)
+      if (tid == 0) gate_open(c.state, seq);
     T *frc = (T *)c.force;
     double *accx = B.acc, *accy = B.acc + B.max_nodes;
     if (B.scheme == kDF) {
@@ -1132,17 +1199,28 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         __syncthreads();
       }
     }
+    if constexpr (SELF_COL >= 0) {
+      // the tiles that read the previous force have all done so
+      if (tid == 0 && !hold_wait(c.state, nhold)) ish[3] |= kFlagExchange;
+    }
     __syncthreads();
-    // Eulerian force f(x) = sum_k F_total D_h ds (Eq. 8) into the force field;
-    // DF also forms the post-IB node velocity u* + f/(2 rho) for the slip
+    // Eulerian force f(x) = sum_k F_total D_h ds (Eq. 8) into the force field
+    // (and, for fused steps, its copy); DF also forms the post-IB node
+    // velocity u* + f/(2 rho) for the slip
     if (FAST || spread_mode == 0) {
+      T *const fpv = (T *)B.fprev;
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double fx, fy;
         gather2<NS>(L, j, L.Ftx, L.Fty, fx, fy);
         const uint32_t p = (uint32_t)y * nx + x;
-        frc[p] = (T)(fx * ds);
-        frc[plane + p] = (T)(fy * ds);
+        const T vx = (T)(fx * ds), vy = (T)(fy * ds);
+        frc[p] = vx;
+        frc[plane + p] = vy;
+        if (fpv) {
+          fpv[j] = vx;
+          fpv[B.max_nodes + j] = vy;
+        }
         if (B.scheme == kDF) {
           const double h = 1.0 / (2.0 * L.nrho[j]);
           L.nux[j] += fx * ds * h;
@@ -1558,6 +1636,200 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
     if (meet) cs->flags |= kCaseHalted;
   }
   __threadfence();
+}
+
+// ---- fused step: one launch per step for a case with a single fixed
+// DF/MDF body (see FusedArgs).  The IB pass needs no post-stream lattice
+// from this launch (it collides its support itself), the tiles need only
+// the force of the previous pass (the hold tiles read and clear it before
+// the pass writes the new one), so nothing in the launch depends on
+// anything but that count, and consecutive steps are ordered by the stream
+// alone.  The tiles start streaming once the pass has done its loads from
+// device memory (gate_wait): beside a chip-wide stream those loads take
+// several times longer, and the pass is the launch's critical path.
+
+// The IB workgroup of a fused step: the pass, then the case-level update of
+// a single-body case (the same as ibm_kernel's), after the hold tiles have
+// all counted themselves, which also holds when the pass does not run.
+template <typename T, int COL>
+__device__ __forceinline__ void fused_ib(const FusedArgs &a, int nhold, double *dyn, double *red,
+                                         int *ish, double *bsh) {
+  const CaseDesc &c = *a.c;
+  CaseState *cs = c.state;
+  const int64_t step = cs->step;
+  const int cur = cs->cur;
+  const bool active = step < cs->target && !(cs->flags & kCaseHalted);
+  if (threadIdx.x == 0) ish[50] = 0;
+  if (active) {
+    const BodyDesc &B = c.bodies[0];
+    if (B.ns == 2)
+      body_step<T, true, 2, true, COL>(c, B, step, cur, dyn, 0, red, ish, bsh, nhold, a.seq, a.nsrc);
+    else
+      body_step<T, true, 4, true, COL>(c, B, step, cur, dyn, 0, red, ish, bsh, nhold, a.seq, a.nsrc);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  // (the pass opened the gate after its loads; a pass that ended early or
+  // did not run opens it here)
+  gate_open(cs, a.seq);
+  const bool met = hold_wait(cs, nhold) && src_wait(cs, a.nsrc);
+  __hip_atomic_store(&cs->hold_seen, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&cs->src_seen, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!active) return;
+  if (ish[50] || !met) {
+    cs->flags |= kCaseHalted;
+  } else {
+    if (ish[51]) {
+      cs->fbox[0] = ish[52]; cs->fbox[1] = ish[53];
+      cs->fbox[2] = ish[54]; cs->fbox[3] = ish[55];
+      cs->fbox_valid = 1;
+    } else {
+      cs->fbox_valid = 0;
+    }
+    cs->cur = cur ^ 1;
+    cs->step = step + 1;
+  }
+  cs->xcnt = 0;
+}
+
+// A source workgroup of a fused step: one node that pushes into the
+// support per thread collides, as a tile does (the same collide function,
+// the force the tiles read, kept in BodyDesc::fprev), from the step's input
+// lattice, and its pushes into the support are staged population-major in
+// BodyDesc::pstage; then the workgroup counts itself.
+template <typename T, int COL>
+__device__ __forceinline__ void fused_src(const FusedArgs &a, int w) {
+  const CaseDesc &c = *a.c;
+  const BodyDesc &B = c.bodies[0];
+  const int u = w * kFusedThreads + (int)threadIdx.x;
+  if (u < B.n_src) {
+    const SrcNode r = B.src[u];
+    const T *fp = (const T *)c.f[a.cur] + r.off;
+    T f[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) f[i] = fp[i * kSeg];
+    T Fx = T(c.fluid_fx), Fy = T(c.fluid_fy);
+    const int mn = B.max_nodes;
+    if (r.map[0] >= 0) {
+      const T *fpv = (const T *)B.fprev;
+      const T fa = fpv[r.map[0]], fb = fpv[mn + r.map[0]];
+      if (fa != T(0) || fb != T(0)) {
+        Fx += fa;
+        Fy += fb;
+      }
+    }
+    collide<T, sizeof(T) == 4, COL>(f, Fx, Fy, c);
+    T *stg = (T *)B.pstage;
+#pragma unroll
+    for (int i = 0; i < 9; i++)
+      if (r.map[i] >= 0) stg[i * mn + r.map[i]] = f[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(&c.state->src_seen, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T, int COL, bool GZG>
+__global__ __launch_bounds__(kFusedThreads) void step_fused_kernel(const FusedArgs a) {
+  extern __shared__ double dyn[];
+  __shared__ double red[6 * (kFusedThreads / 64)];
+  __shared__ int ish[56];
+  __shared__ double bsh[17];
+  int b = blockIdx.x;
+  const int nhold = a.lean.hntx * a.lean.hnty;
+  const int nfw = a.nface;
+  const int lx = threadIdx.x % a.bx, ly = threadIdx.x / a.bx;
+  if (b == 0) {
+    fused_ib<T, COL>(a, nhold, dyn, red, ish, bsh);
+    return;
+  }
+  if (b <= a.nsrc) {
+    fused_src<T, COL>(a, b - 1);
+    return;
+  }
+  b -= a.nsrc;
+  if (b <= nhold) {
+    gate_wait(a.lean.state, a.seq);
+    int tx, ty;
+    if (lean_tile_index<1>(a.lean, b - 1, tx, ty)) lean_tile<T, COL, 1>(a.lean, tx, ty, lx, ly, a.bx, a.by);
+    // every read and clear of the force by this workgroup is done and
+    // written back before it counts itself
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_fetch_add(&((CaseState *)a.lean.state)->hold_seen, 1, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  int r = b - 1 - nhold;
+  if (r < nfw) {
+    // face nodes, one face workgroup (kFaceBlock nodes) per workgroup: the
+    // face work is latency-bound, so it is spread over as many compute
+    // units as the standalone face launch uses
+    if (threadIdx.x >= kFaceBlock) return;
+    face_node<T, COL, GZG>(a.c, a.face_prefix, 1, a.nface, r, (int)threadIdx.x, a.cur, 0);
+    return;
+  }
+  r -= nfw;
+  // the far tiles, neighbours kept on one XCD as in the other launches
+  const int nfar = (int)gridDim.x - 1 - a.nsrc - nhold - nfw;
+  int t = r;
+  if (a.lean.remap) t = (r & 7) * (nfar >> 3) + (r >> 3);
+  int tx, ty;
+  if (!lean_tile_index<2>(a.lean, t, tx, ty)) return;
+  gate_wait(a.lean.state, a.seq);
+  lean_tile<T, COL, 2>(a.lean, tx, ty, lx, ly, a.bx, a.by);
+}
+
+int fused_grid(const FusedArgs &a) {
+  const int nhold = a.lean.hntx * a.lean.hnty;
+  const int nfw = a.nface;
+  int nfar = a.lean.ntiles;
+  if (a.lean.remap) nfar = (nfar + 7) / 8 * 8;
+  return 1 + a.nsrc + nhold + nfw + nfar;
+}
+
+hipError_t launch_step_fused(int precision, int collision, const FusedArgs &a, int lds_bytes,
+                             hipStream_t stream, LaunchTarget *ns) {
+  static bool configured = false;
+  if (!configured) {
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<float, kBGK, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<float, kBGK, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<float, kTRT, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<float, kTRT, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<double, kBGK, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<double, kBGK, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<double, kTRT, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    (void)hipFuncSetAttribute((const void *)step_fused_kernel<double, kTRT, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kIbmDynLds);
+    configured = true;
+  }
+  if (collision != kBGK && collision != kTRT) return hipErrorInvalidValue;
+  if (a.bx <= 0 || a.by <= 0 || a.bx * a.by != kFusedThreads || a.lean.hntx <= 0 || a.lean.hnty <= 0 ||
+      a.nsrc <= 0)
+    return hipErrorInvalidValue;
+  if (lds_bytes > kIbmDynLds) return hipErrorInvalidValue;
+  const dim3 grid(fused_grid(a)), block(kFusedThreads);
+#define IBL_FUSED(TT, CC, GG) return issue(step_fused_kernel<TT, CC, GG>, grid, block, lds_bytes, stream, ns, a)
+  if (precision == kPrecFP64) {
+    if (collision == kBGK) { if (a.gzg) IBL_FUSED(double, kBGK, true); IBL_FUSED(double, kBGK, false); }
+    if (a.gzg) IBL_FUSED(double, kTRT, true);
+    IBL_FUSED(double, kTRT, false);
+  }
+  if (collision == kBGK) { if (a.gzg) IBL_FUSED(float, kBGK, true); IBL_FUSED(float, kBGK, false); }
+  if (a.gzg) IBL_FUSED(float, kTRT, true);
+  IBL_FUSED(float, kTRT, false);
+#undef IBL_FUSED
 }
 
 // ---- boundary-fidelity diagnostics (Sec. 2.8, marker profiles of Sec. 4.2)

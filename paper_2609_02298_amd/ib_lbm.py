@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libib_lbm.so")
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 FP64, FP32_SHIFTED = 0, 1
 BGK, TRT, CMMRT = 0, 1, 2
@@ -45,7 +45,8 @@ EXPORTS = [
     "ib_lbm_sync",
     "ib_lbm_destroy", "ib_lbm_last_error", "ib_lbm_footprint", "ib_lbm_set_launch",
     "ib_lbm_get_launch", "ib_lbm_set_spread", "ib_lbm_set_graph", "ib_lbm_timing_enable",
-    "ib_lbm_set_overlap", "ib_lbm_get_overlap", "ib_lbm_time_collide_stream",
+    "ib_lbm_set_overlap", "ib_lbm_get_overlap", "ib_lbm_set_fused", "ib_lbm_get_fused",
+    "ib_lbm_time_collide_stream",
     "ib_lbm_timing_read", "ib_lbm_batch_create", "ib_lbm_batch_attach", "ib_lbm_batch_detach",
     "ib_lbm_batch_set_target", "ib_lbm_batch_step", "ib_lbm_batch_set_graph",
     "ib_lbm_batch_sync", "ib_lbm_batch_destroy", "ib_lbm_batch_last_error",
@@ -183,6 +184,8 @@ def load_library(path: str = LIB_PATH):
     L.ib_lbm_set_spread.argtypes = [vp, C.c_int32]
     L.ib_lbm_set_graph.argtypes = [vp, C.c_int32]
     L.ib_lbm_set_overlap.argtypes = [vp, C.c_int32]
+    L.ib_lbm_set_fused.argtypes = [vp, C.c_int32]
+    L.ib_lbm_get_fused.argtypes = [vp, C.POINTER(C.c_int32)]
     L.ib_lbm_time_collide_stream.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
     L.ib_lbm_get_overlap.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
     L.ib_lbm_timing_enable.argtypes = [vp, C.c_int32]
@@ -463,6 +466,15 @@ class Sim:
         n = C.c_int64()
         self._check(self.L.ib_lbm_get_overlap(self.h, C.byref(v), C.byref(n)), self.h)
         return bool(v.value), n.value
+
+    def set_fused(self, on: bool):
+        self._check(self.L.ib_lbm_set_fused(self.h, 1 if on else 0), self.h)
+
+    def fused(self) -> bool:
+        """Whether steps run as one fused launch each (after the first step)."""
+        v = C.c_int32()
+        self._check(self.L.ib_lbm_get_fused(self.h, C.byref(v)), self.h)
+        return bool(v.value)
 
     def timing(self, on: bool):
         self._check(self.L.ib_lbm_timing_enable(self.h, 1 if on else 0), self.h)

@@ -420,11 +420,13 @@ def dfc_cmmrt_window():
     return _window_reference("DFC", "P4", "CMMRT")
 
 
-def _check_window(ref, prec, launch=None, pipelined=True):
+def _check_window(ref, prec, launch=None, pipelined=True, fused=None):
     case = ref["case"]
     sim = ib.Sim(case, precision=prec)
     if launch:
         sim.set_launch(**launch)
+    if fused is not None:
+        sim.set_fused(fused)
     f64 = prec == ib.FP64
     for t in WINDOW_CHECKS:
         sim.step(t - sim.steps_done)
@@ -434,6 +436,8 @@ def _check_window(ref, prec, launch=None, pipelined=True):
         if f64:
             assert abs(fs["slip_mean"] - fr["slip_mean"]) < 1e-9 * fr["slip_mean"], t
     assert sim.overlap()[0] == pipelined
+    if fused is not None:
+        assert sim.fused() == fused
     _, ux, uy = sim.fields()
     _, rx, ry = ref["fields"]
     scale = max(np.abs(rx).max(), np.abs(ry).max())
@@ -445,16 +449,18 @@ def _check_window(ref, prec, launch=None, pipelined=True):
     sim.close()
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("prec", [ib.FP32_SHIFTED, ib.FP64])
-def test_headline_window_pipelined(headline_window, prec):
+def test_headline_window_pipelined(headline_window, prec, fused):
     """The benchmark's own configuration, element by element against the
     oracle for 100 steps: 2000 x 800, MDF (k = 5) / Peskin 4-point / TRT,
-    pipelined steps, the launch shape of the shipped tuning table, FP32
-    shifted (the headline) and FP64."""
+    the launch shape of the shipped tuning table, FP32 shifted (the
+    headline) and FP64; as fused steps (one launch per step, the default
+    here) and as two-stream pipelined steps."""
     from paper_2609_02298_amd import autotune
-    say(f"2000x800 MDF/P4/TRT 100-step window prec={prec}")
+    say(f"2000x800 MDF/P4/TRT 100-step window prec={prec} fused={fused}")
     launch = autotune.lookup(2000, 800, ib.TRT, prec)
-    _check_window(headline_window, prec, launch)
+    _check_window(headline_window, prec, launch, fused=fused)
 
 
 @pytest.mark.parametrize("prec", [ib.FP32_SHIFTED, ib.FP64])
@@ -1045,15 +1051,20 @@ def _split_case(scheme, kernel, col, motion=ib.FIXED):
 def test_split_step_is_bitwise_the_plain_step(scheme, kernel, col, motion, prec):
     """Pipelined steps (the collide-stream of step n+1 overlapping the IB
     pass of step n, with only the tiles next to the body waiting for it)
-    change no bit of the result, with direct launches and mixed with graph
-    replays, over several calls."""
+    and fused steps (one launch per step, the IB pass colliding its support
+    itself; fixed DF/MDF bodies with BGK or TRT) change no bit of the
+    result, with direct launches and mixed with graph replays, over several
+    calls."""
     say(f"split step scheme={scheme} kernel={kernel} col={col} motion={motion} prec={prec}")
     case = _split_case(scheme, kernel, col, motion)
+    fusable = motion == ib.FIXED and scheme != ib.DFC and col != ib.CMMRT
     runs = []
-    for overlap, graph in ((False, 0), (True, 0), (True, 7)):
+    for overlap, fused, graph in ((False, False, 0), (True, False, 0), (True, False, 7),
+                                  (True, True, 0), (True, True, 7)):
         sim = ib.Sim(case, precision=prec)
         sim.set_launch(64, 1, 1, 1)
         sim.set_overlap(overlap)
+        sim.set_fused(fused)
         if graph:
             sim.set_graph(graph)
         for n in (1, 20, 29):
@@ -1061,6 +1072,7 @@ def test_split_step_is_bitwise_the_plain_step(scheme, kernel, col, motion, prec)
         sim.sync()
         used, near = sim.overlap()
         assert used == overlap
+        assert sim.fused() == (fused and fusable)
         if overlap:
             assert 0 < near < case["nx"] * case["ny"] // 4
         runs.append((sim.populations(), sim.forces(0), sim.force()))
@@ -1177,6 +1189,7 @@ def test_benchmark_lattice_uses_split_step():
     sim.step(3)
     used, near = sim.overlap()
     assert used and near < case["nx"] * case["ny"] // 25
+    assert sim.fused()
 
 
 def test_time_collide_stream_counts_inner_nodes():
@@ -1208,10 +1221,12 @@ def test_pipelined_graph_replay_is_bitwise_the_direct_steps(prec, walls):
         case.update(bc=(ib.PERIODIC, ib.PERIODIC, ib.ZOU_HE, ib.ZOU_HE), u_bc=0.0,
                     fluid_force=(4e-6, 0.0))
     sims = []
-    for overlap, graph in ((False, 0), (True, 0), (True, 4)):
+    configs = ((False, False, 0), (True, False, 0), (True, False, 4), (True, True, 4))
+    for overlap, fused, graph in configs:
         sim = ib.Sim(case, precision=prec)
         sim.set_launch(64, 1, 1, 1)
         sim.set_overlap(overlap)
+        sim.set_fused(fused)
         sim.set_graph(graph)
         sims.append(sim)
     for n in (5, 10, 3, 8):
@@ -1219,10 +1234,13 @@ def test_pipelined_graph_replay_is_bitwise_the_direct_steps(prec, walls):
             sim.step(n)
         fx = [sim.forces(0)["fx"] for sim in sims]
         pops = [sim.populations() for sim in sims]
-        assert [sim.overlap()[0] for sim in sims] == [False, True, True]
-        assert fx[1] == fx[0] and fx[2] == fx[0]
-        assert np.array_equal(pops[1], pops[0]) and np.array_equal(pops[2], pops[0])
-    assert sims[2].steps_done == 26
+        assert [sim.overlap()[0] for sim in sims] == [False, True, True, True]
+        # fused steps (captured as plain launches) only without the walls
+        assert [sim.fused() for sim in sims] == [False, False, False, not walls]
+        for k in range(1, len(sims)):
+            assert fx[k] == fx[0], k
+            assert np.array_equal(pops[k], pops[0]), k
+    assert sims[2].steps_done == 26 and sims[3].steps_done == 26
     for sim in sims:
         sim.close()
 
@@ -1235,17 +1253,20 @@ def test_split_step_over_many_calls_is_the_plain_step():
     say("split step over 40 calls")
     case = _split_case(ib.MDF, ib.PESKIN4, ib.TRT)
     runs = []
-    for overlap in (False, True):
+    for overlap, fused in ((False, False), (True, False), (True, True)):
         sim = ib.Sim(case, precision=ib.FP32_SHIFTED)
         sim.set_launch(64, 1, 1, 1)
         sim.set_overlap(overlap)
+        sim.set_fused(fused)
         for n in [1, 2, 3] * 13 + [1]:
             sim.step(n)
         sim.sync()
         assert sim.steps_done == 79
         assert sim.overlap()[0] == overlap
+        assert sim.fused() == fused
         runs.append((sim.populations(), sim.forces(0)))
         sim.close()
-    assert np.array_equal(runs[0][0], runs[1][0])
-    for k in ("fx", "fy", "torque", "slip_mean"):
-        assert runs[0][1][k] == runs[1][1][k], k
+    for r in runs[1:]:
+        assert np.array_equal(runs[0][0], r[0])
+        for k in ("fx", "fy", "torque", "slip_mean"):
+            assert runs[0][1][k] == r[1][k], k
