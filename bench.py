@@ -243,7 +243,43 @@ def largest_leg(steps32: int = 60, steps64: int = 30):
                       "avg_launch_us": round(avg * 1e6, 2),
                       "ib_pass_avg_us": round(r["ibm_ms"] / max(r["n_ibm"], 1) * 1e3, 2),
                       "population_bytes": 2 * 9 * nodes * bpn // 18, "launch": r["launch"]}
+    # the plain read + write stream of the same bytes (one FP32 lattice each
+    # way) with the library's reference copy: what a streaming kernel reaches
+    # on this part, beside the 8 TB/s of the roofline's peak
+    ceil = stream_ceiling(9 * lbm_nodes * 4)
+    out["stream_copy"] = ceil
+    for pname in ("fp32", "fp64"):
+        out[pname]["frac_of_stream_copy"] = round(out[pname]["roofline_achieved_GBs"] / ceil["achieved_GBs"], 4)
     return out
+
+
+def stream_ceiling(nbytes: int, reps: int = 20):
+    """Best rate over a few workgroup counts of ib_lbm_stream_copy moving
+    nbytes (read nbytes, write nbytes), HIP events on the launch stream."""
+    import torch
+    import paper_2609_02298_amd as ib
+
+    n = (nbytes + 15) // 16 * 4
+    a = torch.zeros(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = None
+    for wg in (256, 512, 1024):
+        for _ in range(3):
+            ib.stream_copy(a, b, wg)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ib.stream_copy(a, b, wg)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = 2 * 4 * n / us / 1e3
+        if best is None or gbs > best["achieved_GBs"]:
+            best = {"bytes_each_way": 4 * n, "workgroups": wg, "avg_us": round(us, 2),
+                    "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del a, b
+    torch.cuda.empty_cache()
+    return best
 
 
 def copy_calibration(mb: float):

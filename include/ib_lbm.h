@@ -386,6 +386,16 @@ ib_lbm_status ib_lbm_timing_enable(ib_lbm_sim *s, int32_t on);
 ib_lbm_status ib_lbm_time_collide_stream(ib_lbm_sim *s, int32_t launches, double *avg_us,
                                          int64_t *inner_nodes);
 ib_lbm_status ib_lbm_timing_read(ib_lbm_sim *s, int32_t which, double *total_ms, int64_t *launches);
+/* Measurement only: the plain read + write stream that the collide-stream
+ * kernel's HBM fraction is compared with.  Copies `bytes` bytes (a positive
+ * multiple of 16) from device buffer src to device buffer dst (distinct,
+ * 16-byte aligned, owned by the caller) on `stream` (a hipStream_t, NULL for
+ * the null stream) with a grid-stride 16-byte-vector kernel, `workgroups`
+ * workgroups of 1024 threads (256 when 0).  Asynchronous; E_INVALID for a
+ * size, alignment or count outside these rules, E_DEVICE when the launch
+ * fails. */
+ib_lbm_status ib_lbm_stream_copy(const void *src, void *dst, size_t bytes, int32_t workgroups,
+                                 void *stream);
 
 /* ---- batching: many independent sims stepped by shared launches ----
  * All sims of a batch share one precision and one stream.  A batch step is

@@ -783,6 +783,10 @@ ib_lbm_status enqueue_fused(ib_lbm_sim *s, int64_t nsteps, hipStream_t stream, i
     fa.cur = cur;
     fa.seq = (int32_t)(++s->fused_seq);
     fa.nsrc = (s->bodies[0].dev.n_src + kFusedThreads - 1) / kFusedThreads;
+    // FP32: the IB pass bounds the launch, and the tiles wait for its loads
+    // (33.3 against 38.4 us per step on the 2000x800 cylinder); FP64: the
+    // tiles bound it and start at once (43.6 against 47.8 us)
+    fa.gated = s->cd.precision == IB_LBM_FP32_SHIFTED ? 1 : 0;
     HIPCHK(s, launch_step_fused(s->cd.precision, s->cd.collision, fa, s->lds_bytes, stream));
   }
   return IB_LBM_OK;
@@ -1637,6 +1641,17 @@ ib_lbm_status ib_lbm_time_collide_stream(ib_lbm_sim *s, int32_t launches, double
     if (hb.fprev.p) HIPCHK(s, hipMemset(hb.fprev.p, 0, hb.fprev.bytes));
   *avg_us = ms * 1e3 / launches;
   if (inner_nodes) *inner_nodes = (int64_t)(s->cd.nx - 3) * (s->cd.ny - 2);
+  return IB_LBM_OK;
+}
+
+ib_lbm_status ib_lbm_stream_copy(const void *src, void *dst, size_t bytes, int32_t workgroups,
+                                 void *stream) {
+  if (!src || !dst || src == dst || bytes == 0 || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16 ||
+      workgroups < 0 || workgroups > (1 << 20))
+    return IB_LBM_E_INVALID;
+  if (launch_stream_copy(src, dst, bytes / 16, workgroups ? workgroups : 256, (hipStream_t)stream) !=
+      hipSuccess)
+    return IB_LBM_E_DEVICE;
   return IB_LBM_OK;
 }
 

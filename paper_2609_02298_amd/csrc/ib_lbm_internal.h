@@ -355,6 +355,7 @@ struct FusedArgs {
   int32_t cur;  // the step's input lattice (faces and tiles; the IB pass reads the case state)
   int32_t seq;  // the launch's sequence number (CaseState::gate)
   int32_t nsrc; // workgroups of the support's own collision (BodyDesc::n_src nodes)
+  int32_t gated;  // the tiles wait for the IB pass's loads (CaseState::gate)
 };
 int fused_grid(const FusedArgs &a);
 hipError_t launch_step_fused(int precision, int collision, const FusedArgs &a, int lds_bytes,
@@ -362,6 +363,8 @@ hipError_t launch_step_fused(int precision, int collision, const FusedArgs &a, i
 hipError_t launch_zou_he(int precision, const CaseDesc *c, int nx, int ny, int cur, hipStream_t stream,
                          LaunchTarget *ns = nullptr);
 hipError_t launch_init_equilibrium(const CaseDesc &c, int buf, hipStream_t stream);
+// The reference stream of ib_lbm_stream_copy (n 16-byte vectors).
+hipError_t launch_stream_copy(const void *src, void *dst, size_t n, int workgroups, hipStream_t stream);
 hipError_t launch_fields(const CaseDesc &c, int buf, double *rho, double *ux, double *uy,
                          hipStream_t stream);
 hipError_t launch_export(const CaseDesc &c, int buf, double *out, hipStream_t stream);

@@ -766,7 +766,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     bsh[12] = B.radius;
   }
   __syncthreads();
-  const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
+  // the centre for the tables; the later uses read the kinematics from bsh
+  // again, so that no register holds them through the whole pass
+  const double xc = bsh[0], yc = bsh[1];
   constexpr bool in_lds = LDS;
   double *base = LDS ? dyn : B.ws;
   const WsLayout L = carve(base, B);
@@ -1251,13 +1253,14 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     }
     // force on the body: -sum_k F_total ds sum_x D_h (Newton's third law),
     // torque -sum_k r_k x F_total ds (Sec. 2.7)
+    const double xcm = bsh[0], ycm = bsh[1];
     for (int k = tid; k < nb; k += nth) {
       double wsx = 0, wsy = 0;
       for (int j = 0; j < ns; j++) { wsx += WX(L, k, j); wsy += WY(L, k, j); }
       const double wsum = wsx * wsy;
       fsum_x -= L.Ftx[k] * ds * wsum;
       fsum_y -= L.Fty[k] * ds * wsum;
-      tq -= ((L.X[k] - xc) * L.Fty[k] - (L.Y[k] - yc) * L.Ftx[k]) * ds;
+      tq -= ((L.X[k] - xcm) * L.Fty[k] - (L.Y[k] - ycm) * L.Ftx[k]) * ds;
     }
   } else if constexpr (!FAST) {
     // ---- 4b. DFC
@@ -1412,7 +1415,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     for (int k = tid; k < nb; k += nth) {
       fsum_x += L.Ftx[k];
       fsum_y += L.Fty[k];
-      tq += (L.X[k] - xc) * L.Fty[k] - (L.Y[k] - yc) * L.Ftx[k];
+      tq += (L.X[k] - bsh[0]) * L.Fty[k] - (L.Y[k] - bsh[1]) * L.Ftx[k];
     }
   }
   __syncthreads();
@@ -1463,6 +1466,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     // device memory on this serial tail; the descriptor values come from
     // the on-chip copy made with the kinematics)
     const int motion = ish[12], scheme = ish[13], iters = ish[11], box_valid = ish[10];
+    const double xc = bsh[0], yc = bsh[1], vhx = bsh[2], vhy = bsh[3], omh = bsh[4];
     int flags = 0;
     if (!isfinite(a) || !isfinite(b) || !isfinite(cq) || !isfinite(s1)) flags |= kFlagNonfinite;
     const double slip_mean = s1 / nb;
@@ -1645,8 +1649,9 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
 // the pass writes the new one), so nothing in the launch depends on
 // anything but that count, and consecutive steps are ordered by the stream
 // alone.  The tiles start streaming once the pass has done its loads from
-// device memory (gate_wait): beside a chip-wide stream those loads take
-// several times longer, and the pass is the launch's critical path.
+// device memory (gate_wait, when `gated`): beside a chip-wide stream those
+// loads take several times longer, and in FP32 the pass is the launch's
+// critical path (in FP64 the tiles are, and they start at once).
 
 // The IB workgroup of a fused step: the pass, then the case-level update of
 // a single-body case (the same as ibm_kernel's), after the hold tiles have
@@ -1751,7 +1756,7 @@ __global__ __launch_bounds__(kFusedThreads) void step_fused_kernel(const FusedAr
   }
   b -= a.nsrc;
   if (b <= nhold) {
-    gate_wait(a.lean.state, a.seq);
+    if (a.gated) gate_wait(a.lean.state, a.seq);
     int tx, ty;
     if (lean_tile_index<1>(a.lean, b - 1, tx, ty)) lean_tile<T, COL, 1>(a.lean, tx, ty, lx, ly, a.bx, a.by);
     // every read and clear of the force by this workgroup is done and
@@ -1780,7 +1785,7 @@ __global__ __launch_bounds__(kFusedThreads) void step_fused_kernel(const FusedAr
   if (a.lean.remap) t = (r & 7) * (nfar >> 3) + (r >> 3);
   int tx, ty;
   if (!lean_tile_index<2>(a.lean, t, tx, ty)) return;
-  gate_wait(a.lean.state, a.seq);
+  if (a.gated) gate_wait(a.lean.state, a.seq);
   lean_tile<T, COL, 2>(a.lean, tx, ty, lx, ly, a.bx, a.by);
 }
 

@@ -46,7 +46,7 @@ EXPORTS = [
     "ib_lbm_destroy", "ib_lbm_last_error", "ib_lbm_footprint", "ib_lbm_set_launch",
     "ib_lbm_get_launch", "ib_lbm_set_spread", "ib_lbm_set_graph", "ib_lbm_timing_enable",
     "ib_lbm_set_overlap", "ib_lbm_get_overlap", "ib_lbm_set_fused", "ib_lbm_get_fused",
-    "ib_lbm_time_collide_stream",
+    "ib_lbm_time_collide_stream", "ib_lbm_stream_copy",
     "ib_lbm_timing_read", "ib_lbm_batch_create", "ib_lbm_batch_attach", "ib_lbm_batch_detach",
     "ib_lbm_batch_set_target", "ib_lbm_batch_step", "ib_lbm_batch_set_graph",
     "ib_lbm_batch_sync", "ib_lbm_batch_destroy", "ib_lbm_batch_last_error",
@@ -184,6 +184,7 @@ def load_library(path: str = LIB_PATH):
     L.ib_lbm_set_spread.argtypes = [vp, C.c_int32]
     L.ib_lbm_set_graph.argtypes = [vp, C.c_int32]
     L.ib_lbm_set_overlap.argtypes = [vp, C.c_int32]
+    L.ib_lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
     L.ib_lbm_set_fused.argtypes = [vp, C.c_int32]
     L.ib_lbm_get_fused.argtypes = [vp, C.POINTER(C.c_int32)]
     L.ib_lbm_time_collide_stream.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
@@ -312,6 +313,20 @@ def footprint(case: dict, precision: int = FP64) -> int:
     nm = (C.c_int32 * max(1, len(bodies)))(*[
         int(b.get("n_markers", 0)) or int(round(math.pi * b["diameter"])) for b in bodies])
     return int(L.ib_lbm_footprint(C.byref(c), len(bodies), nm))
+
+
+def stream_copy(src, dst, workgroups: int = 0, stream=None):
+    """The reference read + write stream (ib_lbm_stream_copy): copies the
+    bytes of device tensor `src` into device tensor `dst` of the same size
+    on the given (default: current) stream, asynchronously."""
+    L = load_library()
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy: src and dst sizes differ")
+    st = L.ib_lbm_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                              int(workgroups), C.c_void_p(_torch_stream(stream)))
+    if st != 0:
+        raise IbLbmError(st, "ib_lbm_stream_copy failed")
 
 
 class Sim:

@@ -105,3 +105,22 @@ def test_create_rejects_lattices_outside_the_limits_before_any_device_call(nx, n
     st = L.ib_lbm_create(ctypes.byref(cfg), ctypes.byref(h))
     assert st == -1, st
     assert not h.value
+
+
+@pytest.mark.parametrize("src,dst,nbytes,wg", [
+    (0, 4096, 64, 0),          # null source
+    (4096, 0, 64, 0),          # null destination
+    (4096, 4096, 64, 0),       # the same buffer
+    (4096, 8192, 0, 0),        # nothing to copy
+    (4096, 8192, 40, 0),       # not a multiple of 16 bytes
+    (4100, 8192, 64, 0),       # misaligned source
+    (4096, 8200, 64, 0),       # misaligned destination
+    (4096, 8192, 64, -1),      # negative workgroup count
+])
+def test_stream_copy_rejects_bad_arguments_before_any_device_call(src, dst, nbytes, wg):
+    """The reference stream copy validates its arguments before it launches
+    anything: these give IB_LBM_E_INVALID on a host without a GPU."""
+    _ensure_built()
+    L = ib.load_library()
+    st = L.ib_lbm_stream_copy(ctypes.c_void_p(src), ctypes.c_void_p(dst), nbytes, wg, None)
+    assert st == -1, st

@@ -1192,6 +1192,22 @@ def test_benchmark_lattice_uses_split_step():
     assert sim.fused()
 
 
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, 1 << 22])
+def test_stream_copy_copies_every_byte(nbytes):
+    """The reference read + write stream (the benchmark's streaming ceiling)
+    copies exactly, for sizes below, at and beyond one grid-stride round."""
+    import torch
+    say(f"stream copy {nbytes} bytes")
+    g = torch.Generator(device="cpu").manual_seed(nbytes)
+    a = torch.randint(-2**31, 2**31 - 1, (nbytes // 4,), dtype=torch.int32, generator=g).cuda()
+    b = torch.zeros_like(a)
+    for wg in (0, 1, 7):
+        b.zero_()
+        ib.stream_copy(a, b, wg)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), wg
+
+
 def test_time_collide_stream_counts_inner_nodes():
     """The measurement entry point times back-to-back launches of the inner
     collide-stream and reports the inner node count (columns 1..nx-3, rows
