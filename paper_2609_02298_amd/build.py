@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libib_lbm.so")
-SOURCES = ["lbm_kernels.hip", "ibm_kernels.hip", "ib_lbm_api.cpp", "ib_lbm_server.cpp"]
+SOURCES = ["lbm_kernels.hip", "ibm_kernels.hip", "measure_kernels.hip", "ib_lbm_api.cpp",
+           "ib_lbm_server.cpp"]
 ARCH = os.environ.get("IB_LBM_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the generated code

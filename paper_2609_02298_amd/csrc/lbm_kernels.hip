@@ -253,20 +253,6 @@ hipError_t launch_collide_stream_lean(int precision, int collision, const LeanAr
 #undef IBL_DISPATCH
 
 // ------------------------------------------------------------ utilities
-// A plain read + write stream, 16 bytes per thread and round, grid-stride:
-// the reference the collide-stream kernel's HBM fraction is compared with.
-__global__ __launch_bounds__(1024) void stream_copy_kernel(const float4 *__restrict__ a,
-                                                           float4 *__restrict__ b, size_t n) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) b[i] = a[i];
-}
-
-hipError_t launch_stream_copy(const void *src, void *dst, size_t n, int workgroups, hipStream_t stream) {
-  hipLaunchKernelGGL(stream_copy_kernel, dim3(workgroups), dim3(1024), 0, stream, (const float4 *)src,
-                     (float4 *)dst, n);
-  return hipGetLastError();
-}
-
 // Equilibrium start state f^eq(rho0, u_init): u_init is the parabolic inlet
 // profile (W face parabolic), u_bc (any uniform face) or 0.
 template <typename T>
