@@ -836,7 +836,10 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     T *const stg = (T *)B.pstage;
     if constexpr (SELF_COL >= 0) {
       // the launch's source workgroups have staged the support's pushes
-      if (tid == 0 && !src_wait(c.state, nsrc)) ish[3] |= kFlagExchange;
+      if (tid == 0) {
+        if (src_wait(c.state, nsrc)) ish[56] |= 1;
+        else ish[3] |= kFlagExchange;
+      }
       __syncthreads();
     }
     for (int j0 = tid; j0 < S; j0 += UM * nth) {
@@ -1203,7 +1206,10 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     }
     if constexpr (SELF_COL >= 0) {
       // the tiles that read the previous force have all done so
-      if (tid == 0 && !hold_wait(c.state, nhold)) ish[3] |= kFlagExchange;
+      if (tid == 0) {
+        if (hold_wait(c.state, nhold)) ish[56] |= 2;
+        else ish[3] |= kFlagExchange;
+      }
     }
     __syncthreads();
     // Eulerian force f(x) = sum_k F_total D_h ds (Eq. 8) into the force field
@@ -1664,7 +1670,10 @@ __device__ __forceinline__ void fused_ib(const FusedArgs &a, int nhold, double *
   const int64_t step = cs->step;
   const int cur = cs->cur;
   const bool active = step < cs->target && !(cs->flags & kCaseHalted);
-  if (threadIdx.x == 0) ish[50] = 0;
+  if (threadIdx.x == 0) {
+    ish[50] = 0;
+    ish[56] = 0;
+  }
   if (active) {
     const BodyDesc &B = c.bodies[0];
     if (B.ns == 2)
@@ -1674,10 +1683,14 @@ __device__ __forceinline__ void fused_ib(const FusedArgs &a, int nhold, double *
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  // (the pass opened the gate after its loads; a pass that ended early or
-  // did not run opens it here)
-  gate_open(cs, a.seq);
-  const bool met = hold_wait(cs, nhold) && src_wait(cs, a.nsrc);
+  // A pass that ran through has opened the gate and seen both counts
+  // complete; one that ended early or did not run opens the gate and waits
+  // for the counts here, before they are reset for the next launch.
+  bool met = ish[56] == 3;
+  if (!met) {
+    gate_open(cs, a.seq);
+    met = hold_wait(cs, nhold) && src_wait(cs, a.nsrc);
+  }
   __hip_atomic_store(&cs->hold_seen, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(&cs->src_seen, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!active) return;
@@ -1740,7 +1753,9 @@ template <typename T, int COL, bool GZG>
 __global__ __launch_bounds__(kFusedThreads) void step_fused_kernel(const FusedArgs a) {
   extern __shared__ double dyn[];
   __shared__ double red[6 * (kFusedThreads / 64)];
-  __shared__ int ish[56];
+  // ish as in ibm_kernel, and [56]: the counts the pass has seen complete
+  // (1: source workgroups, 2: hold tiles)
+  __shared__ int ish[57];
   __shared__ double bsh[17];
   int b = blockIdx.x;
   const int nhold = a.lean.hntx * a.lean.hnty;

@@ -1261,6 +1261,50 @@ def test_pipelined_graph_replay_is_bitwise_the_direct_steps(prec, walls):
         sim.close()
 
 
+@pytest.mark.parametrize("prec", [ib.FP64, ib.FP32_SHIFTED])
+def test_fused_step_with_general_zero_gradient_faces(prec):
+    """Fused steps on a channel whose south and north faces are zero-gradient
+    as well (the face code's general copy rules, a kernel instance of its
+    own) are bitwise the plain steps."""
+    say(f"fused step, zero-gradient S/N faces, prec={prec}")
+    case = _split_case(ib.MDF, ib.PESKIN4, ib.TRT)
+    case.update(bc=(ib.VEL_UNIFORM, ib.ZERO_GRADIENT, ib.ZERO_GRADIENT, ib.ZERO_GRADIENT))
+    runs = []
+    for overlap in (False, True):
+        sim = ib.Sim(case, precision=prec)
+        sim.set_launch(64, 1, 1, 1)
+        sim.set_overlap(overlap)
+        sim.step(17)
+        sim.step(6)
+        assert sim.fused() == overlap
+        runs.append((sim.populations(), sim.forces(0)))
+        sim.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for k in ("fx", "fy", "torque", "slip_mean"):
+        assert runs[0][1][k] == runs[1][1][k], k
+
+
+def test_fused_step_after_collide_stream_timing_is_the_plain_step():
+    """The collide-stream timing launches consume the IB force without an IB
+    pass; fused steps afterwards (which keep their own copy of that force)
+    still match plain steps bit for bit."""
+    say("fused step after time_collide_stream")
+    case = _split_case(ib.DF, ib.HAT, ib.BGK)
+    runs = []
+    for overlap in (False, True):
+        sim = ib.Sim(case, precision=ib.FP32_SHIFTED)
+        sim.set_launch(64, 1, 1, 1)
+        sim.set_overlap(overlap)
+        sim.step(9)
+        sim.time_collide_stream(3)
+        sim.step(11)
+        assert sim.fused() == overlap
+        runs.append((sim.populations(), sim.forces(0)))
+        sim.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1]["fx"] == runs[1][1]["fx"]
+
+
 def test_split_step_over_many_calls_is_the_plain_step():
     """Pipelined steps issued over many small calls (each IB launch of a
     pipelined step is replicated once per XCD and the first copy to start
