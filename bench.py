@@ -82,7 +82,8 @@ def run_gpu(case, precision, steps, warmup, graph=0, launch=None, tune=True, wan
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
-    sim.sync()
+    # the device-wide synchronize covers the sim's stream (and, for pipelined
+    # steps, the two streams it joins into it)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # MDF passes applied in each timed step (history column 12)
