@@ -791,6 +791,8 @@ ib_lbm_status enqueue_fused(ib_lbm_sim *s, int64_t nsteps, hipStream_t stream, i
     // (33.3 against 38.4 us per step on the 2000x800 cylinder); FP64: the
     // tiles bound it and start at once (43.6 against 47.8 us)
     fa.gated = s->cd.precision == IB_LBM_FP32_SHIFTED ? 1 : 0;
+    fa.cd = s->cd;
+    fa.bd = s->bodies[0].dev;
     HIPCHK(s, launch_step_fused(s->cd.precision, s->cd.collision, fa, s->lds_bytes, stream));
   }
   return IB_LBM_OK;

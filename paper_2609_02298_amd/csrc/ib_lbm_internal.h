@@ -356,6 +356,13 @@ struct FusedArgs {
   int32_t seq;  // the launch's sequence number (CaseState::gate)
   int32_t nsrc; // workgroups of the support's own collision (BodyDesc::n_src nodes)
   int32_t gated;  // the tiles wait for the IB pass's loads (CaseState::gate)
+  // copies of *c and of its single body descriptor, as uploaded: the IB
+  // pass and the source workgroups read them from the kernel arguments
+  // (scalar loads at launch) instead of following c -> bodies -> fields
+  // through device memory, a chain of dependent round trips at the start
+  // of the launch's critical path
+  CaseDesc cd;
+  BodyDesc bd;
 };
 int fused_grid(const FusedArgs &a);
 hipError_t launch_step_fused(int precision, int collision, const FusedArgs &a, int lds_bytes,

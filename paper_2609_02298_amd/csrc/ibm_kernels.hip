@@ -52,6 +52,19 @@ __device__ __forceinline__ double delta1(int kernel, double r) {
   return 0.0;
 }
 
+// A device-memory pointer the compiler cannot place by itself (one read
+// from a descriptor) makes generic (flat) accesses, and a flat access also
+// counts as an LDS operation: the next LDS wait or barrier of the wave then
+// waits until a flat store has reached the cache, a long round trip beside
+// a chip-wide stream.  Stores on the IB pass's late path go through this
+// global-address-space view instead.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T> *to_global(T *p) {
+  return (gmem<T> *)p;
+}
+
 // ---- fixed-order block reductions (wave64 shuffles, then LDS) ----
 // A double moved across lanes by a DPP pattern (both 32-bit halves).
 template <int CTRL>
@@ -759,6 +772,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     ish[14] = c.ny;
     ish[15] = B.integrator;
     bsh[7] = __longlong_as_double((long long)(B.history + (step % B.hist_cap) * kHistCols));
+    bsh[17] = __longlong_as_double((long long)B.markers_out);
     bsh[8] = B.ms;
     bsh[9] = (B.ms - B.mf) * c.grav_x;
     bsh[10] = (B.ms - B.mf) * c.grav_y;
@@ -795,7 +809,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         if (B.scheme == kMDF && B.mdf_coupled) {
           // the other bodies of a coupled case would wait for this one:
           // leave a NaN residual and count this body into every round
-          const int body = (int)(&B - c.bodies);
+          const int body = SELF_COL >= 0 ? 0 : (int)(&B - c.bodies);
           const double nan = __builtin_nan("");
           __hip_atomic_store(&c.state->xr[0][body], nan, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&c.state->xr[1][body], nan, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -911,7 +925,9 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       const double tol = B.mdf_tol;
       const int nmin = tol > 0.0 ? B.mdf_nmin : N;
       const double om0 = fmin(B.omega_mdf, 0.8);
-      const int body = (int)(&B - c.bodies), nbc = c.nbodies;
+      // (a fused step's descriptor is a copy in the kernel arguments: its
+      // single body is body 0)
+      const int body = SELF_COL >= 0 ? 0 : (int)(&B - c.bodies), nbc = c.nbodies;
       CaseState *cs = c.state;
       int round = 0;
       // pass 1's interpolation of u* and rho(X): errors, unrelaxed forces
@@ -1204,6 +1220,11 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
         __syncthreads();
       }
     }
+    // the descriptor fields of the force write, read before the wait below
+    gmem<T> *const gfrc = to_global(frc);
+    gmem<T> *const fpv = to_global((T *)B.fprev);
+    const int fpv_plane = B.max_nodes;
+    const bool is_df = B.scheme == kDF;
     if constexpr (SELF_COL >= 0) {
       // the tiles that read the previous force have all done so
       if (tid == 0) {
@@ -1216,20 +1237,19 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     // (and, for fused steps, its copy); DF also forms the post-IB node
     // velocity u* + f/(2 rho) for the slip
     if (FAST || spread_mode == 0) {
-      T *const fpv = (T *)B.fprev;
       for (int j = tid; j < S; j += nth) {
         const int x = L.nxy[j] & 0xffff, y = L.nxy[j] >> 16;
         double fx, fy;
         gather2<NS>(L, j, L.Ftx, L.Fty, fx, fy);
         const uint32_t p = (uint32_t)y * nx + x;
         const T vx = (T)(fx * ds), vy = (T)(fy * ds);
-        frc[p] = vx;
-        frc[plane + p] = vy;
+        gfrc[p] = vx;
+        gfrc[plane + p] = vy;
         if (fpv) {
           fpv[j] = vx;
-          fpv[B.max_nodes + j] = vy;
+          fpv[fpv_plane + j] = vy;
         }
-        if (B.scheme == kDF) {
+        if (is_df) {
           const double h = 1.0 / (2.0 * L.nrho[j]);
           L.nux[j] += fx * ds * h;
           L.nuy[j] += fy * ds * h;
@@ -1440,7 +1460,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     }
     // the marker's output row (X Y Udx Udy Fx Fy lambda ds), split over
     // the lanes of its group
-    double *mo = B.markers_out + 8 * k;
+    gmem<double> *mo = to_global((double *)__double_as_longlong(bsh[17])) + 8 * k;
     if (h == 0) {
       const double e = sqrt((Ux - L.Udx[k]) * (Ux - L.Udx[k]) + (Uy - L.Udy[k]) * (Uy - L.Udy[k]));
       slip_sum += e;
@@ -1501,20 +1521,21 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
     }
     flags |= ish[3];
     if (ish[6]) flags |= kFlagExchange;
-    bs->fhx = a;
-    bs->fhy = b;
-    bs->torque = cq;
-    bs->slip_mean = slip_mean;
-    bs->slip_max = s4;
-    bs->mdf_res = mdf_res;
-    bs->mdf_iters_done = iters;
-    bs->box[0] = box[0]; bs->box[1] = box[1]; bs->box[2] = box[2]; bs->box[3] = box[3];
-    bs->box_valid = box_valid;
+    gmem<BodyState> *const gbs = to_global(bs);
+    gbs->fhx = a;
+    gbs->fhy = b;
+    gbs->torque = cq;
+    gbs->slip_mean = slip_mean;
+    gbs->slip_max = s4;
+    gbs->mdf_res = mdf_res;
+    gbs->mdf_iters_done = iters;
+    gbs->box[0] = box[0]; gbs->box[1] = box[1]; gbs->box[2] = box[2]; gbs->box[3] = box[3];
+    gbs->box_valid = box_valid;
     if (motion != kPrescribedSin) {
-      bs->vx = vx; bs->vy = vy; bs->om = om;
+      gbs->vx = vx; gbs->vy = vy; gbs->om = om;
     }
-    bs->flags = flags;
-    double *h = (double *)__double_as_longlong(bsh[7]);
+    gbs->flags = flags;
+    gmem<double> *const h = to_global((double *)__double_as_longlong(bsh[7]));
     h[0] = (double)(step + 1); h[1] = a; h[2] = b; h[3] = cq;
     h[4] = xc; h[5] = yc; h[6] = vx; h[7] = vy; h[8] = motion == kFree ? om : omh;
     h[9] = slip_mean; h[10] = s4; h[11] = mdf_res;
@@ -1546,7 +1567,7 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
   // ish: [0..15] flags and switches, [16..48] scan scratch, [50..55] the
   // body's final flags, force-box flag and force box
   __shared__ int ish[56];
-  __shared__ double bsh[17];
+  __shared__ double bsh[18];
   const int slot = replicas > 1 ? (int)blockIdx.x / replicas : (int)blockIdx.x;
   // the ticket is taken by a thread of wave 1 while all threads read the
   // slot and the case state; nothing is written before the outcome is known
@@ -1665,7 +1686,7 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
 template <typename T, int COL>
 __device__ __forceinline__ void fused_ib(const FusedArgs &a, int nhold, double *dyn, double *red,
                                          int *ish, double *bsh) {
-  const CaseDesc &c = *a.c;
+  const CaseDesc &c = a.cd;
   CaseState *cs = c.state;
   const int64_t step = cs->step;
   const int cur = cs->cur;
@@ -1675,7 +1696,7 @@ __device__ __forceinline__ void fused_ib(const FusedArgs &a, int nhold, double *
     ish[56] = 0;
   }
   if (active) {
-    const BodyDesc &B = c.bodies[0];
+    const BodyDesc &B = a.bd;
     if (B.ns == 2)
       body_step<T, true, 2, true, COL>(c, B, step, cur, dyn, 0, red, ish, bsh, nhold, a.seq, a.nsrc);
     else
@@ -1717,8 +1738,8 @@ __device__ __forceinline__ void fused_ib(const FusedArgs &a, int nhold, double *
 // BodyDesc::pstage; then the workgroup counts itself.
 template <typename T, int COL>
 __device__ __forceinline__ void fused_src(const FusedArgs &a, int w) {
-  const CaseDesc &c = *a.c;
-  const BodyDesc &B = c.bodies[0];
+  const CaseDesc &c = a.cd;
+  const BodyDesc &B = a.bd;
   const int u = w * kFusedThreads + (int)threadIdx.x;
   if (u < B.n_src) {
     const SrcNode r = B.src[u];
@@ -1756,7 +1777,7 @@ __global__ __launch_bounds__(kFusedThreads) void step_fused_kernel(const FusedAr
   // ish as in ibm_kernel, and [56]: the counts the pass has seen complete
   // (1: source workgroups, 2: hold tiles)
   __shared__ int ish[57];
-  __shared__ double bsh[17];
+  __shared__ double bsh[18];
   int b = blockIdx.x;
   const int nhold = a.lean.hntx * a.lean.hnty;
   const int nfw = a.nface;
