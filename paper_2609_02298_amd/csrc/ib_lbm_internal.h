@@ -355,7 +355,7 @@ struct FusedArgs {
   int32_t cur;  // the step's input lattice (faces and tiles; the IB pass reads the case state)
   int32_t seq;  // the launch's sequence number (CaseState::gate)
   int32_t nsrc; // workgroups of the support's own collision (BodyDesc::n_src nodes)
-  int32_t gated;  // the tiles wait for the IB pass's loads (CaseState::gate)
+  int32_t gated;  // the tiles wait for the IB pass's kinematics and tables (CaseState::gate)
   // copies of *c and of its single body descriptor, as uploaded: the IB
   // pass and the source workgroups read them from the kernel arguments
   // (scalar loads at launch) instead of following c -> bodies -> fields

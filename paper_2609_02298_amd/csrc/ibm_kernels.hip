@@ -101,11 +101,20 @@ __device__ __forceinline__ double wave_max(double v) {
 // Sums a, b, c, d and maxima m1, m2 over the workgroup, each in a fixed
 // order: wave totals, then the wave totals (one lane of wave 0 each) by the
 // same wave tree.  The results are valid in the threads of wave 0.
+// Threads at or past `nlive` must hold a = b = c = d = +0 and maxima that are
+// 0 or held by a live thread as well (all values are non-negative): a wave
+// with no live thread writes those totals without reducing them, which is
+// what its tree would give.  On the IB pass's one compute unit the FP64
+// wave reductions of sixteen waves compete for four SIMDs.
 __device__ __forceinline__ void block_reduce6(double &a, double &b, double &c, double &d, double &m1,
-                                              double &m2, double *red) {
+                                              double &m2, double *red, int nlive) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d);
-  m1 = wave_max(m1); m2 = wave_max(m2);
+  if (wv * 64 < nlive) {
+    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d);
+    m1 = wave_max(m1); m2 = wave_max(m2);
+  } else {
+    a = 0.0; b = 0.0; c = 0.0; d = 0.0; m1 = 0.0; m2 = 0.0;
+  }
   // (red is used once per pass, so nothing earlier needs a barrier here)
   if (lane == 0) {
     red[6 * wv] = a; red[6 * wv + 1] = b; red[6 * wv + 2] = c; red[6 * wv + 3] = d;
@@ -620,9 +629,10 @@ __device__ __forceinline__ bool hold_wait(CaseState *cs, int nhold) {
 }
 
 // The tiles of a fused step wait here until the IB pass of the launch has
-// done its loads from device memory (CaseState::gate == seq), so that those
-// loads do not queue behind the tiles' streaming.  A schedule, not a
-// dependency: after the spin limit the workgroup goes ahead anyway.
+// read its kinematics and copied its cached tables from device memory
+// (CaseState::gate == seq), so that those dependent loads do not queue
+// behind the tiles' streaming.  A schedule, not a dependency: after the
+// spin limit the workgroup goes ahead anyway.
 constexpr int kGateSpins = 1 << 16;
 __device__ __forceinline__ void gate_wait(const CaseState *cs, int seq) {
   if (threadIdx.x == 0) {
@@ -826,6 +836,14 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       }
     }
   }
+  // fused step: kinematics and tables are in LDS, the tiles may stream.  The
+  // pass's remaining loads from device memory (the staged support
+  // populations) then run beside the stream: opening the gate here rather
+  // than after them shortens the FP32 step by about 2 us (28.1 against 30.6
+  // us on the 2000x800 cylinder; 28.7 with the gate at the kinematics
+  // barrier, 28.7 after the source workgroups' count).
+  if constexpr (SELF_COL >= 0)
+    if (tid == 0) gate_open(c.state, seq);
   if (B.udes == kUdTaylorGreen) {
     // IB-LBM mode of the Taylor-Green check (App. D.1): the fixed markers are
     // driven to the decaying vortex of Eq. D1 at t_{n+1}, origin at node (0, 0)
@@ -891,9 +909,6 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
       }
     }
     __syncthreads();
-    // fused step: the pass's loads from device memory are done
-    if constexpr (SELF_COL >= 0)
-      if (tid == 0) gate_open(c.state, seq);
     T *frc = (T *)c.force;
     double *accx = B.acc, *accy = B.acc + B.max_nodes;
     if (B.scheme == kDF) {
@@ -1446,13 +1461,19 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   }
   __syncthreads();
   // ---- 5. slip with the post-IB velocity, reductions, body update
+  // The marker-space passes leave the velocity at the markers, so no lane
+  // group interpolates here, and marker k's lanes are k, k + nb, ...: the
+  // slip terms then sit in the first nb threads, like the force sums, and
+  // only their waves reduce.  Otherwise lane h of marker k is LPM k + h.
+  const bool mspace = FAST && L.bw > 0 && ish[13] == kMDF;
+  const int nlive = mspace ? nb : LPM * nb;
   double slip_sum = 0, slip_max = 0;
   for (int kk = tid; kk < LPM * nb; kk += nth) {
-    const int k = kk / LPM, h = kk % LPM;
+    const int k = mspace ? kk % nb : kk / LPM, h = mspace ? kk / nb : kk % LPM;
     double Ux, Uy;
     if (!FAST && B.scheme == kDFC) {
       interp_packed_u<NS, LPM, T>(L, k, h, (const T *)L.stage, B.max_nodes, Ux, Uy);
-    } else if (FAST && L.bw > 0 && B.scheme == kMDF) {
+    } else if (mspace) {
       Ux = L.Ux[k];  // the marker-space passes end with the post-IB velocity
       Uy = L.Uy[k];
     } else {
@@ -1486,7 +1507,7 @@ __device__ __forceinline__ void body_step(const CaseDesc &c, const BodyDesc &B, 
   }
   double a = fsum_x, b = fsum_y, cq = tq, m = fmax(resmax, 0.0);
   double s1 = slip_sum, s4 = slip_max;
-  block_reduce6(a, b, cq, s1, m, s4, red);
+  block_reduce6(a, b, cq, s1, m, s4, red, nlive);
   if (tid == 0) {
     // every value is formed in registers and written once (no read-back of
     // device memory on this serial tail; the descriptor values come from
@@ -1675,10 +1696,10 @@ __global__ __launch_bounds__(FAST ? kIbmThreadsFast : kIbmThreads) void ibm_kern
 // the force of the previous pass (the hold tiles read and clear it before
 // the pass writes the new one), so nothing in the launch depends on
 // anything but that count, and consecutive steps are ordered by the stream
-// alone.  The tiles start streaming once the pass has done its loads from
-// device memory (gate_wait, when `gated`): beside a chip-wide stream those
-// loads take several times longer, and in FP32 the pass is the launch's
-// critical path (in FP64 the tiles are, and they start at once).
+// alone.  The tiles start streaming once the pass has its kinematics and
+// tables (gate_wait, when `gated`): beside a chip-wide stream those
+// dependent loads take several times longer.  In FP64 the tiles bound the
+// launch and start at once.
 
 // The IB workgroup of a fused step: the pass, then the case-level update of
 // a single-body case (the same as ibm_kernel's), after the hold tiles have
