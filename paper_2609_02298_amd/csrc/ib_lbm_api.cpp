@@ -789,8 +789,7 @@ ib_lbm_status enqueue_fused(ib_lbm_sim *s, int64_t nsteps, hipStream_t stream, i
     fa.nsrc = (s->bodies[0].dev.n_src + kFusedThreads - 1) / kFusedThreads;
     // FP32: the tiles wait for the IB pass's kinematics and tables (28.1 us
     // per step on the 2000x800 cylinder); FP64: the tiles bound the launch
-    // and start at once (43.6 against 47.8 us with a wait, measured when the
-    // gate stood after the pass's support loads)
+    // and start at once (37.6 against 42.4 us with the same wait)
     fa.gated = s->cd.precision == IB_LBM_FP32_SHIFTED ? 1 : 0;
     fa.cd = s->cd;
     fa.bd = s->bodies[0].dev;
